@@ -1,0 +1,243 @@
+"""Seeded synthetic LP generators.
+
+Every instance has the form of the paper's primal problem (Sec. 2, eq. (LP)):
+``min c'x  s.t.  Ax = b, Gx >= h, l <= x <= u`` with ``K = [A; G]`` stored as
+CSR (equality rows first) and ``q = [b; h]``.
+
+Feasibility and boundedness come from a primal/dual certificate built into the
+data, not from solving anything:
+
+* a primal point ``x0`` inside the bounds with ``b = A x0`` and
+  ``h = G x0 - s`` for a slack ``s >= 0``;
+* a dual point ``y0`` (sign-constrained on the ``G`` rows) and a bound
+  multiplier ``lam0`` in the cone ``Lambda`` of each variable, with
+  ``c = K' y0 + lam0``.
+
+Weak duality then sandwiches the optimum: ``dobj(y0, lam0) <= opt <= c'x0``.
+
+This module only draws random numbers and forms the data.  It holds none of the
+solver's arithmetic and is shared by the oracle tests and by the GPU tests and
+bench, so both sides see the same bytes.  All generators use
+``numpy.random.Generator(PCG64(seed))``.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import numpy as np
+import scipy.sparse as sp
+
+
+@dataclass
+class LPData:
+    """One LP in the paper's stacked form.
+
+    ``row_ptr/col/val`` is the CSR of K (m x n, int32 indices, float64 values),
+    ``m1`` the number of equality rows (they come first).  ``l``/``u`` use
+    -inf/+inf for absent bounds.  ``x0, y0, lam0, s`` are the certificate.
+    """
+    m: int
+    n: int
+    m1: int
+    row_ptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray
+    c: np.ndarray
+    q: np.ndarray
+    l: np.ndarray
+    u: np.ndarray
+    x0: np.ndarray | None = None
+    y0: np.ndarray | None = None
+    lam0: np.ndarray | None = None
+    s: np.ndarray | None = None
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.row_ptr[-1])
+
+    def csr(self) -> sp.csr_matrix:
+        return sp.csr_matrix((self.val, self.col, self.row_ptr), shape=(self.m, self.n))
+
+
+# ----------------------------------------------------------------------------
+# building blocks
+# ----------------------------------------------------------------------------
+
+def _distinct_rows_per_column(rng: np.random.Generator, counts: np.ndarray, m: int):
+    """For column j draw ``counts[j]`` distinct rows uniformly from [0, m).
+
+    Returns (rows, cols) as int64 arrays sorted by (col, row).
+    Duplicates inside a column are redrawn until none remain.
+    """
+    n = counts.shape[0]
+    if np.any(counts > m):
+        raise ValueError("a column asks for more distinct rows than exist")
+    cols = np.repeat(np.arange(n, dtype=np.int64), counts)
+    rows = rng.integers(0, m, size=cols.shape[0], dtype=np.int64)
+    while True:
+        key = cols * m + rows
+        order = np.argsort(key, kind="stable")
+        key = key[order]
+        rows = rows[order]
+        cols = cols[order]
+        dup = np.zeros(key.shape[0], dtype=bool)
+        dup[1:] = key[1:] == key[:-1]
+        nd = int(dup.sum())
+        if nd == 0:
+            return rows, cols
+        rows[dup] = rng.integers(0, m, size=nd, dtype=np.int64)
+
+
+def _to_csr(rows, cols, vals, m, n):
+    """Triplets (no duplicates) -> CSR with columns sorted inside each row."""
+    key = rows * n + cols
+    order = np.argsort(key, kind="stable")
+    r = rows[order]
+    counts = np.bincount(r, minlength=m)
+    row_ptr = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    if row_ptr[-1] >= 2**31:
+        raise ValueError("nnz does not fit int32")
+    return (row_ptr.astype(np.int32), cols[order].astype(np.int32),
+            np.ascontiguousarray(vals[order], dtype=np.float64))
+
+
+def _bounds(rng, n, box_hi=10.0):
+    """n/2 boxed [0, box_hi], n/4 lower-only [0, inf), the rest free.
+
+    Returns (l, u, kind) with kind 0=boxed, 1=lower-only, 2=free, assigned by
+    a seeded permutation.
+    """
+    perm = rng.permutation(n)
+    nb, nl = n // 2, n // 4
+    kind = np.empty(n, dtype=np.int8)
+    kind[perm[:nb]] = 0
+    kind[perm[nb:nb + nl]] = 1
+    kind[perm[nb + nl:]] = 2
+    l = np.where(kind == 2, -np.inf, 0.0)
+    u = np.where(kind == 0, box_hi, np.inf)
+    return l, u, kind
+
+
+def certificate_lp(rng: np.random.Generator, m1: int, m2: int, counts: np.ndarray,
+                   value_sampler=None, row_scale_exp: float | None = None,
+                   meta: dict | None = None) -> LPData:
+    """Random sparse K with the given column counts, plus a certificate.
+
+    Draw order (fixed, part of the recipe): rows per column, values, row
+    scales (if any), bound kinds, x0, s, y0, lam0.
+    """
+    n = counts.shape[0]
+    m = m1 + m2
+    rows, cols = _distinct_rows_per_column(rng, counts, m)
+    vals = rng.standard_normal(rows.shape[0]) if value_sampler is None else value_sampler(rows.shape[0])
+    if row_scale_exp is not None:
+        rs = 10.0 ** rng.uniform(-row_scale_exp, row_scale_exp, size=m)
+        vals = vals * rs[rows]
+    row_ptr, col, val = _to_csr(rows, cols, vals, m, n)
+    K = sp.csr_matrix((val, col, row_ptr), shape=(m, n))
+    l, u, kind = _bounds(rng, n)
+    x0 = rng.uniform(0.0, 5.0, size=n)
+    s = rng.uniform(0.0, 1.0, size=m2)
+    y0 = np.concatenate([rng.standard_normal(m1), rng.uniform(0.0, 1.0, size=m2)])
+    g = rng.standard_normal(n)
+    lam0 = np.where(kind == 0, g, np.where(kind == 1, np.abs(g), 0.0))
+    Kx0 = K @ x0
+    q = np.concatenate([Kx0[:m1], Kx0[m1:] - s])
+    c = K.T @ y0 + lam0
+    return LPData(m=m, n=n, m1=m1, row_ptr=row_ptr, col=col, val=val, c=c, q=q,
+                  l=l, u=u, x0=x0, y0=y0, lam0=lam0, s=s, meta=dict(meta or {}))
+
+
+def power_law_counts(rng, n, kmax=200, exponent=1.534):
+    """Column counts on {1..kmax} with P(k) proportional to k^-exponent.
+
+    With kmax=200 and exponent 1.534 the mean is 10 (P(k=1) ~ 0.42).
+    """
+    k = np.arange(1, kmax + 1, dtype=np.float64)
+    p = k ** (-exponent)
+    p /= p.sum()
+    return rng.choice(kmax, size=n, p=p).astype(np.int64) + 1
+
+
+# ----------------------------------------------------------------------------
+# the workloads
+# ----------------------------------------------------------------------------
+
+def tiny_lp(seed: int = 0, n: int = 1000, m1: int = 200, m2: int = 300, per_col: int = 5) -> LPData:
+    """Tiny random LP: n=1000, m1=200, m2=300, 5 nonzeros per column, N(0,1)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    counts = np.full(n, per_col, dtype=np.int64)
+    return certificate_lp(rng, m1, m2, counts,
+                          meta={"workload": "tiny_random_lp", "seed": seed, "n": n, "m1": m1, "m2": m2})
+
+
+def large_lp(seed: int = 1, n: int = 2_000_000, m1: int = 500_000, m2: int = 500_000) -> LPData:
+    """Large LP: power-law column counts (1..200, mean 10), N(0,1) values times
+    10^U(-3,3) per row.  Defaults are the 2e6 x 1e6, ~2e7-nonzero instance;
+    the 4e6 x 2e6 mixed-precision instance uses n=4e6, m1=m2=1e6, seed 2.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    counts = power_law_counts(rng, n)
+    return certificate_lp(rng, m1, m2, counts, row_scale_exp=3.0,
+                          meta={"workload": "large_powerlaw_lp", "seed": seed, "n": n, "m1": m1, "m2": m2})
+
+
+def batch_member(seed: int, n_lo: float = 2e3, n_hi: float = 2e5) -> LPData:
+    """One member of the batched workload: n log-uniform in [n_lo, n_hi],
+    m = n/2 split 2:3 into equality/inequality rows, 3..8 nonzeros per column."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = int(round(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi)))))
+    m = max(n // 2, 2)
+    m1 = (2 * m) // 5
+    m2 = m - m1
+    counts = rng.integers(3, 9, size=n).astype(np.int64)
+    return certificate_lp(rng, m1, m2, counts,
+                          meta={"workload": "batch_member", "seed": seed, "n": n, "m1": m1, "m2": m2})
+
+
+def box_only_lp(seed: int, n: int = 8) -> LPData:
+    """m = 0: min c'x over a box (closed form: each x_j at the bound c_j pushes to)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    l = rng.uniform(-3.0, 0.0, size=n)
+    u = l + rng.uniform(0.5, 4.0, size=n)
+    c = rng.standard_normal(n)
+    return LPData(m=0, n=n, m1=0, row_ptr=np.zeros(1, np.int32), col=np.zeros(0, np.int32),
+                  val=np.zeros(0), c=c, q=np.zeros(0), l=l, u=u, meta={"workload": "box_only"})
+
+
+def dense_small_lp(seed: int, n: int, m1: int, m2: int, density: float = 0.7, box: float = 4.0) -> LPData:
+    """Small LP with all variables boxed [0, box] (a bounded polytope), random
+    sparse K and a certificate; used for brute-force vertex enumeration."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = m1 + m2
+    mask = rng.uniform(size=(m, n)) < density
+    for i in range(m):
+        if not mask[i].any():
+            mask[i, rng.integers(n)] = True
+    dense = np.where(mask, rng.standard_normal((m, n)), 0.0)
+    rows, cols = np.nonzero(dense)
+    row_ptr, col, val = _to_csr(rows.astype(np.int64), cols.astype(np.int64), dense[rows, cols], m, n)
+    K = sp.csr_matrix((val, col, row_ptr), shape=(m, n))
+    l = np.zeros(n)
+    u = np.full(n, box)
+    x0 = rng.uniform(0.5, box - 0.5, size=n)
+    s = rng.uniform(0.0, 1.0, size=m2)
+    y0 = np.concatenate([rng.standard_normal(m1), rng.uniform(0.0, 1.0, size=m2)])
+    lam0 = rng.standard_normal(n)
+    Kx0 = K @ x0
+    q = np.concatenate([Kx0[:m1], Kx0[m1:] - s])
+    c = K.T @ y0 + lam0
+    return LPData(m=m, n=n, m1=m1, row_ptr=row_ptr, col=col, val=val, c=c, q=q, l=l, u=u,
+                  x0=x0, y0=y0, lam0=lam0, s=s, meta={"workload": "dense_small", "seed": seed})
+
+
+def from_dense(Kd, c, q, l, u, m1) -> LPData:
+    """Wrap a small dense problem given by hand."""
+    Kd = np.atleast_2d(np.asarray(Kd, dtype=np.float64))
+    m, n = Kd.shape
+    rows, cols = np.nonzero(Kd)
+    row_ptr, col, val = _to_csr(rows.astype(np.int64), cols.astype(np.int64), Kd[rows, cols], m, n)
+    return LPData(m=m, n=n, m1=int(m1), row_ptr=row_ptr, col=col, val=val,
+                  c=np.asarray(c, np.float64), q=np.asarray(q, np.float64),
+                  l=np.asarray(l, np.float64), u=np.asarray(u, np.float64), meta={"workload": "hand"})

@@ -1,0 +1,79 @@
+"""Helpers shared by the tests: independent solvers and hand-derivable checks.
+
+Nothing here calls the oracle or the GPU library."""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+
+import numpy as np
+import scipy.optimize as so
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def load_golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def fnum(v):
+    if isinstance(v, str):
+        return float(v)
+    return float(v)
+
+
+def highs(lp):
+    """Solve with scipy's HiGHS: returns (objective, x, y) with y = duals of K rows
+    in the paper's sign convention (y_G >= 0 for Gx >= h)."""
+    K = lp.csr()
+    m1 = lp.m1
+    bounds = [(None if np.isinf(a) else a, None if np.isinf(b) else b) for a, b in zip(lp.l, lp.u)]
+    kw = {}
+    if m1 > 0:
+        kw["A_eq"] = K[:m1]
+        kw["b_eq"] = lp.q[:m1]
+    if lp.m - m1 > 0:
+        kw["A_ub"] = -K[m1:]
+        kw["b_ub"] = -lp.q[m1:]
+    res = so.linprog(lp.c, bounds=bounds, method="highs", **kw)
+    assert res.status == 0, res.message
+    y = np.zeros(lp.m)
+    if m1 > 0:
+        y[:m1] = res.eqlin.marginals
+    if lp.m - m1 > 0:
+        y[m1:] = -res.ineqlin.marginals
+    return res.fun, res.x, y
+
+
+def brute_force_vertices(Kd, q, m1, l, u, c):
+    """Minimum of c'x over the vertices of {Ax=b, Gx>=h, l<=x<=u} (all bounds finite).
+
+    Every vertex makes n linearly independent constraints active, and the
+    equalities are always active: try every choice of n - m1 more from the G
+    rows and the 2n bounds, solve, keep the feasible points."""
+    Kd = np.asarray(Kd, float)
+    m, n = Kd.shape
+    rows = [(Kd[i], q[i]) for i in range(m1, m)]
+    for j in range(n):
+        e = np.zeros(n); e[j] = 1.0
+        rows.append((e, l[j]))
+        rows.append((e, u[j]))
+    best = np.inf
+    best_x = None
+    for pick in itertools.combinations(range(len(rows)), n - m1):
+        M = np.vstack([Kd[:m1]] + [rows[p][0][None, :] for p in pick]) if m1 else \
+            np.vstack([rows[p][0][None, :] for p in pick])
+        rhs = np.concatenate([q[:m1], [rows[p][1] for p in pick]])
+        if abs(np.linalg.det(M)) < 1e-10:
+            continue
+        x = np.linalg.solve(M, rhs)
+        ok = np.all(x >= l - 1e-9) and np.all(x <= u + 1e-9)
+        ok = ok and np.allclose(Kd[:m1] @ x, q[:m1], atol=1e-9)
+        ok = ok and np.all(Kd[m1:] @ x >= q[m1:] - 1e-9)
+        if ok:
+            v = float(c @ x)
+            if v < best:
+                best, best_x = v, x
+    return best, best_x

@@ -1,0 +1,270 @@
+"""Pins of the FP64 CPU oracle against things other than itself:
+HiGHS optima, brute-force vertex enumeration, closed forms, KKT and
+complementary slackness, the fixed-point property of PDHG at an optimum,
+hand-derived termination and scaling values (tests/golden), and the restart
+rule's constants (cuPDLP-C paper, Sec. 2 'Restart criteria')."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2312_14832_amd import gen
+from lp_helpers import brute_force_vertices, fnum, highs, load_golden
+
+
+# ---------------------------------------------------------------- end results
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_objective_matches_highs(oracle_mod, seed):
+    """The paper's LP pair (eq. (LP)): at rel KKT 1e-8 the primal objective
+    agrees with HiGHS to 1e-6 relative."""
+    lp = gen.tiny_lp(seed)
+    ref, _, _ = highs(lp)
+    o = oracle_mod.Oracle(lp)
+    x, y, lam, info = o.solve(1e-8, 400_000)
+    assert info["status"] == "OPTIMAL"
+    assert abs(info["pobj"] - ref) <= 1e-6 * abs(ref)
+    assert abs(info["dobj"] - ref) <= 1e-6 * abs(ref)
+
+
+@pytest.mark.parametrize("seed,n,m1,m2", [(11, 3, 1, 2), (12, 4, 1, 3), (13, 4, 2, 2), (14, 5, 1, 3),
+                                         (15, 5, 0, 4), (16, 3, 0, 3)])
+def test_objective_matches_vertex_enumeration(oracle_mod, seed, n, m1, m2):
+    lp = gen.dense_small_lp(seed, n, m1, m2)
+    Kd = lp.csr().toarray()
+    best, _ = brute_force_vertices(Kd, lp.q, m1, lp.l, lp.u, lp.c)
+    o = oracle_mod.Oracle(lp)
+    _, _, _, info = o.solve(1e-9, 2_000_000)
+    assert info["status"] == "OPTIMAL"
+    assert abs(info["pobj"] - best) <= 1e-6 * max(1.0, abs(best))
+
+
+@pytest.mark.parametrize("seed", [0, 5])
+def test_certificate_sandwich(oracle_mod, seed):
+    """Weak duality with the generator's certificate: dobj(y0,lam0) <= opt <= c'x0."""
+    lp = gen.tiny_lp(seed)
+    lo = lp.q @ lp.y0 + np.sum(np.where(np.isfinite(lp.l), lp.l, 0.0) * np.maximum(lp.lam0, 0)) \
+        - np.sum(np.where(np.isfinite(lp.u), lp.u, 0.0) * np.maximum(-lp.lam0, 0))
+    hi = lp.c @ lp.x0
+    o = oracle_mod.Oracle(lp)
+    _, _, _, info = o.solve(1e-8, 400_000)
+    assert lo - 1e-6 * abs(lo) <= info["pobj"] <= hi + 1e-6 * abs(hi)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_box_only_closed_form(oracle_mod, seed):
+    """m = 0: the optimum puts x_j at l_j when c_j > 0 and at u_j when c_j < 0."""
+    lp = gen.box_only_lp(seed, n=9)
+    o = oracle_mod.Oracle(lp)
+    x, y, lam, info = o.solve(1e-10, 100_000)
+    assert info["status"] == "OPTIMAL"
+    xs = np.where(lp.c > 0, lp.l, lp.u)
+    assert np.allclose(x, xs, rtol=0, atol=1e-8)
+    assert abs(info["pobj"] - lp.c @ xs) <= 1e-9 * abs(lp.c @ xs)
+    assert np.allclose(lam, lp.c, atol=1e-12)
+
+
+@pytest.mark.parametrize("n", [2, 7, 30])
+def test_simplex_closed_form(oracle_mod, n):
+    """min c'x, sum x = 1, x >= 0 has optimum min_j c_j."""
+    rng = np.random.default_rng(n)
+    c = rng.standard_normal(n)
+    lp = gen.from_dense(np.ones((1, n)), c, [1.0], np.zeros(n), np.full(n, np.inf), 1)
+    o = oracle_mod.Oracle(lp)
+    _, _, _, info = o.solve(1e-10, 1_000_000)
+    assert info["status"] == "OPTIMAL"
+    assert abs(info["pobj"] - c.min()) <= 1e-7 * max(1, abs(c.min()))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_fractional_knapsack_closed_form(oracle_mod, seed):
+    """max v'x, w'x <= W, 0 <= x <= 1 (as min -v'x, -w'x >= -W): greedy by v/w."""
+    rng = np.random.default_rng(100 + seed)
+    n = 12
+    v = rng.uniform(1, 5, n); w = rng.uniform(1, 5, n); W = 0.4 * w.sum()
+    order = np.argsort(-v / w)
+    cap, best = W, 0.0
+    for j in order:
+        take = min(1.0, cap / w[j])
+        best += take * v[j]; cap -= take * w[j]
+        if cap <= 0:
+            break
+    lp = gen.from_dense(-w[None, :], -v, [-W], np.zeros(n), np.ones(n), 0)
+    o = oracle_mod.Oracle(lp)
+    _, _, _, info = o.solve(1e-10, 1_000_000)
+    assert info["status"] == "OPTIMAL"
+    assert abs(-info["pobj"] - best) <= 1e-7 * best
+
+
+def test_complementary_slackness(oracle_mod):
+    """At the oracle's 1e-9 point: lam+ (x-l) ~ 0, lam- (u-x) ~ 0, y_G (Gx-h) ~ 0,
+    y_G >= 0, lam in Lambda, and the gap is ~0 (zero duality gap of eq. (LP))."""
+    lp = gen.tiny_lp(4)
+    o = oracle_mod.Oracle(lp)
+    x, y, lam, info = o.solve(1e-9, 1_000_000)
+    K = lp.csr()
+    scale = 1 + np.abs(lp.c).max()
+    fl = np.isfinite(lp.l); fu = np.isfinite(lp.u)
+    assert np.all(np.abs(np.maximum(lam, 0)[fl] * (x - lp.l)[fl]) < 1e-5 * scale)
+    assert np.all(np.abs(np.maximum(-lam, 0)[fu] * (lp.u - x)[fu]) < 1e-5 * scale)
+    Gx = (K @ x)[lp.m1:]
+    assert np.all(y[lp.m1:] >= 0)
+    assert np.all(np.abs(y[lp.m1:] * (Gx - lp.q[lp.m1:])) < 1e-5 * scale)
+    assert np.all(lam[~fl & ~fu] == 0) and np.all(lam[fl & ~fu] >= 0) and np.all(lam[~fl & fu] <= 0)
+    assert abs(info["dobj"] - info["pobj"]) <= 1e-8 * (1 + abs(info["pobj"]))
+
+
+def test_pdhg_fixed_point_at_optimum(oracle_mod):
+    """An optimal primal-dual pair is a fixed point of the primal and dual PDHG
+    updates (Sec. 2, 'Restarted PDHG'): one step from HiGHS's (x*, y*) stays put."""
+    lp = gen.tiny_lp(6)
+    _, xs, ys = highs(lp)
+    o = oracle_mod.Oracle(lp)
+    o.set_start(xs, ys)
+    o.solve(1e-30, 1)
+    st = o.get_state()
+    Dr, Dc, _ = o.scaling()
+    x1 = st["x"] / Dc
+    y1 = st["y"] / Dr
+    assert np.linalg.norm(x1 - xs) <= 1e-7 * np.linalg.norm(xs)
+    assert np.linalg.norm(y1 - ys) <= 1e-7 * np.linalg.norm(ys)
+
+
+# ---------------------------------------------------------------- pieces
+
+def test_termination_quantities_hand_example(oracle_mod):
+    g = load_golden("termination_3var.json")
+    Kd = np.array(g["K"], float)
+    lp = gen.from_dense(Kd, g["c"], g["q"], [fnum(a) for a in g["l"]], [fnum(a) for a in g["u"]], g["m1"])
+    o = oracle_mod.Oracle(lp)
+    r = o.eval_unscaled(np.array(g["x"], float), np.array(g["y"], float))
+    for key, val in g["expect"].items():
+        assert r[key] == pytest.approx(val, rel=1e-14, abs=1e-15), key
+
+
+def test_scaling_hand_examples(oracle_mod):
+    g = load_golden("scaling_hand.json")
+    for case in g["cases"]:
+        Kd = np.array(case["K"], float)
+        m, n = Kd.shape
+        lp = gen.from_dense(Kd, np.ones(n), np.ones(m), np.zeros(n), np.full(n, np.inf), m)
+        o = oracle_mod.Oracle(lp, ruiz_iters=case["ruiz_iters"], pc_alpha=case["pc_alpha"])
+        Dr, Dc, kv = o.scaling()
+        assert np.allclose(Dr, case["Dr"], rtol=1e-15, atol=0), case["name"]
+        assert np.allclose(Dc, case["Dc"], rtol=1e-15, atol=0), case["name"]
+        Kt = np.zeros((m, n))
+        rp, ci = lp.row_ptr, lp.col
+        for i in range(m):
+            for p in range(rp[i], rp[i + 1]):
+                Kt[i, ci[p]] = kv[p]
+        assert np.allclose(Kt, case["Ktilde"], rtol=1e-15, atol=0), case["name"]
+
+
+def test_ruiz_equilibrates_inf_norms(oracle_mod):
+    """Many Ruiz rounds drive every row and column inf-norm of K~ to 1."""
+    lp = gen.large_lp(seed=3, n=3000, m1=700, m2=800)
+    o = oracle_mod.Oracle(lp, ruiz_iters=60, pc_alpha=-1.0)
+    Dr, Dc, kv = o.scaling()
+    A = lp.csr().copy(); A.data = np.abs(kv)
+    rmax = A.max(axis=1).toarray().ravel(); cmax = A.max(axis=0).toarray().ravel()
+    nz_r = np.diff(lp.row_ptr) > 0
+    assert np.all(np.abs(rmax[nz_r] - 1) < 1e-6)
+    assert np.all(np.abs(cmax - 1) < 1e-6)
+    # K~ = D_r^-1 K D_c^-1 exactly as stated
+    rows = np.repeat(np.arange(lp.m), np.diff(lp.row_ptr))
+    assert np.allclose(kv, lp.val / (Dr[rows] * Dc[lp.col]), rtol=1e-13)
+
+
+def test_objective_invariant_under_scaling(oracle_mod):
+    lp = gen.large_lp(seed=4, n=2000, m1=500, m2=500)
+    o = oracle_mod.Oracle(lp)
+    x, y, lam, info = o.solve(1e-4, 200_000)
+    r = o.eval_unscaled(x, y)
+    assert r["pobj"] == pytest.approx(info["pobj"], rel=1e-12)
+    assert r["dobj"] == pytest.approx(info["dobj"], rel=1e-10, abs=1e-10)
+    assert r["rel_kkt"] <= 1e-4 * (1 + 1e-9)
+
+
+@pytest.mark.parametrize("kkt_c,kkt0,prev,t,k,want", [
+    (0.19, 1.0, np.inf, 10, 1000, 1),    # sufficient decay (<= 0.2)
+    (0.2, 1.0, np.inf, 10, 1000, 1),     # boundary: <= is inclusive
+    (0.5, 1.0, 0.4, 10, 1000, 2),        # necessary decay and no local progress
+    (0.5, 1.0, 0.6, 10, 1000, 0),        # progress since the last check
+    (0.8, 1.0, 0.7, 10, 1000, 2),        # boundary 0.8 inclusive
+    (0.81, 1.0, 0.7, 10, 1000, 0),
+    (0.5, 1.0, 0.5, 10, 1000, 0),        # equal -> not strictly greater
+    (0.9, 1.0, np.inf, 36, 100, 3),      # long inner loop t >= 0.36 k
+    (0.9, 1.0, np.inf, 35, 100, 0),
+    (0.9, 1.0, np.inf, 64, 64, 3),       # first check of the first inner loop
+])
+def test_restart_decision_table(oracle_mod, kkt_c, kkt0, prev, t, k, want):
+    """Restart conditions 1-3 with the paper's constants 0.2, 0.8, 0.36."""
+    assert oracle_mod.restart_decision(kkt_c, kkt0, prev, t, k) == want
+
+
+@pytest.mark.parametrize("omega,dx,dy", [(1.0, 2.0, 8.0), (0.3, 1e-3, 5.0), (7.0, 3.0, 0.02)])
+def test_omega_update_is_smoothed_geometric_mean(oracle_mod, omega, dx, dy):
+    got = oracle_mod.omega_update(omega, dx, dy)
+    assert got == pytest.approx(math.sqrt(omega * dy / dx), rel=1e-14)
+    assert oracle_mod.omega_update(omega, 1e-11, dy) == omega
+    assert oracle_mod.omega_update(omega, dx, 0.0) == omega
+
+
+def test_step_rule_constants(oracle_mod):
+    """PDLP adaptive rule: eta' = min((1-kk^-0.3) eta_bar, (1+kk^-0.6) eta), kk from 2."""
+    lo0, hi0 = 1 - 2 ** -0.3, 1 + 2 ** -0.6
+    assert lo0 == pytest.approx(0.18774760364376437, rel=1e-15)
+    assert oracle_mod.step_next(1.0, np.inf, 0) == pytest.approx(hi0, rel=1e-15)
+    assert oracle_mod.step_next(1.0, 1.0, 0) == pytest.approx(lo0, rel=1e-15)
+    # as k grows the cap on growth shrinks to 1 and the shrink factor to 1
+    assert oracle_mod.step_next(1.0, np.inf, 10**8) == pytest.approx(1.0, abs=2e-5)
+    assert oracle_mod.step_next(1.0, 1.0, 10**8) == pytest.approx(1.0, abs=5e-3)
+
+
+# ---------------------------------------------------------------- invariants
+
+def test_iterate_invariants_and_resume(oracle_mod):
+    """x stays in the box, y_G >= 0, averages are convex combinations, and
+    N + N resumed steps equal 2N steps bitwise."""
+    lp = gen.tiny_lp(7)
+    o = oracle_mod.Oracle(lp)
+    o.solve(1e-30, 192)
+    st = o.get_state()
+    Dr, Dc, _ = o.scaling()
+    ls, us = lp.l * Dc, lp.u * Dc
+    for key in ("x", "xbar"):
+        assert np.all(st[key] >= ls) and np.all(st[key] <= us)
+    for key in ("y", "ybar"):
+        assert np.all(st[key][lp.m1:] >= 0)
+    assert st["k"] == 192
+    full = o.get_state_raw()
+    o2 = oracle_mod.Oracle(lp)
+    o2.solve(1e-30, 96)
+    mid = o2.get_state_raw()
+    o3 = oracle_mod.Oracle(lp)
+    o3.set_state_raw(mid)
+    o3.solve(1e-30, 192)
+    assert np.array_equal(o3.get_state_raw()[16:], full[16:])
+
+
+@pytest.mark.parametrize("mut,code", [("nan_val", -3), ("inf_c", -3), ("l_gt_u", -4), ("l_posinf", -4),
+                                      ("col_oob", -2), ("dup", -2), ("m1_gt_m", -2)])
+def test_validation_codes(oracle_mod, mut, code):
+    lp = gen.tiny_lp(0)
+    if mut == "nan_val":
+        lp.val = lp.val.copy(); lp.val[3] = np.nan
+    elif mut == "inf_c":
+        lp.c = lp.c.copy(); lp.c[0] = np.inf
+    elif mut == "l_gt_u":
+        lp.l = lp.l.copy(); lp.u = lp.u.copy(); lp.l[0] = 5.0; lp.u[0] = 4.0
+    elif mut == "l_posinf":
+        lp.l = lp.l.copy(); lp.l[0] = np.inf
+    elif mut == "col_oob":
+        lp.col = lp.col.copy(); lp.col[0] = lp.n
+    elif mut == "dup":
+        lp.col = lp.col.copy(); lp.col[1] = lp.col[0]
+    elif mut == "m1_gt_m":
+        lp.m1 = lp.m + 1
+    with pytest.raises(oracle_mod.OracleError) as ei:
+        oracle_mod.Oracle(lp)
+    assert ei.value.code == code
