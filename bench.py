@@ -1,0 +1,209 @@
+"""Throughput of the restarted-PDHG hot path on one MI355X.
+
+A step is one check window: 64 accepted PDHG iterations (both sparse products
+with their fused dual/primal/averaging epilogues, the step-size tests, and the
+termination/restart check that closes the window) on the 2e6-variable,
+1e6-row, ~2e7-nonzero synthetic LP in FP64.  The timed region is one lp_solve
+of K windows that starts after W warm-up windows; problem data and iterates
+are resident in HBM before it starts (load and scaling are excluded, as in the
+paper's timings).
+
+Besides the JSON fields of the harness contract the line carries:
+  roofline      the dominant kernel's algorithmic bytes per launch divided by
+                its mean hipEvent duration over the timed region, against the
+                8 TB/s HBM peak; `traffic` is the counter-measured HBM bytes per
+                launch from profiles/ (null when the kernel changed since)
+  spmv          the same figure for both SpMV kernels
+  cpu_baseline  the FP64 CPU oracle on a bounded sample of the same instance
+  time_to_tol   wall time of a cold solve to relative KKT error 1e-4
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+ITERS_PER_STEP = 64
+HBM_PEAK_GBS = 8000.0
+KERNEL_NAMES = {0: "k_dual<double>", 1: "k_update<double>"}
+
+
+def kernel_bytes(which, n, m, nnz, s=8):
+    """Algorithmic bytes of one launch of the fused SpMV kernels (accepted
+    step, no check in the window): streamed matrix values and indices, row
+    pointers, the gathered vector counted once, and every vector the epilogue
+    reads or writes."""
+    if which == 0:   # K x' + dual update: reads y, Kx, q; writes y', Kx'
+        return nnz * (s + 4) + 4 * (m + 1) + s * n + 5 * s * m
+    # K'y' + averages + next primal: columns read x', c, l, u, xbar, K'ybar and
+    # write K'y', xbar, K'ybar, x''; rows read y', Kx', ybar, Kxbar, write ybar, Kxbar
+    return nnz * (s + 4) + 4 * (n + 1) + s * m + 10 * s * n + 6 * s * m
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2312_14832_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kernel, workload):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    e = d.get(workload, {}).get(kernel)
+    if not e or e.get("source_sha") != kernel_source_sha():
+        return None
+    return e.get("traffic_bytes")
+
+
+def cpu_baseline(data, iters):
+    from oracle.oracle import Oracle
+    o = Oracle(data)
+    t = time.perf_counter()
+    o.solve(1e-30, iters)
+    dt = time.perf_counter() - t
+    return {"value": iters / dt, "unit": "PDHG iters/sec", "cores": 1, "kind": "oracle",
+            "sample": f"{iters} accepted iterations (one check window incl. start-up products) of the "
+                      f"single-threaded FP64 oracle on the same instance, load and scaling excluded",
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=2_000_000)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-1e-4 solve")
+    ap.add_argument("--ttt-limit", type=float, default=90.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run 5 plain device-to-device copies of this many MiB (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU sharding is a design, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2312_14832_amd import gen, lp
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    if args.copy_probe_mib:
+        nbytes = args.copy_probe_mib << 20
+        a = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": nbytes, "copies": 5}))
+        return
+    n = args.n
+    m1 = m2 = n // 4
+    t0 = time.perf_counter()
+    data = gen.large_lp(seed=args.seed, n=n, m1=m1, m2=m2)
+    gen_s = time.perf_counter() - t0
+    print(f"[bench] generated n={n} m={m1 + m2} nnz={data.nnz} in {gen_s:.1f}s", file=sys.stderr, flush=True)
+
+    stream = torch.cuda.current_stream()
+    t0 = time.perf_counter()
+    prob = lp.Problem(data, precision=args.precision, stream=stream, kernel_timing=1)
+    torch.cuda.synchronize()
+    load_s = time.perf_counter() - t0
+    print(f"[bench] loaded in {load_s:.1f}s ({prob.device_bytes() / 2**30:.2f} GiB on device)",
+          file=sys.stderr, flush=True)
+
+    # warm-up windows (also compiles nothing: kernels are prebuilt)
+    prob.solve(1e-30, ITERS_PER_STEP * max(args.warmup, 0))
+    torch.cuda.synchronize()
+
+    K = args.steps
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = prob.solve(1e-30, ITERS_PER_STEP * K)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = info["iterations"]
+    assert iters == ITERS_PER_STEP * K, info
+    s = 8 if args.precision == "fp64" else 4
+    spmv = {}
+    for w in (0, 1):
+        cnt, ms = prob.kernel_time(w)
+        avg_us = 1e3 * ms / max(cnt, 1)
+        b = kernel_bytes(w, n, m1 + m2, data.nnz, s)
+        spmv[KERNEL_NAMES[w]] = {"launches": cnt, "avg_us": avg_us, "alg_bytes": b,
+                                 "GB_s": b / (avg_us * 1e-6) / 1e9 if avg_us > 0 else None}
+    dom = max(spmv, key=lambda k: spmv[k]["avg_us"] * spmv[k]["launches"])
+    d = spmv[dom]
+    workload = f"large_powerlaw_lp_n{n}"
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": d["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": d["GB_s"] / HBM_PEAK_GBS if d["GB_s"] else None,
+                "traffic": counter_traffic(dom, workload), "alg_bytes_per_launch": d["alg_bytes"]}
+    print(f"[bench] {K} windows in {dt:.3f}s -> {iters / dt:.0f} it/s; "
+          + "; ".join(f"{k} {v['avg_us']:.1f}us {v['GB_s']:.0f}GB/s" for k, v in spmv.items()),
+          file=sys.stderr, flush=True)
+
+    ttt = None
+    if not args.no_ttt:
+        t0 = time.perf_counter()
+        tinfo = prob.solve(1e-4, 10**7, args.ttt_limit)
+        torch.cuda.synchronize()
+        tt = time.perf_counter() - t0
+        ttt = {"tol": 1e-4, "seconds": tt, "status": tinfo["status"], "iterations": tinfo["iterations"],
+               "attempts": tinfo["attempts"], "restarts": tinfo["restarts"], "rel_kkt": tinfo["rel_kkt"],
+               "pobj": tinfo["pobj"], "time_limit_s": args.ttt_limit}
+        print(f"[bench] time to 1e-4: {tt:.2f}s {tinfo['status']} after {tinfo['iterations']} iterations",
+              file=sys.stderr, flush=True)
+    prob.close()
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(data, ITERS_PER_STEP)
+        cpu["threads_note"] = f"host has {os.cpu_count()} logical CPUs; the oracle is single-threaded"
+        print(f"[bench] cpu oracle {cpu['value']:.2f} it/s", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "PDHG iters/sec",
+        "value": iters / dt,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64acc",
+        "data": "synthetic",
+        "config": {"workload": workload, "n": n, "m1": m1, "m2": m2, "nnz": data.nnz, "seed": args.seed,
+                   "precision": args.precision, "iters_per_step": ITERS_PER_STEP,
+                   "generator": "power-law column counts 1..200 (mean 10), N(0,1)*10^U(-3,3) per row, "
+                                "certificate-feasible"},
+        "roofline": roofline,
+        "spmv": spmv,
+        "time_to_tol": ttt,
+        "cpu_baseline": cpu,
+        "load_s": load_s,
+        "gen_s": gen_s,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

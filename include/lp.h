@@ -1,0 +1,164 @@
+/*
+ * lp.h -- C ABI of the MI355X restarted-PDHG LP solver (libpdlp_amd.so).
+ *
+ * Problem (cuPDLP-C paper, Sec. 2, eq. (LP)):
+ *     min c'x   s.t.  A x = b,  G x >= h,  l <= x <= u
+ * passed stacked as K = [A; G] (m x n CSR, the m1 equality rows first) and
+ * q = [b; h].  The dual is  max q'y + l'lam+ - u'lam-  s.t. c - K'y = lam,
+ * y_{m1..m-1} >= 0, lam in Lambda; lam is never stored and is returned as
+ * proj_Lambda(c - K'y) (the remark after the termination criteria).
+ *
+ * Method (Sec. 2, "Restarted PDHG" and "Restart criteria"): PDHG on the
+ * saddle-point problem (eq. (saddle-point)) with the primal update
+ * x+ = proj_X(x - (eta/omega)(c - K'y)) and the dual update
+ * y+ = proj_Y(y + eta*omega*(q - K(2x+ - x))), averaging, and restarts chosen
+ * by the KKT_omega error with the constants 0.2, 0.8 and 0.36.  The solve
+ * stops when the three relative criteria of "Optimality termination criteria"
+ * hold at tolerance tol for the current or the averaged iterate.
+ *
+ * Conventions shared by every call
+ *   - Every call returns int: LP_OK (0) or a negative LP_ERR_* code.  The
+ *     solve outcome is lp_info.status.
+ *   - Indices are int32 and 0-based; values are IEEE binary64.  Absent bounds
+ *     are -INFINITY in l and +INFINITY in u.
+ *   - Input pointers are HOST pointers.  Inputs are copied during the call;
+ *     the library keeps no caller pointer.  Outputs go to caller-allocated
+ *     host buffers.
+ *   - Device memory is allocated by the library at lp_load and released by
+ *     lp_free.  All GPU work is ordered on lp_options.stream (a hipStream_t;
+ *     NULL = the null stream) and every call returns after that work is done.
+ *   - A handle is not thread-safe; separate handles are independent.
+ */
+#ifndef PDLP_AMD_LP_H
+#define PDLP_AMD_LP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define LP_OK 0
+#define LP_ERR_ARG (-1)        /* NULL where a pointer is required, bad option value */
+#define LP_ERR_DIM (-2)        /* m1 > m, row_ptr not monotone / not ending at nnz, column out of range, duplicate (row, col) */
+#define LP_ERR_NAN (-3)        /* NaN or +-inf in K, c or q; NaN in l or u */
+#define LP_ERR_BOUNDS (-4)     /* l_j > u_j, l_j = +inf or u_j = -inf */
+#define LP_ERR_TOO_LARGE (-5)  /* m, n or nnz >= 2^31 */
+#define LP_ERR_STATE (-6)      /* lp_result before any lp_solve; state buffer of the wrong size */
+#define LP_ERR_HIP (-7)        /* a HIP runtime call failed; lp_last_error() has the message */
+#define LP_ERR_NOMEM (-8)      /* host or device allocation failed */
+
+/* lp_options.precision */
+#define LP_FP64 0              /* FP64 values, iterates and reductions */
+#define LP_MIXED 1             /* FP32 matrix values and iterates; FP64 reductions, step size and primal weight */
+
+/* lp_info.status */
+#define LP_NOT_SOLVED 0
+#define LP_OPTIMAL 1           /* relative KKT error <= tol */
+#define LP_ITERATION_LIMIT 2
+#define LP_TIME_LIMIT 3
+#define LP_NUMERICAL 4         /* NaN in a step-size or KKT quantity */
+
+typedef struct lp_problem lp_problem;   /* opaque; owned by the library */
+
+/* K in CSR: row_ptr[m+1] (row_ptr[0] = 0, row_ptr[m] = nnz, non-decreasing),
+ * col[nnz] in [0, n) with no duplicate inside a row (any order), val[nnz]. */
+typedef struct {
+    int64_t m, n, nnz;
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const double *val;
+} lp_csr;
+
+typedef struct {
+    int precision;          /* LP_FP64 or LP_MIXED */
+    void *stream;           /* hipStream_t for all GPU work, NULL = null stream */
+    int ruiz_iters;         /* Ruiz inf-norm equilibration rounds (10) */
+    double pc_alpha;        /* Pock-Chambolle exponent (1); < 0 skips that round */
+    int check_every;        /* accepted steps between termination/restart checks (64) */
+    double kkt_omega_power; /* exponent of omega in KKT_omega (2, as printed) */
+    int fixed_step;         /* 0: adaptive step size; 1: constant step fixed_eta, every step accepted */
+    double fixed_eta;
+    int use_graph;          /* 1: replay the iteration window as a captured hipGraph */
+    int window;             /* attempt slots launched between host polls of the done flag (64) */
+    int kernel_timing;      /* 1: bracket the two SpMV kernels with hipEvents (see lp_kernel_time) */
+    int verbose;
+} lp_options;
+
+typedef struct {
+    int status;                             /* LP_OPTIMAL ... */
+    double pobj, dobj;                      /* c'x and q'y + l'lam+ - u'lam- of the returned point */
+    double rel_primal, rel_dual, rel_gap;   /* the three relative termination quantities */
+    int64_t iterations;                     /* accepted PDHG steps */
+    int64_t attempts;                       /* step attempts, rejected ones included */
+    int64_t restarts;
+    double omega, eta;                      /* final primal weight and next step size */
+    double seconds;                         /* wall time of the last lp_solve (load excluded) */
+} lp_info;
+
+/* Fill *opt with the defaults listed above. */
+void lp_default_options(lp_options *opt);
+
+/* Validate, copy to the GPU, reorder rows/columns into length bins, build
+ * the CSR of K', and apply the diagonal scaling on the GPU.  The scaling is
+ * the diagonal preconditioning the paper's experiments apply before PDHG
+ * (Sec. 3.1).  On success *P owns all device memory; on error *P = NULL.
+ * Errors: LP_ERR_ARG, _DIM, _NAN, _BOUNDS, _TOO_LARGE, _HIP, _NOMEM. */
+int lp_load(lp_problem **P, const lp_csr *K, const double *c, const double *q,
+            const double *l, const double *u, int64_t m1, const lp_options *opt);
+
+/* Start point for the next lp_solve: x0[n], y0[m] in the original (unscaled)
+ * space, either may be NULL (= x projected 0, y = 0).  Both are projected onto
+ * X and Y.  Cancels any state set by lp_set_state. */
+int lp_set_start(lp_problem *P, const double *x0, const double *y0);
+
+/* Run restarted PDHG until the relative KKT error <= tol, max_iters accepted
+ * steps in total, or time_limit_s seconds (<= 0: none).  Starts from the
+ * start point, or resumes from a state given by lp_set_state.  A check runs
+ * every check_every accepted steps and at max_iters.  Returns LP_OK even when
+ * the limit is hit; see lp_info.status.  Errors: LP_ERR_ARG, LP_ERR_HIP. */
+int lp_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit_s);
+
+/* Copy the returned point to host buffers x[n], y[m], lambda[n] (each may be
+ * NULL), unscaled and in the original order; lambda = proj_Lambda(c - K'y).
+ * info may be NULL.  Errors: LP_ERR_STATE before the first lp_solve. */
+int lp_result(const lp_problem *P, double *x, double *y, double *lambda, lp_info *info);
+
+/* Solver state for checkpoint/resume and per-step comparison, as doubles in
+ * the scaled space and the original order: 16 scalars
+ * [eta, omega, W, KKT0, KKT_prev, k, t, attempts, restarts, status, eta_last, 0 ...]
+ * then x[n] y[m] Kx[m] K'y[n] xbar[n] ybar[m] Kxbar[m] K'ybar[n] x_anchor[n]
+ * y_anchor[m].  *len receives 16 + 5n + 5m.  buf may be NULL to query len. */
+int lp_get_state(const lp_problem *P, double *buf, int64_t *len);
+/* Restore such a state (len must match); the next lp_solve resumes from it. */
+int lp_set_state(lp_problem *P, const double *buf, int64_t len);
+
+/* Scaling factors: K~ = D_r^-1 K D_c^-1.  Dr[m], Dc[n]; either may be NULL. */
+int lp_get_scaling(const lp_problem *P, double *Dr, double *Dc);
+
+/* One product with the scaled matrix on the GPU: out = K~ in (transpose = 0,
+ * in[n], out[m]) or out = K~' in (transpose = 1, in[m], out[n]); host
+ * buffers, original order.  Runs the same SpMV kernels as the solve. */
+int lp_spmv(lp_problem *P, int transpose, const double *in, double *out);
+
+/* Launch statistics of the SpMV kernels of the last lp_solve when
+ * kernel_timing was set: which = 0 (K, fused dual step) or 1 (K', fused
+ * averages and primal step); *count launches with *total_ms summed hipEvent
+ * time.  Returns zeros when timing was off. */
+int lp_kernel_time(const lp_problem *P, int which, int64_t *count, double *total_ms);
+
+/* Device bytes held by the handle. */
+int lp_device_bytes(const lp_problem *P, int64_t *bytes);
+
+void lp_free(lp_problem *P);
+const char *lp_strerror(int code);
+/* Message of the last LP_ERR_HIP on this handle ("" when none). */
+const char *lp_last_error(const lp_problem *P);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

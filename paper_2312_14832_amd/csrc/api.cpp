@@ -1,0 +1,943 @@
+// Host side of libpdlp_amd: the C ABI of include/lp.h.
+//
+// lp_load validates the LP of the cuPDLP-C paper's eq. (LP), reorders rows
+// and columns into lane-count segments, builds the CSR of K' by a counting
+// sort (so the K' product needs no atomics), copies everything to the GPU and
+// runs the diagonal scaling there.  lp_solve drives the device-side
+// iteration: it launches fixed windows of attempt slots (optionally replayed
+// as one captured hipGraph) and polls the device done flag once per window.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace pdlp;
+
+namespace {
+
+constexpr int kNScalars = 16;
+
+int lanes_for_len(int64_t L)
+{
+    if (L <= 4) return 1;
+    if (L <= 8) return 2;
+    if (L <= 16) return 4;
+    if (L <= 32) return 8;
+    if (L <= 64) return 16;
+    if (L <= 128) return 32;
+    if (L <= 256) return 64;
+    return 256;
+}
+
+int lane_class(int lanes)
+{
+    switch (lanes) {
+    case 1: return 0;
+    case 2: return 1;
+    case 4: return 2;
+    case 8: return 3;
+    case 16: return 4;
+    case 32: return 5;
+    case 64: return 6;
+    default: return 7;
+    }
+}
+
+constexpr int kLaneOf[8] = {1, 2, 4, 8, 16, 32, 64, 256};
+
+int vblocks(int rows, int lanes)
+{
+    if (lanes >= kBlock) return rows;
+    const int64_t rpb = kBlock / lanes;
+    return (int)((rows + rpb - 1) / rpb);
+}
+
+// Stable counting sort of items by key in [0, nkeys): perm[new] = old.
+void counting_sort(const std::vector<int> &key, int nkeys, std::vector<int> &perm, std::vector<int> &cnt)
+{
+    const int64_t len = (int64_t)key.size();
+    cnt.assign(nkeys + 1, 0);
+    for (int64_t i = 0; i < len; ++i) cnt[key[i] + 1]++;
+    for (int k = 0; k < nkeys; ++k) cnt[k + 1] += cnt[k];
+    std::vector<int> pos(cnt.begin(), cnt.end() - 1);
+    perm.assign(len, 0);
+    for (int64_t i = 0; i < len; ++i) perm[pos[key[i]]++] = (int)i;
+}
+
+void build_segments(const std::vector<int> &cnt, int nkeys, Segments &seg, int &total_vb)
+{
+    seg.nseg = 0;
+    total_vb = 0;
+    for (int k = 0; k < nkeys; ++k) {
+        const int b = cnt[k], e = cnt[k + 1];
+        if (e <= b) continue;
+        const int lanes = kLaneOf[k % 8];
+        const int s = seg.nseg++;
+        seg.row_begin[s] = b;
+        seg.row_end[s] = e;
+        seg.lanes[s] = lanes;
+        seg.vb_begin[s] = total_vb;
+        total_vb += vblocks(e - b, lanes);
+    }
+    seg.vb_begin[seg.nseg] = total_vb;
+    if (seg.nseg == 0) {  // keep find_seg well defined
+        seg.row_begin[0] = seg.row_end[0] = 0;
+        seg.lanes[0] = 1;
+        seg.vb_begin[0] = seg.vb_begin[1] = 0;
+    }
+}
+
+struct HipError {
+    hipError_t e;
+    const char *what;
+};
+
+#define HIPT(expr)                                                       \
+    do {                                                                 \
+        hipError_t _e = (expr);                                          \
+        if (_e != hipSuccess) throw HipError{_e, #expr};                 \
+    } while (0)
+
+}  // namespace
+
+struct lp_problem {
+    int64_t m = 0, n = 0, nnz = 0, m1 = 0;
+    lp_options opt{};
+    hipStream_t stream = nullptr;
+    std::vector<int> perm_r, inv_r, perm_c, inv_c;  // perm: new -> old, inv: old -> new
+    Geo geo{};
+    std::string err;
+    double Nq = 0, Nc = 0, omega0 = 1, eta0 = 1;
+    bool has_result = false, state_ready = false;
+    std::vector<double> xs, ys;
+    bool has_xs = false, has_ys = false;
+    Ctl *hctl = nullptr;            // pinned host mirror of the device controller
+    std::vector<void *> allocs;     // device allocations owned by the handle
+    int64_t dev_bytes = 0;
+    bool mixed = false;
+    Dev<double> d64{};
+    Dev<float> d32{};
+    double *stage_n0 = nullptr, *stage_n1 = nullptr, *stage_m = nullptr, *red_part = nullptr, *red_out = nullptr;
+    void *tmp_n = nullptr, *tmp_m = nullptr;   // T scratch for lp_spmv
+    hipGraphExec_t graph = nullptr;
+    int graph_window = 0;
+    bool own_stream = false;
+    std::vector<hipEvent_t> ev;
+    int64_t t_count[2] = {0, 0};
+    double t_ms[2] = {0, 0};
+    double seconds = 0;
+
+    template <typename T> Dev<T> &dev();
+
+    void *dalloc(size_t bytes)
+    {
+        void *p = nullptr;
+        if (bytes == 0) bytes = 8;
+        bytes = (bytes + 255) & ~(size_t)255;
+        HIPT(hipMalloc(&p, bytes));
+        allocs.push_back(p);
+        dev_bytes += (int64_t)bytes;
+        return p;
+    }
+    void dfree(void *p)
+    {
+        for (auto &a : allocs)
+            if (a == p) {
+                (void)hipFree(p);
+                a = nullptr;
+            }
+    }
+    ~lp_problem()
+    {
+        if (graph) (void)hipGraphExecDestroy(graph);
+        for (auto e : ev) (void)hipEventDestroy(e);
+        for (void *p : allocs)
+            if (p) (void)hipFree(p);
+        if (hctl) (void)hipHostFree(hctl);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+template <> Dev<double> &lp_problem::dev<double>() { return d64; }
+template <> Dev<float> &lp_problem::dev<float>() { return d32; }
+
+namespace {
+
+int fail_hip(lp_problem *P, const HipError &h)
+{
+    char buf[512];
+    snprintf(buf, sizeof(buf), "%s failed: %s", h.what, hipGetErrorString(h.e));
+    if (P) P->err = buf;
+    return LP_ERR_HIP;
+}
+
+template <typename T>
+void upload(lp_problem *P, T *dst, const T *src, int64_t count)
+{
+    if (count > 0) HIPT(hipMemcpyAsync(dst, src, sizeof(T) * (size_t)count, hipMemcpyHostToDevice, P->stream));
+}
+
+template <typename T>
+void download(lp_problem *P, T *dst, const T *src, int64_t count)
+{
+    if (count > 0) HIPT(hipMemcpyAsync(dst, src, sizeof(T) * (size_t)count, hipMemcpyDeviceToHost, P->stream));
+}
+
+void sync(lp_problem *P) { HIPT(hipStreamSynchronize(P->stream)); }
+
+int validate(const lp_csr *K, const double *c, const double *q, const double *l, const double *u, int64_t m1)
+{
+    if (!K) return LP_ERR_ARG;
+    const int64_t m = K->m, n = K->n, nnz = K->nnz;
+    if (m < 0 || n < 0 || nnz < 0 || m1 < 0 || m1 > m) return LP_ERR_DIM;
+    if (m >= (int64_t(1) << 31) || n >= (int64_t(1) << 31) || nnz >= (int64_t(1) << 31)) return LP_ERR_TOO_LARGE;
+    if (!K->row_ptr || (nnz > 0 && (!K->col || !K->val)) || (n > 0 && (!c || !l || !u)) || (m > 0 && !q))
+        return LP_ERR_ARG;
+    if (K->row_ptr[0] != 0 || K->row_ptr[m] != nnz) return LP_ERR_DIM;
+    for (int64_t i = 0; i < m; ++i)
+        if (K->row_ptr[i + 1] < K->row_ptr[i]) return LP_ERR_DIM;
+    std::vector<int64_t> seen((size_t)std::max<int64_t>(n, 1), -1);
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t p = K->row_ptr[i]; p < K->row_ptr[i + 1]; ++p) {
+            const int64_t j = K->col[p];
+            if (j < 0 || j >= n || seen[j] == i) return LP_ERR_DIM;
+            seen[j] = i;
+        }
+    for (int64_t p = 0; p < nnz; ++p)
+        if (!std::isfinite(K->val[p])) return LP_ERR_NAN;
+    for (int64_t j = 0; j < n; ++j) {
+        if (!std::isfinite(c[j]) || std::isnan(l[j]) || std::isnan(u[j])) return LP_ERR_NAN;
+        if (l[j] == INFINITY || u[j] == -INFINITY || l[j] > u[j]) return LP_ERR_BOUNDS;
+    }
+    for (int64_t i = 0; i < m; ++i)
+        if (!std::isfinite(q[i])) return LP_ERR_NAN;
+    return LP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// load: reorder, transpose, upload, scale
+// ---------------------------------------------------------------------------
+
+template <typename T>
+void setup_typed(lp_problem *P, const double *kv64, const double *tv64, const double *cs64, const double *ls64,
+                 const double *us64, const double *qs64, const int *rp, const int *ci, const int *tp,
+                 const int *ti, const double *Dr, const double *Dc)
+{
+    const int64_t m = P->m, n = P->n, nnz = P->nnz;
+    Dev<T> &d = P->dev<T>();
+    d.m = (int)m;
+    d.n = (int)n;
+    d.m1 = (int)P->m1;
+    d.rp = rp; d.ci = ci; d.tp = tp; d.ti = ti;
+    d.Dr = Dr; d.Dc = Dc;
+    auto tvec = [&](int64_t len) { return (T *)P->dalloc(sizeof(T) * (size_t)len); };
+    if (std::is_same<T, double>::value) {
+        d.kv = (const T *)kv64; d.tv = (const T *)tv64;
+        d.cs = (const T *)cs64; d.ls = (const T *)ls64; d.us = (const T *)us64; d.qs = (const T *)qs64;
+    } else {
+        T *kv = tvec(nnz), *tv = tvec(nnz), *cs = tvec(n), *ls = tvec(n), *us = tvec(n), *qs = tvec(m);
+        HIPT(launch_from_double<T>(kv64, kv, nnz, P->stream));
+        HIPT(launch_from_double<T>(tv64, tv, nnz, P->stream));
+        HIPT(launch_from_double<T>(cs64, cs, n, P->stream));
+        HIPT(launch_from_double<T>(ls64, ls, n, P->stream));
+        HIPT(launch_from_double<T>(us64, us, n, P->stream));
+        HIPT(launch_from_double<T>(qs64, qs, m, P->stream));
+        d.kv = kv; d.tv = tv; d.cs = cs; d.ls = ls; d.us = us; d.qs = qs;
+    }
+    for (int b = 0; b < 2; ++b) {
+        d.xb[b] = tvec(n); d.yb[b] = tvec(m); d.Kxb[b] = tvec(m); d.KTyb[b] = tvec(n);
+    }
+    d.xa = tvec(n); d.ya = tvec(m); d.Kxa = tvec(m); d.KTya = tvec(n);
+    d.x0 = tvec(n); d.y0 = tvec(m);
+    d.xo = tvec(n); d.yo = tvec(m); d.KTyo = tvec(n);
+    d.part_primal = (double *)P->dalloc(sizeof(double) * kMaxGrid);
+    d.part_dual = (double *)P->dalloc(sizeof(double) * kMaxGrid * 2);
+    d.part_check = (double *)P->dalloc(sizeof(double) * kMaxGrid * kCheckSums);
+    d.ctl = (Ctl *)P->dalloc(sizeof(Ctl));
+    P->tmp_n = tvec(n);
+    P->tmp_m = tvec(m);
+}
+
+int do_load(lp_problem *P, const lp_csr *K, const double *c, const double *q, const double *l, const double *u)
+{
+    const int64_t m = P->m, n = P->n, nnz = P->nnz, m1 = P->m1;
+    const int32_t *rp0 = K->row_ptr, *ci0 = K->col;
+    const double *v0 = K->val;
+
+    // rows: key = (inequality group, lane class); columns: key = lane class of the column count
+    std::vector<int> key_r((size_t)m), key_c((size_t)n, 0), cnt_r, cnt_c;
+    for (int64_t i = 0; i < m; ++i)
+        key_r[i] = (i >= m1 ? 8 : 0) + lane_class(lanes_for_len(rp0[i + 1] - rp0[i]));
+    std::vector<int> colcount((size_t)n, 0);
+    for (int64_t p = 0; p < nnz; ++p) colcount[ci0[p]]++;
+    for (int64_t j = 0; j < n; ++j) key_c[j] = lane_class(lanes_for_len(colcount[j]));
+    counting_sort(key_r, 16, P->perm_r, cnt_r);
+    counting_sort(key_c, 8, P->perm_c, cnt_c);
+    P->inv_r.assign((size_t)m, 0);
+    P->inv_c.assign((size_t)n, 0);
+    for (int64_t i = 0; i < m; ++i) P->inv_r[P->perm_r[i]] = (int)i;
+    for (int64_t j = 0; j < n; ++j) P->inv_c[P->perm_c[j]] = (int)j;
+    build_segments(cnt_r, 16, P->geo.segK, P->geo.vb_K);
+    build_segments(cnt_c, 8, P->geo.segKT, P->geo.vb_KT);
+
+    // K with permuted rows and renumbered columns, columns sorted in each row
+    std::vector<int> rp((size_t)m + 1), ci((size_t)std::max<int64_t>(nnz, 1));
+    std::vector<double> kv((size_t)std::max<int64_t>(nnz, 1));
+    rp[0] = 0;
+    std::vector<std::pair<int, double>> rowbuf;
+    for (int64_t i = 0; i < m; ++i) {
+        const int o = P->perm_r[i];
+        const int b = rp0[o], e = rp0[o + 1];
+        rowbuf.clear();
+        for (int p = b; p < e; ++p) rowbuf.emplace_back(P->inv_c[ci0[p]], v0[p]);
+        std::sort(rowbuf.begin(), rowbuf.end(),
+                  [](const std::pair<int, double> &a, const std::pair<int, double> &b2) { return a.first < b2.first; });
+        const int base = rp[i];
+        for (size_t t = 0; t < rowbuf.size(); ++t) {
+            ci[base + t] = rowbuf[t].first;
+            kv[base + t] = rowbuf[t].second;
+        }
+        rp[i + 1] = base + (int)rowbuf.size();
+    }
+    // K' by counting sort over the renumbered K: rows of K' come out sorted by row of K
+    std::vector<int> tp((size_t)n + 1, 0), ti((size_t)std::max<int64_t>(nnz, 1));
+    std::vector<double> tv((size_t)std::max<int64_t>(nnz, 1));
+    for (int64_t p = 0; p < nnz; ++p) tp[ci[p] + 1]++;
+    for (int64_t j = 0; j < n; ++j) tp[j + 1] += tp[j];
+    {
+        std::vector<int> pos(tp.begin(), tp.end() - 1);
+        for (int64_t i = 0; i < m; ++i)
+            for (int p = rp[i]; p < rp[i + 1]; ++p) {
+                const int at = pos[ci[p]]++;
+                ti[at] = (int)i;
+                tv[at] = kv[p];
+            }
+    }
+    std::vector<double> cp((size_t)n), lp((size_t)n), up((size_t)n), qp((size_t)m);
+    for (int64_t j = 0; j < n; ++j) {
+        const int o = P->perm_c[j];
+        cp[j] = c[o]; lp[j] = l[o]; up[j] = u[o];
+    }
+    for (int64_t i = 0; i < m; ++i) qp[i] = q[P->perm_r[i]];
+
+    // device copies
+    auto ialloc = [&](int64_t len) { return (int *)P->dalloc(sizeof(int) * (size_t)len); };
+    auto dalloc = [&](int64_t len) { return (double *)P->dalloc(sizeof(double) * (size_t)len); };
+    int *d_rp = ialloc(m + 1), *d_ci = ialloc(nnz), *d_tp = ialloc(n + 1), *d_ti = ialloc(nnz);
+    double *d_kv = dalloc(nnz), *d_tv = dalloc(nnz);
+    double *d_c = dalloc(n), *d_l = dalloc(n), *d_u = dalloc(n), *d_q = dalloc(m);
+    double *Dr = dalloc(m), *Dc = dalloc(n), *r = dalloc(m), *s = dalloc(n);
+    double *cs = dalloc(n), *ls = dalloc(n), *us = dalloc(n), *qs = dalloc(m);
+    P->red_part = dalloc(kMaxGrid);
+    P->red_out = dalloc(8);
+    P->stage_n0 = dalloc(n); P->stage_n1 = dalloc(n); P->stage_m = dalloc(m);
+    upload(P, d_rp, rp.data(), m + 1);
+    upload(P, d_ci, ci.data(), nnz);
+    upload(P, d_kv, kv.data(), nnz);
+    upload(P, d_tp, tp.data(), n + 1);
+    upload(P, d_ti, ti.data(), nnz);
+    upload(P, d_tv, tv.data(), nnz);
+    upload(P, d_c, cp.data(), n);
+    upload(P, d_l, lp.data(), n);
+    upload(P, d_u, up.data(), n);
+    upload(P, d_q, qp.data(), m);
+
+    // scaling: Ruiz inf-norm rounds, then one Pock-Chambolle round; row and
+    // column factors both come from the same current matrix
+    const int M = (int)m, N = (int)n;
+    hipStream_t st = P->stream;
+    HIPT(launch_fill(Dr, 1.0, M, st));
+    HIPT(launch_fill(Dc, 1.0, N, st));
+    const int rounds = P->opt.ruiz_iters + (P->opt.pc_alpha >= 0.0 ? 1 : 0);
+    for (int it = 0; it < rounds; ++it) {
+        const bool pc = it == P->opt.ruiz_iters;
+        if (!pc) {
+            HIPT(launch_row_absmax(d_rp, d_kv, M, r, st));
+            HIPT(launch_row_absmax(d_tp, d_tv, N, s, st));
+        } else {
+            HIPT(launch_row_abspow_sum(d_rp, d_kv, M, 2.0 - P->opt.pc_alpha, r, st));
+            HIPT(launch_row_abspow_sum(d_tp, d_tv, N, P->opt.pc_alpha, s, st));
+        }
+        HIPT(launch_finish_factor(r, M, st));
+        HIPT(launch_finish_factor(s, N, st));
+        HIPT(launch_rescale_rows(d_rp, d_ci, d_kv, M, r, s, st));
+        HIPT(launch_rescale_rows(d_tp, d_ti, d_tv, N, s, r, st));
+        HIPT(launch_mul_inplace(Dr, r, M, st));
+        HIPT(launch_mul_inplace(Dc, s, N, st));
+    }
+    HIPT(launch_scale_vectors(d_c, d_l, d_u, d_q, Dc, Dr, cs, ls, us, qs, N, M, st));
+    double h[5] = {0, 0, 0, 0, 0};
+    HIPT(launch_sumsq(d_q, m, P->red_part, P->red_out + 0, st));
+    HIPT(launch_sumsq(d_c, n, P->red_part, P->red_out + 1, st));
+    HIPT(launch_sumsq(qs, m, P->red_part, P->red_out + 2, st));
+    HIPT(launch_sumsq(cs, n, P->red_part, P->red_out + 3, st));
+    HIPT(launch_absmax(d_kv, nnz, P->red_part, P->red_out + 4, st));
+    download(P, h, P->red_out, 5);
+    sync(P);
+    P->Nq = std::sqrt(h[0]);
+    P->Nc = std::sqrt(h[1]);
+    const double nq = std::sqrt(h[2]), nc = std::sqrt(h[3]);
+    P->omega0 = (nc > 1e-10 && nq > 1e-10) ? nc / nq : 1.0;
+    P->eta0 = h[4] > 0.0 ? 1.0 / h[4] : 1.0;
+    if (P->opt.fixed_step) P->eta0 = P->opt.fixed_eta;
+
+    if (P->mixed) setup_typed<float>(P, d_kv, d_tv, cs, ls, us, qs, d_rp, d_ci, d_tp, d_ti, Dr, Dc);
+    else setup_typed<double>(P, d_kv, d_tv, cs, ls, us, qs, d_rp, d_ci, d_tp, d_ti, Dr, Dc);
+    sync(P);
+    if (P->mixed) {
+        P->dfree(d_kv);
+        P->dfree(d_tv);
+    }
+    P->dfree(r);
+    P->dfree(s);
+    P->dfree(d_c); P->dfree(d_l); P->dfree(d_u); P->dfree(d_q);
+
+    // one grid size for every solver kernel (its workgroups are the partial-sum slots)
+    Geo &g = P->geo;
+    g.vb_n = (int)((n + kBlock - 1) / kBlock);
+    g.vb_m = (int)((m + kBlock - 1) / kBlock);
+    int mx = std::max(std::max(g.vb_K, g.vb_KT + g.vb_m), g.vb_n + g.vb_m);
+    g.grid = std::max(1, std::min(kMaxGrid, mx));
+    return LP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// solve
+// ---------------------------------------------------------------------------
+
+template <typename T>
+void launch_slot(lp_problem *P, int slot, bool timed)
+{
+    Dev<T> &d = P->dev<T>();
+    hipStream_t st = P->stream;
+    if (timed) HIPT(hipEventRecord(P->ev[4 * slot + 0], st));
+    HIPT(launch_dual<T>(d, P->geo, st));
+    if (timed) HIPT(hipEventRecord(P->ev[4 * slot + 1], st));
+    HIPT(launch_step_decide<T>(d, P->geo, st));
+    if (timed) HIPT(hipEventRecord(P->ev[4 * slot + 2], st));
+    HIPT(launch_update<T>(d, P->geo, st));
+    if (timed) HIPT(hipEventRecord(P->ev[4 * slot + 3], st));
+    HIPT(launch_check_reduce<T>(d, P->geo, st));
+    HIPT(launch_check_decide<T>(d, P->geo, P->Nq, P->Nc, st));
+    HIPT(launch_check_apply<T>(d, P->geo, st));
+}
+
+template <typename T>
+void run_check(lp_problem *P)
+{
+    Dev<T> &d = P->dev<T>();
+    HIPT(launch_check_reduce<T>(d, P->geo, P->stream));
+    HIPT(launch_check_decide<T>(d, P->geo, P->Nq, P->Nc, P->stream));
+    HIPT(launch_check_apply<T>(d, P->geo, P->stream));
+}
+
+void put_ctl(lp_problem *P, const Ctl &c, Ctl *dctl)
+{
+    *P->hctl = c;
+    HIPT(hipMemcpyAsync(dctl, P->hctl, sizeof(Ctl), hipMemcpyHostToDevice, P->stream));
+    sync(P);
+}
+
+void get_ctl(lp_problem *P, Ctl *dctl)
+{
+    HIPT(hipMemcpyAsync(P->hctl, dctl, sizeof(Ctl), hipMemcpyDeviceToHost, P->stream));
+    sync(P);
+}
+
+template <typename T>
+void copy_dev(lp_problem *P, T *dst, const T *src, int64_t len)
+{
+    if (len > 0) HIPT(hipMemcpyAsync(dst, src, sizeof(T) * (size_t)len, hipMemcpyDeviceToDevice, P->stream));
+}
+
+template <typename T>
+int do_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit)
+{
+    Dev<T> &d = P->dev<T>();
+    const int64_t m = P->m, n = P->n;
+    hipStream_t st = P->stream;
+    auto t0 = std::chrono::steady_clock::now();
+    P->t_count[0] = P->t_count[1] = 0;
+    P->t_ms[0] = P->t_ms[1] = 0;
+    if (!P->state_ready) {
+        // start point, products, averages/anchor = start, KKT0, first primal trial
+        const double *xs = nullptr, *ys = nullptr;
+        if (P->has_xs) {
+            std::vector<double> tmp((size_t)n);
+            for (int64_t j = 0; j < n; ++j) tmp[j] = P->xs[P->perm_c[j]];
+            upload(P, P->stage_n0, tmp.data(), n);
+            sync(P);
+            xs = P->stage_n0;
+        }
+        if (P->has_ys) {
+            std::vector<double> tmp((size_t)m);
+            for (int64_t i = 0; i < m; ++i) tmp[i] = P->ys[P->perm_r[i]];
+            upload(P, P->stage_m, tmp.data(), m);
+            sync(P);
+            ys = P->stage_m;
+        }
+        HIPT(launch_start<T>(d, xs, ys, 0, st));
+        Ctl c{};
+        c.eta = P->eta0;
+        c.omega = P->omega0;
+        c.KKT_prev = INFINITY;
+        c.mode = MODE_INIT;
+        c.tol = tol;
+        c.kkt_p = P->opt.kkt_omega_power;
+        c.fixed_eta = P->opt.fixed_eta;
+        c.max_iters = max_iters;
+        c.check_every = P->opt.check_every;
+        c.fixed_step = P->opt.fixed_step;
+        c.final_status = LP_ITERATION_LIMIT;
+        put_ctl(P, c, d.ctl);
+        HIPT(launch_spmv<T>(d.rp, d.ci, d.kv, d.xb[0], d.Kxb[0], P->geo.segK, P->geo.vb_K, P->geo.grid, st));
+        HIPT(launch_spmv<T>(d.tp, d.ti, d.tv, d.yb[0], d.KTyb[0], P->geo.segKT, P->geo.vb_KT, P->geo.grid, st));
+        copy_dev(P, d.xa, d.xb[0], n);
+        copy_dev(P, d.x0, d.xb[0], n);
+        copy_dev(P, d.KTya, d.KTyb[0], n);
+        copy_dev(P, d.ya, d.yb[0], m);
+        copy_dev(P, d.y0, d.yb[0], m);
+        copy_dev(P, d.Kxa, d.Kxb[0], m);
+        run_check<T>(P);
+    } else {
+        Ctl c = *P->hctl;   // set by lp_set_state
+        c.mode = MODE_RESUME;
+        c.done = 0;
+        c.status = LP_NOT_SOLVED;
+        c.numerical = 0;
+        c.restart_to = 0;
+        c.copy_out = 0;
+        c.need_primal = 1;
+        c.tol = tol;
+        c.max_iters = max_iters;
+        c.kkt_p = P->opt.kkt_omega_power;
+        c.check_every = P->opt.check_every;
+        c.fixed_step = P->opt.fixed_step;
+        c.fixed_eta = P->opt.fixed_eta;
+        put_ctl(P, c, d.ctl);
+        HIPT(launch_check_apply<T>(d, P->geo, st));
+    }
+    P->state_ready = false;
+    get_ctl(P, d.ctl);
+    if (!P->hctl->done && P->hctl->k >= max_iters) {
+        Ctl c = *P->hctl;
+        c.mode = MODE_FINAL;
+        c.final_status = LP_ITERATION_LIMIT;
+        put_ctl(P, c, d.ctl);
+        run_check<T>(P);
+        get_ctl(P, d.ctl);
+    }
+    const int W = std::max(1, P->opt.window);
+    const bool timed = P->opt.kernel_timing != 0;
+    if (timed && (int)P->ev.size() < 4 * W) {
+        for (auto e : P->ev) (void)hipEventDestroy(e);
+        P->ev.assign(4 * W, nullptr);
+        for (auto &e : P->ev) HIPT(hipEventCreate(&e));
+    }
+    const bool use_graph = P->opt.use_graph && !timed;
+    if (use_graph && (!P->graph || P->graph_window != W)) {
+        if (P->graph) {
+            (void)hipGraphExecDestroy(P->graph);
+            P->graph = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        HIPT(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+        for (int s = 0; s < W; ++s) launch_slot<T>(P, s, false);
+        HIPT(hipStreamEndCapture(st, &g));
+        HIPT(hipGraphInstantiate(&P->graph, g, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(g);
+        P->graph_window = W;
+    }
+    while (!P->hctl->done) {
+        const long long k_before = P->hctl->k;
+        if (use_graph) {
+            HIPT(hipGraphLaunch(P->graph, st));
+        } else {
+            for (int s = 0; s < W; ++s) launch_slot<T>(P, s, timed);
+        }
+        get_ctl(P, d.ctl);
+        if (timed && !P->hctl->done) {
+            // every slot of a window that ended unfinished did real work
+            for (int s = 0; s < W; ++s) {
+                float a = 0, b = 0;
+                HIPT(hipEventElapsedTime(&a, P->ev[4 * s + 0], P->ev[4 * s + 1]));
+                HIPT(hipEventElapsedTime(&b, P->ev[4 * s + 2], P->ev[4 * s + 3]));
+                P->t_ms[0] += a;
+                P->t_ms[1] += b;
+            }
+            P->t_count[0] += W;
+            P->t_count[1] += W;
+        }
+        (void)k_before;
+        if (P->hctl->done) break;
+        if (time_limit > 0.0) {
+            const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+            if (el > time_limit) {
+                Ctl c = *P->hctl;
+                c.mode = MODE_FINAL;
+                c.final_status = LP_TIME_LIMIT;
+                put_ctl(P, c, d.ctl);
+                run_check<T>(P);
+                get_ctl(P, d.ctl);
+                break;
+            }
+        }
+    }
+    sync(P);
+    P->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    P->has_result = true;
+    return LP_OK;
+}
+
+template <typename T>
+int do_result(const lp_problem *Pc, double *x, double *y, double *lam, lp_info *info)
+{
+    lp_problem *P = const_cast<lp_problem *>(Pc);
+    Dev<T> &d = P->dev<T>();
+    const int64_t m = P->m, n = P->n;
+    if (x || y || lam) {
+        HIPT(launch_result<T>(d, P->stage_n0, P->stage_m, P->stage_n1, P->stream));
+        std::vector<double> hx((size_t)n), hy((size_t)m), hl((size_t)n);
+        download(P, hx.data(), P->stage_n0, n);
+        download(P, hy.data(), P->stage_m, m);
+        download(P, hl.data(), P->stage_n1, n);
+        sync(P);
+        for (int64_t j = 0; j < n; ++j) {
+            const int o = P->perm_c[j];
+            if (x) x[o] = hx[j];
+            if (lam) lam[o] = hl[j];
+        }
+        if (y)
+            for (int64_t i = 0; i < m; ++i) y[P->perm_r[i]] = hy[i];
+    }
+    if (info) {
+        get_ctl(P, d.ctl);
+        const Ctl &c = *P->hctl;
+        info->status = c.status;
+        info->pobj = c.out_pobj;
+        info->dobj = c.out_dobj;
+        info->rel_primal = c.out_rel_p;
+        info->rel_dual = c.out_rel_d;
+        info->rel_gap = c.out_rel_g;
+        info->iterations = c.k;
+        info->attempts = c.attempts;
+        info->restarts = c.restarts;
+        info->omega = c.omega;
+        info->eta = c.eta;
+        info->seconds = P->seconds;
+    }
+    return LP_OK;
+}
+
+// state vectors: x y Kx KTy xa ya Kxa KTya x0 y0
+template <typename T>
+void state_vectors(lp_problem *P, T *(&v)[10], bool (&is_n)[10])
+{
+    Dev<T> &d = P->dev<T>();
+    const int c = P->hctl->cur;
+    T *list[10] = {d.xb[c], d.yb[c], d.Kxb[c], d.KTyb[c], d.xa, d.ya, d.Kxa, d.KTya, d.x0, d.y0};
+    const bool nn[10] = {true, false, false, true, true, false, false, true, true, false};
+    for (int i = 0; i < 10; ++i) {
+        v[i] = list[i];
+        is_n[i] = nn[i];
+    }
+}
+
+template <typename T>
+int do_get_state(const lp_problem *Pc, double *buf)
+{
+    lp_problem *P = const_cast<lp_problem *>(Pc);
+    Dev<T> &d = P->dev<T>();
+    get_ctl(P, d.ctl);
+    const Ctl &c = *P->hctl;
+    std::fill(buf, buf + kNScalars, 0.0);
+    buf[0] = c.eta; buf[1] = c.omega; buf[2] = c.W; buf[3] = c.KKT0; buf[4] = c.KKT_prev;
+    buf[5] = (double)c.k; buf[6] = (double)c.t; buf[7] = (double)c.attempts; buf[8] = (double)c.restarts;
+    buf[9] = c.status; buf[10] = c.eta_last;
+    T *v[10];
+    bool is_n[10];
+    state_vectors<T>(P, v, is_n);
+    double *p = buf + kNScalars;
+    std::vector<double> tmp((size_t)std::max(P->m, P->n));
+    for (int i = 0; i < 10; ++i) {
+        const int64_t len = is_n[i] ? P->n : P->m;
+        double *stage = is_n[i] ? P->stage_n0 : P->stage_m;
+        HIPT(launch_to_double<T>(v[i], stage, len, P->stream));
+        download(P, tmp.data(), stage, len);
+        sync(P);
+        const std::vector<int> &perm = is_n[i] ? P->perm_c : P->perm_r;
+        for (int64_t t = 0; t < len; ++t) p[perm[t]] = tmp[t];
+        p += len;
+    }
+    return LP_OK;
+}
+
+template <typename T>
+int do_set_state(lp_problem *P, const double *buf)
+{
+    Dev<T> &d = P->dev<T>();
+    Ctl c{};
+    c.eta = buf[0]; c.omega = buf[1]; c.W = buf[2]; c.KKT0 = buf[3]; c.KKT_prev = buf[4];
+    c.k = (long long)buf[5]; c.t = (long long)buf[6]; c.attempts = (long long)buf[7];
+    c.restarts = (long long)buf[8]; c.eta_last = buf[10];
+    c.cur = 0;
+    *P->hctl = c;
+    T *v[10];
+    bool is_n[10];
+    state_vectors<T>(P, v, is_n);
+    const double *p = buf + kNScalars;
+    std::vector<double> tmp((size_t)std::max(P->m, P->n));
+    for (int i = 0; i < 10; ++i) {
+        const int64_t len = is_n[i] ? P->n : P->m;
+        double *stage = is_n[i] ? P->stage_n0 : P->stage_m;
+        const std::vector<int> &perm = is_n[i] ? P->perm_c : P->perm_r;
+        for (int64_t t = 0; t < len; ++t) tmp[t] = p[perm[t]];
+        upload(P, stage, tmp.data(), len);
+        HIPT(launch_from_double<T>(stage, v[i], len, P->stream));
+        sync(P);
+        p += len;
+    }
+    HIPT(hipMemcpyAsync(d.ctl, P->hctl, sizeof(Ctl), hipMemcpyHostToDevice, P->stream));
+    sync(P);
+    P->state_ready = true;
+    return LP_OK;
+}
+
+template <typename T>
+int do_spmv(lp_problem *P, int transpose, const double *in, double *out)
+{
+    Dev<T> &d = P->dev<T>();
+    const int64_t lin = transpose ? P->m : P->n, lout = transpose ? P->n : P->m;
+    const std::vector<int> &pin = transpose ? P->perm_r : P->perm_c;
+    const std::vector<int> &pout = transpose ? P->perm_c : P->perm_r;
+    double *sin = transpose ? P->stage_m : P->stage_n0;
+    double *sout = transpose ? P->stage_n0 : P->stage_m;
+    T *tin = (T *)(transpose ? P->tmp_m : P->tmp_n);
+    T *tout = (T *)(transpose ? P->tmp_n : P->tmp_m);
+    std::vector<double> tmp((size_t)std::max(lin, lout));
+    for (int64_t t = 0; t < lin; ++t) tmp[t] = in[pin[t]];
+    upload(P, sin, tmp.data(), lin);
+    HIPT(launch_from_double<T>(sin, tin, lin, P->stream));
+    if (transpose)
+        HIPT(launch_spmv<T>(d.tp, d.ti, d.tv, tin, tout, P->geo.segKT, P->geo.vb_KT, P->geo.grid, P->stream));
+    else
+        HIPT(launch_spmv<T>(d.rp, d.ci, d.kv, tin, tout, P->geo.segK, P->geo.vb_K, P->geo.grid, P->stream));
+    HIPT(launch_to_double<T>(tout, sout, lout, P->stream));
+    download(P, tmp.data(), sout, lout);
+    sync(P);
+    for (int64_t t = 0; t < lout; ++t) out[pout[t]] = tmp[t];
+    return LP_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+void lp_default_options(lp_options *o)
+{
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = LP_FP64;
+    o->stream = nullptr;
+    o->ruiz_iters = 10;
+    o->pc_alpha = 1.0;
+    o->check_every = 64;
+    o->kkt_omega_power = 2.0;
+    o->fixed_step = 0;
+    o->fixed_eta = 0.0;
+    o->use_graph = 1;
+    o->window = 64;
+    o->kernel_timing = 0;
+    o->verbose = 0;
+}
+
+int lp_load(lp_problem **out, const lp_csr *K, const double *c, const double *q, const double *l, const double *u,
+            int64_t m1, const lp_options *opt)
+{
+    if (!out) return LP_ERR_ARG;
+    *out = nullptr;
+    int rc = validate(K, c, q, l, u, m1);
+    if (rc != LP_OK) return rc;
+    lp_options o;
+    if (opt) o = *opt;
+    else lp_default_options(&o);
+    if ((o.precision != LP_FP64 && o.precision != LP_MIXED) || o.check_every <= 0 || o.ruiz_iters < 0 ||
+        (o.fixed_step && !(o.fixed_eta > 0.0)) || o.window <= 0)
+        return LP_ERR_ARG;
+    std::unique_ptr<lp_problem> P;
+    try {
+        P.reset(new lp_problem());
+    } catch (...) {
+        return LP_ERR_NOMEM;
+    }
+    P->m = K->m; P->n = K->n; P->nnz = K->nnz; P->m1 = m1;
+    P->opt = o;
+    P->mixed = o.precision == LP_MIXED;
+    P->stream = (hipStream_t)o.stream;
+    try {
+        if (!P->stream) {
+            // a stream of our own (default priority) so the window can be graph-captured
+            HIPT(hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking));
+            P->own_stream = true;
+        }
+        HIPT(hipHostMalloc((void **)&P->hctl, sizeof(Ctl), hipHostMallocDefault));
+        std::memset(P->hctl, 0, sizeof(Ctl));
+        rc = do_load(P.get(), K, c, q, l, u);
+    } catch (const HipError &h) {
+        rc = h.e == hipErrorOutOfMemory ? LP_ERR_NOMEM : LP_ERR_HIP;
+        if (o.verbose) fprintf(stderr, "lp_load: %s failed: %s\n", h.what, hipGetErrorString(h.e));
+    } catch (const std::bad_alloc &) {
+        rc = LP_ERR_NOMEM;
+    }
+    if (rc != LP_OK) return rc;
+    *out = P.release();
+    return LP_OK;
+}
+
+int lp_set_start(lp_problem *P, const double *x0, const double *y0)
+{
+    if (!P) return LP_ERR_ARG;
+    P->has_xs = x0 != nullptr;
+    P->has_ys = y0 != nullptr;
+    if (x0) P->xs.assign(x0, x0 + P->n);
+    if (y0) P->ys.assign(y0, y0 + P->m);
+    P->state_ready = false;
+    return LP_OK;
+}
+
+int lp_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit_s)
+{
+    if (!P || max_iters < 0 || std::isnan(tol)) return LP_ERR_ARG;
+    try {
+        return P->mixed ? do_solve<float>(P, tol, max_iters, time_limit_s)
+                        : do_solve<double>(P, tol, max_iters, time_limit_s);
+    } catch (const HipError &h) {
+        return fail_hip(P, h);
+    } catch (const std::bad_alloc &) {
+        return LP_ERR_NOMEM;
+    }
+}
+
+int lp_result(const lp_problem *P, double *x, double *y, double *lambda, lp_info *info)
+{
+    if (!P) return LP_ERR_ARG;
+    if (!P->has_result) return LP_ERR_STATE;
+    try {
+        return P->mixed ? do_result<float>(P, x, y, lambda, info) : do_result<double>(P, x, y, lambda, info);
+    } catch (const HipError &h) {
+        return fail_hip(const_cast<lp_problem *>(P), h);
+    }
+}
+
+int lp_get_state(const lp_problem *P, double *buf, int64_t *len)
+{
+    if (!P || !len) return LP_ERR_ARG;
+    *len = kNScalars + 5 * P->n + 5 * P->m;
+    if (!buf) return LP_OK;
+    try {
+        return P->mixed ? do_get_state<float>(P, buf) : do_get_state<double>(P, buf);
+    } catch (const HipError &h) {
+        return fail_hip(const_cast<lp_problem *>(P), h);
+    }
+}
+
+int lp_set_state(lp_problem *P, const double *buf, int64_t len)
+{
+    if (!P || !buf) return LP_ERR_ARG;
+    if (len != kNScalars + 5 * P->n + 5 * P->m) return LP_ERR_STATE;
+    try {
+        return P->mixed ? do_set_state<float>(P, buf) : do_set_state<double>(P, buf);
+    } catch (const HipError &h) {
+        return fail_hip(P, h);
+    }
+}
+
+int lp_get_scaling(const lp_problem *Pc, double *Dr, double *Dc)
+{
+    if (!Pc) return LP_ERR_ARG;
+    lp_problem *P = const_cast<lp_problem *>(Pc);
+    try {
+        const double *dDr = P->mixed ? P->d32.Dr : P->d64.Dr;
+        const double *dDc = P->mixed ? P->d32.Dc : P->d64.Dc;
+        std::vector<double> tr((size_t)P->m), tc((size_t)P->n);
+        download(P, tr.data(), dDr, P->m);
+        download(P, tc.data(), dDc, P->n);
+        sync(P);
+        if (Dr)
+            for (int64_t i = 0; i < P->m; ++i) Dr[P->perm_r[i]] = tr[i];
+        if (Dc)
+            for (int64_t j = 0; j < P->n; ++j) Dc[P->perm_c[j]] = tc[j];
+    } catch (const HipError &h) {
+        return fail_hip(P, h);
+    }
+    return LP_OK;
+}
+
+int lp_spmv(lp_problem *P, int transpose, const double *in, double *out)
+{
+    if (!P || !in || !out) return LP_ERR_ARG;
+    try {
+        return P->mixed ? do_spmv<float>(P, transpose, in, out) : do_spmv<double>(P, transpose, in, out);
+    } catch (const HipError &h) {
+        return fail_hip(P, h);
+    }
+}
+
+int lp_kernel_time(const lp_problem *P, int which, int64_t *count, double *total_ms)
+{
+    if (!P || !count || !total_ms || which < 0 || which > 1) return LP_ERR_ARG;
+    *count = P->t_count[which];
+    *total_ms = P->t_ms[which];
+    return LP_OK;
+}
+
+int lp_device_bytes(const lp_problem *P, int64_t *bytes)
+{
+    if (!P || !bytes) return LP_ERR_ARG;
+    *bytes = P->dev_bytes;
+    return LP_OK;
+}
+
+void lp_free(lp_problem *P)
+{
+    if (!P) return;
+    if (P->stream) (void)hipStreamSynchronize(P->stream);
+    else (void)hipDeviceSynchronize();
+    delete P;
+}
+
+const char *lp_strerror(int code)
+{
+    switch (code) {
+    case LP_OK: return "ok";
+    case LP_ERR_ARG: return "invalid argument";
+    case LP_ERR_DIM: return "inconsistent dimensions or CSR structure";
+    case LP_ERR_NAN: return "NaN or infinity in the data";
+    case LP_ERR_BOUNDS: return "inconsistent variable bounds";
+    case LP_ERR_TOO_LARGE: return "problem too large for 32-bit indices";
+    case LP_ERR_STATE: return "call out of order or state of the wrong size";
+    case LP_ERR_HIP: return "HIP runtime error";
+    case LP_ERR_NOMEM: return "out of memory";
+    default: return "unknown error";
+    }
+}
+
+const char *lp_last_error(const lp_problem *P)
+{
+    if (!P) return "";
+    return P->err.c_str();
+}
+
+}  // extern "C"

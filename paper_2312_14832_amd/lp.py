@@ -1,0 +1,209 @@
+"""Thin ctypes binding of libpdlp_amd.so (include/lp.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  The library must have been built (``paper_2312_14832_amd.build``);
+importing this module on a machine without it raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpdlp_amd.so")
+
+LP_FP64, LP_MIXED = 0, 1
+STATUS = {0: "NOT_SOLVED", 1: "OPTIMAL", 2: "ITERATION_LIMIT", 3: "TIME_LIMIT", 4: "NUMERICAL"}
+ERRORS = {-1: "LP_ERR_ARG", -2: "LP_ERR_DIM", -3: "LP_ERR_NAN", -4: "LP_ERR_BOUNDS",
+          -5: "LP_ERR_TOO_LARGE", -6: "LP_ERR_STATE", -7: "LP_ERR_HIP", -8: "LP_ERR_NOMEM"}
+NSCALARS = 16
+
+# every symbol include/lp.h declares
+EXPORTS = ["lp_default_options", "lp_load", "lp_set_start", "lp_solve", "lp_result", "lp_get_state",
+           "lp_set_state", "lp_get_scaling", "lp_spmv", "lp_kernel_time", "lp_device_bytes", "lp_free",
+           "lp_strerror", "lp_last_error"]
+
+
+class LPCsr(C.Structure):
+    _fields_ = [("m", C.c_int64), ("n", C.c_int64), ("nnz", C.c_int64),
+                ("row_ptr", C.POINTER(C.c_int32)), ("col", C.POINTER(C.c_int32)),
+                ("val", C.POINTER(C.c_double))]
+
+
+class LPOptions(C.Structure):
+    _fields_ = [("precision", C.c_int), ("stream", C.c_void_p), ("ruiz_iters", C.c_int),
+                ("pc_alpha", C.c_double), ("check_every", C.c_int), ("kkt_omega_power", C.c_double),
+                ("fixed_step", C.c_int), ("fixed_eta", C.c_double), ("use_graph", C.c_int),
+                ("window", C.c_int), ("kernel_timing", C.c_int), ("verbose", C.c_int)]
+
+
+class LPInfo(C.Structure):
+    _fields_ = [("status", C.c_int), ("pobj", C.c_double), ("dobj", C.c_double),
+                ("rel_primal", C.c_double), ("rel_dual", C.c_double), ("rel_gap", C.c_double),
+                ("iterations", C.c_int64), ("attempts", C.c_int64), ("restarts", C.c_int64),
+                ("omega", C.c_double), ("eta", C.c_double), ("seconds", C.c_double)]
+
+
+_lib = None
+
+
+def library():
+    """Load libpdlp_amd.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2312_14832_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        L.lp_default_options.argtypes = [C.POINTER(LPOptions)]
+        L.lp_default_options.restype = None
+        L.lp_load.argtypes = [C.POINTER(C.c_void_p), C.POINTER(LPCsr), dp, dp, dp, dp, C.c_int64,
+                              C.POINTER(LPOptions)]
+        L.lp_set_start.argtypes = [C.c_void_p, dp, dp]
+        L.lp_solve.argtypes = [C.c_void_p, C.c_double, C.c_int64, C.c_double]
+        L.lp_result.argtypes = [C.c_void_p, dp, dp, dp, C.POINTER(LPInfo)]
+        L.lp_get_state.argtypes = [C.c_void_p, dp, C.POINTER(C.c_int64)]
+        L.lp_set_state.argtypes = [C.c_void_p, dp, C.c_int64]
+        L.lp_get_scaling.argtypes = [C.c_void_p, dp, dp]
+        L.lp_spmv.argtypes = [C.c_void_p, C.c_int, dp, dp]
+        L.lp_kernel_time.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+        L.lp_device_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+        L.lp_free.argtypes = [C.c_void_p]
+        L.lp_free.restype = None
+        L.lp_strerror.argtypes = [C.c_int]
+        L.lp_strerror.restype = C.c_char_p
+        L.lp_last_error.argtypes = [C.c_void_p]
+        L.lp_last_error.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+class LPError(RuntimeError):
+    def __init__(self, code, msg=""):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def default_options(**kw) -> LPOptions:
+    o = LPOptions()
+    library().lp_default_options(C.byref(o))
+    for k, v in kw.items():
+        if k == "precision" and isinstance(v, str):
+            v = {"fp64": LP_FP64, "mixed": LP_MIXED}[v]
+        if k == "stream" and v is not None and not isinstance(v, int):
+            v = int(v.cuda_stream)  # a torch.cuda.Stream
+        setattr(o, k, v)
+    return o
+
+
+class Problem:
+    """One LP loaded on the GPU (lp_load); see include/lp.h for semantics."""
+
+    def __init__(self, lp, **options):
+        L = library()
+        self.m, self.n, self.m1 = int(lp.m), int(lp.n), int(lp.m1)
+        self.opt = default_options(**options)
+        rp = np.ascontiguousarray(lp.row_ptr, np.int32)
+        ci = np.ascontiguousarray(lp.col, np.int32)
+        v = _f64(lp.val)
+        K = LPCsr(self.m, self.n, int(rp[-1]), rp.ctypes.data_as(C.POINTER(C.c_int32)),
+                  ci.ctypes.data_as(C.POINTER(C.c_int32)), _dp(v))
+        c, q, l, u = _f64(lp.c), _f64(lp.q), _f64(lp.l), _f64(lp.u)
+        h = C.c_void_p()
+        rc = L.lp_load(C.byref(h), C.byref(K), _dp(c), _dp(q), _dp(l), _dp(u), self.m1, C.byref(self.opt))
+        if rc != 0:
+            raise LPError(rc, L.lp_strerror(rc).decode())
+        self.h = h
+
+    def _check(self, rc):
+        if rc != 0:
+            raise LPError(rc, library().lp_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.lp_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def set_start(self, x=None, y=None):
+        xs = None if x is None else _f64(x)
+        ys = None if y is None else _f64(y)
+        self._check(library().lp_set_start(self.h, _dp(xs), _dp(ys)))
+
+    def solve(self, tol=1e-4, max_iters=10**7, time_limit=0.0):
+        self._check(library().lp_solve(self.h, float(tol), int(max_iters), float(time_limit)))
+        return self.info()
+
+    def info(self):
+        inf = LPInfo()
+        self._check(library().lp_result(self.h, None, None, None, C.byref(inf)))
+        d = {k: getattr(inf, k) for k, _ in LPInfo._fields_}
+        d["status"] = STATUS[inf.status]
+        d["rel_kkt"] = max(inf.rel_primal, inf.rel_dual, inf.rel_gap)
+        return d
+
+    def result(self):
+        x = np.empty(self.n); y = np.empty(self.m); lam = np.empty(self.n)
+        inf = LPInfo()
+        self._check(library().lp_result(self.h, _dp(x), _dp(y), _dp(lam), C.byref(inf)))
+        return x, y, lam, self.info()
+
+    def get_state(self):
+        ln = C.c_int64()
+        self._check(library().lp_get_state(self.h, None, C.byref(ln)))
+        buf = np.empty(ln.value)
+        self._check(library().lp_get_state(self.h, _dp(buf), C.byref(ln)))
+        return buf
+
+    def set_state(self, buf):
+        buf = _f64(buf)
+        self._check(library().lp_set_state(self.h, _dp(buf), buf.size))
+
+    def scaling(self):
+        Dr = np.empty(self.m); Dc = np.empty(self.n)
+        self._check(library().lp_get_scaling(self.h, _dp(Dr), _dp(Dc)))
+        return Dr, Dc
+
+    def spmv(self, v, transpose=False):
+        v = _f64(v)
+        out = np.empty(self.n if transpose else self.m)
+        self._check(library().lp_spmv(self.h, int(bool(transpose)), _dp(v), _dp(out)))
+        return out
+
+    def kernel_time(self, which):
+        cnt = C.c_int64(); ms = C.c_double()
+        self._check(library().lp_kernel_time(self.h, int(which), C.byref(cnt), C.byref(ms)))
+        return cnt.value, ms.value
+
+    def device_bytes(self):
+        b = C.c_int64()
+        self._check(library().lp_device_bytes(self.h, C.byref(b)))
+        return b.value
+
+
+STATE_VECTORS = [("x", "n"), ("y", "m"), ("Kx", "m"), ("KTy", "n"), ("xbar", "n"), ("ybar", "m"),
+                 ("Kxbar", "m"), ("KTybar", "n"), ("x0", "n"), ("y0", "m")]
+SCALAR_NAMES = ["eta_hat", "omega", "W", "KKT0", "KKT_prev", "k", "t", "attempts", "restarts",
+                "status", "eta_last"]
+
+
+def unpack_state(buf, n, m):
+    d = {name: buf[i] for i, name in enumerate(SCALAR_NAMES)}
+    p = NSCALARS
+    for name, dim in STATE_VECTORS:
+        ln = n if dim == "n" else m
+        d[name] = buf[p:p + ln].copy()
+        p += ln
+    return d

@@ -18,3 +18,13 @@ def oracle_mod():
     from oracle import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def lpmod():
+    """The HIP library's binding; GPU tests only."""
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2312_14832_amd import lp
+    lp.library()
+    return lp

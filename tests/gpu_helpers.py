@@ -1,0 +1,98 @@
+"""Shared helpers for the GPU tests (they call the HIP library through the C ABI)."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+VECS = ["x", "y", "Kx", "KTy", "xbar", "ybar", "Kxbar", "KTybar", "x0", "y0"]
+FLOAT_SCALARS = ["eta_hat", "omega", "W", "KKT0", "eta_last"]
+INT_SCALARS = ["k", "t", "attempts", "restarts"]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+U64 = 2.0 ** -53
+
+
+def vec_diff(sg: dict, so: dict):
+    """Largest normwise relative difference over the state's vectors:
+    |a-b| / (|b| + 1e-4 sqrt(len)), so |a-b| <= tol |b| + tol*1e-4 sqrt(len)."""
+    worst, where = 0.0, ""
+    for v in VECS:
+        a, b = sg[v], so[v]
+        num = np.linalg.norm(a - b)
+        den = np.linalg.norm(b) + 1e-4 * np.sqrt(max(len(b), 1))
+        r = num / den if den > 0 else num
+        if not np.isfinite(r):
+            r = np.inf
+        if r > worst:
+            worst, where = r, v
+    return worst, where
+
+
+def scalar_diff(sg: dict, so: dict):
+    """Relative differences of the FP scalars (eta, omega, W, KKT0, eta_last)."""
+    out = {}
+    for s in FLOAT_SCALARS:
+        a, b = sg[s], so[s]
+        if np.isinf(a) and np.isinf(b) and np.sign(a) == np.sign(b):
+            out[s] = 0.0
+        else:
+            out[s] = abs(a - b) / max(abs(b), 1e-300)
+    return out
+
+
+def step_condition(prev: dict, cur: dict):
+    """kappa = |z| / |z_k - z_{k-1}| over x and y.  The step-size test divides
+    sums of squares of iterate differences, so an ulp-level difference in the
+    iterates moves eta_bar (and everything it feeds: eta, W, omega, KKT0)
+    by about u * kappa relative; this is the scale of the scalar tolerance."""
+    kap = 1.0
+    for v in ("x", "y"):
+        d = np.linalg.norm(cur[v] - prev[v])
+        nv = np.linalg.norm(cur[v])
+        if d > 0:
+            kap = max(kap, nv / d)
+    return kap
+
+
+def state_diff(sg: dict, so: dict):
+    """(worst vector difference, where, worst scalar difference, where)."""
+    wv, vv = vec_diff(sg, so)
+    sd = scalar_diff(sg, so)
+    ws = max(sd, key=sd.get)
+    return wv, vv, sd[ws], ws
+
+
+def ints_equal(sg, so):
+    return all(int(sg[k]) == int(so[k]) for k in INT_SCALARS)
+
+
+def kkt_scale(st: dict, Dr, Dc, data, kkt_p=2.0):
+    """Magnitude of the terms inside KKT_omega before they cancel:
+    sqrt(w(|Kx|^2+|q~|^2) + (|c~|^2+|K'y|^2)/w + (|c~'x|+|q~'y|)^2), w=omega^p.
+    An absolute error of u times this is the rounding floor of KKT0."""
+    w = st["omega"] ** kkt_p
+    qs = data.q / Dr
+    cs = data.c / Dc
+    t1 = np.dot(st["Kx"], st["Kx"]) + np.dot(qs, qs)
+    t2 = np.dot(cs, cs) + np.dot(st["KTy"], st["KTy"])
+    t3 = abs(np.dot(cs, st["x"])) + abs(np.dot(qs, st["y"]))
+    return float(np.sqrt(w * t1 + t2 / w + t3 * t3))
+
+
+def perturbed(raw, rel, seed):
+    """The state with every vector entry scaled by (1 + rel*N(0,1))."""
+    rng = np.random.default_rng(seed)
+    out = raw.copy()
+    out[16:] *= 1 + rel * rng.standard_normal(out.size - 16)
+    return out
+
+
+def gpu_state(lpmod, p):
+    """The GPU handle's state as a dict (same layout as the oracle's)."""
+    return lpmod.unpack_state(p.get_state(), p.n, p.m)

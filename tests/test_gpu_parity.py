@@ -1,0 +1,315 @@
+"""GPU parity of the HIP restarted-PDHG path against the FP64 CPU oracle,
+through the C ABI: scaling, both sparse products, per-step iterates, final
+objectives, resume, determinism and edge cases."""
+import numpy as np
+import pytest
+
+from paper_2312_14832_amd import gen
+from gpu_helpers import (U64, gpu_state, ints_equal, kkt_scale, perturbed, say, scalar_diff, state_diff,
+                         step_condition, vec_diff)
+
+pytestmark = pytest.mark.gpu
+
+PER_STEP_TOL = 1e-10
+
+
+def scalar_tol(kappa):
+    # 1e-10 where well conditioned; u * kappa * 64 where the step-size ratio
+    # of difference norms amplifies rounding (see step_condition)
+    return max(PER_STEP_TOL, 64.0 * U64 * kappa)
+
+
+def assert_states_close(sg, so, kappa, label, kscale=None):
+    """Vectors to 1e-10; eta, W, eta_last, omega to the conditioning-derived
+    tolerance; KKT0 absolutely against the size of its terms."""
+    wv, vv = vec_diff(sg, so)
+    assert wv < PER_STEP_TOL, (label, vv, wv)
+    sd = scalar_diff(sg, so)
+    for name, r in sd.items():
+        if name == "KKT0" and kscale is not None:
+            assert abs(sg["KKT0"] - so["KKT0"]) <= PER_STEP_TOL * kscale, (label, name, sg["KKT0"], so["KKT0"])
+        else:
+            assert r < scalar_tol(kappa), (label, name, r, kappa)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_scaling_matches_oracle(lpmod, oracle_mod, seed):
+    say(f"case scaling seed={seed}")
+    data = gen.tiny_lp(seed)
+    p = lpmod.Problem(data)
+    o = oracle_mod.Oracle(data)
+    Dr, Dc = p.scaling()
+    Dr_o, Dc_o, _ = o.scaling()
+    assert np.max(np.abs(Dr - Dr_o) / Dr_o) < 1e-13
+    assert np.max(np.abs(Dc - Dc_o) / Dc_o) < 1e-13
+
+
+@pytest.mark.parametrize("maker", ["tiny", "powerlaw", "long_rows"])
+def test_spmv_matches_oracle(lpmod, oracle_mod, maker):
+    say(f"case spmv {maker}")
+    if maker == "tiny":
+        data = gen.tiny_lp(3)
+    elif maker == "powerlaw":
+        data = gen.large_lp(seed=5, n=20000, m1=5000, m2=5000)
+    else:
+        data = long_rows_lp(7)
+    p = lpmod.Problem(data)
+    o = oracle_mod.Oracle(data)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(data.n)
+    y = rng.standard_normal(data.m)
+    for tr, v in [(False, x), (True, y)]:
+        g = p.spmv(v, transpose=tr)
+        r = o.spmv(v, transpose=tr)
+        err = np.abs(g - r) / (np.abs(r) + 1e-12 * np.abs(r).max() + 1e-300)
+        assert np.max(err) < 1e-11, (tr, np.max(err))
+
+
+def long_rows_lp(seed):
+    """Columns with 300-3000 nonzeros (rows of K' on the workgroup-per-row
+    path), rows with up to ~2000 nonzeros, empty rows and empty columns."""
+    rng = np.random.default_rng(seed)
+    n, m1, m2 = 600, 300, 500
+    counts = rng.integers(0, 6, size=n)
+    counts[:5] = [300, 800, 3000 // 4, 700, 799]
+    counts[10:20] = 0
+    from paper_2312_14832_amd.gen import certificate_lp
+    lpd = certificate_lp(np.random.Generator(np.random.PCG64(seed)), m1, m2, counts.astype(np.int64))
+    return lpd
+
+
+LOCKSTEP_POINTS = [0, 1, 2, 7, 62, 63, 64, 65, 100, 126, 127, 128, 191, 255, 300, 383, 511, 640, 767, 900, 1023]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_lockstep_one_step_fp64(lpmod, oracle_mod, seed):
+    """Per-iteration parity: from the oracle's state after k accepted steps,
+    one more accepted step on the GPU (including the check and restart that
+    fall on k+1) equals the oracle's next state."""
+    data = gen.tiny_lp(seed)
+    p = lpmod.Problem(data)
+    o = oracle_mod.Oracle(data)
+    Dr, Dc, _ = o.scaling()
+    o.solve(1e-30, max(LOCKSTEP_POINTS) + 1)
+    total = o.get_state()
+    rows = []
+    for k in LOCKSTEP_POINTS:
+        if k >= total["k"]:
+            break
+        say(f"case lockstep seed={seed} k={k}")
+        o.solve(1e-30, k)
+        sk = o.get_state()
+        raw = o.get_state_raw()
+        o.solve(1e-30, k + 1)
+        so = o.get_state()
+        p.set_state(raw)
+        p.solve(1e-30, k + 1)
+        sg = gpu_state(lpmod, p)
+        assert ints_equal(sg, so), (k, {s_: (sg[s_], so[s_]) for s_ in ("k", "t", "attempts", "restarts")})
+        kap = step_condition(sk, so)
+        rows.append((k, kap) + state_diff(sg, so))
+        assert_states_close(sg, so, kap, f"k={k}", kkt_scale(so, Dr, Dc, data))
+    for r in rows:
+        say("k=%5d kappa=%9.3g  vec %9.2e (%s)  scalar %9.2e (%s)" % r)
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_lockstep_windows_fp64(lpmod, oracle_mod, seed):
+    """Short windows of 8 accepted steps that straddle checks and restarts."""
+    data = gen.tiny_lp(seed)
+    p = lpmod.Problem(data)
+    o = oracle_mod.Oracle(data)
+    Dr, Dc, _ = o.scaling()
+    for k in [60, 124, 188, 252, 316, 508, 764]:
+        say(f"case window seed={seed} k={k}")
+        o.solve(1e-30, k)
+        raw = o.get_state_raw()
+        o.solve(1e-30, k + 7)
+        prev = o.get_state()
+        o.solve(1e-30, k + 8)
+        so = o.get_state()
+        p.set_state(raw)
+        p.solve(1e-30, k + 8)
+        sg = gpu_state(lpmod, p)
+        assert ints_equal(sg, so)
+        assert_states_close(sg, so, step_condition(prev, so), f"window k={k}", kkt_scale(so, Dr, Dc, data))
+
+
+@pytest.mark.parametrize("seed", [0, 2])
+def test_free_running_trajectory(lpmod, oracle_mod, seed):
+    """Fresh GPU runs of k steps against the oracle.  Up to k=120 the two agree
+    to 1e-10.  Later the method itself amplifies rounding (the adaptive step
+    divides by norms of iterate differences): there the GPU must stay inside
+    the band in which the oracle differs from itself when its state is
+    perturbed by 1e-15 (x100 margin), i.e. it behaves as an ulp perturbation.
+    Within the first check window the 1e-10 bar holds outright."""
+    data = gen.tiny_lp(seed)
+    p = lpmod.Problem(data)
+    o = oracle_mod.Oracle(data)
+    o.solve(1e-30, 1)
+    raw1 = o.get_state_raw()
+    rows = []
+    for k in [2, 5, 10, 30, 63, 64, 65, 100, 120, 190, 256, 320]:
+        say(f"case free seed={seed} k={k}")
+        o.solve(1e-30, k)
+        so = o.get_state()
+        p.solve(1e-30, k)
+        sg = gpu_state(lpmod, p)
+        wv, vv = vec_diff(sg, so)
+        band = 0.0
+        for r in range(3):
+            q = oracle_mod.Oracle(data)
+            q.set_state_raw(perturbed(raw1, 1e-15, r))
+            q.solve(1e-30, k)
+            band = max(band, vec_diff(q.get_state(), so)[0])
+        rows.append((k, wv, vv, band))
+        if k <= 64:
+            assert wv < PER_STEP_TOL, (k, vv, wv)
+            assert ints_equal(sg, so)
+        assert wv <= max(PER_STEP_TOL, 100.0 * band), (k, vv, wv, band)
+    for r in rows:
+        say("k=%4d gpu-vs-oracle %9.2e (%s)  oracle-vs-perturbed-oracle %9.2e" % r)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
+def test_final_result_at_1e4(lpmod, oracle_mod, seed):
+    """Solve to rel KKT 1e-4.  The GPU's point, unscaled and evaluated by the
+    oracle on the original data, meets the three criteria at 1e-4; its
+    objective is within the gap tolerance of the oracle's own 1e-4 objective
+    (two 1e-4 points of a chaotic iteration can differ that much; the oracle
+    differs from itself by up to ~3e-5 relative under 1e-15 perturbations)."""
+    say(f"case final seed={seed}")
+    data = gen.tiny_lp(seed)
+    p = lpmod.Problem(data)
+    info = p.solve(1e-4, 200000)
+    assert info["status"] == "OPTIMAL"
+    o = oracle_mod.Oracle(data)
+    _, _, _, io = o.solve(1e-4, 200000)
+    x, y, lam, _ = p.result()
+    ev = o.eval_unscaled(x, y)
+    assert ev["rel_kkt"] <= 1e-4 * (1 + 1e-6)
+    assert ev["pobj"] == pytest.approx(info["pobj"], rel=1e-12)
+    assert ev["dobj"] == pytest.approx(info["dobj"], rel=1e-9, abs=1e-9)
+    assert ev["bound_viol"] <= 1e-12 * (1 + np.abs(data.x0).max()) and ev["sign_viol"] == 0.0
+    eps = 1e-4
+    assert abs(info["pobj"] - io["pobj"]) <= eps * (1 + abs(io["pobj"]) + abs(io["dobj"]))
+    assert 0.5 * io["iterations"] <= info["iterations"] <= 2.0 * io["iterations"]
+    fl, fu = np.isfinite(data.l), np.isfinite(data.u)
+    assert np.all(lam[~fl & ~fu] == 0) and np.all(lam[fl & ~fu] >= 0) and np.all(lam[~fl & fu] <= 0)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_final_objective_at_1e8(lpmod, oracle_mod, seed):
+    """At rel KKT 1e-8 the GPU objective matches the oracle's (and HiGHS's) to 1e-6 relative."""
+    say(f"case final 1e-8 seed={seed}")
+    from lp_helpers import highs
+    data = gen.tiny_lp(seed)
+    p = lpmod.Problem(data)
+    info = p.solve(1e-8, 400000)
+    assert info["status"] == "OPTIMAL"
+    o = oracle_mod.Oracle(data)
+    _, _, _, io = o.solve(1e-8, 400000)
+    ref, _, _ = highs(data)
+    assert abs(info["pobj"] - io["pobj"]) <= 1e-6 * abs(io["pobj"])
+    assert abs(info["pobj"] - ref) <= 1e-6 * abs(ref)
+    x, y, _, _ = p.result()
+    assert o.eval_unscaled(x, y)["rel_kkt"] <= 1e-8 * (1 + 1e-6)
+
+
+def test_resume_is_bitwise(lpmod):
+    say("case resume")
+    data = gen.tiny_lp(5)
+    p = lpmod.Problem(data)
+    p.solve(1e-30, 256)
+    full = p.get_state()
+    p.solve(1e-30, 128)
+    mid = p.get_state()
+    p.set_state(mid)
+    p.solve(1e-30, 256)
+    assert np.array_equal(p.get_state()[16:], full[16:])
+
+
+def test_deterministic_and_graph_equals_stream(lpmod):
+    say("case determinism")
+    data = gen.tiny_lp(6)
+    a = lpmod.Problem(data, use_graph=1)
+    b = lpmod.Problem(data, use_graph=0)
+    a.solve(1e-30, 500)
+    s1 = a.get_state()
+    a.solve(1e-30, 500)
+    s2 = a.get_state()
+    b.solve(1e-30, 500)
+    s3 = b.get_state()
+    assert np.array_equal(s1, s2)
+    assert np.array_equal(s1, s3)
+
+
+def test_warm_start_matches_oracle(lpmod, oracle_mod):
+    say("case warm start")
+    data = gen.tiny_lp(8)
+    rng = np.random.default_rng(3)
+    xs = data.x0 + 0.1 * rng.standard_normal(data.n)
+    ys = data.y0 + 0.1 * rng.standard_normal(data.m)
+    p = lpmod.Problem(data)
+    o = oracle_mod.Oracle(data)
+    p.set_start(xs, ys)
+    o.set_start(xs, ys)
+    p.solve(1e-30, 60)
+    o.solve(1e-30, 60)
+    so = o.get_state()
+    o.set_start(xs, ys)
+    o.solve(1e-30, 59)
+    assert_states_close(gpu_state(lpmod, p), so, step_condition(o.get_state(), so), "warm")
+
+
+@pytest.mark.parametrize("case", ["box_only", "long_rows", "simplex", "fixed_step"])
+def test_edge_cases(lpmod, oracle_mod, case):
+    say(f"case edge {case}")
+    kw = {}
+    if case == "box_only":
+        data = gen.box_only_lp(3, n=700)
+    elif case == "long_rows":
+        data = long_rows_lp(7)
+    elif case == "simplex":
+        c = np.random.default_rng(4).standard_normal(1000)
+        data = gen.from_dense(np.ones((1, 1000)), c, [1.0], np.zeros(1000), np.full(1000, np.inf), 1)
+    else:
+        data = gen.tiny_lp(9)
+        kw = dict(fixed_step=1, fixed_eta=0.05)
+    p = lpmod.Problem(data, **kw)
+    o = oracle_mod.Oracle(data, **kw)
+    Dr, Dc, _ = o.scaling()
+    for k in [0, 1, 63, 64, 300]:
+        say(f"case edge {case} k={k}")
+        o.solve(1e-30, k)
+        raw = o.get_state_raw()
+        prev = o.get_state()
+        o.solve(1e-30, k + 1)
+        so = o.get_state()
+        if so["k"] < k + 1:
+            break  # the oracle met rel KKT <= 1e-30 exactly: no further step exists
+        p.set_state(raw)
+        p.solve(1e-30, k + 1)
+        sg = gpu_state(lpmod, p)
+        assert ints_equal(sg, so), (case, k, {s_: (sg[s_], so[s_]) for s_ in ("k", "t", "attempts", "restarts")})
+        assert_states_close(sg, so, step_condition(prev, so), f"{case} k={k}", kkt_scale(so, Dr, Dc, data))
+    info = p.solve(1e-8, 200000)
+    _, _, _, io = o.solve(1e-8, 200000)
+    assert info["status"] == io["status"]
+    if io["status"] == "OPTIMAL":
+        assert abs(info["pobj"] - io["pobj"]) <= 1e-6 * max(1.0, abs(io["pobj"]))
+
+
+def test_iteration_limit_and_output(lpmod, oracle_mod):
+    say("case iteration limit")
+    data = gen.tiny_lp(2)
+    p = lpmod.Problem(data)
+    o = oracle_mod.Oracle(data)
+    info = p.solve(1e-9, 100)
+    _, _, _, io = o.solve(1e-9, 100)
+    assert info["status"] == "ITERATION_LIMIT" == io["status"]
+    xg, yg, lg, _ = p.result()
+    xo, yo, lo, _ = o.result()
+    assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo)
+    assert np.linalg.norm(yg - yo) <= 1e-10 * np.linalg.norm(yo)
+    assert info["rel_kkt"] == pytest.approx(io["rel_kkt"], rel=1e-9)
