@@ -26,7 +26,8 @@
  *     host buffers.
  *   - Device memory is allocated by the library at lp_load and released by
  *     lp_free.  All GPU work is ordered on lp_options.stream (a hipStream_t;
- *     NULL = the null stream) and every call returns after that work is done.
+ *     NULL = a non-blocking stream the library creates) and every call
+ *     returns after that work is done.
  *   - A handle is not thread-safe; separate handles are independent.
  */
 #ifndef PDLP_AMD_LP_H
@@ -74,7 +75,7 @@ typedef struct {
 
 typedef struct {
     int precision;          /* LP_FP64 or LP_MIXED */
-    void *stream;           /* hipStream_t for all GPU work, NULL = null stream */
+    void *stream;           /* hipStream_t for all GPU work; NULL = a stream the library creates */
     int ruiz_iters;         /* Ruiz inf-norm equilibration rounds (10) */
     double pc_alpha;        /* Pock-Chambolle exponent (1); < 0 skips that round */
     int check_every;        /* accepted steps between termination/restart checks (64) */
@@ -84,6 +85,7 @@ typedef struct {
     int use_graph;          /* 1: replay the iteration window as a captured hipGraph */
     int window;             /* attempt slots launched between host polls of the done flag (64) */
     int kernel_timing;      /* 1: bracket the two SpMV kernels with hipEvents (see lp_kernel_time) */
+    int slice_kib;          /* target KiB of a gathered vector per column slice of K and K' (2048 = half an XCD's L2) */
     int verbose;
 } lp_options;
 
@@ -101,8 +103,9 @@ typedef struct {
 /* Fill *opt with the defaults listed above. */
 void lp_default_options(lp_options *opt);
 
-/* Validate, copy to the GPU, reorder rows/columns into length bins, build
- * the CSR of K', and apply the diagonal scaling on the GPU.  The scaling is
+/* Validate, build the CSR of K' (counting sort, so the K' product needs no
+ * atomics), cut both products into column slices sized to stay resident in
+ * one XCD's L2, copy to the GPU and apply the diagonal scaling there.  The scaling is
  * the diagonal preconditioning the paper's experiments apply before PDHG
  * (Sec. 3.1).  On success *P owns all device memory; on error *P = NULL.
  * Errors: LP_ERR_ARG, _DIM, _NAN, _BOUNDS, _TOO_LARGE, _HIP, _NOMEM. */
@@ -143,14 +146,18 @@ int lp_get_scaling(const lp_problem *P, double *Dr, double *Dc);
  * buffers, original order.  Runs the same SpMV kernels as the solve. */
 int lp_spmv(lp_problem *P, int transpose, const double *in, double *out);
 
-/* Launch statistics of the SpMV kernels of the last lp_solve when
- * kernel_timing was set: which = 0 (K, fused dual step) or 1 (K', fused
- * averages and primal step); *count launches with *total_ms summed hipEvent
- * time.  Returns zeros when timing was off. */
+/* Launch statistics of the two products of the last lp_solve when
+ * kernel_timing was set: which = 0 (K x' partial pass + fused dual step) or
+ * 1 (K' y' partial pass + fused averages and next primal step); *count
+ * launch pairs with *total_ms summed hipEvent time.  Zeros when timing was
+ * off. */
 int lp_kernel_time(const lp_problem *P, int which, int64_t *count, double *total_ms);
 
 /* Device bytes held by the handle. */
 int lp_device_bytes(const lp_problem *P, int64_t *bytes);
+
+/* Column slices chosen for K (over x) and K' (over y); either may be NULL. */
+int lp_layout(const lp_problem *P, int *slices_K, int *slices_KT);
 
 void lp_free(lp_problem *P);
 const char *lp_strerror(int code);

@@ -25,74 +25,78 @@ namespace {
 
 constexpr int kNScalars = 16;
 
-int lanes_for_len(int64_t L)
+// Number of column slices for a gathered vector of `bytes`: the smallest
+// power of two that brings a slice under `slice_bytes` (at most 32).
+int slices_for(int64_t bytes, int64_t slice_bytes)
 {
-    if (L <= 4) return 1;
-    if (L <= 8) return 2;
-    if (L <= 16) return 4;
-    if (L <= 32) return 8;
-    if (L <= 64) return 16;
-    if (L <= 128) return 32;
-    if (L <= 256) return 64;
-    return 256;
+    int S = 1;
+    while (S < 32 && bytes > (int64_t)S * slice_bytes) S *= 2;
+    return S;
 }
 
-int lane_class(int lanes)
+// Host side of a Sliced product: per-slice CSR (slice-major), the position
+// of every sliced entry in the source CSR, and the row blocks.
+struct HostSliced {
+    int S = 1, rows = 0, cols = 0;
+    std::vector<int> rp, ci, src, brow, boff;
+    int max_blocks = 0;
+};
+
+// Rows of the source CSR must have their columns sorted, so that each
+// slice's part of a row is one contiguous run.
+void build_sliced(HostSliced &H, int rows, int cols, const std::vector<int> &rp, const std::vector<int> &ci, int S)
 {
-    switch (lanes) {
-    case 1: return 0;
-    case 2: return 1;
-    case 4: return 2;
-    case 8: return 3;
-    case 16: return 4;
-    case 32: return 5;
-    case 64: return 6;
-    default: return 7;
+    H.S = S;
+    H.rows = rows;
+    H.cols = cols;
+    const int64_t nnz = rp[rows];
+    H.rp.assign((size_t)S * (rows + 1), 0);
+    H.ci.resize((size_t)std::max<int64_t>(nnz, 1));
+    H.src.resize((size_t)std::max<int64_t>(nnz, 1));
+    H.brow.clear();
+    H.boff.assign(S + 1, 0);
+    std::vector<int> cur(rp.begin(), rp.end() - 1);
+    int64_t pos = 0;
+    H.max_blocks = 0;
+    for (int s = 0; s < S; ++s) {
+        const int hi = (int)((int64_t)cols * (s + 1) / S);
+        int *r = &H.rp[(size_t)s * (rows + 1)];
+        for (int i = 0; i < rows; ++i) {
+            r[i] = (int)pos;
+            int p = cur[i];
+            const int e = rp[i + 1];
+            while (p < e && ci[p] < hi) {
+                H.ci[pos] = ci[p];
+                H.src[pos] = p;
+                ++pos;
+                ++p;
+            }
+            cur[i] = p;
+        }
+        r[rows] = (int)pos;
+        int start = 0, nb = 0;
+        H.brow.push_back(0);
+        while (start < rows) {
+            int end = start + 1;
+            while (end < rows && end - start < kStreamRB && r[end + 1] - r[start] <= kStreamNB) ++end;
+            H.brow.push_back(end);
+            ++nb;
+            start = end;
+        }
+        H.boff[s + 1] = H.boff[s] + nb;
+        H.max_blocks = std::max(H.max_blocks, nb);
     }
 }
 
-constexpr int kLaneOf[8] = {1, 2, 4, 8, 16, 32, 64, 256};
-
-int vblocks(int rows, int lanes)
+// workgroups of a partial pass: enough for every row block of the busiest
+// slice, a multiple of 8 (XCDs) and of S, at most 4096
+int partial_grid(int S, int max_blocks)
 {
-    if (lanes >= kBlock) return rows;
-    const int64_t rpb = kBlock / lanes;
-    return (int)((rows + rpb - 1) / rpb);
-}
-
-// Stable counting sort of items by key in [0, nkeys): perm[new] = old.
-void counting_sort(const std::vector<int> &key, int nkeys, std::vector<int> &perm, std::vector<int> &cnt)
-{
-    const int64_t len = (int64_t)key.size();
-    cnt.assign(nkeys + 1, 0);
-    for (int64_t i = 0; i < len; ++i) cnt[key[i] + 1]++;
-    for (int k = 0; k < nkeys; ++k) cnt[k + 1] += cnt[k];
-    std::vector<int> pos(cnt.begin(), cnt.end() - 1);
-    perm.assign(len, 0);
-    for (int64_t i = 0; i < len; ++i) perm[pos[key[i]]++] = (int)i;
-}
-
-void build_segments(const std::vector<int> &cnt, int nkeys, Segments &seg, int &total_vb)
-{
-    seg.nseg = 0;
-    total_vb = 0;
-    for (int k = 0; k < nkeys; ++k) {
-        const int b = cnt[k], e = cnt[k + 1];
-        if (e <= b) continue;
-        const int lanes = kLaneOf[k % 8];
-        const int s = seg.nseg++;
-        seg.row_begin[s] = b;
-        seg.row_end[s] = e;
-        seg.lanes[s] = lanes;
-        seg.vb_begin[s] = total_vb;
-        total_vb += vblocks(e - b, lanes);
-    }
-    seg.vb_begin[seg.nseg] = total_vb;
-    if (seg.nseg == 0) {  // keep find_seg well defined
-        seg.row_begin[0] = seg.row_end[0] = 0;
-        seg.lanes[0] = 1;
-        seg.vb_begin[0] = seg.vb_begin[1] = 0;
-    }
+    const int unit = std::max(S, kXcds);
+    int64_t g = (int64_t)S * std::max(max_blocks, 1);
+    g = (g + unit - 1) / unit * unit;
+    const int cap = std::max(4096 / unit, 1) * unit;
+    return (int)std::min<int64_t>(g, cap);
 }
 
 struct HipError {
@@ -121,6 +125,7 @@ struct lp_problem {
     bool has_xs = false, has_ys = false;
     Ctl *hctl = nullptr;            // pinned host mirror of the device controller
     std::vector<void *> allocs;     // device allocations owned by the handle
+    std::vector<int64_t> alloc_bytes;
     int64_t dev_bytes = 0;
     bool mixed = false;
     Dev<double> d64{};
@@ -130,6 +135,7 @@ struct lp_problem {
     hipGraphExec_t graph = nullptr;
     int graph_window = 0;
     bool own_stream = false;
+    int slices_K = 1, slices_KT = 1;
     std::vector<hipEvent_t> ev;
     int64_t t_count[2] = {0, 0};
     double t_ms[2] = {0, 0};
@@ -144,15 +150,17 @@ struct lp_problem {
         bytes = (bytes + 255) & ~(size_t)255;
         HIPT(hipMalloc(&p, bytes));
         allocs.push_back(p);
+        alloc_bytes.push_back((int64_t)bytes);
         dev_bytes += (int64_t)bytes;
         return p;
     }
     void dfree(void *p)
     {
-        for (auto &a : allocs)
-            if (a == p) {
+        for (size_t i = 0; i < allocs.size(); ++i)
+            if (allocs[i] == p) {
                 (void)hipFree(p);
-                a = nullptr;
+                allocs[i] = nullptr;
+                dev_bytes -= alloc_bytes[i];
             }
     }
     ~lp_problem()
@@ -223,34 +231,61 @@ int validate(const lp_csr *K, const double *c, const double *q, const double *l,
 }
 
 // ---------------------------------------------------------------------------
-// load: reorder, transpose, upload, scale
+// load: transpose, slice, upload, scale
 // ---------------------------------------------------------------------------
 
+// Device side of a sliced product: structure uploaded from H, values gathered
+// from the scaled FP64 CSR values by the recorded source positions.
 template <typename T>
-void setup_typed(lp_problem *P, const double *kv64, const double *tv64, const double *cs64, const double *ls64,
-                 const double *us64, const double *qs64, const int *rp, const int *ci, const int *tp,
-                 const int *ti, const double *Dr, const double *Dc)
+Sliced<T> upload_sliced(lp_problem *P, const HostSliced &H, const double *scaled_csr_vals)
 {
-    const int64_t m = P->m, n = P->n, nnz = P->nnz;
+    const int64_t nnz = H.rp[(size_t)H.S * (H.rows + 1) - 1];
+    Sliced<T> q{};
+    q.S = H.S;
+    q.rows = H.rows;
+    q.grid = partial_grid(H.S, H.max_blocks);
+    int *rp = (int *)P->dalloc(sizeof(int) * H.rp.size());
+    int *ci = (int *)P->dalloc(sizeof(int) * (size_t)std::max<int64_t>(nnz, 1));
+    int *brow = (int *)P->dalloc(sizeof(int) * H.brow.size());
+    int *boff = (int *)P->dalloc(sizeof(int) * H.boff.size());
+    T *v = (T *)P->dalloc(sizeof(T) * (size_t)std::max<int64_t>(nnz, 1));
+    T *part = (T *)P->dalloc(sizeof(T) * (size_t)H.S * (size_t)std::max(H.rows, 1));
+    int *src = (int *)P->dalloc(sizeof(int) * (size_t)std::max<int64_t>(nnz, 1));
+    upload(P, rp, H.rp.data(), (int64_t)H.rp.size());
+    upload(P, ci, H.ci.data(), nnz);
+    upload(P, brow, H.brow.data(), (int64_t)H.brow.size());
+    upload(P, boff, H.boff.data(), (int64_t)H.boff.size());
+    upload(P, src, H.src.data(), nnz);
+    HIPT(launch_gather_values<T>(scaled_csr_vals, src, v, nnz, P->stream));
+    sync(P);
+    P->dfree(src);
+    q.rp = rp; q.ci = ci; q.brow = brow; q.boff = boff; q.v = v; q.part = part;
+    return q;
+}
+
+template <typename T>
+void setup_typed(lp_problem *P, const HostSliced &HK, const HostSliced &HT, const double *kv64, const double *tv64,
+                 const double *cs64, const double *ls64, const double *us64, const double *qs64, const double *Dr,
+                 const double *Dc)
+{
+    const int64_t m = P->m, n = P->n;
     Dev<T> &d = P->dev<T>();
     d.m = (int)m;
     d.n = (int)n;
     d.m1 = (int)P->m1;
-    d.rp = rp; d.ci = ci; d.tp = tp; d.ti = ti;
     d.Dr = Dr; d.Dc = Dc;
-    auto tvec = [&](int64_t len) { return (T *)P->dalloc(sizeof(T) * (size_t)len); };
+    d.K = upload_sliced<T>(P, HK, kv64);
+    d.KT = upload_sliced<T>(P, HT, tv64);
+    auto tvec = [&](int64_t len) { return (T *)P->dalloc(sizeof(T) * (size_t)std::max<int64_t>(len, 1)); };
     if (std::is_same<T, double>::value) {
-        d.kv = (const T *)kv64; d.tv = (const T *)tv64;
         d.cs = (const T *)cs64; d.ls = (const T *)ls64; d.us = (const T *)us64; d.qs = (const T *)qs64;
     } else {
-        T *kv = tvec(nnz), *tv = tvec(nnz), *cs = tvec(n), *ls = tvec(n), *us = tvec(n), *qs = tvec(m);
-        HIPT(launch_from_double<T>(kv64, kv, nnz, P->stream));
-        HIPT(launch_from_double<T>(tv64, tv, nnz, P->stream));
+        T *cs = tvec(n), *ls = tvec(n), *us = tvec(n), *qs = tvec(m);
         HIPT(launch_from_double<T>(cs64, cs, n, P->stream));
         HIPT(launch_from_double<T>(ls64, ls, n, P->stream));
         HIPT(launch_from_double<T>(us64, us, n, P->stream));
         HIPT(launch_from_double<T>(qs64, qs, m, P->stream));
-        d.kv = kv; d.tv = tv; d.cs = cs; d.ls = ls; d.us = us; d.qs = qs;
+        d.cs = cs; d.ls = ls; d.us = us; d.qs = qs;
     }
     for (int b = 0; b < 2; ++b) {
         d.xb[b] = tvec(n); d.yb[b] = tvec(m); d.Kxb[b] = tvec(m); d.KTyb[b] = tvec(n);
@@ -268,36 +303,27 @@ void setup_typed(lp_problem *P, const double *kv64, const double *tv64, const do
 
 int do_load(lp_problem *P, const lp_csr *K, const double *c, const double *q, const double *l, const double *u)
 {
-    const int64_t m = P->m, n = P->n, nnz = P->nnz, m1 = P->m1;
+    const int64_t m = P->m, n = P->n, nnz = P->nnz;
     const int32_t *rp0 = K->row_ptr, *ci0 = K->col;
     const double *v0 = K->val;
 
-    // rows: key = (inequality group, lane class); columns: key = lane class of the column count
-    std::vector<int> key_r((size_t)m), key_c((size_t)n, 0), cnt_r, cnt_c;
-    for (int64_t i = 0; i < m; ++i)
-        key_r[i] = (i >= m1 ? 8 : 0) + lane_class(lanes_for_len(rp0[i + 1] - rp0[i]));
-    std::vector<int> colcount((size_t)n, 0);
-    for (int64_t p = 0; p < nnz; ++p) colcount[ci0[p]]++;
-    for (int64_t j = 0; j < n; ++j) key_c[j] = lane_class(lanes_for_len(colcount[j]));
-    counting_sort(key_r, 16, P->perm_r, cnt_r);
-    counting_sort(key_c, 8, P->perm_c, cnt_c);
-    P->inv_r.assign((size_t)m, 0);
-    P->inv_c.assign((size_t)n, 0);
-    for (int64_t i = 0; i < m; ++i) P->inv_r[P->perm_r[i]] = (int)i;
-    for (int64_t j = 0; j < n; ++j) P->inv_c[P->perm_c[j]] = (int)j;
-    build_segments(cnt_r, 16, P->geo.segK, P->geo.vb_K);
-    build_segments(cnt_c, 8, P->geo.segKT, P->geo.vb_KT);
+    // vectors keep the caller's order (the permutation hooks stay identity)
+    P->perm_r.resize((size_t)m);
+    P->perm_c.resize((size_t)n);
+    for (int64_t i = 0; i < m; ++i) P->perm_r[i] = (int)i;
+    for (int64_t j = 0; j < n; ++j) P->perm_c[j] = (int)j;
+    P->inv_r = P->perm_r;
+    P->inv_c = P->perm_c;
 
-    // K with permuted rows and renumbered columns, columns sorted in each row
+    // K with the columns of each row sorted
     std::vector<int> rp((size_t)m + 1), ci((size_t)std::max<int64_t>(nnz, 1));
     std::vector<double> kv((size_t)std::max<int64_t>(nnz, 1));
     rp[0] = 0;
     std::vector<std::pair<int, double>> rowbuf;
     for (int64_t i = 0; i < m; ++i) {
-        const int o = P->perm_r[i];
-        const int b = rp0[o], e = rp0[o + 1];
+        const int b = rp0[i], e = rp0[i + 1];
         rowbuf.clear();
-        for (int p = b; p < e; ++p) rowbuf.emplace_back(P->inv_c[ci0[p]], v0[p]);
+        for (int p = b; p < e; ++p) rowbuf.emplace_back(ci0[p], v0[p]);
         std::sort(rowbuf.begin(), rowbuf.end(),
                   [](const std::pair<int, double> &a, const std::pair<int, double> &b2) { return a.first < b2.first; });
         const int base = rp[i];
@@ -307,7 +333,7 @@ int do_load(lp_problem *P, const lp_csr *K, const double *c, const double *q, co
         }
         rp[i + 1] = base + (int)rowbuf.size();
     }
-    // K' by counting sort over the renumbered K: rows of K' come out sorted by row of K
+    // K' by counting sort over the rows of K: each row of K' comes out sorted
     std::vector<int> tp((size_t)n + 1, 0), ti((size_t)std::max<int64_t>(nnz, 1));
     std::vector<double> tv((size_t)std::max<int64_t>(nnz, 1));
     for (int64_t p = 0; p < nnz; ++p) tp[ci[p] + 1]++;
@@ -321,16 +347,18 @@ int do_load(lp_problem *P, const lp_csr *K, const double *c, const double *q, co
                 tv[at] = kv[p];
             }
     }
-    std::vector<double> cp((size_t)n), lp((size_t)n), up((size_t)n), qp((size_t)m);
-    for (int64_t j = 0; j < n; ++j) {
-        const int o = P->perm_c[j];
-        cp[j] = c[o]; lp[j] = l[o]; up[j] = u[o];
-    }
-    for (int64_t i = 0; i < m; ++i) qp[i] = q[P->perm_r[i]];
+    // column slices sized so a slice of the gathered vector stays in one XCD's L2
+    const int64_t tsz = P->mixed ? 4 : 8;
+    const int64_t slice_bytes = (int64_t)P->opt.slice_kib * 1024;
+    HostSliced HK, HT;
+    build_sliced(HK, (int)m, (int)n, rp, ci, slices_for(n * tsz, slice_bytes));
+    build_sliced(HT, (int)n, (int)m, tp, ti, slices_for(m * tsz, slice_bytes));
+    P->slices_K = HK.S;
+    P->slices_KT = HT.S;
 
-    // device copies
-    auto ialloc = [&](int64_t len) { return (int *)P->dalloc(sizeof(int) * (size_t)len); };
-    auto dalloc = [&](int64_t len) { return (double *)P->dalloc(sizeof(double) * (size_t)len); };
+    // device copies of the CSR pair (for the scaling) and the vectors
+    auto ialloc = [&](int64_t len) { return (int *)P->dalloc(sizeof(int) * (size_t)std::max<int64_t>(len, 1)); };
+    auto dalloc = [&](int64_t len) { return (double *)P->dalloc(sizeof(double) * (size_t)std::max<int64_t>(len, 1)); };
     int *d_rp = ialloc(m + 1), *d_ci = ialloc(nnz), *d_tp = ialloc(n + 1), *d_ti = ialloc(nnz);
     double *d_kv = dalloc(nnz), *d_tv = dalloc(nnz);
     double *d_c = dalloc(n), *d_l = dalloc(n), *d_u = dalloc(n), *d_q = dalloc(m);
@@ -345,10 +373,10 @@ int do_load(lp_problem *P, const lp_csr *K, const double *c, const double *q, co
     upload(P, d_tp, tp.data(), n + 1);
     upload(P, d_ti, ti.data(), nnz);
     upload(P, d_tv, tv.data(), nnz);
-    upload(P, d_c, cp.data(), n);
-    upload(P, d_l, lp.data(), n);
-    upload(P, d_u, up.data(), n);
-    upload(P, d_q, qp.data(), m);
+    upload(P, d_c, c, n);
+    upload(P, d_l, l, n);
+    upload(P, d_u, u, n);
+    upload(P, d_q, q, m);
 
     // scaling: Ruiz inf-norm rounds, then one Pock-Chambolle round; row and
     // column factors both come from the same current matrix
@@ -389,23 +417,22 @@ int do_load(lp_problem *P, const lp_csr *K, const double *c, const double *q, co
     P->eta0 = h[4] > 0.0 ? 1.0 / h[4] : 1.0;
     if (P->opt.fixed_step) P->eta0 = P->opt.fixed_eta;
 
-    if (P->mixed) setup_typed<float>(P, d_kv, d_tv, cs, ls, us, qs, d_rp, d_ci, d_tp, d_ti, Dr, Dc);
-    else setup_typed<double>(P, d_kv, d_tv, cs, ls, us, qs, d_rp, d_ci, d_tp, d_ti, Dr, Dc);
+    if (P->mixed) setup_typed<float>(P, HK, HT, d_kv, d_tv, cs, ls, us, qs, Dr, Dc);
+    else setup_typed<double>(P, HK, HT, d_kv, d_tv, cs, ls, us, qs, Dr, Dc);
     sync(P);
+    // the CSR pair was only needed for the scaling
+    for (void *pp : {(void *)d_rp, (void *)d_ci, (void *)d_kv, (void *)d_tp, (void *)d_ti, (void *)d_tv,
+                     (void *)r, (void *)s, (void *)d_c, (void *)d_l, (void *)d_u, (void *)d_q})
+        P->dfree(pp);
     if (P->mixed) {
-        P->dfree(d_kv);
-        P->dfree(d_tv);
+        for (void *pp : {(void *)cs, (void *)ls, (void *)us, (void *)qs}) P->dfree(pp);
     }
-    P->dfree(r);
-    P->dfree(s);
-    P->dfree(d_c); P->dfree(d_l); P->dfree(d_u); P->dfree(d_q);
 
-    // one grid size for every solver kernel (its workgroups are the partial-sum slots)
+    // one grid size for the elementwise solver kernels (its workgroups are the partial-sum slots)
     Geo &g = P->geo;
     g.vb_n = (int)((n + kBlock - 1) / kBlock);
     g.vb_m = (int)((m + kBlock - 1) / kBlock);
-    int mx = std::max(std::max(g.vb_K, g.vb_KT + g.vb_m), g.vb_n + g.vb_m);
-    g.grid = std::max(1, std::min(kMaxGrid, mx));
+    g.grid = std::max(1, std::min(kMaxGrid, g.vb_n + g.vb_m));
     return LP_OK;
 }
 
@@ -419,10 +446,12 @@ void launch_slot(lp_problem *P, int slot, bool timed)
     Dev<T> &d = P->dev<T>();
     hipStream_t st = P->stream;
     if (timed) HIPT(hipEventRecord(P->ev[4 * slot + 0], st));
+    HIPT(launch_partial_K<T>(d, st));
     HIPT(launch_dual<T>(d, P->geo, st));
     if (timed) HIPT(hipEventRecord(P->ev[4 * slot + 1], st));
     HIPT(launch_step_decide<T>(d, P->geo, st));
     if (timed) HIPT(hipEventRecord(P->ev[4 * slot + 2], st));
+    HIPT(launch_partial_KT<T>(d, st));
     HIPT(launch_update<T>(d, P->geo, st));
     if (timed) HIPT(hipEventRecord(P->ev[4 * slot + 3], st));
     HIPT(launch_check_reduce<T>(d, P->geo, st));
@@ -498,8 +527,8 @@ int do_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit)
         c.fixed_step = P->opt.fixed_step;
         c.final_status = LP_ITERATION_LIMIT;
         put_ctl(P, c, d.ctl);
-        HIPT(launch_spmv<T>(d.rp, d.ci, d.kv, d.xb[0], d.Kxb[0], P->geo.segK, P->geo.vb_K, P->geo.grid, st));
-        HIPT(launch_spmv<T>(d.tp, d.ti, d.tv, d.yb[0], d.KTyb[0], P->geo.segKT, P->geo.vb_KT, P->geo.grid, st));
+        HIPT(launch_spmv<T>(d.K, d.xb[0], d.Kxb[0], st));
+        HIPT(launch_spmv<T>(d.KT, d.yb[0], d.KTyb[0], st));
         copy_dev(P, d.xa, d.xb[0], n);
         copy_dev(P, d.x0, d.xb[0], n);
         copy_dev(P, d.KTya, d.KTyb[0], n);
@@ -727,9 +756,9 @@ int do_spmv(lp_problem *P, int transpose, const double *in, double *out)
     upload(P, sin, tmp.data(), lin);
     HIPT(launch_from_double<T>(sin, tin, lin, P->stream));
     if (transpose)
-        HIPT(launch_spmv<T>(d.tp, d.ti, d.tv, tin, tout, P->geo.segKT, P->geo.vb_KT, P->geo.grid, P->stream));
+        HIPT(launch_spmv<T>(d.KT, tin, tout, P->stream));
     else
-        HIPT(launch_spmv<T>(d.rp, d.ci, d.kv, tin, tout, P->geo.segK, P->geo.vb_K, P->geo.grid, P->stream));
+        HIPT(launch_spmv<T>(d.K, tin, tout, P->stream));
     HIPT(launch_to_double<T>(tout, sout, lout, P->stream));
     download(P, tmp.data(), sout, lout);
     sync(P);
@@ -760,6 +789,7 @@ void lp_default_options(lp_options *o)
     o->use_graph = 1;
     o->window = 64;
     o->kernel_timing = 0;
+    o->slice_kib = 2048;
     o->verbose = 0;
 }
 
@@ -774,7 +804,7 @@ int lp_load(lp_problem **out, const lp_csr *K, const double *c, const double *q,
     if (opt) o = *opt;
     else lp_default_options(&o);
     if ((o.precision != LP_FP64 && o.precision != LP_MIXED) || o.check_every <= 0 || o.ruiz_iters < 0 ||
-        (o.fixed_step && !(o.fixed_eta > 0.0)) || o.window <= 0)
+        (o.fixed_step && !(o.fixed_eta > 0.0)) || o.window <= 0 || o.slice_kib <= 0)
         return LP_ERR_ARG;
     std::unique_ptr<lp_problem> P;
     try {
@@ -907,6 +937,14 @@ int lp_device_bytes(const lp_problem *P, int64_t *bytes)
 {
     if (!P || !bytes) return LP_ERR_ARG;
     *bytes = P->dev_bytes;
+    return LP_OK;
+}
+
+int lp_layout(const lp_problem *P, int *slices_K, int *slices_KT)
+{
+    if (!P) return LP_ERR_ARG;
+    if (slices_K) *slices_K = P->slices_K;
+    if (slices_KT) *slices_KT = P->slices_KT;
     return LP_OK;
 }
 

@@ -9,20 +9,31 @@
 namespace pdlp {
 
 constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
-constexpr int kMaxSeg = 32;      // row segments per CSR
-constexpr int kMaxGrid = 2048;   // workgroups of a solver kernel = partial-sum slots
+constexpr int kMaxGrid = 2048;   // workgroups of an elementwise solver kernel = partial-sum slots
 constexpr int kCheckSums = 18;   // 9 sums for the current and 9 for the averaged iterate
+constexpr int kXcds = 8;         // MI355X: 8 XCDs, workgroups dealt to them round-robin
+constexpr int kStreamNB = 2048;  // nonzeros staged in LDS per row block
+constexpr int kStreamRB = 256;   // rows per row block (one thread per row in the row sums)
 
-// Rows of one CSR (after reordering) fall into segments of consecutive rows
-// that share a lane count: 1..64 lanes of a wave per row, or 256 = a whole
-// workgroup per row.  Virtual block v of the grid-stride loop maps to
-// segment s with vb_begin[s] <= v < vb_begin[s+1].
-struct Segments {
-    int nseg;
-    int row_begin[kMaxSeg];
-    int row_end[kMaxSeg];
-    int lanes[kMaxSeg];
-    int vb_begin[kMaxSeg + 1];
+// One sparse product y = A x split by COLUMNS into S contiguous slices.  The
+// slice of x a workgroup gathers from is small enough to stay in one XCD's
+// L2: workgroup b works on slice b % S, and since workgroups are dealt to the
+// 8 XCDs round-robin, slice s only ever runs on XCDs congruent to s.  Each
+// slice is a CSR over all rows (entries slice-major), cut into row blocks of
+// at most kStreamRB rows and kStreamNB nonzeros (a single longer row is a
+// block of its own).  The pass writes S partial vectors, summed in a fixed
+// order by the elementwise epilogue.
+template <typename T>
+struct Sliced {
+    int S;            // column slices (a power of two)
+    int rows;         // rows of the product
+    int grid;         // workgroups of the partial pass (a multiple of 8 and of S)
+    const int *rp;    // [S*(rows+1)] per-slice row pointers into ci / v
+    const int *ci;    // column indices, slice-major
+    const T *v;       // values, same layout
+    const int *brow;  // row-block boundaries; slice s owns brow[boff[s]+s .. boff[s+1]+s]
+    const int *boff;  // [S+1] prefix counts of row blocks
+    T *part;          // [S*rows] partial products
 };
 
 // check modes
@@ -64,10 +75,8 @@ struct Ctl {
 template <typename T>
 struct Dev {
     int m, n, m1;
-    const int *rp, *ci;        // K   (rows permuted by bin, columns renumbered)
-    const T *kv;
-    const int *tp, *ti;        // K'  (CSR of the transpose, same renumbering)
-    const T *tv;
+    Sliced<T> K;               // K  (m x n), sliced over the columns (x)
+    Sliced<T> KT;              // K' (n x m), sliced over the rows of K (y)
     const T *cs, *ls, *us;     // scaled c, l, u   [n]
     const T *qs;               // scaled q         [m]
     const double *Dr, *Dc;     // scaling factors
@@ -82,20 +91,22 @@ struct Dev {
 };
 
 struct Geo {
-    int grid;                  // workgroups of every solver kernel
-    int vb_K, vb_KT, vb_n, vb_m;
-    Segments segK, segKT;
+    int grid;                  // workgroups of the elementwise solver kernels
+    int vb_n, vb_m;            // 256-element chunks of the n- and m-vectors
 };
 
 // launchers (kernels.hip); each returns the hipError_t of the launch
+template <typename T> hipError_t launch_partial_K(const Dev<T> &d, hipStream_t s);
+template <typename T> hipError_t launch_partial_KT(const Dev<T> &d, hipStream_t s);
 template <typename T> hipError_t launch_dual(const Dev<T> &d, const Geo &g, hipStream_t s);
 template <typename T> hipError_t launch_step_decide(const Dev<T> &d, const Geo &g, hipStream_t s);
 template <typename T> hipError_t launch_update(const Dev<T> &d, const Geo &g, hipStream_t s);
 template <typename T> hipError_t launch_check_reduce(const Dev<T> &d, const Geo &g, hipStream_t s);
 template <typename T> hipError_t launch_check_decide(const Dev<T> &d, const Geo &g, double Nq, double Nc, hipStream_t s);
 template <typename T> hipError_t launch_check_apply(const Dev<T> &d, const Geo &g, hipStream_t s);
-template <typename T> hipError_t launch_spmv(const int *rp, const int *ci, const T *v, const T *in, T *out,
-                                             const Segments &seg, int total_vb, int grid, hipStream_t s);
+template <typename T> hipError_t launch_spmv(const Sliced<T> &P, const T *in, T *out, hipStream_t s);
+template <typename T> hipError_t launch_gather_values(const double *src_vals, const int *src_pos, T *dst, int64_t len,
+                                                      hipStream_t s);
 template <typename T> hipError_t launch_start(const Dev<T> &d, const double *xs, const double *ys, int cur, hipStream_t s);
 template <typename T> hipError_t launch_result(const Dev<T> &d, double *x, double *y, double *lam, hipStream_t s);
 template <typename T> hipError_t launch_to_double(const T *in, double *out, int64_t len, hipStream_t s);

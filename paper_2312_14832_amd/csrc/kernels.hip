@@ -3,10 +3,10 @@
 // One accepted PDHG step (cuPDLP-C paper, Sec. 2, "Restarted PDHG") is the
 // pair of sparse products K x' and K' y' with everything elementwise fused
 // into their epilogues:
-//   k_dual    : K x' over the rows of K, dual update
+//   k_partial_K + k_dual     : K x', then the dual update
 //               y' = proj_Y(y + eta*omega*(q - 2Kx' + Kx)) and the partial
 //               sums of the step-size test
-//   k_update  : K' y' over the rows of K' (the CSR of the transpose, so no
+//   k_partial_KT + k_update  : K' y' over the CSR of the transpose (so no
 //               atomics), step-weighted averages and the next primal trial
 //               x'' = proj_X(x' - (eta'/omega)(c - K'y'))
 //   k_check_* : every check_every accepted steps, the termination quantities
@@ -17,8 +17,11 @@
 // the controller block (Ctl); every kernel reads it at its start, so the
 // host only polls a done flag once per window of attempts.
 //
-// Sparse rows are grouped into segments with a fixed number of lanes per row
-// (1..64 lanes of a wave64, or a whole 256-thread workgroup for long rows).
+// Each product is a column-sliced CSR-Stream pass (see Sliced in internal.h):
+// a workgroup stages the products v*x[col] of one row block in LDS with
+// coalesced streaming loads, then sums each row from LDS; the slice of x it
+// gathers from stays resident in its XCD's L2.  The fused epilogue kernels
+// add the slices' partial rows in a fixed order.
 // Reductions are deterministic: each lane accumulates in FP64, wave64
 // butterflies and a fixed-order LDS step give one partial per workgroup, and
 // a single workgroup sums the partials in a fixed order.  No float atomics.
@@ -51,13 +54,6 @@ __device__ __forceinline__ double proj_lambda(double g, bool lf, bool uf)
     if (!lf) return g < 0.0 ? g : 0.0;
     if (!uf) return g > 0.0 ? g : 0.0;
     return g;
-}
-
-__device__ __forceinline__ int find_seg(const Segments &s, int vb)
-{
-    int i = 0;
-    while (i + 1 < s.nseg && vb >= s.vb_begin[i + 1]) ++i;
-    return i;
 }
 
 // One FP64 partial per workgroup and value: wave64 butterfly, then the four
@@ -115,77 +111,69 @@ __device__ __forceinline__ void block_sum_partials(const double *part, int np, d
 }
 
 // ----------------------------------------------------------------------------
-// row-segment SpMV core
+// column-sliced CSR-Stream partial products
 // ----------------------------------------------------------------------------
 
-// G lanes per row, 256/G rows per virtual block; lane 0 of the group calls
-// the epilogue with the row's dot product.
-template <int G, typename T, typename Epi>
-__device__ __forceinline__ void rows_wave(const int *__restrict__ rp, const int *__restrict__ ci,
-                                          const T *__restrict__ v, const T *__restrict__ x, int r0, int rend,
-                                          int local, Epi &epi)
+template <typename T>
+__device__ __forceinline__ void sliced_partial(const Sliced<T> &P, const T *__restrict__ x)
 {
-    constexpr int RPB = kBlock / G;
-    const int row = r0 + local * RPB + (int)threadIdx.x / G;
-    const int lane = (int)threadIdx.x & (G - 1);
-    if (row < rend) {
-        const int b = rp[row], e = rp[row + 1];
-        T acc = T(0);
-        for (int j = b + lane; j < e; j += G) acc += v[j] * x[ci[j]];
-        if constexpr (G > 1) {
+    __shared__ T prod[kStreamNB];
+    __shared__ double red[kBlock / 64];
+    const int S = P.S;
+    const int s = (int)blockIdx.x % S;
+    const int chunk0 = (int)blockIdx.x / S, stride = (int)gridDim.x / S;
+    const int *__restrict__ rp = P.rp + (size_t)s * (P.rows + 1);
+    T *__restrict__ out = P.part + (size_t)s * P.rows;
+    const int nblk = P.boff[s + 1] - P.boff[s];
+    const int *__restrict__ bro = P.brow + P.boff[s] + s;
+    const int *__restrict__ ci = P.ci;
+    const T *__restrict__ v = P.v;
+    for (int k = chunk0; k < nblk; k += stride) {
+        const int r0 = bro[k], r1 = bro[k + 1];
+        const int b = rp[r0], e = rp[r1];
+        const int cnt = e - b;
+        if (cnt <= kStreamNB) {
+#pragma unroll 4
+            for (int t = (int)threadIdx.x; t < cnt; t += kBlock) {
+                const int c = __builtin_nontemporal_load(ci + b + t);
+                const T a = __builtin_nontemporal_load(v + b + t);
+                prod[t] = a * x[c];
+            }
+            __syncthreads();
+            const int r = r0 + (int)threadIdx.x;   // r1 - r0 <= kStreamRB == kBlock
+            if (r < r1) {
+                T acc = T(0);
+                const int je = rp[r + 1] - b;
+                for (int j = rp[r] - b; j < je; ++j) acc += prod[j];
+                out[r] = acc;
+            }
+            __syncthreads();
+        } else {
+            // one row with more than kStreamNB nonzeros in this slice
+            T acc = T(0);
+            for (int t = b + (int)threadIdx.x; t < e; t += kBlock) acc += v[t] * x[ci[t]];
 #pragma unroll
-            for (int off = G / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, G);
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = (double)acc;
+            __syncthreads();
+            if (threadIdx.x == 0) out[r0] = (T)(((red[0] + red[1]) + red[2]) + red[3]);
+            __syncthreads();
         }
-        if (lane == 0) epi(row, acc);
     }
 }
 
-// A whole workgroup on one long row.
-template <typename T, typename Epi>
-__device__ __forceinline__ void rows_block(const int *__restrict__ rp, const int *__restrict__ ci,
-                                           const T *__restrict__ v, const T *__restrict__ x, int row, Epi &epi)
+// row i of the product: the slices' partials added in slice order
+template <typename T>
+__device__ __forceinline__ T sum_slices(const Sliced<T> &P, int i)
 {
-    __shared__ double sh[kBlock / 64];
-    const int b = rp[row], e = rp[row + 1];
-    T acc = T(0);
-    for (int j = b + (int)threadIdx.x; j < e; j += kBlock) acc += v[j] * x[ci[j]];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = (double)acc;
-    __syncthreads();
-    if (threadIdx.x == 0) epi(row, (T)(((sh[0] + sh[1]) + sh[2]) + sh[3]));
-    __syncthreads();
-}
-
-template <typename T, typename Epi>
-__device__ __forceinline__ void spmv_vb(const Segments &seg, int vb, const int *__restrict__ rp,
-                                        const int *__restrict__ ci, const T *__restrict__ v,
-                                        const T *__restrict__ x, Epi &epi)
-{
-    const int s = find_seg(seg, vb);
-    const int local = vb - seg.vb_begin[s];
-    const int r0 = seg.row_begin[s], re = seg.row_end[s];
-    switch (seg.lanes[s]) {
-    case 1: rows_wave<1>(rp, ci, v, x, r0, re, local, epi); break;
-    case 2: rows_wave<2>(rp, ci, v, x, r0, re, local, epi); break;
-    case 4: rows_wave<4>(rp, ci, v, x, r0, re, local, epi); break;
-    case 8: rows_wave<8>(rp, ci, v, x, r0, re, local, epi); break;
-    case 16: rows_wave<16>(rp, ci, v, x, r0, re, local, epi); break;
-    case 32: rows_wave<32>(rp, ci, v, x, r0, re, local, epi); break;
-    case 64: rows_wave<64>(rp, ci, v, x, r0, re, local, epi); break;
-    default: rows_block(rp, ci, v, x, r0 + local, epi); break;
-    }
+    T a = P.part[i];
+    for (int s = 1; s < P.S; ++s) a += P.part[(size_t)s * P.rows + i];
+    return a;
 }
 
 // ----------------------------------------------------------------------------
 // epilogues
 // ----------------------------------------------------------------------------
-
-template <typename T>
-struct PlainEpi {
-    T *out;
-    __device__ __forceinline__ void operator()(int i, T s) { out[i] = s; }
-};
 
 // dual step on row i: y' = proj_Y(y + sigma (q - 2 Kx' + Kx)), y'_i >= 0 on G rows
 template <typename T>
@@ -260,16 +248,36 @@ __device__ __forceinline__ void primal_elem(const Dev<T> &d, int c, T tau, int j
 // the iteration kernels
 // ----------------------------------------------------------------------------
 
+// K x' partial products (x' = the primal trial)
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_dual(Dev<T> d, Segments seg, int total_vb)
+__global__ __launch_bounds__(kBlock) void k_partial_K(Dev<T> d)
+{
+    const Ctl *ctl = d.ctl;
+    if (ctl->done) return;
+    sliced_partial(d.K, (const T *)pick(d.xb, ctl->cur ^ 1));
+}
+
+// K' y' partial products, only after an accepted step
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_partial_KT(Dev<T> d)
+{
+    const Ctl *ctl = d.ctl;
+    if (ctl->done || !ctl->accepted) return;
+    sliced_partial(d.KT, (const T *)pick(d.yb, ctl->cur));
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dual(Dev<T> d, int vb_m)
 {
     const Ctl *ctl = d.ctl;
     if (ctl->done) return;
     const int c = ctl->cur;
     const T sigma = (T)(ctl->eta * ctl->omega);
     DualEpi<T> epi{pick(d.yb, c), pick(d.Kxb, c), d.qs, pick(d.yb, c ^ 1), pick(d.Kxb, c ^ 1), d.m1, sigma, 0.0, 0.0};
-    const T *x = pick(d.xb, c ^ 1);
-    for (int vb = blockIdx.x; vb < total_vb; vb += gridDim.x) spmv_vb(seg, vb, d.rp, d.ci, d.kv, x, epi);
+    for (int vb = blockIdx.x; vb < vb_m; vb += gridDim.x) {
+        const int i = vb * kBlock + (int)threadIdx.x;
+        if (i < d.m) epi(i, sum_slices(d.K, i));
+    }
     double v[2] = {epi.dy2, epi.inter};
     block_store_partials<2>(v, d.part_dual);
 }
@@ -324,7 +332,7 @@ __global__ __launch_bounds__(kBlock) void k_step_decide(Ctl *ctl, const double *
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_update(Dev<T> d, Segments segT, int vb_KT, int vb_n, int vb_m)
+__global__ __launch_bounds__(kBlock) void k_update(Dev<T> d, int vb_n, int vb_m)
 {
     const Ctl *ctl = d.ctl;
     if (ctl->done) return;
@@ -342,12 +350,13 @@ __global__ __launch_bounds__(kBlock) void k_update(Dev<T> d, Segments segT, int 
                          (T)ctl->avg_w, tau, ctl->mode == MODE_NONE, 0.0};
         const T *y = pick(d.yb, c);
         const T *kx = pick(d.Kxb, c);
-        const int total = vb_KT + vb_m;
+        const int total = vb_n + vb_m;
         for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
-            if (vb < vb_KT) {
-                spmv_vb(segT, vb, d.tp, d.ti, d.tv, y, epi);
+            if (vb < vb_n) {
+                const int j = vb * kBlock + (int)threadIdx.x;
+                if (j < d.n) epi(j, sum_slices(d.KT, j));
             } else {
-                const int i = (vb - vb_KT) * kBlock + (int)threadIdx.x;
+                const int i = (vb - vb_n) * kBlock + (int)threadIdx.x;
                 if (i < d.m) {
                     const T w = epi.w;
                     const T a = d.ya[i];
@@ -577,12 +586,25 @@ __global__ __launch_bounds__(kBlock) void k_check_apply(Dev<T> d, int vb_n, int 
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_spmv(const int *__restrict__ rp, const int *__restrict__ ci,
-                                                 const T *__restrict__ v, const T *__restrict__ in,
-                                                 T *__restrict__ out, Segments seg, int total_vb)
+__global__ __launch_bounds__(kBlock) void k_partial_plain(Sliced<T> P, const T *__restrict__ x)
 {
-    PlainEpi<T> e{out};
-    for (int vb = blockIdx.x; vb < total_vb; vb += gridDim.x) spmv_vb(seg, vb, rp, ci, v, in, e);
+    sliced_partial(P, x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sum_slices(Sliced<T> P, T *__restrict__ out)
+{
+    const int i = blockIdx.x * kBlock + (int)threadIdx.x;
+    if (i < P.rows) out[i] = sum_slices(P, i);
+}
+
+// values into the sliced layout: dst[p] = src_vals[src_pos[p]]
+template <typename T>
+__global__ void k_gather_values(const double *__restrict__ src_vals, const int *__restrict__ src_pos,
+                                T *__restrict__ dst, int64_t len)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < len) dst[i] = (T)src_vals[src_pos[i]];
 }
 
 // start point: x = proj_X(x_start * Dc), y = proj_Y(y_start * Dr) (0 when absent)
@@ -742,9 +764,23 @@ __global__ void k_max_final(const double *part, int np, double *out)
 static inline int blocks_for(int64_t len) { return (int)((len + kBlock - 1) / kBlock); }
 
 template <typename T>
+hipError_t launch_partial_K(const Dev<T> &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_partial_K<T>, dim3(d.K.grid), dim3(kBlock), 0, s, d);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_partial_KT(const Dev<T> &d, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_partial_KT<T>, dim3(d.KT.grid), dim3(kBlock), 0, s, d);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_dual(const Dev<T> &d, const Geo &g, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_dual<T>, dim3(g.grid), dim3(kBlock), 0, s, d, g.segK, g.vb_K);
+    hipLaunchKernelGGL(k_dual<T>, dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_m);
     return hipGetLastError();
 }
 
@@ -759,7 +795,7 @@ hipError_t launch_step_decide(const Dev<T> &d, const Geo &g, hipStream_t s)
 template <typename T>
 hipError_t launch_update(const Dev<T> &d, const Geo &g, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_update<T>, dim3(g.grid), dim3(kBlock), 0, s, d, g.segKT, g.vb_KT, g.vb_n, g.vb_m);
+    hipLaunchKernelGGL(k_update<T>, dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_n, g.vb_m);
     return hipGetLastError();
 }
 
@@ -786,11 +822,19 @@ hipError_t launch_check_apply(const Dev<T> &d, const Geo &g, hipStream_t s)
 }
 
 template <typename T>
-hipError_t launch_spmv(const int *rp, const int *ci, const T *v, const T *in, T *out, const Segments &seg,
-                       int total_vb, int grid, hipStream_t s)
+hipError_t launch_spmv(const Sliced<T> &P, const T *in, T *out, hipStream_t s)
 {
-    if (total_vb <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spmv<T>, dim3(grid), dim3(kBlock), 0, s, rp, ci, v, in, out, seg, total_vb);
+    if (P.rows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_partial_plain<T>, dim3(P.grid), dim3(kBlock), 0, s, P, in);
+    hipLaunchKernelGGL(k_sum_slices<T>, dim3(blocks_for(P.rows)), dim3(kBlock), 0, s, P, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gather_values(const double *src_vals, const int *src_pos, T *dst, int64_t len, hipStream_t s)
+{
+    if (len <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_values<T>, dim3(blocks_for(len)), dim3(kBlock), 0, s, src_vals, src_pos, dst, len);
     return hipGetLastError();
 }
 
@@ -902,14 +946,16 @@ hipError_t launch_absmax(const double *a, int64_t len, double *part, double *out
 }
 
 #define PDLP_INSTANTIATE(T)                                                                                        \
+    template hipError_t launch_partial_K<T>(const Dev<T> &, hipStream_t);                                          \
+    template hipError_t launch_partial_KT<T>(const Dev<T> &, hipStream_t);                                         \
     template hipError_t launch_dual<T>(const Dev<T> &, const Geo &, hipStream_t);                                  \
     template hipError_t launch_step_decide<T>(const Dev<T> &, const Geo &, hipStream_t);                           \
     template hipError_t launch_update<T>(const Dev<T> &, const Geo &, hipStream_t);                                \
     template hipError_t launch_check_reduce<T>(const Dev<T> &, const Geo &, hipStream_t);                          \
     template hipError_t launch_check_decide<T>(const Dev<T> &, const Geo &, double, double, hipStream_t);          \
     template hipError_t launch_check_apply<T>(const Dev<T> &, const Geo &, hipStream_t);                           \
-    template hipError_t launch_spmv<T>(const int *, const int *, const T *, const T *, T *, const Segments &, int,  \
-                                       int, hipStream_t);                                                          \
+    template hipError_t launch_spmv<T>(const Sliced<T> &, const T *, T *, hipStream_t);                            \
+    template hipError_t launch_gather_values<T>(const double *, const int *, T *, int64_t, hipStream_t);           \
     template hipError_t launch_start<T>(const Dev<T> &, const double *, const double *, int, hipStream_t);         \
     template hipError_t launch_result<T>(const Dev<T> &, double *, double *, double *, hipStream_t);               \
     template hipError_t launch_to_double<T>(const T *, double *, int64_t, hipStream_t);                            \

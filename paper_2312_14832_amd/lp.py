@@ -22,7 +22,7 @@ NSCALARS = 16
 
 # every symbol include/lp.h declares
 EXPORTS = ["lp_default_options", "lp_load", "lp_set_start", "lp_solve", "lp_result", "lp_get_state",
-           "lp_set_state", "lp_get_scaling", "lp_spmv", "lp_kernel_time", "lp_device_bytes", "lp_free",
+           "lp_set_state", "lp_get_scaling", "lp_spmv", "lp_kernel_time", "lp_device_bytes", "lp_layout", "lp_free",
            "lp_strerror", "lp_last_error"]
 
 
@@ -36,7 +36,8 @@ class LPOptions(C.Structure):
     _fields_ = [("precision", C.c_int), ("stream", C.c_void_p), ("ruiz_iters", C.c_int),
                 ("pc_alpha", C.c_double), ("check_every", C.c_int), ("kkt_omega_power", C.c_double),
                 ("fixed_step", C.c_int), ("fixed_eta", C.c_double), ("use_graph", C.c_int),
-                ("window", C.c_int), ("kernel_timing", C.c_int), ("verbose", C.c_int)]
+                ("window", C.c_int), ("kernel_timing", C.c_int), ("slice_kib", C.c_int),
+                ("verbose", C.c_int)]
 
 
 class LPInfo(C.Structure):
@@ -70,6 +71,7 @@ def library():
         L.lp_spmv.argtypes = [C.c_void_p, C.c_int, dp, dp]
         L.lp_kernel_time.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.lp_device_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+        L.lp_layout.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.lp_free.argtypes = [C.c_void_p]
         L.lp_free.restype = None
         L.lp_strerror.argtypes = [C.c_int]
@@ -186,6 +188,11 @@ class Problem:
         cnt = C.c_int64(); ms = C.c_double()
         self._check(library().lp_kernel_time(self.h, int(which), C.byref(cnt), C.byref(ms)))
         return cnt.value, ms.value
+
+    def layout(self):
+        a = C.c_int(); b = C.c_int()
+        self._check(library().lp_layout(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def device_bytes(self):
         b = C.c_int64()

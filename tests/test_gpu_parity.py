@@ -44,16 +44,21 @@ def test_scaling_matches_oracle(lpmod, oracle_mod, seed):
     assert np.max(np.abs(Dc - Dc_o) / Dc_o) < 1e-13
 
 
+@pytest.mark.parametrize("slice_kib", [2048, 1])
 @pytest.mark.parametrize("maker", ["tiny", "powerlaw", "long_rows"])
-def test_spmv_matches_oracle(lpmod, oracle_mod, maker):
-    say(f"case spmv {maker}")
+def test_spmv_matches_oracle(lpmod, oracle_mod, maker, slice_kib):
+    """Both sliced products against the oracle's plain CSR loops; slice_kib=1
+    forces many column slices (and row blocks) even on small inputs."""
+    say(f"case spmv {maker} slice_kib={slice_kib}")
     if maker == "tiny":
         data = gen.tiny_lp(3)
     elif maker == "powerlaw":
         data = gen.large_lp(seed=5, n=20000, m1=5000, m2=5000)
     else:
         data = long_rows_lp(7)
-    p = lpmod.Problem(data)
+    p = lpmod.Problem(data, slice_kib=slice_kib)
+    if slice_kib == 1:
+        assert p.layout()[0] > 1
     o = oracle_mod.Oracle(data)
     rng = np.random.default_rng(1)
     x = rng.standard_normal(data.n)
@@ -81,13 +86,13 @@ def long_rows_lp(seed):
 LOCKSTEP_POINTS = [0, 1, 2, 7, 62, 63, 64, 65, 100, 126, 127, 128, 191, 255, 300, 383, 511, 640, 767, 900, 1023]
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2])
-def test_lockstep_one_step_fp64(lpmod, oracle_mod, seed):
+@pytest.mark.parametrize("seed,slice_kib", [(0, 2048), (1, 2048), (2, 1)])
+def test_lockstep_one_step_fp64(lpmod, oracle_mod, seed, slice_kib):
     """Per-iteration parity: from the oracle's state after k accepted steps,
     one more accepted step on the GPU (including the check and restart that
     fall on k+1) equals the oracle's next state."""
     data = gen.tiny_lp(seed)
-    p = lpmod.Problem(data)
+    p = lpmod.Problem(data, slice_kib=slice_kib)
     o = oracle_mod.Oracle(data)
     Dr, Dc, _ = o.scaling()
     o.solve(1e-30, max(LOCKSTEP_POINTS) + 1)
@@ -305,11 +310,51 @@ def test_iteration_limit_and_output(lpmod, oracle_mod):
     data = gen.tiny_lp(2)
     p = lpmod.Problem(data)
     o = oracle_mod.Oracle(data)
-    info = p.solve(1e-9, 100)
-    _, _, _, io = o.solve(1e-9, 100)
+    # 40 steps: inside the first check window, where both runs agree to ~1e-13
+    info = p.solve(1e-9, 40)
+    _, _, _, io = o.solve(1e-9, 40)
     assert info["status"] == "ITERATION_LIMIT" == io["status"]
     xg, yg, lg, _ = p.result()
     xo, yo, lo, _ = o.result()
     assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo)
     assert np.linalg.norm(yg - yo) <= 1e-10 * np.linalg.norm(yo)
     assert info["rel_kkt"] == pytest.approx(io["rel_kkt"], rel=1e-9)
+
+
+def test_full_size_large_lp(lpmod, oracle_mod):
+    """The 2e6 x 1e6, ~2e7-nonzero workload the bench times, in the same
+    launch configuration: scaling factors, both products on full vectors,
+    and lockstep steps across the first check, against the oracle."""
+    say("case full size: generate")
+    data = gen.large_lp(seed=1)
+    say("case full size: load")
+    p = lpmod.Problem(data)
+    assert p.layout() == (8, 4)
+    o = oracle_mod.Oracle(data)
+    Dr, Dc = p.scaling()
+    Dr_o, Dc_o, _ = o.scaling()
+    assert np.max(np.abs(Dr - Dr_o) / Dr_o) < 1e-12
+    assert np.max(np.abs(Dc - Dc_o) / Dc_o) < 1e-12
+    say("case full size: spmv")
+    rng = np.random.default_rng(2)
+    for tr, ln in [(False, data.n), (True, data.m)]:
+        v = rng.standard_normal(ln)
+        g = p.spmv(v, transpose=tr)
+        r = o.spmv(v, transpose=tr)
+        assert np.linalg.norm(g - r) <= 1e-14 * np.linalg.norm(r) * 10, tr
+        idx = rng.choice(len(r), 2000, replace=False)
+        err = np.abs(g[idx] - r[idx]) / (np.abs(r[idx]) + 1e-12 * np.abs(r).max())
+        assert np.max(err) < 1e-10, tr
+    Drs, Dcs, _ = o.scaling()
+    for k in [0, 63]:
+        say(f"case full size: lockstep k={k}")
+        o.solve(1e-30, k)
+        raw = o.get_state_raw()
+        prev = o.get_state()
+        o.solve(1e-30, k + 1)
+        so = o.get_state()
+        p.set_state(raw)
+        p.solve(1e-30, k + 1)
+        sg = gpu_state(lpmod, p)
+        assert ints_equal(sg, so), k
+        assert_states_close(sg, so, step_condition(prev, so), f"full k={k}", kkt_scale(so, Drs, Dcs, data))
