@@ -32,7 +32,9 @@ if ROOT not in sys.path:
 
 ITERS_PER_STEP = 64
 HBM_PEAK_GBS = 8000.0
-KERNEL_NAMES = {0: "k_dual<double>", 1: "k_update<double>"}
+def kernel_names(precision):
+    t = "double" if precision == "fp64" else "float"
+    return {0: f"k_partial_K<{t}>+k_dual<{t}>", 1: f"k_partial_KT<{t}>+k_update<{t}>"}
 
 
 def kernel_bytes(which, n, m, nnz, s=8):
@@ -147,11 +149,11 @@ def main():
         cnt, ms = prob.kernel_time(w)
         avg_us = 1e3 * ms / max(cnt, 1)
         b = kernel_bytes(w, n, m1 + m2, data.nnz, s)
-        spmv[KERNEL_NAMES[w]] = {"launches": cnt, "avg_us": avg_us, "alg_bytes": b,
+        spmv[kernel_names(args.precision)[w]] = {"launches": cnt, "avg_us": avg_us, "alg_bytes": b,
                                  "GB_s": b / (avg_us * 1e-6) / 1e9 if avg_us > 0 else None}
     dom = max(spmv, key=lambda k: spmv[k]["avg_us"] * spmv[k]["launches"])
     d = spmv[dom]
-    workload = f"large_powerlaw_lp_n{n}"
+    workload = f"large_powerlaw_lp_n{n}" + ("" if args.precision == "fp64" else "_mixed")
     roofline = {"kernel": dom, "bound": "hbm", "achieved": d["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": d["GB_s"] / HBM_PEAK_GBS if d["GB_s"] else None,
                 "traffic": counter_traffic(dom, workload), "alg_bytes_per_launch": d["alg_bytes"]}
