@@ -94,6 +94,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-1e-4 solve")
     ap.add_argument("--ttt-limit", type=float, default=90.0)
+    ap.add_argument("--workload", choices=["large", "batch"], default="large",
+                    help="large: one 2e6x1e6 LP (default); batch: 512 uneven LPs solved together")
+    ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--seq-sample", type=int, default=32,
+                    help="batch workload: instances solved one by one for the sequential comparison")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run 5 plain device-to-device copies of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -116,6 +121,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": nbytes, "copies": 5}))
         return
+    if args.workload == "batch":
+        return bench_batch(args)
     n = args.n
     m1 = m2 = n // 4
     t0 = time.perf_counter()
@@ -201,6 +208,87 @@ def main():
         "spmv": spmv,
         "time_to_tol": ttt,
         "cpu_baseline": cpu,
+        "load_s": load_s,
+        "gen_s": gen_s,
+    }
+    print(json.dumps(out))
+
+
+def bench_batch(args):
+    """Time to rel KKT 1e-4 of a batch of uneven LPs solved together, against
+    solving the same instances one after another on the same GPU.
+
+    Workload: `args.batch_count` members of the batched generator (seeds
+    1000..), n log-uniform in [2e3, 2e5], m = n/2 split 2:3, 3..8 nonzeros per
+    column; FP32 iterates with FP64 reductions (or FP64 with --precision
+    fp64).  The sequential leg solves every (count/seq_sample)-th instance
+    with the single-LP path (load excluded) and scales the sum up.
+    """
+    import numpy as np
+    import torch
+    from paper_2312_14832_amd import gen, lp
+
+    t0 = time.perf_counter()
+    lps = [gen.batch_member(1000 + i) for i in range(args.batch_count)]
+    gen_s = time.perf_counter() - t0
+    nnz = sum(p.nnz for p in lps)
+    print(f"[bench] generated {len(lps)} LPs, sum n={sum(p.n for p in lps)}, sum nnz={nnz} in {gen_s:.1f}s",
+          file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    bt = lp.Batch(lps, precision=args.precision, stream=torch.cuda.current_stream())
+    load_s = time.perf_counter() - t0
+    print(f"[bench] batch loaded in {load_s:.1f}s ({bt.device_bytes() / 2**30:.2f} GiB)", file=sys.stderr, flush=True)
+    # warm-up: a short solve (graph capture, caches)
+    bt.solve(1e-30, 64 * max(args.warmup, 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt.solve(1e-4, 10**6, args.ttt_limit)
+    torch.cuda.synchronize()
+    batch_s = time.perf_counter() - t0
+    infos = [bt.info(i) for i in range(len(lps))]
+    solved = sum(1 for d in infos if d["status"] == "OPTIMAL")
+    iters = np.array([d["iterations"] for d in infos])
+    print(f"[bench] batch: {solved}/{len(lps)} optimal in {batch_s:.2f}s; iterations median {np.median(iters):.0f} "
+          f"max {iters.max()}", file=sys.stderr, flush=True)
+    bt.close()
+    stride = max(1, len(lps) // max(args.seq_sample, 1))
+    sample = list(range(0, len(lps), stride))
+    seq_s = 0.0
+    seq_iters = []
+    for i in sample:
+        p = lp.Problem(lps[i], precision=args.precision, stream=torch.cuda.current_stream())
+        p.solve(1e-30, 64)   # same warm-up as the batch
+        t1 = time.perf_counter()
+        d = p.solve(1e-4, 10**6, args.ttt_limit)
+        torch.cuda.synchronize()
+        seq_s += time.perf_counter() - t1
+        seq_iters.append(d["iterations"])
+        p.close()
+    seq_est = seq_s * len(lps) / len(sample)
+    print(f"[bench] sequential: {len(sample)} instances in {seq_s:.2f}s -> {seq_est:.1f}s for all "
+          f"(speedup {seq_est / batch_s:.1f}x)", file=sys.stderr, flush=True)
+    out = {
+        "metric": "batch time-to-1e-4 KKT",
+        "value": len(lps) / batch_s,
+        "unit": "LPs/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * batch_s,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64acc",
+        "data": "synthetic",
+        "config": {"workload": f"batch_{len(lps)}_uneven_lps", "count": len(lps), "sum_nnz": nnz,
+                   "seeds": [1000, 1000 + len(lps) - 1], "precision": args.precision, "tol": 1e-4},
+        "batch_seconds": batch_s,
+        "solved": solved,
+        "iterations_median": float(np.median(iters)),
+        "iterations_max": int(iters.max()),
+        "sequential": {"sample": len(sample), "stride": stride, "seconds_sample": seq_s,
+                       "seconds_extrapolated": seq_est, "speedup": seq_est / batch_s,
+                       "iterations_median": float(np.median(seq_iters))},
         "load_s": load_s,
         "gen_s": gen_s,
     }

@@ -160,6 +160,33 @@ int lp_device_bytes(const lp_problem *P, int64_t *bytes);
 int lp_layout(const lp_problem *P, int *slices_K, int *slices_KT);
 
 void lp_free(lp_problem *P);
+
+/* ------------------------------------------------------------------------
+ * Batched solves: many independent LPs of the form above advanced together
+ * by one set of kernels per iteration (one captured hipGraph window), each
+ * with its own step size, primal weight, restarts and termination.  The
+ * method per instance is exactly the one lp_solve runs.
+ * ------------------------------------------------------------------------ */
+typedef struct lp_batch lp_batch;   /* opaque; owned by the library */
+
+/* count instances: K[i], c[i], q[i], l[i], u[i], m1[i] as in lp_load (host
+ * pointers, copied).  Options apply to every instance.  Same error codes as
+ * lp_load (the first failing instance decides). */
+int lp_batch_load(lp_batch **B, int32_t count, const lp_csr *K, const double *const *c, const double *const *q,
+                  const double *const *l, const double *const *u, const int64_t *m1, const lp_options *opt);
+/* Solve every instance (cold start, or resume when lp_batch_set_state was
+ * called for every instance since the last solve) until each is optimal at
+ * tol, reaches max_iters accepted steps, or the time limit ends the call. */
+int lp_batch_solve(lp_batch *B, double tol, int64_t max_iters, double time_limit_s);
+/* Result of instance i as lp_result; info->seconds is the time into the last
+ * lp_batch_solve at which the host saw instance i finish. */
+int lp_batch_result(const lp_batch *B, int32_t i, double *x, double *y, double *lambda, lp_info *info);
+/* State of instance i in the layout of lp_get_state. */
+int lp_batch_get_state(const lp_batch *B, int32_t i, double *buf, int64_t *len);
+int lp_batch_set_state(lp_batch *B, int32_t i, const double *buf, int64_t len);
+int lp_batch_device_bytes(const lp_batch *B, int64_t *bytes);
+void lp_batch_free(lp_batch *B);
+const char *lp_batch_last_error(const lp_batch *B);
 const char *lp_strerror(int code);
 /* Message of the last LP_ERR_HIP on this handle ("" when none). */
 const char *lp_last_error(const lp_problem *P);

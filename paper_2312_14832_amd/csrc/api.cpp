@@ -17,6 +17,7 @@
 #include <string>
 #include <vector>
 
+#include "host_util.h"
 #include "internal.h"
 
 using namespace pdlp;
@@ -74,15 +75,10 @@ void build_sliced(HostSliced &H, int rows, int cols, const std::vector<int> &rp,
             cur[i] = p;
         }
         r[rows] = (int)pos;
-        int start = 0, nb = 0;
         H.brow.push_back(0);
-        while (start < rows) {
-            int end = start + 1;
-            while (end < rows && end - start < kStreamRB && r[end + 1] - r[start] <= kStreamNB) ++end;
-            H.brow.push_back(end);
-            ++nb;
-            start = end;
-        }
+        const size_t before = H.brow.size();
+        row_blocks(r, 0, rows, H.brow);
+        const int nb = (int)(H.brow.size() - before);
         H.boff[s + 1] = H.boff[s] + nb;
         H.max_blocks = std::max(H.max_blocks, nb);
     }
@@ -98,17 +94,6 @@ int partial_grid(int S, int max_blocks)
     const int cap = std::max(4096 / unit, 1) * unit;
     return (int)std::min<int64_t>(g, cap);
 }
-
-struct HipError {
-    hipError_t e;
-    const char *what;
-};
-
-#define HIPT(expr)                                                       \
-    do {                                                                 \
-        hipError_t _e = (expr);                                          \
-        if (_e != hipSuccess) throw HipError{_e, #expr};                 \
-    } while (0)
 
 }  // namespace
 
@@ -201,35 +186,6 @@ void download(lp_problem *P, T *dst, const T *src, int64_t count)
 
 void sync(lp_problem *P) { HIPT(hipStreamSynchronize(P->stream)); }
 
-int validate(const lp_csr *K, const double *c, const double *q, const double *l, const double *u, int64_t m1)
-{
-    if (!K) return LP_ERR_ARG;
-    const int64_t m = K->m, n = K->n, nnz = K->nnz;
-    if (m < 0 || n < 0 || nnz < 0 || m1 < 0 || m1 > m) return LP_ERR_DIM;
-    if (m >= (int64_t(1) << 31) || n >= (int64_t(1) << 31) || nnz >= (int64_t(1) << 31)) return LP_ERR_TOO_LARGE;
-    if (!K->row_ptr || (nnz > 0 && (!K->col || !K->val)) || (n > 0 && (!c || !l || !u)) || (m > 0 && !q))
-        return LP_ERR_ARG;
-    if (K->row_ptr[0] != 0 || K->row_ptr[m] != nnz) return LP_ERR_DIM;
-    for (int64_t i = 0; i < m; ++i)
-        if (K->row_ptr[i + 1] < K->row_ptr[i]) return LP_ERR_DIM;
-    std::vector<int64_t> seen((size_t)std::max<int64_t>(n, 1), -1);
-    for (int64_t i = 0; i < m; ++i)
-        for (int64_t p = K->row_ptr[i]; p < K->row_ptr[i + 1]; ++p) {
-            const int64_t j = K->col[p];
-            if (j < 0 || j >= n || seen[j] == i) return LP_ERR_DIM;
-            seen[j] = i;
-        }
-    for (int64_t p = 0; p < nnz; ++p)
-        if (!std::isfinite(K->val[p])) return LP_ERR_NAN;
-    for (int64_t j = 0; j < n; ++j) {
-        if (!std::isfinite(c[j]) || std::isnan(l[j]) || std::isnan(u[j])) return LP_ERR_NAN;
-        if (l[j] == INFINITY || u[j] == -INFINITY || l[j] > u[j]) return LP_ERR_BOUNDS;
-    }
-    for (int64_t i = 0; i < m; ++i)
-        if (!std::isfinite(q[i])) return LP_ERR_NAN;
-    return LP_OK;
-}
-
 // ---------------------------------------------------------------------------
 // load: transpose, slice, upload, scale
 // ---------------------------------------------------------------------------
@@ -304,9 +260,6 @@ void setup_typed(lp_problem *P, const HostSliced &HK, const HostSliced &HT, cons
 int do_load(lp_problem *P, const lp_csr *K, const double *c, const double *q, const double *l, const double *u)
 {
     const int64_t m = P->m, n = P->n, nnz = P->nnz;
-    const int32_t *rp0 = K->row_ptr, *ci0 = K->col;
-    const double *v0 = K->val;
-
     // vectors keep the caller's order (the permutation hooks stay identity)
     P->perm_r.resize((size_t)m);
     P->perm_c.resize((size_t)n);
@@ -315,38 +268,11 @@ int do_load(lp_problem *P, const lp_csr *K, const double *c, const double *q, co
     P->inv_r = P->perm_r;
     P->inv_c = P->perm_c;
 
-    // K with the columns of each row sorted
-    std::vector<int> rp((size_t)m + 1), ci((size_t)std::max<int64_t>(nnz, 1));
-    std::vector<double> kv((size_t)std::max<int64_t>(nnz, 1));
-    rp[0] = 0;
-    std::vector<std::pair<int, double>> rowbuf;
-    for (int64_t i = 0; i < m; ++i) {
-        const int b = rp0[i], e = rp0[i + 1];
-        rowbuf.clear();
-        for (int p = b; p < e; ++p) rowbuf.emplace_back(ci0[p], v0[p]);
-        std::sort(rowbuf.begin(), rowbuf.end(),
-                  [](const std::pair<int, double> &a, const std::pair<int, double> &b2) { return a.first < b2.first; });
-        const int base = rp[i];
-        for (size_t t = 0; t < rowbuf.size(); ++t) {
-            ci[base + t] = rowbuf[t].first;
-            kv[base + t] = rowbuf[t].second;
-        }
-        rp[i + 1] = base + (int)rowbuf.size();
-    }
-    // K' by counting sort over the rows of K: each row of K' comes out sorted
-    std::vector<int> tp((size_t)n + 1, 0), ti((size_t)std::max<int64_t>(nnz, 1));
-    std::vector<double> tv((size_t)std::max<int64_t>(nnz, 1));
-    for (int64_t p = 0; p < nnz; ++p) tp[ci[p] + 1]++;
-    for (int64_t j = 0; j < n; ++j) tp[j + 1] += tp[j];
-    {
-        std::vector<int> pos(tp.begin(), tp.end() - 1);
-        for (int64_t i = 0; i < m; ++i)
-            for (int p = rp[i]; p < rp[i + 1]; ++p) {
-                const int at = pos[ci[p]]++;
-                ti[at] = (int)i;
-                tv[at] = kv[p];
-            }
-    }
+    // K with the columns of each row sorted, and K' by a counting sort
+    std::vector<int> rp, ci, tp, ti;
+    std::vector<double> kv, tv;
+    append_sorted_rows(K, 0, rp, ci, kv);
+    transpose_csr((int)m, (int)n, rp, ci, kv, tp, ti, tv);
     // column slices sized so a slice of the gathered vector stays in one XCD's L2
     const int64_t tsz = P->mixed ? 4 : 8;
     const int64_t slice_bytes = (int64_t)P->opt.slice_kib * 1024;
@@ -382,25 +308,7 @@ int do_load(lp_problem *P, const lp_csr *K, const double *c, const double *q, co
     // column factors both come from the same current matrix
     const int M = (int)m, N = (int)n;
     hipStream_t st = P->stream;
-    HIPT(launch_fill(Dr, 1.0, M, st));
-    HIPT(launch_fill(Dc, 1.0, N, st));
-    const int rounds = P->opt.ruiz_iters + (P->opt.pc_alpha >= 0.0 ? 1 : 0);
-    for (int it = 0; it < rounds; ++it) {
-        const bool pc = it == P->opt.ruiz_iters;
-        if (!pc) {
-            HIPT(launch_row_absmax(d_rp, d_kv, M, r, st));
-            HIPT(launch_row_absmax(d_tp, d_tv, N, s, st));
-        } else {
-            HIPT(launch_row_abspow_sum(d_rp, d_kv, M, 2.0 - P->opt.pc_alpha, r, st));
-            HIPT(launch_row_abspow_sum(d_tp, d_tv, N, P->opt.pc_alpha, s, st));
-        }
-        HIPT(launch_finish_factor(r, M, st));
-        HIPT(launch_finish_factor(s, N, st));
-        HIPT(launch_rescale_rows(d_rp, d_ci, d_kv, M, r, s, st));
-        HIPT(launch_rescale_rows(d_tp, d_ti, d_tv, N, s, r, st));
-        HIPT(launch_mul_inplace(Dr, r, M, st));
-        HIPT(launch_mul_inplace(Dc, s, N, st));
-    }
+    HIPT(scale_csr_pair(d_rp, d_ci, d_kv, M, d_tp, d_ti, d_tv, N, Dr, Dc, r, s, P->opt.ruiz_iters, P->opt.pc_alpha, st));
     HIPT(launch_scale_vectors(d_c, d_l, d_u, d_q, Dc, Dr, cs, ls, us, qs, N, M, st));
     double h[5] = {0, 0, 0, 0, 0};
     HIPT(launch_sumsq(d_q, m, P->red_part, P->red_out + 0, st));
@@ -798,7 +706,7 @@ int lp_load(lp_problem **out, const lp_csr *K, const double *c, const double *q,
 {
     if (!out) return LP_ERR_ARG;
     *out = nullptr;
-    int rc = validate(K, c, q, l, u, m1);
+    int rc = validate_lp(K, c, q, l, u, m1);
     if (rc != LP_OK) return rc;
     lp_options o;
     if (opt) o = *opt;

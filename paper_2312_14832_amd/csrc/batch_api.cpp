@@ -1,0 +1,668 @@
+// Host side of the batched solver (lp_batch_* in include/lp.h).
+//
+// lp_batch_load concatenates the instances block-diagonally (each one's
+// vectors padded to whole 256-element chunks), scales the whole
+// block-diagonal matrix at once (row and column scaling never mixes blocks,
+// so every instance gets exactly its own scaling), cuts the rows of K and K'
+// into CSR-Stream row blocks that never straddle instances, and deals the
+// instances to the 8 XCDs by a longest-processing-time rule on their
+// nonzeros.  lp_batch_solve replays a captured window of attempt slots until
+// every instance is done.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "host_util.h"
+#include "internal.h"
+
+using namespace pdlp;
+
+namespace {
+constexpr int kNScalars = 16;
+
+int64_t pad256(int64_t v) { return (v + kBlock - 1) / kBlock * kBlock; }
+}  // namespace
+
+struct lp_batch {
+    int B = 0;
+    lp_options opt{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool mixed = false;
+    std::vector<int64_t> n, m, m1, noff, moff;
+    int64_t Ntot = 0, Mtot = 0;
+    std::vector<double> Nq, Nc, omega0, eta0;
+    Arena arena;
+    BDev<double> b64{};
+    BDev<float> b32{};
+    Ctl *hctl = nullptr;   // pinned mirror, B entries
+    double *stage_n0 = nullptr, *stage_n1 = nullptr, *stage_m = nullptr;
+    hipGraphExec_t graph = nullptr;
+    int graph_window = 0;
+    bool has_result = false;
+    std::vector<char> state_set;
+    std::vector<double> finish_s;   // per instance: seconds into the last solve when it finished
+    double seconds = 0;
+    std::string err;
+
+    template <typename T> BDev<T> &dev();
+    ~lp_batch()
+    {
+        if (graph) (void)hipGraphExecDestroy(graph);
+        if (hctl) (void)hipHostFree(hctl);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+};
+
+template <> BDev<double> &lp_batch::dev<double>() { return b64; }
+template <> BDev<float> &lp_batch::dev<float>() { return b32; }
+
+namespace {
+
+void bsync(lp_batch *P) { HIPT(hipStreamSynchronize(P->stream)); }
+
+int fail(lp_batch *P, const HipError &h)
+{
+    char buf[512];
+    snprintf(buf, sizeof(buf), "%s failed: %s", h.what, hipGetErrorString(h.e));
+    if (P) P->err = buf;
+    return h.e == hipErrorOutOfMemory ? LP_ERR_NOMEM : LP_ERR_HIP;
+}
+
+// row blocks of every instance's padded row range, dealt to XCDs
+BlockList make_blocks(lp_batch *P, const std::vector<int> &rp, const std::vector<int64_t> &off,
+                      const std::vector<int64_t> &len_pad, const std::vector<int> &xcd_of)
+{
+    const int B = P->B;
+    std::vector<int> r0, r1, inst;
+    for (int i = 0; i < B; ++i) {
+        std::vector<int> ends;
+        row_blocks(rp.data(), (int)off[i], (int)(off[i] + len_pad[i]), ends);
+        int start = (int)off[i];
+        for (int e : ends) {
+            r0.push_back(start);
+            r1.push_back(e);
+            inst.push_back(i);
+            start = e;
+        }
+    }
+    BlockList L{};
+    L.nblk = (int)r0.size();
+    std::vector<int> order;
+    int maxper = 1;
+    for (int x = 0; x < kXcds; ++x) {
+        L.xoff[x] = (int)order.size();
+        for (int k = 0; k < L.nblk; ++k)
+            if (xcd_of[inst[k]] == x) order.push_back(k);
+        maxper = std::max(maxper, (int)order.size() - L.xoff[x]);
+    }
+    L.xoff[kXcds] = (int)order.size();
+    L.grid = kXcds * std::min(maxper, 512);
+    int *d_r0 = P->arena.make<int>(L.nblk), *d_r1 = P->arena.make<int>(L.nblk);
+    int *d_inst = P->arena.make<int>(L.nblk), *d_order = P->arena.make<int>(L.nblk);
+    h2d(P->stream, d_r0, r0.data(), L.nblk);
+    h2d(P->stream, d_r1, r1.data(), L.nblk);
+    h2d(P->stream, d_inst, inst.data(), L.nblk);
+    h2d(P->stream, d_order, order.data(), L.nblk);
+    bsync(P);
+    L.r0 = d_r0; L.r1 = d_r1; L.inst = d_inst; L.order = d_order;
+    return L;
+}
+
+int do_batch_load(lp_batch *P, const lp_csr *K, const double *const *c, const double *const *q,
+                  const double *const *l, const double *const *u)
+{
+    const int B = P->B;
+    hipStream_t st = P->stream;
+    // offsets of the padded concatenation
+    P->noff.assign(B + 1, 0);
+    P->moff.assign(B + 1, 0);
+    std::vector<int64_t> npad(B), mpad(B);
+    for (int i = 0; i < B; ++i) {
+        npad[i] = pad256(P->n[i]);
+        mpad[i] = pad256(P->m[i]);
+        P->noff[i + 1] = P->noff[i] + npad[i];
+        P->moff[i + 1] = P->moff[i] + mpad[i];
+    }
+    P->Ntot = P->noff[B];
+    P->Mtot = P->moff[B];
+    if (P->Ntot >= (int64_t(1) << 31) || P->Mtot >= (int64_t(1) << 31)) return LP_ERR_TOO_LARGE;
+    // block-diagonal K (padding rows empty) and its transpose
+    std::vector<int> rp, ci, tp, ti;
+    std::vector<double> kv, tv;
+    rp.push_back(0);
+    for (int i = 0; i < B; ++i) {
+        append_sorted_rows(&K[i], (int)P->noff[i], rp, ci, kv);
+        for (int64_t r = P->m[i]; r < mpad[i]; ++r) rp.push_back((int)ci.size());
+    }
+    if ((int64_t)ci.size() >= (int64_t(1) << 31)) return LP_ERR_TOO_LARGE;
+    const int64_t nnz = (int64_t)ci.size();
+    transpose_csr((int)P->Mtot, (int)P->Ntot, rp, ci, kv, tp, ti, tv);
+    // vectors; padding entries: zero data, bounds [0,0]
+    std::vector<double> hc(P->Ntot, 0.0), hl(P->Ntot, 0.0), hu(P->Ntot, 0.0), hq(P->Mtot, 0.0);
+    std::vector<int> m1g(B);
+    for (int i = 0; i < B; ++i) {
+        std::copy(c[i], c[i] + P->n[i], hc.begin() + P->noff[i]);
+        std::copy(l[i], l[i] + P->n[i], hl.begin() + P->noff[i]);
+        std::copy(u[i], u[i] + P->n[i], hu.begin() + P->noff[i]);
+        std::copy(q[i], q[i] + P->m[i], hq.begin() + P->moff[i]);
+        m1g[i] = (int)(P->moff[i] + P->m1[i]);
+    }
+    const int N = (int)P->Ntot, M = (int)P->Mtot;
+    Arena &A = P->arena;
+    int *d_rp = A.make<int>(M + 1), *d_ci = A.make<int>(nnz), *d_tp = A.make<int>(N + 1), *d_ti = A.make<int>(nnz);
+    double *d_kv = A.make<double>(nnz), *d_tv = A.make<double>(nnz);
+    double *d_c = A.make<double>(N), *d_l = A.make<double>(N), *d_u = A.make<double>(N), *d_q = A.make<double>(M);
+    double *Dr = A.make<double>(M), *Dc = A.make<double>(N), *r = A.make<double>(M), *s = A.make<double>(N);
+    double *cs = A.make<double>(N), *ls = A.make<double>(N), *us = A.make<double>(N), *qs = A.make<double>(M);
+    P->stage_n0 = A.make<double>(N);
+    P->stage_n1 = A.make<double>(N);
+    P->stage_m = A.make<double>(M);
+    h2d(st, d_rp, rp.data(), M + 1);
+    h2d(st, d_ci, ci.data(), nnz);
+    h2d(st, d_kv, kv.data(), nnz);
+    h2d(st, d_tp, tp.data(), N + 1);
+    h2d(st, d_ti, ti.data(), nnz);
+    h2d(st, d_tv, tv.data(), nnz);
+    h2d(st, d_c, hc.data(), N);
+    h2d(st, d_l, hl.data(), N);
+    h2d(st, d_u, hu.data(), N);
+    h2d(st, d_q, hq.data(), M);
+    HIPT(scale_csr_pair(d_rp, d_ci, d_kv, M, d_tp, d_ti, d_tv, N, Dr, Dc, r, s, P->opt.ruiz_iters, P->opt.pc_alpha, st));
+    HIPT(launch_scale_vectors(d_c, d_l, d_u, d_q, Dc, Dr, cs, ls, us, qs, N, M, st));
+    // per-instance norms: |q|, |c| (unscaled), |q~|, |c~|, max |K~|
+    std::vector<int64_t> on(B + 1), om(B + 1), oz(B + 1);
+    for (int i = 0; i <= B; ++i) {
+        on[i] = P->noff[i];
+        om[i] = P->moff[i];
+        oz[i] = rp[P->moff[i]];
+    }
+    int64_t *d_on = A.make<int64_t>(B + 1), *d_om = A.make<int64_t>(B + 1), *d_oz = A.make<int64_t>(B + 1);
+    double *d_norms = A.make<double>(5 * (int64_t)B);
+    h2d(st, d_on, on.data(), B + 1);
+    h2d(st, d_om, om.data(), B + 1);
+    h2d(st, d_oz, oz.data(), B + 1);
+    HIPT(launch_seg_sumsq(d_q, d_om, B, d_norms + 0 * B, st));
+    HIPT(launch_seg_sumsq(d_c, d_on, B, d_norms + 1 * B, st));
+    HIPT(launch_seg_sumsq(qs, d_om, B, d_norms + 2 * B, st));
+    HIPT(launch_seg_sumsq(cs, d_on, B, d_norms + 3 * B, st));
+    HIPT(launch_seg_absmax(d_kv, d_oz, B, d_norms + 4 * B, st));
+    std::vector<double> h(5 * (size_t)B);
+    d2h(st, h.data(), d_norms, 5 * (int64_t)B);
+    bsync(P);
+    P->Nq.resize(B); P->Nc.resize(B); P->omega0.resize(B); P->eta0.resize(B);
+    for (int i = 0; i < B; ++i) {
+        P->Nq[i] = std::sqrt(h[i]);
+        P->Nc[i] = std::sqrt(h[B + i]);
+        const double nq = std::sqrt(h[2 * B + i]), nc = std::sqrt(h[3 * B + i]);
+        P->omega0[i] = (nc > 1e-10 && nq > 1e-10) ? nc / nq : 1.0;
+        P->eta0[i] = h[4 * B + i] > 0.0 ? 1.0 / h[4 * B + i] : 1.0;
+        if (P->opt.fixed_step) P->eta0[i] = P->opt.fixed_eta;
+    }
+    // instances to XCDs: longest processing time first on nonzeros
+    std::vector<int> idx(B), xcd_of(B, 0);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::vector<int64_t> work(B);
+    for (int i = 0; i < B; ++i) work[i] = rp[P->moff[i + 1]] - rp[P->moff[i]] + npad[i] + mpad[i];
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return work[a] > work[b]; });
+    int64_t load[kXcds] = {0};
+    for (int i : idx) {
+        int best = 0;
+        for (int x = 1; x < kXcds; ++x)
+            if (load[x] < load[best]) best = x;
+        xcd_of[i] = best;
+        load[best] += work[i];
+    }
+    // chunk tables
+    std::vector<int> cin((size_t)(N / kBlock)), cim((size_t)(M / kBlock)), nc0(B), ncc(B), mc0(B), mcc(B);
+    for (int i = 0; i < B; ++i) {
+        nc0[i] = (int)(P->noff[i] / kBlock);
+        ncc[i] = (int)(npad[i] / kBlock);
+        mc0[i] = (int)(P->moff[i] / kBlock);
+        mcc[i] = (int)(mpad[i] / kBlock);
+        for (int k = 0; k < ncc[i]; ++k) cin[nc0[i] + k] = i;
+        for (int k = 0; k < mcc[i]; ++k) cim[mc0[i] + k] = i;
+    }
+
+    auto setup = [&](auto tag) {
+        using T = decltype(tag);
+        BDev<T> &b = P->dev<T>();
+        Dev<T> &d = b.d;
+        d.n = N;
+        d.m = M;
+        d.m1 = 0;
+        d.Dr = Dr;
+        d.Dc = Dc;
+        b.B = B;
+        b.ncn = N / kBlock;
+        b.ncm = M / kBlock;
+        b.krp = d_rp; b.kci = d_ci; b.trp = d_tp; b.tci = d_ti;
+        if (std::is_same<T, double>::value) {
+            b.kv = (const T *)d_kv; b.tv = (const T *)d_tv;
+            d.cs = (const T *)cs; d.ls = (const T *)ls; d.us = (const T *)us; d.qs = (const T *)qs;
+        } else {
+            T *kvT = A.make<T>(nnz), *tvT = A.make<T>(nnz);
+            T *csT = A.make<T>(N), *lsT = A.make<T>(N), *usT = A.make<T>(N), *qsT = A.make<T>(M);
+            HIPT(launch_from_double<T>(d_kv, kvT, nnz, st));
+            HIPT(launch_from_double<T>(d_tv, tvT, nnz, st));
+            HIPT(launch_from_double<T>(cs, csT, N, st));
+            HIPT(launch_from_double<T>(ls, lsT, N, st));
+            HIPT(launch_from_double<T>(us, usT, N, st));
+            HIPT(launch_from_double<T>(qs, qsT, M, st));
+            b.kv = kvT; b.tv = tvT;
+            d.cs = csT; d.ls = lsT; d.us = usT; d.qs = qsT;
+        }
+        for (int k = 0; k < 2; ++k) {
+            d.xb[k] = A.make<T>(N); d.yb[k] = A.make<T>(M); d.Kxb[k] = A.make<T>(M); d.KTyb[k] = A.make<T>(N);
+        }
+        d.xa = A.make<T>(N); d.ya = A.make<T>(M); d.Kxa = A.make<T>(M); d.KTya = A.make<T>(N);
+        d.x0 = A.make<T>(N); d.y0 = A.make<T>(M);
+        d.xo = A.make<T>(N); d.yo = A.make<T>(M); d.KTyo = A.make<T>(N);
+        b.prodK = A.make<T>(M);
+        b.prodKT = A.make<T>(N);
+        d.part_primal = A.make<double>(b.ncn);
+        d.part_dual = A.make<double>(2 * (int64_t)b.ncm);
+        d.part_check = A.make<double>((int64_t)kCheckSums * (b.ncn + b.ncm));
+        b.ctl = A.make<Ctl>(B);
+        d.ctl = b.ctl;
+        int *d_cin = A.make<int>(b.ncn), *d_cim = A.make<int>(b.ncm);
+        int *d_nc0 = A.make<int>(B), *d_ncc = A.make<int>(B), *d_mc0 = A.make<int>(B), *d_mcc = A.make<int>(B);
+        int *d_m1g = A.make<int>(B);
+        double *d_Nq = A.make<double>(B), *d_Nc = A.make<double>(B);
+        h2d(st, d_cin, cin.data(), b.ncn);
+        h2d(st, d_cim, cim.data(), b.ncm);
+        h2d(st, d_nc0, nc0.data(), B);
+        h2d(st, d_ncc, ncc.data(), B);
+        h2d(st, d_mc0, mc0.data(), B);
+        h2d(st, d_mcc, mcc.data(), B);
+        h2d(st, d_m1g, m1g.data(), B);
+        h2d(st, d_Nq, P->Nq.data(), B);
+        h2d(st, d_Nc, P->Nc.data(), B);
+        b.cinst_n = d_cin; b.cinst_m = d_cim;
+        b.nc0 = d_nc0; b.ncc = d_ncc; b.mc0 = d_mc0; b.mcc = d_mcc;
+        b.m1g = d_m1g; b.Nq = d_Nq; b.Nc = d_Nc;
+        b.LK = make_blocks(P, rp, P->moff, mpad, xcd_of);
+        b.LT = make_blocks(P, tp, P->noff, npad, xcd_of);
+        bsync(P);
+    };
+    if (P->mixed) setup(float{});
+    else setup(double{});
+    // controller blocks start zeroed (buffer 0 current)
+    HIPT(hipMemcpyAsync(P->mixed ? P->b32.ctl : P->b64.ctl, P->hctl, sizeof(Ctl) * (size_t)B, hipMemcpyHostToDevice,
+                        st));
+    bsync(P);
+    for (void *pp : {(void *)r, (void *)s, (void *)d_c, (void *)d_l, (void *)d_u, (void *)d_q}) A.release(pp);
+    if (P->mixed)
+        for (void *pp : {(void *)d_kv, (void *)d_tv, (void *)cs, (void *)ls, (void *)us, (void *)qs}) A.release(pp);
+    return LP_OK;
+}
+
+template <typename T>
+void batch_slot(lp_batch *P)
+{
+    BDev<T> &b = P->dev<T>();
+    hipStream_t st = P->stream;
+    HIPT(launch_batch_product<T>(b, 0, st));
+    HIPT(launch_batch_dual<T>(b, st));
+    HIPT(launch_batch_step_decide<T>(b, st));
+    HIPT(launch_batch_product<T>(b, 1, st));
+    HIPT(launch_batch_update<T>(b, st));
+    HIPT(launch_batch_check<T>(b, st));
+}
+
+void put_ctls(lp_batch *P, Ctl *d)
+{
+    HIPT(hipMemcpyAsync(d, P->hctl, sizeof(Ctl) * (size_t)P->B, hipMemcpyHostToDevice, P->stream));
+    bsync(P);
+}
+
+void get_ctls(lp_batch *P, const Ctl *d)
+{
+    HIPT(hipMemcpyAsync(P->hctl, d, sizeof(Ctl) * (size_t)P->B, hipMemcpyDeviceToHost, P->stream));
+    bsync(P);
+}
+
+Ctl fresh_ctl(const lp_batch *P, int i, double tol, int64_t max_iters)
+{
+    Ctl c{};
+    c.eta = P->eta0[i];
+    c.omega = P->omega0[i];
+    c.KKT_prev = INFINITY;
+    c.tol = tol;
+    c.kkt_p = P->opt.kkt_omega_power;
+    c.fixed_eta = P->opt.fixed_eta;
+    c.max_iters = max_iters;
+    c.check_every = P->opt.check_every;
+    c.fixed_step = P->opt.fixed_step;
+    c.final_status = LP_ITERATION_LIMIT;
+    return c;
+}
+
+template <typename T>
+int do_batch_solve(lp_batch *P, double tol, int64_t max_iters, double time_limit)
+{
+    BDev<T> &b = P->dev<T>();
+    Dev<T> &d = b.d;
+    hipStream_t st = P->stream;
+    const int B = P->B;
+    const int64_t N = P->Ntot, M = P->Mtot;
+    auto t0 = std::chrono::steady_clock::now();
+    auto elapsed = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
+    const bool resume = std::all_of(P->state_set.begin(), P->state_set.end(), [](char v) { return v != 0; }) && B > 0;
+    if (!resume) {
+        HIPT(launch_batch_start<T>(b, st));
+        for (int i = 0; i < B; ++i) {
+            P->hctl[i] = fresh_ctl(P, i, tol, max_iters);
+            P->hctl[i].mode = MODE_INIT;
+        }
+        put_ctls(P, b.ctl);
+        HIPT(launch_batch_product_plain<T>(b, 0, d.xb[0], d.Kxb[0], st));
+        HIPT(launch_batch_product_plain<T>(b, 1, d.yb[0], d.KTyb[0], st));
+        d2d(st, d.xa, (const T *)d.xb[0], N);
+        d2d(st, d.x0, (const T *)d.xb[0], N);
+        d2d(st, d.KTya, (const T *)d.KTyb[0], N);
+        d2d(st, d.ya, (const T *)d.yb[0], M);
+        d2d(st, d.y0, (const T *)d.yb[0], M);
+        d2d(st, d.Kxa, (const T *)d.Kxb[0], M);
+        HIPT(launch_batch_check<T>(b, st));
+    } else {
+        for (int i = 0; i < B; ++i) {
+            Ctl &c = P->hctl[i];
+            c.mode = MODE_RESUME;
+            c.done = 0;
+            c.status = LP_NOT_SOLVED;
+            c.numerical = 0;
+            c.restart_to = 0;
+            c.copy_out = 0;
+            c.need_primal = 1;
+            c.tol = tol;
+            c.max_iters = max_iters;
+            c.kkt_p = P->opt.kkt_omega_power;
+            c.check_every = P->opt.check_every;
+            c.fixed_step = P->opt.fixed_step;
+            c.fixed_eta = P->opt.fixed_eta;
+        }
+        put_ctls(P, b.ctl);
+        // resume only needs the first primal trial: the apply step alone
+        HIPT(launch_batch_apply<T>(b, st));
+    }
+    std::fill(P->state_set.begin(), P->state_set.end(), 0);
+    get_ctls(P, b.ctl);
+    bool any_at_limit = false;
+    for (int i = 0; i < B; ++i)
+        if (!P->hctl[i].done && P->hctl[i].k >= max_iters) any_at_limit = true;
+    if (any_at_limit) {
+        HIPT(launch_batch_set_final(b.ctl, B, LP_ITERATION_LIMIT, st));
+        HIPT(launch_batch_check<T>(b, st));
+        get_ctls(P, b.ctl);
+    }
+    P->finish_s.assign(B, -1.0);
+    const int W = std::max(1, P->opt.window);
+    if (P->opt.use_graph && (!P->graph || P->graph_window != W)) {
+        if (P->graph) {
+            (void)hipGraphExecDestroy(P->graph);
+            P->graph = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        HIPT(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+        for (int s = 0; s < W; ++s) batch_slot<T>(P);
+        HIPT(hipStreamEndCapture(st, &g));
+        HIPT(hipGraphInstantiate(&P->graph, g, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(g);
+        P->graph_window = W;
+    }
+    auto note_finished = [&] {
+        int left = 0;
+        const double now = elapsed();
+        for (int i = 0; i < B; ++i) {
+            if (P->hctl[i].done && P->finish_s[i] < 0) P->finish_s[i] = now;
+            if (!P->hctl[i].done) ++left;
+        }
+        return left;
+    };
+    int left = note_finished();
+    while (left > 0) {
+        if (P->opt.use_graph) HIPT(hipGraphLaunch(P->graph, st));
+        else
+            for (int s = 0; s < W; ++s) batch_slot<T>(P);
+        get_ctls(P, b.ctl);
+        left = note_finished();
+        if (left > 0 && time_limit > 0.0 && elapsed() > time_limit) {
+            HIPT(launch_batch_set_final(b.ctl, B, LP_TIME_LIMIT, st));
+            HIPT(launch_batch_check<T>(b, st));
+            get_ctls(P, b.ctl);
+            left = note_finished();
+            break;
+        }
+    }
+    bsync(P);
+    P->seconds = elapsed();
+    P->has_result = true;
+    return LP_OK;
+}
+
+template <typename T>
+int do_batch_result(lp_batch *P, int i, double *x, double *y, double *lam, lp_info *info)
+{
+    BDev<T> &b = P->dev<T>();
+    if (x || y || lam) {
+        HIPT(launch_result<T>(b.d, P->stage_n0, P->stage_m, P->stage_n1, P->stream));
+        if (x) d2h(P->stream, x, (const double *)P->stage_n0 + P->noff[i], P->n[i]);
+        if (lam) d2h(P->stream, lam, (const double *)P->stage_n1 + P->noff[i], P->n[i]);
+        if (y) d2h(P->stream, y, (const double *)P->stage_m + P->moff[i], P->m[i]);
+        bsync(P);
+    }
+    if (info) {
+        Ctl c;
+        HIPT(hipMemcpyAsync(&c, b.ctl + i, sizeof(Ctl), hipMemcpyDeviceToHost, P->stream));
+        bsync(P);
+        info->status = c.status;
+        info->pobj = c.out_pobj;
+        info->dobj = c.out_dobj;
+        info->rel_primal = c.out_rel_p;
+        info->rel_dual = c.out_rel_d;
+        info->rel_gap = c.out_rel_g;
+        info->iterations = c.k;
+        info->attempts = c.attempts;
+        info->restarts = c.restarts;
+        info->omega = c.omega;
+        info->eta = c.eta;
+        info->seconds = P->finish_s.empty() ? 0.0 : P->finish_s[i];
+    }
+    return LP_OK;
+}
+
+template <typename T>
+void state_vecs(lp_batch *P, int cur, T *(&v)[10], bool (&is_n)[10])
+{
+    Dev<T> &d = P->dev<T>().d;
+    T *list[10] = {d.xb[cur], d.yb[cur], d.Kxb[cur], d.KTyb[cur], d.xa, d.ya, d.Kxa, d.KTya, d.x0, d.y0};
+    const bool nn[10] = {true, false, false, true, true, false, false, true, true, false};
+    for (int k = 0; k < 10; ++k) {
+        v[k] = list[k];
+        is_n[k] = nn[k];
+    }
+}
+
+template <typename T>
+int do_batch_get_state(lp_batch *P, int i, double *buf)
+{
+    BDev<T> &b = P->dev<T>();
+    Ctl c;
+    HIPT(hipMemcpyAsync(&c, b.ctl + i, sizeof(Ctl), hipMemcpyDeviceToHost, P->stream));
+    bsync(P);
+    std::fill(buf, buf + kNScalars, 0.0);
+    buf[0] = c.eta; buf[1] = c.omega; buf[2] = c.W; buf[3] = c.KKT0; buf[4] = c.KKT_prev;
+    buf[5] = (double)c.k; buf[6] = (double)c.t; buf[7] = (double)c.attempts; buf[8] = (double)c.restarts;
+    buf[9] = c.status; buf[10] = c.eta_last;
+    T *v[10];
+    bool is_n[10];
+    state_vecs<T>(P, c.cur, v, is_n);
+    double *p = buf + kNScalars;
+    for (int k = 0; k < 10; ++k) {
+        const int64_t len = is_n[k] ? P->n[i] : P->m[i];
+        const int64_t off = is_n[k] ? P->noff[i] : P->moff[i];
+        double *stage = is_n[k] ? P->stage_n0 : P->stage_m;
+        HIPT(launch_to_double<T>(v[k] + off, stage, len, P->stream));
+        d2h(P->stream, p, (const double *)stage, len);
+        bsync(P);
+        p += len;
+    }
+    return LP_OK;
+}
+
+template <typename T>
+int do_batch_set_state(lp_batch *P, int i, const double *buf)
+{
+    BDev<T> &b = P->dev<T>();
+    Ctl c{};
+    HIPT(hipMemcpyAsync(&c, b.ctl + i, sizeof(Ctl), hipMemcpyDeviceToHost, P->stream));
+    bsync(P);
+    const int old_cur = c.cur;
+    c.eta = buf[0]; c.omega = buf[1]; c.W = buf[2]; c.KKT0 = buf[3]; c.KKT_prev = buf[4];
+    c.k = (long long)buf[5]; c.t = (long long)buf[6]; c.attempts = (long long)buf[7];
+    c.restarts = (long long)buf[8]; c.eta_last = buf[10];
+    // the state goes to the instance's current buffers
+    c.cur = old_cur;
+    T *v[10];
+    bool is_n[10];
+    state_vecs<T>(P, c.cur, v, is_n);
+    const double *p = buf + kNScalars;
+    for (int k = 0; k < 10; ++k) {
+        const int64_t len = is_n[k] ? P->n[i] : P->m[i];
+        const int64_t off = is_n[k] ? P->noff[i] : P->moff[i];
+        double *stage = is_n[k] ? P->stage_n0 : P->stage_m;
+        h2d(P->stream, stage, p, len);
+        HIPT(launch_from_double<T>(stage, v[k] + off, len, P->stream));
+        bsync(P);
+        p += len;
+    }
+    P->hctl[i] = c;
+    HIPT(hipMemcpyAsync(b.ctl + i, &P->hctl[i], sizeof(Ctl), hipMemcpyHostToDevice, P->stream));
+    bsync(P);
+    P->state_set[i] = 1;
+    return LP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lp_batch_load(lp_batch **out, int32_t count, const lp_csr *K, const double *const *c, const double *const *q,
+                  const double *const *l, const double *const *u, const int64_t *m1, const lp_options *opt)
+{
+    if (!out) return LP_ERR_ARG;
+    *out = nullptr;
+    if (count <= 0 || !K || !c || !q || !l || !u || !m1) return LP_ERR_ARG;
+    for (int i = 0; i < count; ++i) {
+        const int rc = validate_lp(&K[i], c[i], q[i], l[i], u[i], m1[i]);
+        if (rc != LP_OK) return rc;
+    }
+    lp_options o;
+    if (opt) o = *opt;
+    else lp_default_options(&o);
+    if ((o.precision != LP_FP64 && o.precision != LP_MIXED) || o.check_every <= 0 || o.ruiz_iters < 0 ||
+        (o.fixed_step && !(o.fixed_eta > 0.0)) || o.window <= 0)
+        return LP_ERR_ARG;
+    std::unique_ptr<lp_batch> P(new lp_batch());
+    P->B = count;
+    P->opt = o;
+    P->mixed = o.precision == LP_MIXED;
+    P->stream = (hipStream_t)o.stream;
+    for (int i = 0; i < count; ++i) {
+        P->n.push_back(K[i].n);
+        P->m.push_back(K[i].m);
+        P->m1.push_back(m1[i]);
+    }
+    P->state_set.assign(count, 0);
+    int rc;
+    try {
+        if (!P->stream) {
+            HIPT(hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking));
+            P->own_stream = true;
+        }
+        HIPT(hipHostMalloc((void **)&P->hctl, sizeof(Ctl) * (size_t)count, hipHostMallocDefault));
+        std::memset(P->hctl, 0, sizeof(Ctl) * (size_t)count);
+        rc = do_batch_load(P.get(), K, c, q, l, u);
+    } catch (const HipError &h) {
+        rc = fail(P.get(), h);
+    } catch (const std::bad_alloc &) {
+        rc = LP_ERR_NOMEM;
+    }
+    if (rc != LP_OK) return rc;
+    *out = P.release();
+    return LP_OK;
+}
+
+int lp_batch_solve(lp_batch *P, double tol, int64_t max_iters, double time_limit_s)
+{
+    if (!P || max_iters < 0 || std::isnan(tol)) return LP_ERR_ARG;
+    try {
+        return P->mixed ? do_batch_solve<float>(P, tol, max_iters, time_limit_s)
+                        : do_batch_solve<double>(P, tol, max_iters, time_limit_s);
+    } catch (const HipError &h) {
+        return fail(P, h);
+    }
+}
+
+int lp_batch_result(const lp_batch *Pc, int32_t i, double *x, double *y, double *lambda, lp_info *info)
+{
+    lp_batch *P = const_cast<lp_batch *>(Pc);
+    if (!P || i < 0 || i >= P->B) return LP_ERR_ARG;
+    if (!P->has_result) return LP_ERR_STATE;
+    try {
+        return P->mixed ? do_batch_result<float>(P, i, x, y, lambda, info)
+                        : do_batch_result<double>(P, i, x, y, lambda, info);
+    } catch (const HipError &h) {
+        return fail(P, h);
+    }
+}
+
+int lp_batch_get_state(const lp_batch *Pc, int32_t i, double *buf, int64_t *len)
+{
+    lp_batch *P = const_cast<lp_batch *>(Pc);
+    if (!P || !len || i < 0 || i >= P->B) return LP_ERR_ARG;
+    *len = kNScalars + 5 * P->n[i] + 5 * P->m[i];
+    if (!buf) return LP_OK;
+    try {
+        return P->mixed ? do_batch_get_state<float>(P, i, buf) : do_batch_get_state<double>(P, i, buf);
+    } catch (const HipError &h) {
+        return fail(P, h);
+    }
+}
+
+int lp_batch_set_state(lp_batch *P, int32_t i, const double *buf, int64_t len)
+{
+    if (!P || !buf || i < 0 || i >= P->B) return LP_ERR_ARG;
+    if (len != kNScalars + 5 * P->n[i] + 5 * P->m[i]) return LP_ERR_STATE;
+    try {
+        return P->mixed ? do_batch_set_state<float>(P, i, buf) : do_batch_set_state<double>(P, i, buf);
+    } catch (const HipError &h) {
+        return fail(P, h);
+    }
+}
+
+int lp_batch_device_bytes(const lp_batch *P, int64_t *bytes)
+{
+    if (!P || !bytes) return LP_ERR_ARG;
+    *bytes = P->arena.bytes;
+    return LP_OK;
+}
+
+void lp_batch_free(lp_batch *P)
+{
+    if (!P) return;
+    (void)hipStreamSynchronize(P->stream);
+    delete P;
+}
+
+const char *lp_batch_last_error(const lp_batch *P) { return P ? P->err.c_str() : ""; }
+
+}  // extern "C"

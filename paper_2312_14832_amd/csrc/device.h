@@ -1,0 +1,463 @@
+// Device-side building blocks shared by the single-LP and the batched
+// restarted-PDHG kernels: projections, deterministic reductions, the fused
+// dual/primal/averaging element updates, the KKT check sums, the step-size
+// and restart decisions, and the CSR-Stream row-block product.
+#pragma once
+
+#include "internal.h"
+
+#include <cmath>
+
+namespace pdlp {
+
+// ----------------------------------------------------------------------------
+// small device helpers
+// ----------------------------------------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ T clampv(T v, T lo, T hi)
+{
+    // projection onto [lo, hi]; NaN passes through
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+template <typename P>
+__device__ __forceinline__ P pick(P const (&a)[2], int i)
+{
+    return i ? a[1] : a[0];
+}
+
+__device__ __forceinline__ double proj_lambda(double g, bool lf, bool uf)
+{
+    if (!lf && !uf) return 0.0;
+    if (!lf) return g < 0.0 ? g : 0.0;
+    if (!uf) return g > 0.0 ? g : 0.0;
+    return g;
+}
+
+// One FP64 partial per workgroup and value: wave64 butterfly, then the four
+// wave results added in a fixed order.
+template <int NV>
+__device__ __forceinline__ void block_store_partials(double (&v)[NV], double *out)
+{
+    __shared__ double sh[kBlock / 64][NV];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double a = v[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+        v[i] = a;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) sh[wave][i] = v[i];
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        const int i = threadIdx.x;
+        out[(size_t)blockIdx.x * NV + i] = ((sh[0][i] + sh[1][i]) + sh[2][i]) + sh[3][i];
+    }
+}
+
+// Sum np partials of NV values each inside one workgroup; every thread gets
+// the same (deterministic) totals.
+template <int NV>
+__device__ __forceinline__ void block_sum_partials(const double *part, int np, double (&out)[NV])
+{
+    __shared__ double sh[kBlock / 64][NV];
+    double acc[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    for (int b = threadIdx.x; b < np; b += kBlock) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[i] += part[(size_t)b * NV + i];
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc[i] += __shfl_xor(acc[i], off);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) sh[wave][i] = acc[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) out[i] = ((sh[0][i] + sh[1][i]) + sh[2][i]) + sh[3][i];
+    __syncthreads();
+}
+
+// ----------------------------------------------------------------------------
+// column-sliced CSR-Stream partial products
+// ----------------------------------------------------------------------------
+
+// row i of the product: the slices' partials added in slice order
+template <typename T>
+__device__ __forceinline__ T sum_slices(const Sliced<T> &P, int i)
+{
+    T a = P.part[i];
+    for (int s = 1; s < P.S; ++s) a += P.part[(size_t)s * P.rows + i];
+    return a;
+}
+
+// ----------------------------------------------------------------------------
+// epilogues
+// ----------------------------------------------------------------------------
+
+// dual step on row i: y' = proj_Y(y + sigma (q - 2 Kx' + Kx)), y'_i >= 0 on G rows
+template <typename T>
+struct DualEpi {
+    const T *__restrict__ y;
+    const T *__restrict__ kx;
+    const T *__restrict__ q;
+    T *__restrict__ yn;
+    T *__restrict__ kxn;
+    int m1;
+    T sigma;
+    double dy2, inter;
+    __device__ __forceinline__ void operator()(int i, T s)
+    {
+        const T yo = y[i], ko = kx[i];
+        T val = yo + sigma * (q[i] - T(2) * s + ko);
+        if (i >= m1 && val < T(0)) val = T(0);
+        yn[i] = val;
+        kxn[i] = s;
+        const double d = (double)val - (double)yo;
+        dy2 += d * d;
+        inter += d * ((double)s - (double)ko);
+    }
+};
+
+// after an accepted step, on column j: K'y' stored, averages moved, and the
+// next primal trial x'' = proj_X(x' - tau (c - K'y'))
+template <typename T>
+struct UpdateEpi {
+    const T *__restrict__ x;
+    const T *__restrict__ cs;
+    const T *__restrict__ ls;
+    const T *__restrict__ us;
+    T *__restrict__ kty;
+    T *__restrict__ xa;
+    T *__restrict__ ktya;
+    T *__restrict__ xn;
+    T w, tau;
+    bool primal;
+    double dx2;
+    __device__ __forceinline__ void operator()(int j, T s)
+    {
+        kty[j] = s;
+        const T xj = x[j];
+        const T a = xa[j];
+        xa[j] = a + w * (xj - a);
+        const T b = ktya[j];
+        ktya[j] = b + w * (s - b);
+        if (primal) {
+            const T nv = clampv(xj - tau * (cs[j] - s), ls[j], us[j]);
+            xn[j] = nv;
+            const double d = (double)nv - (double)xj;
+            dx2 += d * d;
+        }
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ void primal_elem(const Dev<T> &d, int c, T tau, int j, double &dx2)
+{
+    const T *x = pick(d.xb, c);
+    const T *kty = pick(d.KTyb, c);
+    T *xn = pick(d.xb, c ^ 1);
+    const T xj = x[j];
+    const T nv = clampv(xj - tau * (d.cs[j] - kty[j]), d.ls[j], d.us[j]);
+    xn[j] = nv;
+    const double dd = (double)nv - (double)xj;
+    dx2 += dd * dd;
+}
+
+// the 9 check sums of one iterate; s[0..3] rows, s[4..8] columns:
+// |r_p|^2 unscaled, |r_p|^2 scaled, q'y, |y-y0|^2,
+// |r_d|^2 unscaled, |r_d|^2 scaled, c'x, l'lam+ - u'lam-, |x-x0|^2
+template <typename T>
+__device__ __forceinline__ void row_sums(const Dev<T> &d, int i, int m1, const T *y, const T *kx, double *s)
+{
+    const double k = (double)kx[i], q = (double)d.qs[i];
+    double r = k - q;
+    if (i >= m1) {
+        const double t = q - k;
+        r = t > 0.0 ? t : 0.0;
+    }
+    const double ru = r * d.Dr[i];
+    s[0] += ru * ru;
+    s[1] += r * r;
+    const double yi = (double)y[i];
+    s[2] += q * yi;
+    const double dd = yi - (double)d.y0[i];
+    s[3] += dd * dd;
+}
+
+template <typename T>
+__device__ __forceinline__ void col_sums(const Dev<T> &d, int j, const T *x, const T *kty, double *s)
+{
+    const double cj = (double)d.cs[j], lj = (double)d.ls[j], uj = (double)d.us[j];
+    const bool lf = isfinite(lj), uf = isfinite(uj);
+    const double g = cj - (double)kty[j];
+    const double lam = proj_lambda(g, lf, uf);
+    const double rd = g - lam;
+    const double rdu = rd * d.Dc[j];
+    s[4] += rdu * rdu;
+    s[5] += rd * rd;
+    const double xj = (double)x[j];
+    s[6] += cj * xj;
+    double b = 0.0;
+    if (lf && lam > 0.0) b += lj * lam;
+    if (uf && lam < 0.0) b += uj * lam;
+    s[7] += b;
+    const double dd = xj - (double)d.x0[j];
+    s[8] += dd * dd;
+}
+
+
+// Adaptive step-size test (PDLP's rule; the paper uses eta without stating
+// the rule): eta_bar = (omega|dx|^2 + |dy|^2/omega) / (2|dy.K dx|),
+// eta' = min((1-kk^-0.3) eta_bar, (1+kk^-0.6) eta) with kk counting from 2;
+// accept iff eta <= eta_bar.  Called by one thread per LP.
+__device__ inline void step_decision(Ctl *ctl, double dx2, double dy2, double inter)
+{
+    const double eta = ctl->eta, omega = ctl->omega;
+    double eta_new = eta;
+    bool accept = true;
+    ctl->attempts += 1;
+    if (!ctl->fixed_step) {
+        const double N = omega * dx2 + dy2 / omega;
+        const double D = 2.0 * fabs(inter);
+        if (isnan(N) || isnan(D)) {
+            ctl->numerical = 1;
+            ctl->accepted = 0;
+            ctl->mode = MODE_CHECK;
+            return;
+        }
+        const double eta_bar = D > 0.0 ? N / D : INFINITY;
+        const double kk = (double)(ctl->k + 1) + 1.0;
+        const double lo = (1.0 - pow(kk, -0.3)) * eta_bar;
+        const double hi = (1.0 + pow(kk, -0.6)) * eta;
+        eta_new = lo < hi ? lo : hi;
+        accept = eta <= eta_bar;
+    }
+    if (accept) {
+        ctl->W += eta;
+        ctl->avg_w = eta / ctl->W;
+        ctl->eta_last = eta;
+        ctl->k += 1;
+        ctl->t += 1;
+        ctl->cur ^= 1;
+        ctl->accepted = 1;
+        ctl->mode = (ctl->k % ctl->check_every == 0 || ctl->k >= ctl->max_iters) ? MODE_CHECK : MODE_NONE;
+    } else {
+        ctl->accepted = 0;
+        ctl->mode = MODE_NONE;
+    }
+    ctl->eta = eta_new;
+}
+
+// Termination (the three relative criteria on the unscaled problem),
+// candidate choice and restart conditions 1-3 on KKT_omega (scaled problem),
+// primal-weight update.  S holds the 9 check sums of the current iterate then
+// the 9 of the average.  Called by one thread per LP.
+__device__ inline void check_decision(Ctl *ctl, const double *S, double Nq, double Nc)
+{
+    const double wp = pow(ctl->omega, ctl->kkt_p);
+    double rel[2], kkt[2];
+    for (int z = 0; z < 2; ++z) {
+        const double *e = S + 9 * z;
+        const double pobj = e[6], dobj = e[2] + e[7], gap = dobj - pobj;
+        const double rp = sqrt(e[0]) / (1.0 + Nq);
+        const double rd = sqrt(e[4]) / (1.0 + Nc);
+        const double rg = fabs(gap) / (1.0 + fabs(dobj) + fabs(pobj));
+        double r = rp;
+        if (rd > r) r = rd;
+        if (rg > r) r = rg;
+        if (isnan(rp) || isnan(rd) || isnan(rg)) r = NAN;
+        rel[z] = r;
+        kkt[z] = sqrt(wp * e[1] + e[5] / wp + gap * gap);
+        ctl->rel_p[z] = rp;
+        ctl->rel_d[z] = rd;
+        ctl->rel_g[z] = rg;
+        ctl->pobj[z] = pobj;
+        ctl->dobj[z] = dobj;
+        ctl->kkt[z] = kkt[z];
+    }
+    const int mode = ctl->mode;
+    ctl->restart_to = 0;
+    ctl->copy_out = 0;
+    ctl->need_primal = 0;
+    if (mode == MODE_INIT) {
+        ctl->KKT0 = kkt[0];
+        ctl->KKT_prev = INFINITY;
+        ctl->need_primal = 1;
+        return;
+    }
+    auto finish = [&](int status, int sel) {
+        ctl->status = status;
+        ctl->out_sel = sel;
+        ctl->copy_out = 1;
+        ctl->done = 1;
+        ctl->out_rel_p = ctl->rel_p[sel];
+        ctl->out_rel_d = ctl->rel_d[sel];
+        ctl->out_rel_g = ctl->rel_g[sel];
+        ctl->out_pobj = ctl->pobj[sel];
+        ctl->out_dobj = ctl->dobj[sel];
+    };
+    if (ctl->numerical || isnan(rel[0]) || isnan(rel[1])) {
+        finish(LP_NUMERICAL, 0);
+        return;
+    }
+    const int use_avg = rel[1] < rel[0] ? 1 : 0;
+    if (rel[0] <= ctl->tol || rel[1] <= ctl->tol) {
+        finish(LP_OPTIMAL, use_avg);
+        return;
+    }
+    int at_limit = 0;
+    if (mode == MODE_FINAL) at_limit = ctl->final_status;
+    else if (ctl->k >= ctl->max_iters) at_limit = LP_ITERATION_LIMIT;
+    if (at_limit) finish(at_limit, use_avg);
+    if (mode == MODE_CHECK && ctl->k % ctl->check_every == 0) {
+        const int cand_cur = kkt[0] < kkt[1];
+        const double kz = cand_cur ? kkt[0] : kkt[1];
+        const double *ez = S + (cand_cur ? 0 : 9);
+        int why = 0;
+        if (kz <= 0.2 * ctl->KKT0) why = 1;
+        else if (kz <= 0.8 * ctl->KKT0 && kz > ctl->KKT_prev) why = 2;
+        else if ((double)ctl->t >= 0.36 * (double)ctl->k) why = 3;
+        ctl->KKT_prev = kz;
+        if (why) {
+            const double dx = sqrt(ez[8]), dy = sqrt(ez[3]);
+            double om = ctl->omega;
+            if (dx > 1e-10 && dy > 1e-10) om = exp(0.5 * log(dy / dx) + 0.5 * log(om));
+            ctl->omega = om;
+            const double wp2 = pow(om, ctl->kkt_p);
+            const double gz = (ez[2] + ez[7]) - ez[6];
+            ctl->KKT0 = sqrt(wp2 * ez[1] + ez[5] / wp2 + gz * gz);
+            ctl->KKT_prev = INFINITY;
+            ctl->W = 0.0;
+            ctl->t = 0;
+            ctl->restarts += 1;
+            ctl->restart_to = cand_cur ? 1 : 2;
+        }
+    }
+    ctl->need_primal = ctl->done ? 0 : 1;
+}
+
+// restart / output bookkeeping on column j (current buffer c):
+// rt = 2 restart to the average, 1 restart to the current point; co copies
+// the chosen point (sel: 0 current, 1 average) to the output buffers; np
+// computes the next primal trial with step tau
+template <typename T>
+__device__ __forceinline__ void apply_col(const Dev<T> &d, int j, int c, int rt, int co, int sel, int np, T tau,
+                                          double &dx2)
+{
+    T *x = pick(d.xb, c), *kty = pick(d.KTyb, c);
+    if (co) {
+        d.xo[j] = sel ? d.xa[j] : x[j];
+        d.KTyo[j] = sel ? d.KTya[j] : kty[j];
+    }
+    if (rt == 2) {
+        const T a = d.xa[j];
+        x[j] = a;
+        d.x0[j] = a;
+        kty[j] = d.KTya[j];
+    } else if (rt == 1) {
+        const T a = x[j];
+        d.xa[j] = a;
+        d.x0[j] = a;
+        d.KTya[j] = kty[j];
+    }
+    if (np) primal_elem(d, c, tau, j, dx2);
+}
+
+template <typename T>
+__device__ __forceinline__ void apply_row(const Dev<T> &d, int i, int c, int rt, int co, int sel)
+{
+    T *y = pick(d.yb, c), *kx = pick(d.Kxb, c);
+    if (co) d.yo[i] = sel ? d.ya[i] : y[i];
+    if (rt == 2) {
+        const T a = d.ya[i];
+        y[i] = a;
+        d.y0[i] = a;
+        kx[i] = d.Kxa[i];
+    } else if (rt == 1) {
+        const T a = y[i];
+        d.ya[i] = a;
+        d.y0[i] = a;
+        d.Kxa[i] = kx[i];
+    }
+}
+
+// averaging of row i after an accepted step (weight w)
+template <typename T>
+__device__ __forceinline__ void average_row(const Dev<T> &d, int i, int c, T w)
+{
+    const T *y = pick(d.yb, c), *kx = pick(d.Kxb, c);
+    const T a = d.ya[i];
+    d.ya[i] = a + w * (y[i] - a);
+    const T b = d.Kxa[i];
+    d.Kxa[i] = b + w * (kx[i] - b);
+}
+
+// CSR-Stream sums of one row block [r0, r1) of a CSR (global row pointers rp,
+// at most kStreamRB rows): products staged in LDS, one thread per row sums
+// them in index order.  A block of one row longer than kStreamNB is summed
+// by the whole workgroup.  Every thread of the workgroup must call it.
+template <typename T>
+__device__ __forceinline__ void stream_block(const int *__restrict__ rp, const int *__restrict__ ci,
+                                             const T *__restrict__ v, const T *__restrict__ x, int r0, int r1,
+                                             T *__restrict__ out, T *prod, double *red)
+{
+    const int b = rp[r0], e = rp[r1];
+    const int cnt = e - b;
+    if (cnt <= kStreamNB) {
+#pragma unroll 4
+        for (int t = (int)threadIdx.x; t < cnt; t += kBlock) {
+            const int col = __builtin_nontemporal_load(ci + b + t);
+            const T a = __builtin_nontemporal_load(v + b + t);
+            prod[t] = a * x[col];
+        }
+        __syncthreads();
+        const int r = r0 + (int)threadIdx.x;
+        if (r < r1) {
+            T acc = T(0);
+            const int je = rp[r + 1] - b;
+            for (int j = rp[r] - b; j < je; ++j) acc += prod[j];
+            out[r] = acc;
+        }
+        __syncthreads();
+    } else {
+        T acc = T(0);
+        for (int t = b + (int)threadIdx.x; t < e; t += kBlock) acc += v[t] * x[ci[t]];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = (double)acc;
+        __syncthreads();
+        if (threadIdx.x == 0) out[r0] = (T)(((red[0] + red[1]) + red[2]) + red[3]);
+        __syncthreads();
+    }
+}
+
+// One column slice's partial products (see Sliced): workgroup b takes slice
+// b % S and walks that slice's row blocks with stride gridDim / S.
+template <typename T>
+__device__ __forceinline__ void sliced_partial(const Sliced<T> &P, const T *__restrict__ x)
+{
+    __shared__ T prod[kStreamNB];
+    __shared__ double red[kBlock / 64];
+    const int S = P.S;
+    const int s = (int)blockIdx.x % S;
+    const int chunk0 = (int)blockIdx.x / S, stride = (int)gridDim.x / S;
+    const int *rp = P.rp + (size_t)s * (P.rows + 1);
+    T *out = P.part + (size_t)s * P.rows;
+    const int nblk = P.boff[s + 1] - P.boff[s];
+    const int *bro = P.brow + P.boff[s] + s;
+    for (int k = chunk0; k < nblk; k += stride) stream_block(rp, P.ci, P.v, x, bro[k], bro[k + 1], out, prod, red);
+}
+
+}  // namespace pdlp

@@ -1,0 +1,82 @@
+// Host-side helpers shared by the single-LP and the batched C ABI.
+#include "host_util.h"
+
+namespace pdlp {
+
+int validate_lp(const lp_csr *K, const double *c, const double *q, const double *l, const double *u, int64_t m1)
+{
+    if (!K) return LP_ERR_ARG;
+    const int64_t m = K->m, n = K->n, nnz = K->nnz;
+    if (m < 0 || n < 0 || nnz < 0 || m1 < 0 || m1 > m) return LP_ERR_DIM;
+    if (m >= (int64_t(1) << 31) || n >= (int64_t(1) << 31) || nnz >= (int64_t(1) << 31)) return LP_ERR_TOO_LARGE;
+    if (!K->row_ptr || (nnz > 0 && (!K->col || !K->val)) || (n > 0 && (!c || !l || !u)) || (m > 0 && !q))
+        return LP_ERR_ARG;
+    if (K->row_ptr[0] != 0 || K->row_ptr[m] != nnz) return LP_ERR_DIM;
+    for (int64_t i = 0; i < m; ++i)
+        if (K->row_ptr[i + 1] < K->row_ptr[i]) return LP_ERR_DIM;
+    std::vector<int64_t> seen((size_t)std::max<int64_t>(n, 1), -1);
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t p = K->row_ptr[i]; p < K->row_ptr[i + 1]; ++p) {
+            const int64_t j = K->col[p];
+            if (j < 0 || j >= n || seen[j] == i) return LP_ERR_DIM;
+            seen[j] = i;
+        }
+    for (int64_t p = 0; p < nnz; ++p)
+        if (!std::isfinite(K->val[p])) return LP_ERR_NAN;
+    for (int64_t j = 0; j < n; ++j) {
+        if (!std::isfinite(c[j]) || std::isnan(l[j]) || std::isnan(u[j])) return LP_ERR_NAN;
+        if (l[j] == INFINITY || u[j] == -INFINITY || l[j] > u[j]) return LP_ERR_BOUNDS;
+    }
+    for (int64_t i = 0; i < m; ++i)
+        if (!std::isfinite(q[i])) return LP_ERR_NAN;
+    return LP_OK;
+}
+
+void append_sorted_rows(const lp_csr *K, int col_off, std::vector<int> &rp, std::vector<int> &ci,
+                        std::vector<double> &v)
+{
+    if (rp.empty()) rp.push_back(0);
+    std::vector<std::pair<int, double>> row;
+    for (int64_t i = 0; i < K->m; ++i) {
+        row.clear();
+        for (int64_t p = K->row_ptr[i]; p < K->row_ptr[i + 1]; ++p) row.emplace_back(K->col[p], K->val[p]);
+        std::sort(row.begin(), row.end(),
+                  [](const std::pair<int, double> &a, const std::pair<int, double> &b) { return a.first < b.first; });
+        for (const auto &e : row) {
+            ci.push_back(e.first + col_off);
+            v.push_back(e.second);
+        }
+        rp.push_back((int)ci.size());
+    }
+}
+
+void transpose_csr(int rows, int cols, const std::vector<int> &rp, const std::vector<int> &ci,
+                   const std::vector<double> &v, std::vector<int> &tp, std::vector<int> &ti, std::vector<double> &tv)
+{
+    const int64_t nnz = rp[rows];
+    tp.assign((size_t)cols + 1, 0);
+    ti.assign((size_t)std::max<int64_t>(nnz, 1), 0);
+    tv.assign((size_t)std::max<int64_t>(nnz, 1), 0.0);
+    for (int64_t p = 0; p < nnz; ++p) tp[ci[p] + 1]++;
+    for (int j = 0; j < cols; ++j) tp[j + 1] += tp[j];
+    std::vector<int> pos(tp.begin(), tp.end() - 1);
+    for (int i = 0; i < rows; ++i)
+        for (int p = rp[i]; p < rp[i + 1]; ++p) {
+            const int at = pos[ci[p]]++;
+            ti[at] = i;
+            tv[at] = v[p];
+        }
+}
+
+void row_blocks(const int *rp, int r_begin, int r_end, std::vector<int> &ends)
+{
+    int start = r_begin;
+    while (start < r_end) {
+        int end = start + 1;
+        while (end < r_end && end - start < kStreamRB && rp[end + 1] - rp[start] <= kStreamNB) ++end;
+        ends.push_back(end);
+        start = end;
+    }
+}
+
+}  // namespace pdlp

@@ -1,0 +1,96 @@
+// Host-side helpers shared by the single-LP and the batched C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <utility>
+#include <vector>
+
+#include "internal.h"
+
+namespace pdlp {
+
+struct HipError {
+    hipError_t e;
+    const char *what;
+};
+
+#define HIPT(expr)                                                       \
+    do {                                                                 \
+        hipError_t _e = (expr);                                          \
+        if (_e != hipSuccess) throw pdlp::HipError{_e, #expr};           \
+    } while (0)
+
+// Device allocations owned by one handle, released together.
+struct Arena {
+    std::vector<void *> ptrs;
+    std::vector<int64_t> sizes;
+    int64_t bytes = 0;
+    void *alloc(size_t n)
+    {
+        void *p = nullptr;
+        if (n == 0) n = 8;
+        n = (n + 255) & ~(size_t)255;
+        HIPT(hipMalloc(&p, n));
+        ptrs.push_back(p);
+        sizes.push_back((int64_t)n);
+        bytes += (int64_t)n;
+        return p;
+    }
+    template <typename T> T *make(int64_t count) { return (T *)alloc(sizeof(T) * (size_t)std::max<int64_t>(count, 1)); }
+    void release(void *p)
+    {
+        for (size_t i = 0; i < ptrs.size(); ++i)
+            if (ptrs[i] == p) {
+                (void)hipFree(p);
+                ptrs[i] = nullptr;
+                bytes -= sizes[i];
+            }
+    }
+    ~Arena()
+    {
+        for (void *p : ptrs)
+            if (p) (void)hipFree(p);
+    }
+};
+
+template <typename T>
+inline void h2d(hipStream_t st, T *dst, const T *src, int64_t count)
+{
+    if (count > 0) HIPT(hipMemcpyAsync(dst, src, sizeof(T) * (size_t)count, hipMemcpyHostToDevice, st));
+}
+
+template <typename T>
+inline void d2h(hipStream_t st, T *dst, const T *src, int64_t count)
+{
+    if (count > 0) HIPT(hipMemcpyAsync(dst, src, sizeof(T) * (size_t)count, hipMemcpyDeviceToHost, st));
+}
+
+template <typename T>
+inline void d2d(hipStream_t st, T *dst, const T *src, int64_t count)
+{
+    if (count > 0) HIPT(hipMemcpyAsync(dst, src, sizeof(T) * (size_t)count, hipMemcpyDeviceToDevice, st));
+}
+
+// The input rules of lp_load (LP_ERR_* codes of lp.h).
+int validate_lp(const lp_csr *K, const double *c, const double *q, const double *l, const double *u, int64_t m1);
+
+// Append the rows of K (columns sorted inside each row, columns shifted by
+// col_off) to a CSR under construction.
+void append_sorted_rows(const lp_csr *K, int col_off, std::vector<int> &rp, std::vector<int> &ci,
+                        std::vector<double> &v);
+
+// CSR of the transpose by a counting sort over the rows (each output row
+// comes out sorted by the input row index).
+void transpose_csr(int rows, int cols, const std::vector<int> &rp, const std::vector<int> &ci,
+                   const std::vector<double> &v, std::vector<int> &tp, std::vector<int> &ti, std::vector<double> &tv);
+
+// CSR-Stream row blocks of rows [r_begin, r_end): at most kStreamRB rows and
+// kStreamNB nonzeros each (a longer single row is a block of its own).
+// Appends block end rows to `ends` (the first block starts at r_begin).
+void row_blocks(const int *rp, int r_begin, int r_end, std::vector<int> &ends);
+
+}  // namespace pdlp

@@ -95,6 +95,51 @@ struct Geo {
     int vb_n, vb_m;            // 256-element chunks of the n- and m-vectors
 };
 
+// Row blocks of one product of a batch, dealt to XCDs by instance: the
+// blocks of XCD x are order[xoff[x] .. xoff[x+1]); block k covers rows
+// [r0[k], r1[k]) of instance inst[k].
+struct BlockList {
+    int nblk;
+    const int *r0, *r1, *inst, *order;
+    int xoff[kXcds + 1];
+    int grid;                 // workgroups of the product kernel (a multiple of 8)
+};
+
+// A batch of LPs concatenated block-diagonally.  Every instance's n- and
+// m-vectors are padded to whole 256-element chunks, so each chunk (one
+// workgroup of the elementwise kernels) belongs to one instance; padding
+// entries are inert (bounds [0,0], zero data, unit scaling).
+template <typename T>
+struct BDev {
+    Dev<T> d;                 // concatenated vectors; d.n, d.m are the padded totals; d.K, d.KT unused
+    int B;                    // instances
+    int ncn, ncm;             // n-chunks and m-chunks in total
+    const int *krp, *kci;     // K:  CSR over all padded rows, global column indices
+    const T *kv;
+    const int *trp, *tci;     // K': CSR over all padded columns of K
+    const T *tv;
+    BlockList LK, LT;
+    T *prodK, *prodKT;        // the products K x' [m] and K' y' [n]
+    const int *cinst_n, *cinst_m;  // instance of each n-chunk / m-chunk
+    const int *nc0, *ncc, *mc0, *mcc;  // per instance: first chunk and chunk count, n and m side
+    const int *m1g;           // per instance: first inequality row (global index)
+    const double *Nq, *Nc;    // per instance: |q|, |c| of the unscaled data
+    Ctl *ctl;                 // [B]
+};
+
+template <typename T> hipError_t launch_batch_product(const BDev<T> &b, int which, hipStream_t s);
+template <typename T> hipError_t launch_batch_product_plain(const BDev<T> &b, int which, const T *in, T *out,
+                                                            hipStream_t s);
+template <typename T> hipError_t launch_batch_dual(const BDev<T> &b, hipStream_t s);
+template <typename T> hipError_t launch_batch_step_decide(const BDev<T> &b, hipStream_t s);
+template <typename T> hipError_t launch_batch_update(const BDev<T> &b, hipStream_t s);
+template <typename T> hipError_t launch_batch_check(const BDev<T> &b, hipStream_t s);
+template <typename T> hipError_t launch_batch_apply(const BDev<T> &b, hipStream_t s);
+template <typename T> hipError_t launch_batch_start(const BDev<T> &b, hipStream_t s);
+hipError_t launch_batch_set_final(Ctl *ctl, int B, int status, hipStream_t s);
+hipError_t launch_seg_sumsq(const double *a, const int64_t *off, int B, double *out, hipStream_t s);
+hipError_t launch_seg_absmax(const double *a, const int64_t *off, int B, double *out, hipStream_t s);
+
 // launchers (kernels.hip); each returns the hipError_t of the launch
 template <typename T> hipError_t launch_partial_K(const Dev<T> &d, hipStream_t s);
 template <typename T> hipError_t launch_partial_KT(const Dev<T> &d, hipStream_t s);
@@ -123,6 +168,9 @@ hipError_t launch_fill(double *a, double v, int len, hipStream_t s);
 hipError_t launch_scale_vectors(const double *c, const double *l, const double *u, const double *q,
                                 const double *Dc, const double *Dr, double *cs, double *ls, double *us,
                                 double *qs, int n, int m, hipStream_t s);
+hipError_t scale_csr_pair(const int *rp, const int *ci, double *kv, int m, const int *tp, const int *ti, double *tv,
+                          int n, double *Dr, double *Dc, double *r, double *s, int ruiz_iters, double alpha,
+                          hipStream_t st);
 // deterministic sum of squares / max |.| over a vector: partials then one workgroup
 hipError_t launch_sumsq(const double *a, int64_t len, double *part, double *out, hipStream_t s);
 hipError_t launch_absmax(const double *a, int64_t len, double *part, double *out, hipStream_t s);

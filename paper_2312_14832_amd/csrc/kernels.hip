@@ -25,224 +25,11 @@
 // Reductions are deterministic: each lane accumulates in FP64, wave64
 // butterflies and a fixed-order LDS step give one partial per workgroup, and
 // a single workgroup sums the partials in a fixed order.  No float atomics.
-#include "internal.h"
+#include "device.h"
 
 #include <cmath>
 
 namespace pdlp {
-
-// ----------------------------------------------------------------------------
-// small device helpers
-// ----------------------------------------------------------------------------
-
-template <typename T>
-__device__ __forceinline__ T clampv(T v, T lo, T hi)
-{
-    // projection onto [lo, hi]; NaN passes through
-    return v < lo ? lo : (v > hi ? hi : v);
-}
-
-template <typename P>
-__device__ __forceinline__ P pick(P const (&a)[2], int i)
-{
-    return i ? a[1] : a[0];
-}
-
-__device__ __forceinline__ double proj_lambda(double g, bool lf, bool uf)
-{
-    if (!lf && !uf) return 0.0;
-    if (!lf) return g < 0.0 ? g : 0.0;
-    if (!uf) return g > 0.0 ? g : 0.0;
-    return g;
-}
-
-// One FP64 partial per workgroup and value: wave64 butterfly, then the four
-// wave results added in a fixed order.
-template <int NV>
-__device__ __forceinline__ void block_store_partials(double (&v)[NV], double *out)
-{
-    __shared__ double sh[kBlock / 64][NV];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        double a = v[i];
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
-        v[i] = a;
-    }
-    if (lane == 0) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) sh[wave][i] = v[i];
-    }
-    __syncthreads();
-    if (threadIdx.x < NV) {
-        const int i = threadIdx.x;
-        out[(size_t)blockIdx.x * NV + i] = ((sh[0][i] + sh[1][i]) + sh[2][i]) + sh[3][i];
-    }
-}
-
-// Sum np partials of NV values each inside one workgroup; every thread gets
-// the same (deterministic) totals.
-template <int NV>
-__device__ __forceinline__ void block_sum_partials(const double *part, int np, double (&out)[NV])
-{
-    __shared__ double sh[kBlock / 64][NV];
-    double acc[NV];
-#pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-    for (int b = threadIdx.x; b < np; b += kBlock) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) acc[i] += part[(size_t)b * NV + i];
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) acc[i] += __shfl_xor(acc[i], off);
-    }
-    if (lane == 0) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) sh[wave][i] = acc[i];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < NV; ++i) out[i] = ((sh[0][i] + sh[1][i]) + sh[2][i]) + sh[3][i];
-    __syncthreads();
-}
-
-// ----------------------------------------------------------------------------
-// column-sliced CSR-Stream partial products
-// ----------------------------------------------------------------------------
-
-template <typename T>
-__device__ __forceinline__ void sliced_partial(const Sliced<T> &P, const T *__restrict__ x)
-{
-    __shared__ T prod[kStreamNB];
-    __shared__ double red[kBlock / 64];
-    const int S = P.S;
-    const int s = (int)blockIdx.x % S;
-    const int chunk0 = (int)blockIdx.x / S, stride = (int)gridDim.x / S;
-    const int *__restrict__ rp = P.rp + (size_t)s * (P.rows + 1);
-    T *__restrict__ out = P.part + (size_t)s * P.rows;
-    const int nblk = P.boff[s + 1] - P.boff[s];
-    const int *__restrict__ bro = P.brow + P.boff[s] + s;
-    const int *__restrict__ ci = P.ci;
-    const T *__restrict__ v = P.v;
-    for (int k = chunk0; k < nblk; k += stride) {
-        const int r0 = bro[k], r1 = bro[k + 1];
-        const int b = rp[r0], e = rp[r1];
-        const int cnt = e - b;
-        if (cnt <= kStreamNB) {
-#pragma unroll 4
-            for (int t = (int)threadIdx.x; t < cnt; t += kBlock) {
-                const int c = __builtin_nontemporal_load(ci + b + t);
-                const T a = __builtin_nontemporal_load(v + b + t);
-                prod[t] = a * x[c];
-            }
-            __syncthreads();
-            const int r = r0 + (int)threadIdx.x;   // r1 - r0 <= kStreamRB == kBlock
-            if (r < r1) {
-                T acc = T(0);
-                const int je = rp[r + 1] - b;
-                for (int j = rp[r] - b; j < je; ++j) acc += prod[j];
-                out[r] = acc;
-            }
-            __syncthreads();
-        } else {
-            // one row with more than kStreamNB nonzeros in this slice
-            T acc = T(0);
-            for (int t = b + (int)threadIdx.x; t < e; t += kBlock) acc += v[t] * x[ci[t]];
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = (double)acc;
-            __syncthreads();
-            if (threadIdx.x == 0) out[r0] = (T)(((red[0] + red[1]) + red[2]) + red[3]);
-            __syncthreads();
-        }
-    }
-}
-
-// row i of the product: the slices' partials added in slice order
-template <typename T>
-__device__ __forceinline__ T sum_slices(const Sliced<T> &P, int i)
-{
-    T a = P.part[i];
-    for (int s = 1; s < P.S; ++s) a += P.part[(size_t)s * P.rows + i];
-    return a;
-}
-
-// ----------------------------------------------------------------------------
-// epilogues
-// ----------------------------------------------------------------------------
-
-// dual step on row i: y' = proj_Y(y + sigma (q - 2 Kx' + Kx)), y'_i >= 0 on G rows
-template <typename T>
-struct DualEpi {
-    const T *__restrict__ y;
-    const T *__restrict__ kx;
-    const T *__restrict__ q;
-    T *__restrict__ yn;
-    T *__restrict__ kxn;
-    int m1;
-    T sigma;
-    double dy2, inter;
-    __device__ __forceinline__ void operator()(int i, T s)
-    {
-        const T yo = y[i], ko = kx[i];
-        T val = yo + sigma * (q[i] - T(2) * s + ko);
-        if (i >= m1 && val < T(0)) val = T(0);
-        yn[i] = val;
-        kxn[i] = s;
-        const double d = (double)val - (double)yo;
-        dy2 += d * d;
-        inter += d * ((double)s - (double)ko);
-    }
-};
-
-// after an accepted step, on column j: K'y' stored, averages moved, and the
-// next primal trial x'' = proj_X(x' - tau (c - K'y'))
-template <typename T>
-struct UpdateEpi {
-    const T *__restrict__ x;
-    const T *__restrict__ cs;
-    const T *__restrict__ ls;
-    const T *__restrict__ us;
-    T *__restrict__ kty;
-    T *__restrict__ xa;
-    T *__restrict__ ktya;
-    T *__restrict__ xn;
-    T w, tau;
-    bool primal;
-    double dx2;
-    __device__ __forceinline__ void operator()(int j, T s)
-    {
-        kty[j] = s;
-        const T xj = x[j];
-        const T a = xa[j];
-        xa[j] = a + w * (xj - a);
-        const T b = ktya[j];
-        ktya[j] = b + w * (s - b);
-        if (primal) {
-            const T nv = clampv(xj - tau * (cs[j] - s), ls[j], us[j]);
-            xn[j] = nv;
-            const double d = (double)nv - (double)xj;
-            dx2 += d * d;
-        }
-    }
-};
-
-template <typename T>
-__device__ __forceinline__ void primal_elem(const Dev<T> &d, int c, T tau, int j, double &dx2)
-{
-    const T *x = pick(d.xb, c);
-    const T *kty = pick(d.KTyb, c);
-    T *xn = pick(d.xb, c ^ 1);
-    const T xj = x[j];
-    const T nv = clampv(xj - tau * (d.cs[j] - kty[j]), d.ls[j], d.us[j]);
-    xn[j] = nv;
-    const double dd = (double)nv - (double)xj;
-    dx2 += dd * dd;
-}
 
 // ----------------------------------------------------------------------------
 // the iteration kernels
@@ -294,41 +81,7 @@ __global__ __launch_bounds__(kBlock) void k_step_decide(Ctl *ctl, const double *
     block_sum_partials<1>(pp, np, a);
     block_sum_partials<2>(pd, np, b);
     if (threadIdx.x != 0) return;
-    const double dx2 = a[0], dy2 = b[0], inter = b[1];
-    const double eta = ctl->eta, omega = ctl->omega;
-    double eta_new = eta;
-    bool accept = true;
-    ctl->attempts += 1;
-    if (!ctl->fixed_step) {
-        const double N = omega * dx2 + dy2 / omega;
-        const double D = 2.0 * fabs(inter);
-        if (isnan(N) || isnan(D)) {
-            ctl->numerical = 1;
-            ctl->accepted = 0;
-            ctl->mode = MODE_CHECK;
-            return;
-        }
-        const double eta_bar = D > 0.0 ? N / D : INFINITY;
-        const double kk = (double)(ctl->k + 1) + 1.0;
-        const double lo = (1.0 - pow(kk, -0.3)) * eta_bar;
-        const double hi = (1.0 + pow(kk, -0.6)) * eta;
-        eta_new = lo < hi ? lo : hi;
-        accept = eta <= eta_bar;
-    }
-    if (accept) {
-        ctl->W += eta;
-        ctl->avg_w = eta / ctl->W;
-        ctl->eta_last = eta;
-        ctl->k += 1;
-        ctl->t += 1;
-        ctl->cur ^= 1;
-        ctl->accepted = 1;
-        ctl->mode = (ctl->k % ctl->check_every == 0 || ctl->k >= ctl->max_iters) ? MODE_CHECK : MODE_NONE;
-    } else {
-        ctl->accepted = 0;
-        ctl->mode = MODE_NONE;
-    }
-    ctl->eta = eta_new;
+    step_decision(ctl, a[0], b[0], b[1]);
 }
 
 template <typename T>
@@ -348,8 +101,6 @@ __global__ __launch_bounds__(kBlock) void k_update(Dev<T> d, int vb_n, int vb_m)
     } else {
         UpdateEpi<T> epi{pick(d.xb, c), d.cs, d.ls, d.us, pick(d.KTyb, c), d.xa, d.KTya, pick(d.xb, c ^ 1),
                          (T)ctl->avg_w, tau, ctl->mode == MODE_NONE, 0.0};
-        const T *y = pick(d.yb, c);
-        const T *kx = pick(d.Kxb, c);
         const int total = vb_n + vb_m;
         for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
             if (vb < vb_n) {
@@ -357,61 +108,13 @@ __global__ __launch_bounds__(kBlock) void k_update(Dev<T> d, int vb_n, int vb_m)
                 if (j < d.n) epi(j, sum_slices(d.KT, j));
             } else {
                 const int i = (vb - vb_n) * kBlock + (int)threadIdx.x;
-                if (i < d.m) {
-                    const T w = epi.w;
-                    const T a = d.ya[i];
-                    d.ya[i] = a + w * (y[i] - a);
-                    const T b = d.Kxa[i];
-                    d.Kxa[i] = b + w * (kx[i] - b);
-                }
+                if (i < d.m) average_row(d, i, c, epi.w);
             }
         }
         dx2 = epi.dx2;
     }
     double v[1] = {dx2};
     block_store_partials<1>(v, d.part_primal);
-}
-
-// the 9 check sums of one iterate; s[0..3] rows, s[4..8] columns:
-// |r_p|^2 unscaled, |r_p|^2 scaled, q'y, |y-y0|^2,
-// |r_d|^2 unscaled, |r_d|^2 scaled, c'x, l'lam+ - u'lam-, |x-x0|^2
-template <typename T>
-__device__ __forceinline__ void row_sums(const Dev<T> &d, int i, const T *y, const T *kx, double *s)
-{
-    const double k = (double)kx[i], q = (double)d.qs[i];
-    double r = k - q;
-    if (i >= d.m1) {
-        const double t = q - k;
-        r = t > 0.0 ? t : 0.0;
-    }
-    const double ru = r * d.Dr[i];
-    s[0] += ru * ru;
-    s[1] += r * r;
-    const double yi = (double)y[i];
-    s[2] += q * yi;
-    const double dd = yi - (double)d.y0[i];
-    s[3] += dd * dd;
-}
-
-template <typename T>
-__device__ __forceinline__ void col_sums(const Dev<T> &d, int j, const T *x, const T *kty, double *s)
-{
-    const double cj = (double)d.cs[j], lj = (double)d.ls[j], uj = (double)d.us[j];
-    const bool lf = isfinite(lj), uf = isfinite(uj);
-    const double g = cj - (double)kty[j];
-    const double lam = proj_lambda(g, lf, uf);
-    const double rd = g - lam;
-    const double rdu = rd * d.Dc[j];
-    s[4] += rdu * rdu;
-    s[5] += rd * rd;
-    const double xj = (double)x[j];
-    s[6] += cj * xj;
-    double b = 0.0;
-    if (lf && lam > 0.0) b += lj * lam;
-    if (uf && lam < 0.0) b += uj * lam;
-    s[7] += b;
-    const double dd = xj - (double)d.x0[j];
-    s[8] += dd * dd;
 }
 
 template <typename T>
@@ -434,8 +137,8 @@ __global__ __launch_bounds__(kBlock) void k_check_reduce(Dev<T> d, int vb_n, int
         } else {
             const int i = (vb - vb_n) * kBlock + (int)threadIdx.x;
             if (i < d.m) {
-                row_sums(d, i, y, kx, s);
-                row_sums(d, i, d.ya, d.Kxa, s + 9);
+                row_sums(d, i, d.m1, y, kx, s);
+                row_sums(d, i, d.m1, d.ya, d.Kxa, s + 9);
             }
         }
     }
@@ -450,86 +153,7 @@ __global__ __launch_bounds__(kBlock) void k_check_decide(Ctl *ctl, const double 
     double S[kCheckSums];
     block_sum_partials<kCheckSums>(part, np, S);
     if (threadIdx.x != 0) return;
-    const double wp = pow(ctl->omega, ctl->kkt_p);
-    double rel[2], kkt[2];
-    for (int z = 0; z < 2; ++z) {
-        const double *e = S + 9 * z;
-        const double pobj = e[6], dobj = e[2] + e[7], gap = dobj - pobj;
-        const double rp = sqrt(e[0]) / (1.0 + Nq);
-        const double rd = sqrt(e[4]) / (1.0 + Nc);
-        const double rg = fabs(gap) / (1.0 + fabs(dobj) + fabs(pobj));
-        double r = rp;
-        if (rd > r) r = rd;
-        if (rg > r) r = rg;
-        if (isnan(rp) || isnan(rd) || isnan(rg)) r = NAN;
-        rel[z] = r;
-        kkt[z] = sqrt(wp * e[1] + e[5] / wp + gap * gap);
-        ctl->rel_p[z] = rp;
-        ctl->rel_d[z] = rd;
-        ctl->rel_g[z] = rg;
-        ctl->pobj[z] = pobj;
-        ctl->dobj[z] = dobj;
-        ctl->kkt[z] = kkt[z];
-    }
-    const int mode = ctl->mode;
-    ctl->restart_to = 0;
-    ctl->copy_out = 0;
-    ctl->need_primal = 0;
-    if (mode == MODE_INIT) {
-        ctl->KKT0 = kkt[0];
-        ctl->KKT_prev = INFINITY;
-        ctl->need_primal = 1;
-        return;
-    }
-    auto finish = [&](int status, int sel) {
-        ctl->status = status;
-        ctl->out_sel = sel;
-        ctl->copy_out = 1;
-        ctl->done = 1;
-        ctl->out_rel_p = ctl->rel_p[sel];
-        ctl->out_rel_d = ctl->rel_d[sel];
-        ctl->out_rel_g = ctl->rel_g[sel];
-        ctl->out_pobj = ctl->pobj[sel];
-        ctl->out_dobj = ctl->dobj[sel];
-    };
-    if (ctl->numerical || isnan(rel[0]) || isnan(rel[1])) {
-        finish(LP_NUMERICAL, 0);
-        return;
-    }
-    const int use_avg = rel[1] < rel[0] ? 1 : 0;
-    if (rel[0] <= ctl->tol || rel[1] <= ctl->tol) {
-        finish(LP_OPTIMAL, use_avg);
-        return;
-    }
-    int at_limit = 0;
-    if (mode == MODE_FINAL) at_limit = ctl->final_status;
-    else if (ctl->k >= ctl->max_iters) at_limit = LP_ITERATION_LIMIT;
-    if (at_limit) finish(at_limit, use_avg);
-    if (mode == MODE_CHECK && ctl->k % ctl->check_every == 0) {
-        const int cand_cur = kkt[0] < kkt[1];
-        const double kz = cand_cur ? kkt[0] : kkt[1];
-        const double *ez = S + (cand_cur ? 0 : 9);
-        int why = 0;
-        if (kz <= 0.2 * ctl->KKT0) why = 1;
-        else if (kz <= 0.8 * ctl->KKT0 && kz > ctl->KKT_prev) why = 2;
-        else if ((double)ctl->t >= 0.36 * (double)ctl->k) why = 3;
-        ctl->KKT_prev = kz;
-        if (why) {
-            const double dx = sqrt(ez[8]), dy = sqrt(ez[3]);
-            double om = ctl->omega;
-            if (dx > 1e-10 && dy > 1e-10) om = exp(0.5 * log(dy / dx) + 0.5 * log(om));
-            ctl->omega = om;
-            const double wp2 = pow(om, ctl->kkt_p);
-            const double gz = (ez[2] + ez[7]) - ez[6];
-            ctl->KKT0 = sqrt(wp2 * ez[1] + ez[5] / wp2 + gz * gz);
-            ctl->KKT_prev = INFINITY;
-            ctl->W = 0.0;
-            ctl->t = 0;
-            ctl->restarts += 1;
-            ctl->restart_to = cand_cur ? 1 : 2;
-        }
-    }
-    ctl->need_primal = ctl->done ? 0 : 1;
+    check_decision(ctl, S, Nq, Nc);
 }
 
 template <typename T>
@@ -541,44 +165,13 @@ __global__ __launch_bounds__(kBlock) void k_check_apply(Dev<T> d, int vb_n, int 
     const int np = ctl->need_primal;
     const T tau = (T)(ctl->eta / ctl->omega);
     double dx2 = 0.0;
-    T *x = pick(d.xb, c), *kty = pick(d.KTyb, c), *y = pick(d.yb, c), *kx = pick(d.Kxb, c);
     for (int vb = blockIdx.x; vb < vb_n + vb_m; vb += gridDim.x) {
         if (vb < vb_n) {
             const int j = vb * kBlock + (int)threadIdx.x;
-            if (j < d.n) {
-                if (co) {
-                    d.xo[j] = sel ? d.xa[j] : x[j];
-                    d.KTyo[j] = sel ? d.KTya[j] : kty[j];
-                }
-                if (rt == 2) {
-                    const T a = d.xa[j];
-                    x[j] = a;
-                    d.x0[j] = a;
-                    kty[j] = d.KTya[j];
-                } else if (rt == 1) {
-                    const T a = x[j];
-                    d.xa[j] = a;
-                    d.x0[j] = a;
-                    d.KTya[j] = kty[j];
-                }
-                if (np) primal_elem(d, c, tau, j, dx2);
-            }
+            if (j < d.n) apply_col(d, j, c, rt, co, sel, np, tau, dx2);
         } else {
             const int i = (vb - vb_n) * kBlock + (int)threadIdx.x;
-            if (i < d.m) {
-                if (co) d.yo[i] = sel ? d.ya[i] : y[i];
-                if (rt == 2) {
-                    const T a = d.ya[i];
-                    y[i] = a;
-                    d.y0[i] = a;
-                    kx[i] = d.Kxa[i];
-                } else if (rt == 1) {
-                    const T a = y[i];
-                    d.ya[i] = a;
-                    d.y0[i] = a;
-                    d.Kxa[i] = kx[i];
-                }
-            }
+            if (i < d.m) apply_row(d, i, c, rt, co, sel);
         }
     }
     double v[1] = {dx2};
@@ -942,6 +535,37 @@ hipError_t launch_absmax(const double *a, int64_t len, double *part, double *out
     if (g < 1) g = 1;
     hipLaunchKernelGGL(k_absmax_part, dim3(g), dim3(kBlock), 0, s, a, len, part);
     hipLaunchKernelGGL(k_max_final, dim3(1), dim3(kBlock), 0, s, (const double *)part, g, out);
+    return hipGetLastError();
+}
+
+// The diagonal scaling on the device: ruiz_iters Ruiz rounds (factors sqrt
+// of the inf-norm of each row of K and of K', both from the same current
+// matrix), then one Pock-Chambolle round with exponent alpha (skipped when
+// alpha < 0).  Scales both CSR copies in place and accumulates Dr, Dc.
+hipError_t scale_csr_pair(const int *rp, const int *ci, double *kv, int m, const int *tp, const int *ti, double *tv,
+                          int n, double *Dr, double *Dc, double *r, double *s, int ruiz_iters, double alpha,
+                          hipStream_t st)
+{
+    hipError_t e;
+    if ((e = launch_fill(Dr, 1.0, m, st)) != hipSuccess) return e;
+    if ((e = launch_fill(Dc, 1.0, n, st)) != hipSuccess) return e;
+    const int rounds = ruiz_iters + (alpha >= 0.0 ? 1 : 0);
+    for (int it = 0; it < rounds; ++it) {
+        const bool pc = it == ruiz_iters;
+        if (!pc) {
+            (void)launch_row_absmax(rp, kv, m, r, st);
+            (void)launch_row_absmax(tp, tv, n, s, st);
+        } else {
+            (void)launch_row_abspow_sum(rp, kv, m, 2.0 - alpha, r, st);
+            (void)launch_row_abspow_sum(tp, tv, n, alpha, s, st);
+        }
+        (void)launch_finish_factor(r, m, st);
+        (void)launch_finish_factor(s, n, st);
+        (void)launch_rescale_rows(rp, ci, kv, m, r, s, st);
+        (void)launch_rescale_rows(tp, ti, tv, n, s, r, st);
+        (void)launch_mul_inplace(Dr, r, m, st);
+        if ((e = launch_mul_inplace(Dc, s, n, st)) != hipSuccess) return e;
+    }
     return hipGetLastError();
 }
 

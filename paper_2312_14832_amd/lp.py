@@ -23,7 +23,9 @@ NSCALARS = 16
 # every symbol include/lp.h declares
 EXPORTS = ["lp_default_options", "lp_load", "lp_set_start", "lp_solve", "lp_result", "lp_get_state",
            "lp_set_state", "lp_get_scaling", "lp_spmv", "lp_kernel_time", "lp_device_bytes", "lp_layout", "lp_free",
-           "lp_strerror", "lp_last_error"]
+           "lp_strerror", "lp_last_error", "lp_batch_load", "lp_batch_solve", "lp_batch_result",
+           "lp_batch_get_state", "lp_batch_set_state", "lp_batch_device_bytes", "lp_batch_free",
+           "lp_batch_last_error"]
 
 
 class LPCsr(C.Structure):
@@ -78,6 +80,18 @@ def library():
         L.lp_strerror.restype = C.c_char_p
         L.lp_last_error.argtypes = [C.c_void_p]
         L.lp_last_error.restype = C.c_char_p
+        PP = C.POINTER(C.POINTER(C.c_double))
+        L.lp_batch_load.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(LPCsr), PP, PP, PP, PP,
+                                    C.POINTER(C.c_int64), C.POINTER(LPOptions)]
+        L.lp_batch_solve.argtypes = [C.c_void_p, C.c_double, C.c_int64, C.c_double]
+        L.lp_batch_result.argtypes = [C.c_void_p, C.c_int32, dp, dp, dp, C.POINTER(LPInfo)]
+        L.lp_batch_get_state.argtypes = [C.c_void_p, C.c_int32, dp, C.POINTER(C.c_int64)]
+        L.lp_batch_set_state.argtypes = [C.c_void_p, C.c_int32, dp, C.c_int64]
+        L.lp_batch_device_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+        L.lp_batch_free.argtypes = [C.c_void_p]
+        L.lp_batch_free.restype = None
+        L.lp_batch_last_error.argtypes = [C.c_void_p]
+        L.lp_batch_last_error.restype = C.c_char_p
         _lib = L
     return _lib
 
@@ -214,3 +228,85 @@ def unpack_state(buf, n, m):
         d[name] = buf[p:p + ln].copy()
         p += ln
     return d
+
+
+def _info_dict(inf):
+    d = {k: getattr(inf, k) for k, _ in LPInfo._fields_}
+    d["status"] = STATUS[inf.status]
+    d["rel_kkt"] = max(inf.rel_primal, inf.rel_dual, inf.rel_gap)
+    return d
+
+
+class Batch:
+    """Many LPs solved together (lp_batch_*); see include/lp.h."""
+
+    def __init__(self, lps, **options):
+        L = library()
+        self.count = len(lps)
+        self.dims = [(int(p.n), int(p.m)) for p in lps]
+        self.opt = default_options(**options)
+        keep = []
+        Ks = (LPCsr * self.count)()
+        arr = {k: (C.POINTER(C.c_double) * self.count)() for k in "cqlu"}
+        m1 = (C.c_int64 * self.count)()
+        for i, p in enumerate(lps):
+            rp = np.ascontiguousarray(p.row_ptr, np.int32)
+            ci = np.ascontiguousarray(p.col, np.int32)
+            v = _f64(p.val)
+            keep += [rp, ci, v]
+            Ks[i] = LPCsr(int(p.m), int(p.n), int(rp[-1]), rp.ctypes.data_as(C.POINTER(C.c_int32)),
+                          ci.ctypes.data_as(C.POINTER(C.c_int32)), _dp(v))
+            for k in "cqlu":
+                a = _f64(getattr(p, k))
+                keep.append(a)
+                arr[k][i] = _dp(a)
+            m1[i] = int(p.m1)
+        h = C.c_void_p()
+        rc = L.lp_batch_load(C.byref(h), self.count, Ks, arr["c"], arr["q"], arr["l"], arr["u"], m1,
+                             C.byref(self.opt))
+        if rc != 0:
+            raise LPError(rc, L.lp_strerror(rc).decode())
+        self.h = h
+
+    def _check(self, rc):
+        if rc != 0:
+            raise LPError(rc, library().lp_batch_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.lp_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def solve(self, tol=1e-4, max_iters=10**7, time_limit=0.0):
+        self._check(library().lp_batch_solve(self.h, float(tol), int(max_iters), float(time_limit)))
+
+    def info(self, i):
+        inf = LPInfo()
+        self._check(library().lp_batch_result(self.h, int(i), None, None, None, C.byref(inf)))
+        return _info_dict(inf)
+
+    def result(self, i):
+        n, m = self.dims[i]
+        x = np.empty(n); y = np.empty(m); lam = np.empty(n)
+        inf = LPInfo()
+        self._check(library().lp_batch_result(self.h, int(i), _dp(x), _dp(y), _dp(lam), C.byref(inf)))
+        return x, y, lam, _info_dict(inf)
+
+    def get_state(self, i):
+        ln = C.c_int64()
+        self._check(library().lp_batch_get_state(self.h, int(i), None, C.byref(ln)))
+        buf = np.empty(ln.value)
+        self._check(library().lp_batch_get_state(self.h, int(i), _dp(buf), C.byref(ln)))
+        return buf
+
+    def set_state(self, i, buf):
+        buf = _f64(buf)
+        self._check(library().lp_batch_set_state(self.h, int(i), _dp(buf), buf.size))
+
+    def device_bytes(self):
+        b = C.c_int64()
+        self._check(library().lp_batch_device_bytes(self.h, C.byref(b)))
+        return b.value

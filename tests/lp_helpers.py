@@ -77,3 +77,16 @@ def brute_force_vertices(Kd, q, m1, l, u, c):
             if v < best:
                 best, best_x = v, x
     return best, best_x
+
+
+def objective_band(eps, data, x_ref, y_ref, pobj, dobj):
+    """How far the objectives of two points that both meet the termination
+    criteria at eps can be apart, to first order.  With primal residual r_p
+    and dual residual r_d, convexity of the LP value function in q and c
+    gives opt - |y*||r_p| <= c'x <= opt + |x*||r_d| + |gap|; the criteria bound
+    |r_p| <= eps(1+|q|), |r_d| <= eps(1+|c|), |gap| <= eps(1+|p|+|d|).  The
+    band is twice that sum, with (x*, y*) taken from a reference point."""
+    per = (eps * (1 + abs(pobj) + abs(dobj))
+           + np.linalg.norm(y_ref) * eps * (1 + np.linalg.norm(data.q))
+           + np.linalg.norm(x_ref) * eps * (1 + np.linalg.norm(data.c)))
+    return 2.0 * per

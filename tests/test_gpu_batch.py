@@ -1,0 +1,113 @@
+"""Batched solves (lp_batch_*): every instance of one batch follows the same
+method as a single solve, with its own step size, primal weight, restarts and
+termination.  Checked per instance against the FP64 oracle (lockstep steps,
+1e-4 results) and against single-LP GPU runs."""
+import numpy as np
+import pytest
+
+from paper_2312_14832_amd import gen
+from lp_helpers import objective_band
+from gpu_helpers import (gpu_state, ints_equal, kkt_scale, say, scalar_diff, step_condition, vec_diff)
+
+pytestmark = pytest.mark.gpu
+
+PER_STEP_TOL = 1e-10
+U64 = 2.0 ** -53
+
+
+def small_batch(count=10, seed0=1000):
+    """Uneven small members of the batched workload (n log-uniform in
+    [200, 6000]) plus a box-only instance (m = 0) and one with long rows."""
+    lps = [gen.batch_member(seed0 + i, n_lo=200, n_hi=6000) for i in range(count)]
+    lps.append(gen.box_only_lp(5, n=300))
+    rng = np.random.Generator(np.random.PCG64(77))
+    counts = rng.integers(0, 5, size=400)
+    counts[:3] = [600, 900, 2400]   # a row of K' longer than one LDS row block
+    lps.append(gen.certificate_lp(rng, 1000, 1500, counts.astype(np.int64)))
+    return lps
+
+
+def test_batch_lockstep_fp64(lpmod, oracle_mod):
+    lps = small_batch()
+    bt = lpmod.Batch(lps)
+    oracles = [oracle_mod.Oracle(p) for p in lps]
+    for k in [0, 1, 63, 64, 200, 511]:
+        say(f"case batch lockstep k={k}")
+        raws, prevs, nexts = [], [], []
+        for o in oracles:
+            o.solve(1e-30, k)
+            raws.append(o.get_state_raw())
+            prevs.append(o.get_state())
+            o.solve(1e-30, k + 1)
+            nexts.append(o.get_state())
+        for i, raw in enumerate(raws):
+            bt.set_state(i, raw)
+        bt.solve(1e-30, k + 1)
+        for i, (p, o) in enumerate(zip(lps, oracles)):
+            so = nexts[i]
+            if so["k"] < k + 1:
+                continue  # the oracle met rel KKT <= 1e-30 exactly
+            sg = lpmod.unpack_state(bt.get_state(i), p.n, p.m)
+            assert ints_equal(sg, so), (k, i)
+            wv, vv = vec_diff(sg, so)
+            assert wv < PER_STEP_TOL, (k, i, vv, wv)
+            kap = step_condition(prevs[i], so)
+            Dr, Dc, _ = o.scaling()
+            for name, r in scalar_diff(sg, so).items():
+                if name == "KKT0":
+                    assert abs(sg["KKT0"] - so["KKT0"]) <= PER_STEP_TOL * kkt_scale(so, Dr, Dc, p), (k, i)
+                else:
+                    assert r < max(PER_STEP_TOL, 64 * U64 * kap), (k, i, name, r, kap)
+
+
+def test_batch_matches_single_lp_runs(lpmod):
+    """Free-running batch instances against single-LP GPU runs of the same
+    instances inside the first check window (both deterministic; only the
+    summation order of the reductions differs)."""
+    lps = small_batch(6, seed0=2000)
+    bt = lpmod.Batch(lps)
+    bt.solve(1e-30, 40)
+    for i, p in enumerate(lps):
+        say(f"case batch vs single i={i}")
+        single = lpmod.Problem(p)
+        single.solve(1e-30, 40)
+        sg = lpmod.unpack_state(bt.get_state(i), p.n, p.m)
+        ss = gpu_state(lpmod, single)
+        assert ints_equal(sg, ss), i
+        wv, vv = vec_diff(sg, ss)
+        assert wv < PER_STEP_TOL, (i, vv, wv)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_solves_to_1e4(lpmod, oracle_mod, precision):
+    lps = small_batch(10, seed0=3000)
+    bt = lpmod.Batch(lps, precision=precision)
+    bt.solve(1e-4, 200000, 120.0)
+    slack = 0.0 if precision == "fp64" else 2e-6
+    for i, p in enumerate(lps):
+        x, y, lam, info = bt.result(i)
+        say(f"case batch {precision} i={i}: {info['status']} k={info['iterations']} pobj={info['pobj']:.9g}")
+        assert info["status"] == "OPTIMAL", (i, info)
+        o = oracle_mod.Oracle(p)
+        ev = o.eval_unscaled(x, y)
+        assert ev["rel_kkt"] <= 1e-4 * (1 + 1e-6) + slack, (i, ev)
+        xo, yo, _, io = o.solve(1e-4, 200000)
+        band = objective_band(1e-4, p, xo, yo, io["pobj"], io["dobj"])
+        assert abs(info["pobj"] - io["pobj"]) <= band, (i, info, io, band)
+
+
+def test_batch_resume_bitwise(lpmod):
+    say("case batch resume")
+    lps = small_batch(5, seed0=4000)
+    bt = lpmod.Batch(lps)
+    bt.solve(1e-30, 256)
+    full = [bt.get_state(i) for i in range(len(lps))]
+    bt.solve(1e-30, 128)
+    mid = [bt.get_state(i) for i in range(len(lps))]
+    for i, s in enumerate(mid):
+        bt.set_state(i, s)
+    bt.solve(1e-30, 256)
+    for i in range(len(lps)):
+        if full[i][5] < 256:
+            continue  # met rel KKT <= 1e-30 exactly before 256 steps: its state stopped there
+        assert np.array_equal(bt.get_state(i)[16:], full[i][16:]), i

@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 from paper_2312_14832_amd import gen
+from lp_helpers import objective_band
 from gpu_helpers import (U64, gpu_state, ints_equal, kkt_scale, perturbed, say, scalar_diff, state_diff,
                          step_condition, vec_diff)
 
@@ -71,12 +72,12 @@ def test_spmv_matches_oracle(lpmod, oracle_mod, maker, slice_kib):
 
 
 def long_rows_lp(seed):
-    """Columns with 300-3000 nonzeros (rows of K' on the workgroup-per-row
-    path), rows with up to ~2000 nonzeros, empty rows and empty columns."""
+    """Columns with 300-3000 nonzeros (rows of K' past the LDS row-block size
+    take the whole-workgroup path), empty rows and empty columns."""
     rng = np.random.default_rng(seed)
-    n, m1, m2 = 600, 300, 500
+    n, m1, m2 = 600, 1500, 2000
     counts = rng.integers(0, 6, size=n)
-    counts[:5] = [300, 800, 3000 // 4, 700, 799]
+    counts[:5] = [300, 800, 3000, 700, 2500]   # rows of K' longer than one LDS row block
     counts[10:20] = 0
     from paper_2312_14832_amd.gen import certificate_lp
     lpd = certificate_lp(np.random.Generator(np.random.PCG64(seed)), m1, m2, counts.astype(np.int64))
@@ -180,9 +181,11 @@ def test_free_running_trajectory(lpmod, oracle_mod, seed):
 def test_final_result_at_1e4(lpmod, oracle_mod, seed):
     """Solve to rel KKT 1e-4.  The GPU's point, unscaled and evaluated by the
     oracle on the original data, meets the three criteria at 1e-4; its
-    objective is within the gap tolerance of the oracle's own 1e-4 objective
-    (two 1e-4 points of a chaotic iteration can differ that much; the oracle
-    differs from itself by up to ~3e-5 relative under 1e-15 perturbations)."""
+    objective is inside the first-order band in which two points meeting the
+    criteria at 1e-4 can lie (lp_helpers.objective_band): a chaotic iteration
+    ends at a different 1e-4 point for ulp-different arithmetic, and the
+    oracle differs from itself by up to ~3e-5 relative under 1e-15
+    perturbations."""
     say(f"case final seed={seed}")
     data = gen.tiny_lp(seed)
     p = lpmod.Problem(data)
@@ -196,8 +199,8 @@ def test_final_result_at_1e4(lpmod, oracle_mod, seed):
     assert ev["pobj"] == pytest.approx(info["pobj"], rel=1e-12)
     assert ev["dobj"] == pytest.approx(info["dobj"], rel=1e-9, abs=1e-9)
     assert ev["bound_viol"] <= 1e-12 * (1 + np.abs(data.x0).max()) and ev["sign_viol"] == 0.0
-    eps = 1e-4
-    assert abs(info["pobj"] - io["pobj"]) <= eps * (1 + abs(io["pobj"]) + abs(io["dobj"]))
+    xo, yo, _, _ = o.result()
+    assert abs(info["pobj"] - io["pobj"]) <= objective_band(1e-4, data, xo, yo, io["pobj"], io["dobj"])
     assert 0.5 * io["iterations"] <= info["iterations"] <= 2.0 * io["iterations"]
     fl, fu = np.isfinite(data.l), np.isfinite(data.u)
     assert np.all(lam[~fl & ~fu] == 0) and np.all(lam[fl & ~fu] >= 0) and np.all(lam[~fl & fu] <= 0)
