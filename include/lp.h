@@ -191,6 +191,64 @@ const char *lp_strerror(int code);
 /* Message of the last LP_ERR_HIP on this handle ("" when none). */
 const char *lp_last_error(const lp_problem *P);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start for a parametric LP family (fixed K; b, h, c vary).
+ * A network maps a standardized sketch of an instance's perturbation to a
+ * primal-dual start point for lp_set_start: `layers` ReLU layers of width
+ * `hidden`, a linear layer to `rank` coefficients, and a linear layer of
+ * width out_dim (= n + m; its bias starts at the base solution).  Shapes are
+ * row-major with the batch first.  Data arguments of the calls below are
+ * DEVICE pointers (float32) supplied by the caller; parameters move through
+ * host buffers.  The cold-start solve stays the fallback: a warm solve that
+ * fails is redone cold by the caller.
+ * ------------------------------------------------------------------------ */
+#define LPW_BF16 0   /* bf16 weights and activations on MFMA, FP32 accumulation */
+#define LPW_FP32 1   /* FP32 throughout (checking mode) */
+
+typedef struct lpw_net lpw_net;
+typedef struct {
+    int in_dim;      /* sketch features (256) */
+    int hidden;      /* width of the ReLU layers (1024) */
+    int layers;      /* ReLU layers (3) */
+    int rank;        /* coefficients of the low-rank output (64) */
+    int out_dim;     /* n + m of the family */
+    int max_batch;   /* rows per call (256) */
+    int precision;   /* LPW_BF16 or LPW_FP32 */
+    void *stream;    /* hipStream_t, NULL = null stream */
+} lpw_config;
+
+void lpw_default_config(lpw_config *cfg);
+int lpw_create(lpw_net **net, const lpw_config *cfg);
+/* Parameters as one flat float vector, layer by layer: W_l [in x out] then
+ * b_l [out]. */
+int64_t lpw_param_count(const lpw_net *net);
+int lpw_set_params(lpw_net *net, const float *host_params);   /* also resets Adam */
+int lpw_get_params(const lpw_net *net, float *host_params);
+/* Input standardization: features become (x - mu) / sigma (sigma > 0). */
+int lpw_set_norm(lpw_net *net, const float *host_mu, const float *host_sigma);
+/* Z[B x out_dim] = net(X[B x in_dim]) on the device, B <= max_batch. */
+int lpw_forward(lpw_net *net, const float *X, int B, float *Z);
+/* Mean squared error against Zstar[B x out_dim] and its gradient (kept on
+ * the device; lpw_get_grads copies it out).  *loss may be NULL. */
+int lpw_loss_grad(lpw_net *net, const float *X, const float *Zstar, int B, double *loss);
+int lpw_get_grads(const lpw_net *net, float *host_grads);
+/* One Adam update with the stored gradient. */
+int lpw_adam_step(lpw_net *net, float lr, float beta1, float beta2, float eps);
+/* lpw_loss_grad then lpw_adam_step(lr, 0.9, 0.999, 1e-8). */
+int lpw_train_step(lpw_net *net, const float *X, const float *Zstar, int B, float lr, double *loss);
+/* The GEMM kernel alone: C[M x N] = op(A) op(B), op = transpose when
+ * trans_* != 0 (A stored [M x K] or [K x M] with leading dimension lda, B
+ * stored [K x N] or [N x K]); A, B are bfloat16 bits (uint16) in LPW_BF16
+ * mode and float in LPW_FP32 mode; C is float.  Device pointers. */
+int lpw_gemm(int precision, int trans_a, int trans_b, int M, int N, int K, const void *A, int lda, const void *B,
+             int ldb, float *C, int ldc, void *stream);
+/* out[B x rows] = D[B x cols] S' for a sparse S (CSR rows x cols, float),
+ * the sketch of each instance's perturbation vector.  Device pointers. */
+int lpw_sketch(const int *row_ptr, const int *col, const float *val, int rows, const float *D, int cols, int B,
+               float *out, void *stream);
+void lpw_free(lpw_net *net);
+const char *lpw_last_error(const lpw_net *net);
+
 #ifdef __cplusplus
 }
 #endif

@@ -241,3 +241,53 @@ def from_dense(Kd, c, q, l, u, m1) -> LPData:
     return LPData(m=m, n=n, m1=int(m1), row_ptr=row_ptr, col=col, val=val,
                   c=np.asarray(c, np.float64), q=np.asarray(q, np.float64),
                   l=np.asarray(l, np.float64), u=np.asarray(u, np.float64), meta={"workload": "hand"})
+
+
+# ----------------------------------------------------------------------------
+# parametric family for the learned warm start
+# ----------------------------------------------------------------------------
+
+def parametric_base(seed: int = 4, n: int = 200_000, m1: int = 50_000, m2: int = 50_000,
+                    per_col: int = 10) -> LPData:
+    """The fixed-K family's base instance: per_col N(0,1) nonzeros per column
+    at distinct uniform rows, with its certificate (x0, s, y0, lam0)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    counts = np.full(n, per_col, dtype=np.int64)
+    return certificate_lp(rng, m1, m2, counts,
+                          meta={"workload": "parametric_base", "seed": seed, "n": n, "m1": m1, "m2": m2})
+
+
+def parametric_instance(base: LPData, seed: int, rel: float = 0.1) -> LPData:
+    """A member of the family: the base certificate perturbed by rel*N(0,1)
+    relative noise and kept valid (x0 clipped into its bounds, slack >= 0,
+    inequality duals >= 0, lam0 projected onto each variable's cone), then
+    b, h, c rebuilt from it, so every member is feasible and bounded."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n, m, m1 = base.n, base.m, base.m1
+    xi = rng.standard_normal(n)
+    x0 = np.clip(base.x0 + rel * base.x0 * xi, base.l, base.u)
+    s = np.maximum(base.s * (1.0 + rel * rng.standard_normal(m - m1)), 0.0)
+    y0 = base.y0 + rel * np.abs(base.y0) * rng.standard_normal(m)
+    y0[m1:] = np.maximum(y0[m1:], 0.0)
+    lam = base.lam0 + rel * np.abs(base.lam0) * rng.standard_normal(n)
+    fl, fu = np.isfinite(base.l), np.isfinite(base.u)
+    lam = np.where(fl & fu, lam, np.where(fl, np.maximum(lam, 0.0), np.where(fu, np.minimum(lam, 0.0), 0.0)))
+    K = base.csr()
+    Kx0 = K @ x0
+    q = np.concatenate([Kx0[:m1], Kx0[m1:] - s])
+    c = K.T @ y0 + lam
+    return LPData(m=m, n=n, m1=m1, row_ptr=base.row_ptr, col=base.col, val=base.val, c=c, q=q,
+                  l=base.l, u=base.u, x0=x0, y0=y0, lam0=lam, s=s,
+                  meta={"workload": "parametric_instance", "seed": seed})
+
+
+def sketch_matrix(dim: int, rows: int = 256, per_col: int = 8, seed: int = 4242):
+    """Sparse random sketch S (rows x dim): per_col entries +-1/sqrt(per_col)
+    in every column at distinct random rows.  Returned as CSR arrays."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    r = np.argsort(rng.random((dim, rows)), axis=1)[:, :per_col]          # distinct rows per column
+    sign = np.where(rng.random((dim, per_col)) < 0.5, -1.0, 1.0) / np.sqrt(per_col)
+    cols = np.repeat(np.arange(dim, dtype=np.int64), per_col)
+    rr = r.ravel().astype(np.int64)
+    rp, ci, v = _to_csr(rr, cols, sign.ravel(), rows, dim)
+    return rp, ci, v.astype(np.float32)

@@ -268,3 +268,34 @@ def test_validation_codes(oracle_mod, mut, code):
     with pytest.raises(oracle_mod.OracleError) as ei:
         oracle_mod.Oracle(lp)
     assert ei.value.code == code
+
+
+def test_parametric_family_stays_feasible_and_bounded(oracle_mod):
+    """Every member carries a valid certificate: x0 in bounds with b = A x0,
+    Gx0 - h = s >= 0, y_G >= 0, c - K'y0 = lam0 in Lambda; so the oracle finds an
+    optimum between the certificate's dual and primal objectives."""
+    base = gen.parametric_base(7, n=600, m1=150, m2=150, per_col=6)
+    K = base.csr()
+    for seed in (1, 2, 3):
+        p = gen.parametric_instance(base, seed)
+        assert np.all(p.x0 >= p.l) and np.all(p.x0 <= p.u)
+        r = K @ p.x0 - p.q
+        assert np.allclose(r[:p.m1], 0, atol=1e-9) and np.all(r[p.m1:] >= -1e-9)
+        assert np.all(p.y0[p.m1:] >= 0)
+        lam = p.c - K.T @ p.y0
+        fl, fu = np.isfinite(p.l), np.isfinite(p.u)
+        assert np.all(np.abs(lam[~fl & ~fu]) < 1e-9) and np.all(lam[fl & ~fu] >= -1e-9)
+        o = oracle_mod.Oracle(p)
+        _, _, _, info = o.solve(1e-7, 500000)
+        assert info["status"] == "OPTIMAL"
+        lo = p.q @ p.y0 + np.sum(np.where(fl, p.l, 0) * np.maximum(lam, 0)) - np.sum(np.where(fu, p.u, 0) * np.maximum(-lam, 0))
+        assert lo - 1e-5 * abs(lo) <= info["pobj"] <= p.c @ p.x0 + 1e-5 * abs(p.c @ p.x0)
+
+
+def test_sketch_matrix_structure():
+    rp, ci, v = gen.sketch_matrix(1000, rows=64, per_col=8, seed=1)
+    assert rp[-1] == 8000 and np.allclose(np.abs(v), 1 / np.sqrt(8))
+    cols = np.bincount(ci, minlength=1000)
+    assert np.all(cols == 8)
+    rows = np.repeat(np.arange(64), np.diff(rp))
+    assert len(set(zip(rows.tolist(), ci.tolist()))) == 8000   # distinct rows per column
