@@ -94,7 +94,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-1e-4 solve")
     ap.add_argument("--ttt-limit", type=float, default=90.0)
-    ap.add_argument("--workload", choices=["large", "batch"], default="large",
+    ap.add_argument("--ws-train", type=int, default=512, help="warmstart: training instances")
+    ap.add_argument("--ws-eval", type=int, default=128, help="warmstart: held-out instances")
+    ap.add_argument("--ws-epochs", type=int, default=120)
+    ap.add_argument("--workload", choices=["large", "batch", "warmstart"], default="large",
                     help="large: one 2e6x1e6 LP (default); batch: 512 uneven LPs solved together")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--seq-sample", type=int, default=32,
@@ -123,6 +126,8 @@ def main():
         return
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "warmstart":
+        return bench_warmstart(args)
     n = args.n
     m1 = m2 = n // 4
     t0 = time.perf_counter()
@@ -291,6 +296,93 @@ def bench_batch(args):
                        "iterations_median": float(np.median(seq_iters))},
         "load_s": load_s,
         "gen_s": gen_s,
+    }
+    print(json.dumps(out))
+
+
+def bench_warmstart(args):
+    """Learned warm start on the parametric family (fixed K: n=2e5,
+    m1=m2=5e4, 10 nonzeros per column; b, h, c from the base certificate
+    perturbed by 10% relative noise).  Training labels: this solver (batched,
+    FP64) to rel KKT 1e-5; network 256 -> 3x1024 ReLU -> 64 -> n+m in BF16 on
+    the GPU.  Held-out instances are solved cold, from the base solution
+    alone (ablation), and from the network's prediction (sketch + inference
+    time included; a failed warm solve falls back to cold).
+    """
+    import numpy as np
+    import torch
+    from paper_2312_14832_amd import gen, warmstart as ws
+
+    log = lambda msg: print(f"[bench] {msg}", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    base = gen.parametric_base(4)
+    fam = ws.Family(base)
+    train_lps = [gen.parametric_instance(base, 10_000 + i) for i in range(args.ws_train)]
+    eval_lps = [gen.parametric_instance(base, 30_000 + i) for i in range(args.ws_eval)]
+    log("instances generated")
+    log(f"generated family n={base.n} m={base.m} nnz={base.nnz}: {len(train_lps)} train, {len(eval_lps)} held out "
+        f"in {time.perf_counter() - t0:.1f}s")
+    t0 = time.perf_counter()
+    Z, infos = ws.solve_labels(train_lps, tol=1e-5, group=64, max_iters=20000, log=log)
+    label_s = time.perf_counter() - t0
+    ok = sum(1 for i in infos if i["status"] == "OPTIMAL")
+    log(f"labels: {ok}/{len(infos)} optimal at 1e-5 in {label_s:.1f}s")
+    keep = np.array([i["status"] == "OPTIMAL" for i in infos])
+    X = fam.sketch(train_lps)
+    sel = torch.from_numpy(np.nonzero(keep)[0]).cuda()
+    X = X.index_select(0, sel).contiguous()
+    Zd = torch.from_numpy(Z[keep]).cuda()
+    mu = X.mean(0).cpu().numpy()
+    sig = X.std(0).cpu().numpy() + 1e-6
+    zbase = Z[keep].mean(0)
+    net = ws.Net(base.n + base.m, max_batch=256)
+    net.init_params(0, out_bias=zbase)
+    net.set_norm(mu, sig)
+    t0 = time.perf_counter()
+    losses = ws.train(net, X, Zd, epochs=args.ws_epochs, batch=256, lr=1e-3, log=log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    rows = []
+    for i, p in enumerate(eval_lps):
+        ic, tc, _ = ws.solve_with_start(p, None)
+        ib, tb, fbb = ws.solve_with_start(p, zbase.astype(np.float64))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pred = net.forward(fam.sketch([p]))[0].cpu().numpy().astype(np.float64)
+        inf_s = time.perf_counter() - t1
+        iw, tw, fbw = ws.solve_with_start(p, pred)
+        rows.append((ic["iterations"], tc, ib["iterations"], tb, fbb, iw["iterations"], tw + inf_s, fbw, inf_s,
+                     ic["status"], iw["status"]))
+        if i % 16 == 0:
+            log(f"eval {i}: cold {ic['iterations']} it {tc:.3f}s | base {ib['iterations']} | "
+                f"net {iw['iterations']} it {tw + inf_s:.3f}s")
+    r = np.array([[a[0], a[1], a[2], a[3], a[4], a[5], a[6], a[7], a[8]] for a in rows], dtype=np.float64)
+    gm = lambda v: float(np.exp(np.mean(np.log(np.maximum(v, 1e-12)))))
+    summ = {
+        "cold": {"iters_mean": r[:, 0].mean(), "iters_median": float(np.median(r[:, 0])), "time_mean_s": r[:, 1].mean(),
+                 "time_geomean_s": gm(r[:, 1])},
+        "base_start": {"iters_mean": r[:, 2].mean(), "iters_median": float(np.median(r[:, 2])),
+                       "time_mean_s": r[:, 3].mean(), "fallbacks": int(r[:, 4].sum())},
+        "net_start": {"iters_mean": r[:, 5].mean(), "iters_median": float(np.median(r[:, 5])),
+                      "time_mean_s": r[:, 6].mean(), "time_geomean_s": gm(r[:, 6]), "fallbacks": int(r[:, 7].sum()),
+                      "inference_mean_s": r[:, 8].mean()},
+    }
+    log(f"cold {summ['cold']['iters_mean']:.0f} it {summ['cold']['time_mean_s']:.3f}s | base "
+        f"{summ['base_start']['iters_mean']:.0f} it | net {summ['net_start']['iters_mean']:.0f} it "
+        f"{summ['net_start']['time_mean_s']:.3f}s")
+    out = {
+        "metric": "time-to-1e-4 KKT, warm-start vs plain",
+        "value": summ["cold"]["time_mean_s"] / summ["net_start"]["time_mean_s"],
+        "unit": "x speedup (mean cold time / mean warm time)",
+        "n_gpus": 1, "steps": len(eval_lps), "warmup": 0,
+        "ms_per_step": 1e3 * summ["net_start"]["time_mean_s"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64 solve, bf16 network",
+        "data": "synthetic",
+        "config": {"workload": "parametric_family_n200000", "n": base.n, "m1": base.m1, "m2": base.m - base.m1,
+                   "nnz": base.nnz, "train": len(train_lps), "train_used": int(keep.sum()), "held_out": len(eval_lps),
+                   "label_tol": 1e-5, "tol": 1e-4, "epochs": args.ws_epochs, "perturbation": 0.1},
+        "summary": summ,
+        "training": {"loss_first": losses[0], "loss_last": losses[-1], "seconds": train_s, "label_seconds": label_s},
     }
     print(json.dumps(out))
 
