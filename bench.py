@@ -137,11 +137,11 @@ def main():
 
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
-    prob = lp.Problem(data, precision=args.precision, stream=stream, kernel_timing=1)
+    prob = lp.Problem(data, precision=args.precision, stream=stream, kernel_timing=1, autotune=1)
     torch.cuda.synchronize()
     load_s = time.perf_counter() - t0
-    print(f"[bench] loaded in {load_s:.1f}s ({prob.device_bytes() / 2**30:.2f} GiB on device)",
-          file=sys.stderr, flush=True)
+    print(f"[bench] loaded in {load_s:.1f}s ({prob.device_bytes() / 2**30:.2f} GiB on device), "
+          f"column slices (K, K') = {prob.layout()}", file=sys.stderr, flush=True)
 
     # warm-up windows (also compiles nothing: kernels are prebuilt)
     prob.solve(1e-30, ITERS_PER_STEP * max(args.warmup, 0))
@@ -173,6 +173,7 @@ def main():
           + "; ".join(f"{k} {v['avg_us']:.1f}us {v['GB_s']:.0f}GB/s" for k, v in spmv.items()),
           file=sys.stderr, flush=True)
 
+    prob_layout = prob.layout()
     ttt = None
     if not args.no_ttt:
         t0 = time.perf_counter()
@@ -207,6 +208,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "n": n, "m1": m1, "m2": m2, "nnz": data.nnz, "seed": args.seed,
                    "precision": args.precision, "iters_per_step": ITERS_PER_STEP,
+                   "column_slices": list(prob_layout),
                    "generator": "power-law column counts 1..200 (mean 10), N(0,1)*10^U(-3,3) per row, "
                                 "certificate-feasible"},
         "roofline": roofline,

@@ -86,6 +86,8 @@ typedef struct {
     int window;             /* attempt slots launched between host polls of the done flag (64) */
     int kernel_timing;      /* 1: bracket the two SpMV kernels with hipEvents (see lp_kernel_time) */
     int slice_kib;          /* target KiB of a gathered vector per column slice of K and K' (2048 = half an XCD's L2) */
+    int autotune;           /* 1: at lp_load, time the slice count from slice_kib and its halved/doubled
+                               neighbours on the actual matrix and keep the fastest, per product (0) */
     int verbose;
 } lp_options;
 

@@ -119,8 +119,10 @@ struct lp_problem {
     void *tmp_n = nullptr, *tmp_m = nullptr;   // T scratch for lp_spmv
     hipGraphExec_t graph = nullptr;
     int graph_window = 0;
+    bool graph_timed = false, graph_events_failed = false;
     bool own_stream = false;
     int slices_K = 1, slices_KT = 1;
+    std::vector<std::pair<int, float>> tune_log_K, tune_log_KT;   // (slices, ms) tried by the autotuner
     std::vector<hipEvent_t> ev;
     int64_t t_count[2] = {0, 0};
     double t_ms[2] = {0, 0};
@@ -220,9 +222,69 @@ Sliced<T> upload_sliced(lp_problem *P, const HostSliced &H, const double *scaled
 }
 
 template <typename T>
+void free_sliced(lp_problem *P, Sliced<T> &q)
+{
+    for (const void *p : {(const void *)q.rp, (const void *)q.ci, (const void *)q.brow, (const void *)q.boff,
+                          (const void *)q.v, (const void *)q.part})
+        P->dfree(const_cast<void *>(p));
+    q = Sliced<T>{};
+}
+
+// Mean time of one product (partial pass + slice sums) on a vector of ones.
+template <typename T>
+float time_product(lp_problem *P, const Sliced<T> &q, T *in, T *out, int64_t in_len)
+{
+    std::vector<T> ones((size_t)std::max<int64_t>(in_len, 1), T(1));
+    upload(P, in, ones.data(), in_len);
+    hipEvent_t a, b;
+    HIPT(hipEventCreate(&a));
+    HIPT(hipEventCreate(&b));
+    for (int r = 0; r < 2; ++r) HIPT(launch_spmv<T>(q, in, out, P->stream));
+    HIPT(hipEventRecord(a, P->stream));
+    const int reps = 5;
+    for (int r = 0; r < reps; ++r) HIPT(launch_spmv<T>(q, in, out, P->stream));
+    HIPT(hipEventRecord(b, P->stream));
+    HIPT(hipEventSynchronize(b));
+    float ms = 0;
+    HIPT(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms / reps;
+}
+
+// Autotuner for the column slicing of one product: times the default slice
+// count and its neighbours (halved, doubled) on the actual matrix and keeps
+// the fastest.
+template <typename T>
+Sliced<T> tuned_sliced(lp_problem *P, const HostSliced &H0, const std::vector<int> &rp, const std::vector<int> &ci,
+                       const double *vals, T *in, T *out, int64_t in_len, std::vector<std::pair<int, float>> &log)
+{
+    Sliced<T> best = upload_sliced<T>(P, H0, vals);
+    float best_ms = time_product<T>(P, best, in, out, in_len);
+    log.emplace_back(H0.S, best_ms);
+    for (int S : {H0.S / 2, H0.S * 2}) {
+        if (S < 1 || S > 32) continue;
+        HostSliced H;
+        build_sliced(H, H0.rows, H0.cols, rp, ci, S);
+        Sliced<T> q = upload_sliced<T>(P, H, vals);
+        const float ms = time_product<T>(P, q, in, out, in_len);
+        log.emplace_back(S, ms);
+        if (ms < best_ms) {
+            free_sliced<T>(P, best);
+            best = q;
+            best_ms = ms;
+        } else {
+            free_sliced<T>(P, q);
+        }
+    }
+    return best;
+}
+
+template <typename T>
 void setup_typed(lp_problem *P, const HostSliced &HK, const HostSliced &HT, const double *kv64, const double *tv64,
                  const double *cs64, const double *ls64, const double *us64, const double *qs64, const double *Dr,
-                 const double *Dc)
+                 const double *Dc, const std::vector<int> &rp, const std::vector<int> &ci, const std::vector<int> &tp,
+                 const std::vector<int> &ti)
 {
     const int64_t m = P->m, n = P->n;
     Dev<T> &d = P->dev<T>();
@@ -230,9 +292,18 @@ void setup_typed(lp_problem *P, const HostSliced &HK, const HostSliced &HT, cons
     d.n = (int)n;
     d.m1 = (int)P->m1;
     d.Dr = Dr; d.Dc = Dc;
-    d.K = upload_sliced<T>(P, HK, kv64);
-    d.KT = upload_sliced<T>(P, HT, tv64);
     auto tvec = [&](int64_t len) { return (T *)P->dalloc(sizeof(T) * (size_t)std::max<int64_t>(len, 1)); };
+    P->tmp_n = tvec(n);
+    P->tmp_m = tvec(m);
+    if (P->opt.autotune) {
+        d.K = tuned_sliced<T>(P, HK, rp, ci, kv64, (T *)P->tmp_n, (T *)P->tmp_m, n, P->tune_log_K);
+        d.KT = tuned_sliced<T>(P, HT, tp, ti, tv64, (T *)P->tmp_m, (T *)P->tmp_n, m, P->tune_log_KT);
+    } else {
+        d.K = upload_sliced<T>(P, HK, kv64);
+        d.KT = upload_sliced<T>(P, HT, tv64);
+    }
+    P->slices_K = d.K.S;
+    P->slices_KT = d.KT.S;
     if (std::is_same<T, double>::value) {
         d.cs = (const T *)cs64; d.ls = (const T *)ls64; d.us = (const T *)us64; d.qs = (const T *)qs64;
     } else {
@@ -253,8 +324,6 @@ void setup_typed(lp_problem *P, const HostSliced &HK, const HostSliced &HT, cons
     d.part_dual = (double *)P->dalloc(sizeof(double) * kMaxGrid * 2);
     d.part_check = (double *)P->dalloc(sizeof(double) * kMaxGrid * kCheckSums);
     d.ctl = (Ctl *)P->dalloc(sizeof(Ctl));
-    P->tmp_n = tvec(n);
-    P->tmp_m = tvec(m);
 }
 
 int do_load(lp_problem *P, const lp_csr *K, const double *c, const double *q, const double *l, const double *u)
@@ -325,8 +394,8 @@ int do_load(lp_problem *P, const lp_csr *K, const double *c, const double *q, co
     P->eta0 = h[4] > 0.0 ? 1.0 / h[4] : 1.0;
     if (P->opt.fixed_step) P->eta0 = P->opt.fixed_eta;
 
-    if (P->mixed) setup_typed<float>(P, HK, HT, d_kv, d_tv, cs, ls, us, qs, Dr, Dc);
-    else setup_typed<double>(P, HK, HT, d_kv, d_tv, cs, ls, us, qs, Dr, Dc);
+    if (P->mixed) setup_typed<float>(P, HK, HT, d_kv, d_tv, cs, ls, us, qs, Dr, Dc, rp, ci, tp, ti);
+    else setup_typed<double>(P, HK, HT, d_kv, d_tv, cs, ls, us, qs, Dr, Dc, rp, ci, tp, ti);
     sync(P);
     // the CSR pair was only needed for the scaling
     for (void *pp : {(void *)d_rp, (void *)d_ci, (void *)d_kv, (void *)d_tp, (void *)d_ti, (void *)d_tv,
@@ -362,7 +431,7 @@ void launch_slot(lp_problem *P, int slot, bool timed)
     HIPT(launch_partial_KT<T>(d, st));
     HIPT(launch_update<T>(d, P->geo, st));
     if (timed) HIPT(hipEventRecord(P->ev[4 * slot + 3], st));
-    HIPT(launch_check_reduce<T>(d, P->geo, st));
+    // the check sums of a check step come from the update kernel itself
     HIPT(launch_check_decide<T>(d, P->geo, P->Nq, P->Nc, st));
     HIPT(launch_check_apply<T>(d, P->geo, st));
 }
@@ -479,19 +548,35 @@ int do_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit)
         P->ev.assign(4 * W, nullptr);
         for (auto &e : P->ev) HIPT(hipEventCreate(&e));
     }
-    const bool use_graph = P->opt.use_graph && !timed;
-    if (use_graph && (!P->graph || P->graph_window != W)) {
+    // the window is captured once per handle (with the timing events when
+    // kernel_timing is set, as event-record nodes); if the runtime refuses
+    // to capture event records, timed runs fall back to plain launches
+    bool use_graph = P->opt.use_graph && !(timed && P->graph_events_failed);
+    if (use_graph && (!P->graph || P->graph_window != W || P->graph_timed != timed)) {
         if (P->graph) {
             (void)hipGraphExecDestroy(P->graph);
             P->graph = nullptr;
         }
         hipGraph_t g = nullptr;
         HIPT(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
-        for (int s = 0; s < W; ++s) launch_slot<T>(P, s, false);
-        HIPT(hipStreamEndCapture(st, &g));
-        HIPT(hipGraphInstantiate(&P->graph, g, nullptr, nullptr, 0));
-        (void)hipGraphDestroy(g);
-        P->graph_window = W;
+        bool ok = true;
+        try {
+            for (int s = 0; s < W; ++s) launch_slot<T>(P, s, timed);
+        } catch (const HipError &) {
+            ok = false;
+        }
+        const hipError_t ec = hipStreamEndCapture(st, &g);
+        if (ok && ec == hipSuccess && hipGraphInstantiate(&P->graph, g, nullptr, nullptr, 0) == hipSuccess) {
+            P->graph_window = W;
+            P->graph_timed = timed;
+        } else {
+            (void)hipGetLastError();
+            P->graph = nullptr;
+            if (!timed) HIPT(ec != hipSuccess ? ec : hipErrorUnknown);
+            P->graph_events_failed = true;
+            use_graph = false;
+        }
+        if (g) (void)hipGraphDestroy(g);
     }
     while (!P->hctl->done) {
         const long long k_before = P->hctl->k;
@@ -698,6 +783,7 @@ void lp_default_options(lp_options *o)
     o->window = 64;
     o->kernel_timing = 0;
     o->slice_kib = 2048;
+    o->autotune = 0;
     o->verbose = 0;
 }
 

@@ -69,9 +69,22 @@ __device__ __forceinline__ void block_sum_partials(const double *part, int np, d
     double acc[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-    for (int b = threadIdx.x; b < np; b += kBlock) {
+    // four strided partials per thread are loaded before any is added, so
+    // their load latencies overlap
+    constexpr int U = NV <= 2 ? 4 : 1;
+    for (int b = threadIdx.x; b < np; b += U * kBlock) {
+        double t[U][NV];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) acc[i] += part[(size_t)b * NV + i];
+        for (int u = 0; u < U; ++u) {
+            const int idx = b + u * kBlock;
+#pragma unroll
+            for (int i = 0; i < NV; ++i) t[u][i] = idx < np ? part[(size_t)idx * NV + i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) acc[i] += t[u][i];
+        }
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -440,6 +453,33 @@ __device__ __forceinline__ void stream_block(const int *__restrict__ rp, const i
         __syncthreads();
         if (threadIdx.x == 0) out[r0] = (T)(((red[0] + red[1]) + red[2]) + red[3]);
         __syncthreads();
+    }
+}
+
+// The 18 check sums of the current and the averaged iterate over the
+// elements this workgroup owns in a grid-stride walk of the n-chunks then the
+// m-chunks (the same walk as the elementwise solver kernels, so a thread
+// only reads entries it wrote itself earlier in the same kernel).
+template <typename T>
+__device__ __forceinline__ void check_sums_pass(const Dev<T> &d, int c, int vb_n, int vb_m, double (&s)[kCheckSums])
+{
+#pragma unroll
+    for (int i = 0; i < kCheckSums; ++i) s[i] = 0.0;
+    const T *x = pick(d.xb, c), *kty = pick(d.KTyb, c), *y = pick(d.yb, c), *kx = pick(d.Kxb, c);
+    for (int vb = blockIdx.x; vb < vb_n + vb_m; vb += gridDim.x) {
+        if (vb < vb_n) {
+            const int j = vb * kBlock + (int)threadIdx.x;
+            if (j < d.n) {
+                col_sums(d, j, x, kty, s);
+                col_sums(d, j, (const T *)d.xa, (const T *)d.KTya, s + 9);
+            }
+        } else {
+            const int i = (vb - vb_n) * kBlock + (int)threadIdx.x;
+            if (i < d.m) {
+                row_sums(d, i, d.m1, y, kx, s);
+                row_sums(d, i, d.m1, (const T *)d.ya, (const T *)d.Kxa, s + 9);
+            }
+        }
     }
 }
 

@@ -115,6 +115,12 @@ __global__ __launch_bounds__(kBlock) void k_update(Dev<T> d, int vb_n, int vb_m)
     }
     double v[1] = {dx2};
     block_store_partials<1>(v, d.part_primal);
+    if (ctl->mode == MODE_CHECK) {
+        // a check follows this step: its sums come from here, not a separate pass
+        double cs[kCheckSums];
+        check_sums_pass(d, c, vb_n, vb_m, cs);
+        block_store_partials<kCheckSums>(cs, d.part_check);
+    }
 }
 
 template <typename T>
@@ -122,31 +128,11 @@ __global__ __launch_bounds__(kBlock) void k_check_reduce(Dev<T> d, int vb_n, int
 {
     const Ctl *ctl = d.ctl;
     if (ctl->mode == MODE_NONE || ctl->done) return;
-    const int c = ctl->cur;
-    const T *x = pick(d.xb, c), *kty = pick(d.KTyb, c), *y = pick(d.yb, c), *kx = pick(d.Kxb, c);
     double s[kCheckSums];
-#pragma unroll
-    for (int i = 0; i < kCheckSums; ++i) s[i] = 0.0;
-    for (int vb = blockIdx.x; vb < vb_n + vb_m; vb += gridDim.x) {
-        if (vb < vb_n) {
-            const int j = vb * kBlock + (int)threadIdx.x;
-            if (j < d.n) {
-                col_sums(d, j, x, kty, s);
-                col_sums(d, j, d.xa, d.KTya, s + 9);
-            }
-        } else {
-            const int i = (vb - vb_n) * kBlock + (int)threadIdx.x;
-            if (i < d.m) {
-                row_sums(d, i, d.m1, y, kx, s);
-                row_sums(d, i, d.m1, d.ya, d.Kxa, s + 9);
-            }
-        }
-    }
+    check_sums_pass(d, ctl->cur, vb_n, vb_m, s);
     block_store_partials<kCheckSums>(s, d.part_check);
 }
 
-// Termination (three relative criteria, unscaled), candidate choice and
-// restart conditions 1-3 on KKT_omega (scaled), primal-weight update.
 __global__ __launch_bounds__(kBlock) void k_check_decide(Ctl *ctl, const double *part, int np, double Nq, double Nc)
 {
     if (ctl->mode == MODE_NONE || ctl->done) return;

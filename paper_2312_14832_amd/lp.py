@@ -39,7 +39,7 @@ class LPOptions(C.Structure):
                 ("pc_alpha", C.c_double), ("check_every", C.c_int), ("kkt_omega_power", C.c_double),
                 ("fixed_step", C.c_int), ("fixed_eta", C.c_double), ("use_graph", C.c_int),
                 ("window", C.c_int), ("kernel_timing", C.c_int), ("slice_kib", C.c_int),
-                ("verbose", C.c_int)]
+                ("autotune", C.c_int), ("verbose", C.c_int)]
 
 
 class LPInfo(C.Structure):
