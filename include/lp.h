@@ -119,6 +119,12 @@ int lp_load(lp_problem **P, const lp_csr *K, const double *c, const double *q,
  * X and Y.  Cancels any state set by lp_set_state. */
 int lp_set_start(lp_problem *P, const double *x0, const double *y0);
 
+/* Primal weight omega the next start uses instead of |c~|/|q~| (omega <= 0
+ * restores that default).  For warm starts of a parametric family, where a
+ * converged member's weight suits its neighbours.  Errors: LP_ERR_ARG for
+ * NaN or infinity. */
+int lp_set_start_weight(lp_problem *P, double omega);
+
 /* Run restarted PDHG until the relative KKT error <= tol, max_iters accepted
  * steps in total, or time_limit_s seconds (<= 0: none).  Starts from the
  * start point, or resumes from a state given by lp_set_state.  A check runs

@@ -34,6 +34,7 @@ def lib():
                                dp, dp, dp, dp, C.c_int64, C.POINTER(_Opts)]
         L.orc_load.restype = C.c_int
         L.orc_set_start.argtypes = [C.c_void_p, dp, dp]
+        L.orc_set_start_weight.argtypes = [C.c_void_p, C.c_double]
         L.orc_solve.argtypes = [C.c_void_p, C.c_double, C.c_int64, C.c_double]
         L.orc_result.argtypes = [C.c_void_p, dp, dp, dp, dp]
         L.orc_state_len.argtypes = [C.c_void_p]
@@ -103,6 +104,9 @@ class Oracle:
         xs = None if x is None else _f64(x)
         ys = None if y is None else _f64(y)
         lib().orc_set_start(self.h, _dp(xs), _dp(ys))
+
+    def set_start_weight(self, omega):
+        lib().orc_set_start_weight(self.h, float(omega))
 
     def solve(self, tol=1e-4, max_iters=10**6, time_limit=0.0):
         rc = lib().orc_solve(self.h, tol, int(max_iters), float(time_limit))

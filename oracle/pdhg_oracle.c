@@ -88,6 +88,7 @@ typedef struct {
     /* warm start (unscaled), optional */
     double *xs, *ys;
     int has_xs, has_ys;
+    double omega_start;             /* > 0: primal weight of the next start */
     /* output (scaled) */
     double *xo, *yo, *KTyo;
     double out_rel_p, out_rel_d, out_rel_g, out_pobj, out_dobj;
@@ -300,6 +301,14 @@ int orc_load(orc_t **out, int64_t m, int64_t n, int64_t nnz, const int32_t *rp, 
     return ORC_OK;
 }
 
+int orc_set_start_weight(orc_t *P, double omega)
+{
+    if (!P) return ORC_ERR_ARG;
+    P->omega_start = omega > 0.0 ? omega : 0.0;
+    P->state_ready = 0;
+    return ORC_OK;
+}
+
 int orc_set_start(orc_t *P, const double *x, const double *y)
 {
     if (!P) return ORC_ERR_ARG;
@@ -396,6 +405,7 @@ static void init_state(orc_t *P)
     }
     double nc = norm2(P->cs, n), nq = norm2(P->qs, m);
     P->omega = (nc > 1e-10 && nq > 1e-10) ? nc / nq : 1.0;
+    if (P->omega_start > 0.0) P->omega = P->omega_start;
     double kmax = 0.0;
     for (int64_t p = 0; p < P->nnz; ++p)
         if (fabs(P->kv[p]) > kmax) kmax = fabs(P->kv[p]);

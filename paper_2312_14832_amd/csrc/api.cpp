@@ -108,6 +108,7 @@ struct lp_problem {
     bool has_result = false, state_ready = false;
     std::vector<double> xs, ys;
     bool has_xs = false, has_ys = false;
+    double omega_start = 0.0;       // > 0: primal weight of the next cold/warm start
     Ctl *hctl = nullptr;            // pinned host mirror of the device controller
     std::vector<void *> allocs;     // device allocations owned by the handle
     std::vector<int64_t> alloc_bytes;
@@ -493,7 +494,7 @@ int do_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit)
         HIPT(launch_start<T>(d, xs, ys, 0, st));
         Ctl c{};
         c.eta = P->eta0;
-        c.omega = P->omega0;
+        c.omega = P->omega_start > 0.0 ? P->omega_start : P->omega0;
         c.KKT_prev = INFINITY;
         c.mode = MODE_INIT;
         c.tol = tol;
@@ -837,6 +838,14 @@ int lp_set_start(lp_problem *P, const double *x0, const double *y0)
     P->has_ys = y0 != nullptr;
     if (x0) P->xs.assign(x0, x0 + P->n);
     if (y0) P->ys.assign(y0, y0 + P->m);
+    P->state_ready = false;
+    return LP_OK;
+}
+
+int lp_set_start_weight(lp_problem *P, double omega)
+{
+    if (!P || std::isnan(omega) || std::isinf(omega)) return LP_ERR_ARG;
+    P->omega_start = omega > 0.0 ? omega : 0.0;
     P->state_ready = false;
     return LP_OK;
 }

@@ -21,7 +21,7 @@ ERRORS = {-1: "LP_ERR_ARG", -2: "LP_ERR_DIM", -3: "LP_ERR_NAN", -4: "LP_ERR_BOUN
 NSCALARS = 16
 
 # every symbol include/lp.h declares
-EXPORTS = ["lp_default_options", "lp_load", "lp_set_start", "lp_solve", "lp_result", "lp_get_state",
+EXPORTS = ["lp_default_options", "lp_load", "lp_set_start", "lp_set_start_weight", "lp_solve", "lp_result", "lp_get_state",
            "lp_set_state", "lp_get_scaling", "lp_spmv", "lp_kernel_time", "lp_device_bytes", "lp_layout", "lp_free",
            "lp_strerror", "lp_last_error", "lp_batch_load", "lp_batch_solve", "lp_batch_result",
            "lp_batch_get_state", "lp_batch_set_state", "lp_batch_device_bytes", "lp_batch_free",
@@ -65,6 +65,7 @@ def library():
         L.lp_load.argtypes = [C.POINTER(C.c_void_p), C.POINTER(LPCsr), dp, dp, dp, dp, C.c_int64,
                               C.POINTER(LPOptions)]
         L.lp_set_start.argtypes = [C.c_void_p, dp, dp]
+        L.lp_set_start_weight.argtypes = [C.c_void_p, C.c_double]
         L.lp_solve.argtypes = [C.c_void_p, C.c_double, C.c_int64, C.c_double]
         L.lp_result.argtypes = [C.c_void_p, dp, dp, dp, C.POINTER(LPInfo)]
         L.lp_get_state.argtypes = [C.c_void_p, dp, C.POINTER(C.c_int64)]
@@ -157,6 +158,9 @@ class Problem:
         xs = None if x is None else _f64(x)
         ys = None if y is None else _f64(y)
         self._check(library().lp_set_start(self.h, _dp(xs), _dp(ys)))
+
+    def set_start_weight(self, omega):
+        self._check(library().lp_set_start_weight(self.h, float(omega)))
 
     def solve(self, tol=1e-4, max_iters=10**7, time_limit=0.0):
         self._check(library().lp_solve(self.h, float(tol), int(max_iters), float(time_limit)))

@@ -251,17 +251,20 @@ def train(net, X, Z, epochs=50, batch=256, lr=1e-3, seed=0, log=None):
     return losses
 
 
-def solve_with_start(p, start=None, tol=1e-4, max_iters=200000, precision="fp64"):
-    """Solve one instance (optionally warm); a warm solve that does not end
-    OPTIMAL is redone cold.  Returns (info, seconds, used_fallback)."""
+def solve_with_start(p, start=None, tol=1e-4, max_iters=200000, precision="fp64", omega=0.0):
+    """Solve one instance (optionally warm: start point and, if omega > 0, the
+    primal weight); a warm solve that does not end OPTIMAL is redone cold.
+    Returns (info, seconds, used_fallback)."""
     prob = lpmod.Problem(p, precision=precision)
     t0 = time.perf_counter()
     if start is not None:
         prob.set_start(start[:p.n], start[p.n:])
+        prob.set_start_weight(omega)
     info = prob.solve(tol, max_iters)
     fallback = False
     if start is not None and info["status"] != "OPTIMAL":
         prob.set_start(None, None)
+        prob.set_start_weight(0.0)
         info = prob.solve(tol, max_iters)
         fallback = True
     dt = time.perf_counter() - t0

@@ -252,8 +252,11 @@ def test_deterministic_and_graph_equals_stream(lpmod):
     assert np.array_equal(s1, s3)
 
 
-def test_warm_start_matches_oracle(lpmod, oracle_mod):
-    say("case warm start")
+@pytest.mark.parametrize("omega", [0.0, 0.37])
+def test_warm_start_matches_oracle(lpmod, oracle_mod, omega):
+    """Warm start (point, and with omega > 0 the primal weight) against the
+    oracle started the same way, inside the first check window."""
+    say(f"case warm start omega={omega}")
     data = gen.tiny_lp(8)
     rng = np.random.default_rng(3)
     xs = data.x0 + 0.1 * rng.standard_normal(data.n)
@@ -261,10 +264,14 @@ def test_warm_start_matches_oracle(lpmod, oracle_mod):
     p = lpmod.Problem(data)
     o = oracle_mod.Oracle(data)
     p.set_start(xs, ys)
+    p.set_start_weight(omega)
     o.set_start(xs, ys)
+    o.set_start_weight(omega)
     p.solve(1e-30, 60)
     o.solve(1e-30, 60)
     so = o.get_state()
+    if omega > 0:
+        assert so["omega"] == omega  # no restart yet: the weight is the one given
     o.set_start(xs, ys)
     o.solve(1e-30, 59)
     assert_states_close(gpu_state(lpmod, p), so, step_condition(o.get_state(), so), "warm")
