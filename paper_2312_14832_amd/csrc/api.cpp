@@ -38,16 +38,18 @@ int slices_for(int64_t bytes, int64_t slice_bytes)
 // Host side of a Sliced product: per-slice CSR (slice-major), the position
 // of every sliced entry in the source CSR, and the row blocks.
 struct HostSliced {
-    int S = 1, rows = 0, cols = 0;
+    int S = 1, rows = 0, cols = 0, nb = kStreamNB;
     std::vector<int> rp, ci, src, brow, boff;
     int max_blocks = 0;
 };
 
 // Rows of the source CSR must have their columns sorted, so that each
 // slice's part of a row is one contiguous run.
-void build_sliced(HostSliced &H, int rows, int cols, const std::vector<int> &rp, const std::vector<int> &ci, int S)
+void build_sliced(HostSliced &H, int rows, int cols, const std::vector<int> &rp, const std::vector<int> &ci, int S,
+                  int nb = kStreamNB)
 {
     H.S = S;
+    H.nb = nb;
     H.rows = rows;
     H.cols = cols;
     const int64_t nnz = rp[rows];
@@ -77,7 +79,7 @@ void build_sliced(HostSliced &H, int rows, int cols, const std::vector<int> &rp,
         r[rows] = (int)pos;
         H.brow.push_back(0);
         const size_t before = H.brow.size();
-        row_blocks(r, 0, rows, H.brow);
+        row_blocks(r, 0, rows, H.brow, H.nb);
         const int nb = (int)(H.brow.size() - before);
         H.boff[s + 1] = H.boff[s] + nb;
         H.max_blocks = std::max(H.max_blocks, nb);
@@ -253,23 +255,25 @@ float time_product(lp_problem *P, const Sliced<T> &q, T *in, T *out, int64_t in_
     return ms / reps;
 }
 
-// Autotuner for the column slicing of one product: times the default slice
-// count and its neighbours (halved, doubled) on the actual matrix and keeps
-// the fastest.
+// Autotuner for one product: times the default slice count, its neighbours
+// (halved, doubled) and smaller row blocks on the actual matrix and keeps
+// the fastest layout.
 template <typename T>
 Sliced<T> tuned_sliced(lp_problem *P, const HostSliced &H0, const std::vector<int> &rp, const std::vector<int> &ci,
                        const double *vals, T *in, T *out, int64_t in_len, std::vector<std::pair<int, float>> &log)
 {
     Sliced<T> best = upload_sliced<T>(P, H0, vals);
     float best_ms = time_product<T>(P, best, in, out, in_len);
-    log.emplace_back(H0.S, best_ms);
-    for (int S : {H0.S / 2, H0.S * 2}) {
+    log.emplace_back(H0.S * 100000 + H0.nb, best_ms);
+    const std::pair<int, int> cands[] = {{H0.S / 2, kStreamNB}, {H0.S * 2, kStreamNB}, {H0.S, kStreamNB / 2}};
+    for (const auto &cand : cands) {
+        const int S = cand.first, nb = cand.second;
         if (S < 1 || S > 32) continue;
         HostSliced H;
-        build_sliced(H, H0.rows, H0.cols, rp, ci, S);
+        build_sliced(H, H0.rows, H0.cols, rp, ci, S, nb);
         Sliced<T> q = upload_sliced<T>(P, H, vals);
         const float ms = time_product<T>(P, q, in, out, in_len);
-        log.emplace_back(S, ms);
+        log.emplace_back(S * 100000 + nb, ms);
         if (ms < best_ms) {
             free_sliced<T>(P, best);
             best = q;

@@ -428,6 +428,7 @@ __device__ __forceinline__ void stream_block(const int *__restrict__ rp, const i
 {
     const int b = rp[r0], e = rp[r1];
     const int cnt = e - b;
+    // a multi-row block never exceeds kStreamNB nonzeros, only a single row can
     if (cnt <= kStreamNB) {
 #pragma unroll 4
         for (int t = (int)threadIdx.x; t < cnt; t += kBlock) {
