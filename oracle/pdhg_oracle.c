@@ -57,6 +57,12 @@
 
 #define ORC_NSCALARS 16
 
+/* ORC_MUT (default 0) plants one known mistake, for the tests that check
+ * the pins catch it.  Never defined in the oracle the other tests use. */
+#ifndef ORC_MUT
+#define ORC_MUT 0
+#endif
+
 typedef struct {
     int ruiz_iters;     /* Ruiz rounds (10) */
     double pc_alpha;    /* Pock-Chambolle exponent (1); < 0 disables the round */
@@ -111,7 +117,7 @@ static double proj_lambda(double g, int lfin, int ufin)
 {
     if (!lfin && !ufin) return 0.0;            /* {0} */
     if (!lfin && ufin) return g < 0.0 ? g : 0.0;   /* R- */
-    if (lfin && !ufin) return g > 0.0 ? g : 0.0;   /* R+ */
+    if (lfin && !ufin) return ORC_MUT == 3 ? g : (g > 0.0 ? g : 0.0);   /* R+ */
     return g;                                  /* R */
 }
 
@@ -142,7 +148,7 @@ double orc_step_next(double eta, double eta_bar, int64_t k_accepted)
 {
     /* PDLP adaptive rule; kk counts steps from 1 */
     double kk = (double)(k_accepted + 1) + 1.0;
-    double a = (1.0 - pow(kk, -0.3)) * eta_bar;
+    double a = (1.0 - pow(kk, ORC_MUT == 5 ? -0.03 : -0.3)) * eta_bar;
     double b = (1.0 + pow(kk, -0.6)) * eta;
     return a < b ? a : b;
 }
@@ -213,7 +219,7 @@ static void scale_problem(orc_t *P)
                 int64_t j = P->ci[p];
                 if (!pc) {
                     if (a > r[i]) r[i] = a;
-                    if (a > s[j]) s[j] = a;
+                    if (ORC_MUT == 6 ? r[i] > s[j] : a > s[j]) s[j] = ORC_MUT == 6 ? r[i] : a;
                 } else {
                     r[i] += pow(a, 2.0 - P->o.pc_alpha);
                     s[j] += pow(a, P->o.pc_alpha);
@@ -355,7 +361,7 @@ static void eval_point(const orc_t *P, const double *x, const double *y, const d
         e->cx += P->cs[j] * x[j];
         double b = 0.0;
         if (lf && lam > 0.0) b += P->ls[j] * lam;
-        if (uf && lam < 0.0) b += P->us[j] * lam;   /* -u * lam-  with lam- = -lam */
+        if (uf && lam < 0.0) b += (ORC_MUT == 4 ? -1.0 : 1.0) * P->us[j] * lam;   /* -u * lam-  with lam- = -lam */
         e->bnd += b;
         double d = x[j] - P->x0[j];
         e->dx2 += d * d;
@@ -374,7 +380,7 @@ static void eval_point(const orc_t *P, const double *x, const double *y, const d
 
 static double kkt_omega(const orc_t *P, const orc_eval_t *e, double omega)
 {
-    double wp = pow(omega, P->o.kkt_p);
+    double wp = pow(omega, ORC_MUT == 8 ? 1.0 : P->o.kkt_p);
     return sqrt(wp * e->rp2_s + e->rd2_s / wp + e->gap * e->gap);
 }
 
@@ -439,10 +445,11 @@ static int pdhg_step(orc_t *P)
     for (;;) {
         double tau = eta / omega, sigma = eta * omega;
         for (int64_t j = 0; j < n; ++j)
-            P->xt[j] = clampx(P->x[j] - tau * (P->cs[j] - P->KTy[j]), P->ls[j], P->us[j]);
+            P->xt[j] = clampx(P->x[j] - tau * (P->cs[j] - (ORC_MUT == 1 ? -1.0 : 1.0) * P->KTy[j]), P->ls[j], P->us[j]);
         spmv_K(P, P->xt, P->Kxt);
         for (int64_t i = 0; i < m; ++i) {
-            double v = P->y[i] + sigma * (P->qs[i] - 2.0 * P->Kxt[i] + P->Kx[i]);
+            double v = ORC_MUT == 2 ? P->y[i] + sigma * (P->qs[i] - P->Kxt[i])
+                                    : P->y[i] + sigma * (P->qs[i] - 2.0 * P->Kxt[i] + P->Kx[i]);
             if (i >= P->m1 && v < 0.0) v = 0.0;
             P->yt[i] = v;
         }
@@ -475,7 +482,7 @@ static int pdhg_step(orc_t *P)
     spmv_KT(P, P->yt, P->KTyt);
     P->eta_last = eta;
     P->W += eta;
-    double w = eta / P->W;
+    double w = ORC_MUT == 7 ? 1.0 / (double)(P->t + 1) : eta / P->W;
     for (int64_t j = 0; j < n; ++j) {
         P->xa[j] += w * (P->xt[j] - P->xa[j]);
         P->KTya[j] += w * (P->KTyt[j] - P->KTya[j]);
@@ -655,6 +662,26 @@ int orc_set_state(orc_t *P, const double *buf)
     return ORC_OK;
 }
 
+/* KKT_omega of a point (x, y) of the scaled problem (restart criteria),
+ * with the anchor at the point itself. */
+double orc_kkt_omega(orc_t *P, const double *x, const double *y, double omega)
+{
+    double *Kx = xalloc(P->m, sizeof(double)), *KTy = xalloc(P->n, sizeof(double));
+    double *x0s = xalloc(P->n, sizeof(double)), *y0s = xalloc(P->m, sizeof(double));
+    spmv_K(P, x, Kx);
+    spmv_KT(P, y, KTy);
+    memcpy(x0s, P->x0, sizeof(double) * (size_t)P->n);
+    memcpy(y0s, P->y0, sizeof(double) * (size_t)P->m);
+    memcpy(P->x0, x, sizeof(double) * (size_t)P->n);
+    memcpy(P->y0, y, sizeof(double) * (size_t)P->m);
+    orc_eval_t e;
+    eval_point(P, x, y, Kx, KTy, &e);
+    memcpy(P->x0, x0s, sizeof(double) * (size_t)P->n);
+    memcpy(P->y0, y0s, sizeof(double) * (size_t)P->m);
+    free(Kx); free(KTy); free(x0s); free(y0s);
+    return kkt_omega(P, &e, omega);
+}
+
 int orc_get_scaling(const orc_t *P, double *Dr, double *Dc, double *kv)
 {
     if (!P) return ORC_ERR_ARG;
@@ -703,7 +730,7 @@ int orc_eval_unscaled(const orc_t *P, const double *x, const double *y, double *
         rd2 += rd * rd;
         cx += P->c[j] * x[j];
         if (lf && lam > 0.0) bnd += P->l[j] * lam;
-        if (uf && lam < 0.0) bnd += P->u[j] * lam;
+        if (uf && lam < 0.0) bnd += (ORC_MUT == 4 ? -1.0 : 1.0) * P->u[j] * lam;
         double lo = P->l[j] - x[j], hi = x[j] - P->u[j];
         if (lo > bviol) bviol = lo;
         if (hi > bviol) bviol = hi;

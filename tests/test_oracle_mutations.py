@@ -1,0 +1,52 @@
+"""The pins have teeth: the oracle is rebuilt with one planted mistake at a
+time (a flipped sign, a dropped term, a wrong exponent or index, a wrong
+averaging weight) and at least one pin must fail for each.  The planted
+builds live in a temporary directory and are used by this file only."""
+import pytest
+
+from oracle import build as obuild
+import test_oracle_pins as pins
+
+MUTATIONS = {
+    1: "primal step uses c + K'y",
+    2: "dual step drops the extrapolation (K x+ instead of K(2x+ - x))",
+    3: "Lambda = R+ case returns c - K'y unprojected",
+    4: "dual objective adds +u lam- instead of -u lam-",
+    5: "step-rule shrink exponent -0.03 instead of -0.3",
+    6: "Ruiz column factor taken from the row maxima",
+    7: "uniform instead of step-size weights in the averages",
+    8: "KKT_omega uses omega instead of omega^2",
+}
+
+CHECKS = [
+    ("two PDHG steps by hand", pins.check_two_steps_golden),
+    ("KKT_omega by hand", pins.check_kkt_omega_golden),
+    ("termination quantities by hand", pins.check_termination_golden),
+    ("scaling by hand", pins.check_scaling_golden),
+    ("step rule constants", pins.check_step_rule),
+    ("step-weighted averages", pins.check_step_weighted_averages),
+    ("vertex enumeration", lambda om, libpath=None: pins.check_vertex_objective(om, 11, 3, 1, 2, libpath,
+                                                                                  max_iters=200_000)),
+]
+
+
+@pytest.fixture(scope="module")
+def mutant_dir(tmp_path_factory):
+    return tmp_path_factory.mktemp("oracle_mutants")
+
+
+def test_pins_pass_on_the_oracle(oracle_mod):
+    for name, fn in CHECKS:
+        fn(oracle_mod)
+
+
+@pytest.mark.parametrize("mut", sorted(MUTATIONS))
+def test_pins_catch_planted_mistake(oracle_mod, mutant_dir, mut):
+    path = obuild.build(force=True, mutation=mut, out=str(mutant_dir / f"liborc_mut{mut}.so"))
+    caught = []
+    for name, fn in CHECKS:
+        try:
+            fn(oracle_mod, libpath=path)
+        except AssertionError:
+            caught.append(name)
+    assert caught, f"no pin fails with mistake {mut}: {MUTATIONS[mut]}"

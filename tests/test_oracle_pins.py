@@ -30,11 +30,15 @@ def test_objective_matches_highs(oracle_mod, seed):
 @pytest.mark.parametrize("seed,n,m1,m2", [(11, 3, 1, 2), (12, 4, 1, 3), (13, 4, 2, 2), (14, 5, 1, 3),
                                          (15, 5, 0, 4), (16, 3, 0, 3)])
 def test_objective_matches_vertex_enumeration(oracle_mod, seed, n, m1, m2):
+    check_vertex_objective(oracle_mod, seed, n, m1, m2)
+
+
+def check_vertex_objective(om, seed, n, m1, m2, libpath=None, max_iters=2_000_000):
     lp = gen.dense_small_lp(seed, n, m1, m2)
     Kd = lp.csr().toarray()
     best, _ = brute_force_vertices(Kd, lp.q, m1, lp.l, lp.u, lp.c)
-    o = oracle_mod.Oracle(lp)
-    _, _, _, info = o.solve(1e-9, 2_000_000)
+    o = om.Oracle(lp, libpath=libpath)
+    _, _, _, info = o.solve(1e-9, max_iters)
     assert info["status"] == "OPTIMAL"
     assert abs(info["pobj"] - best) <= 1e-6 * max(1.0, abs(best))
 
@@ -132,23 +136,96 @@ def test_pdhg_fixed_point_at_optimum(oracle_mod):
 
 # ---------------------------------------------------------------- pieces
 
+def _golden_lp(g):
+    return gen.from_dense(np.array(g["K"], float), g["c"], g["q"], [fnum(a) for a in g["l"]],
+                          [fnum(a) for a in g["u"]], g["m1"])
+
+
 def test_termination_quantities_hand_example(oracle_mod):
+    check_termination_golden(oracle_mod)
+
+
+def check_termination_golden(om, libpath=None):
     g = load_golden("termination_3var.json")
-    Kd = np.array(g["K"], float)
-    lp = gen.from_dense(Kd, g["c"], g["q"], [fnum(a) for a in g["l"]], [fnum(a) for a in g["u"]], g["m1"])
-    o = oracle_mod.Oracle(lp)
+    o = om.Oracle(_golden_lp(g), libpath=libpath)
     r = o.eval_unscaled(np.array(g["x"], float), np.array(g["y"], float))
     for key, val in g["expect"].items():
         assert r[key] == pytest.approx(val, rel=1e-14, abs=1e-15), key
 
 
+def test_kkt_omega_hand_example(oracle_mod):
+    check_kkt_omega_golden(oracle_mod)
+
+
+def check_kkt_omega_golden(om, libpath=None):
+    """KKT_omega (Sec. 2, restart criteria) of a hand-evaluated point at three
+    primal weights; one variable has Lambda = R+ with c - K'y < 0."""
+    g = load_golden("kkt_omega_3var.json")
+    o = om.Oracle(_golden_lp(g), ruiz_iters=0, pc_alpha=-1.0, libpath=libpath)
+    x, y = np.array(g["x"], float), np.array(g["y"], float)
+    for case in g["expect"]:
+        assert o.kkt_omega(x, y, case["omega"]) == pytest.approx(case["kkt"], rel=1e-14), case
+
+
+def test_two_pdhg_steps_hand_example(oracle_mod):
+    check_two_steps_golden(oracle_mod)
+
+
+def check_two_steps_golden(om, libpath=None):
+    """Two constant-size PDHG steps from a hand-chosen start (Sec. 2), with
+    active bounds on both sides and a clipped y_G; the averages and KKT0."""
+    g = load_golden("pdhg_two_steps_3var.json")
+    o = om.Oracle(_golden_lp(g), ruiz_iters=0, pc_alpha=-1.0, fixed_step=True, fixed_eta=g["eta"],
+                  libpath=libpath)
+    o.set_start(np.array(g["x_start"], float), np.array(g["y_start"], float))
+    o.set_start_weight(g["omega"])
+    e = g["expect"]
+    o.solve(1e-30, 1)
+    st = o.get_state()
+    assert np.array_equal(st["x"], e["x1"]) and np.array_equal(st["y"], e["y1"])
+    assert st["KKT0"] == pytest.approx(e["KKT0"], rel=1e-14)
+    o.solve(1e-30, 2)
+    st = o.get_state()
+    assert np.array_equal(st["x"], e["x2"]) and np.array_equal(st["y"], e["y2"])
+    assert np.array_equal(st["xbar"], e["xbar2"]) and np.array_equal(st["ybar"], e["ybar2"])
+    assert st["k"] == 2 and st["W"] == 2 * g["eta"] and st["omega"] == g["omega"]
+
+
+def test_averages_are_step_weighted(oracle_mod):
+    check_step_weighted_averages(oracle_mod)
+
+
+def check_step_weighted_averages(om, libpath=None):
+    """Under the adaptive rule the averages are sum(eta_k z_k)/sum(eta_k) over
+    the accepted iterates (Sec. 2); steps are taken one by one and the
+    weighted mean is formed here from the recorded iterates and step sizes."""
+    lp = gen.tiny_lp(9)
+    o = om.Oracle(lp, libpath=libpath)
+    xs, ys, etas = [], [], []
+    for k in range(1, 41):
+        o.solve(1e-30, k)
+        st = o.get_state()
+        assert st["k"] == k and st["restarts"] == 0
+        xs.append(st["x"].copy()); ys.append(st["y"].copy()); etas.append(st["eta_last"])
+    etas = np.array(etas)
+    assert etas.max() / etas.min() > 1.05          # the steps really differ
+    w = etas / etas.sum()
+    assert st["W"] == pytest.approx(etas.sum(), rel=1e-14)
+    assert np.allclose(st["xbar"], w @ np.array(xs), rtol=1e-12, atol=1e-14)
+    assert np.allclose(st["ybar"], w @ np.array(ys), rtol=1e-12, atol=1e-14)
+
+
 def test_scaling_hand_examples(oracle_mod):
+    check_scaling_golden(oracle_mod)
+
+
+def check_scaling_golden(om, libpath=None):
     g = load_golden("scaling_hand.json")
     for case in g["cases"]:
         Kd = np.array(case["K"], float)
         m, n = Kd.shape
         lp = gen.from_dense(Kd, np.ones(n), np.ones(m), np.zeros(n), np.full(n, np.inf), m)
-        o = oracle_mod.Oracle(lp, ruiz_iters=case["ruiz_iters"], pc_alpha=case["pc_alpha"])
+        o = om.Oracle(lp, ruiz_iters=case["ruiz_iters"], pc_alpha=case["pc_alpha"], libpath=libpath)
         Dr, Dc, kv = o.scaling()
         assert np.allclose(Dr, case["Dr"], rtol=1e-15, atol=0), case["name"]
         assert np.allclose(Dc, case["Dc"], rtol=1e-15, atol=0), case["name"]
@@ -211,14 +288,19 @@ def test_omega_update_is_smoothed_geometric_mean(oracle_mod, omega, dx, dy):
 
 
 def test_step_rule_constants(oracle_mod):
+    check_step_rule(oracle_mod)
+
+
+def check_step_rule(om, libpath=None):
     """PDLP adaptive rule: eta' = min((1-kk^-0.3) eta_bar, (1+kk^-0.6) eta), kk from 2."""
+    step_next = om.lib(libpath).orc_step_next
     lo0, hi0 = 1 - 2 ** -0.3, 1 + 2 ** -0.6
     assert lo0 == pytest.approx(0.18774760364376437, rel=1e-15)
-    assert oracle_mod.step_next(1.0, np.inf, 0) == pytest.approx(hi0, rel=1e-15)
-    assert oracle_mod.step_next(1.0, 1.0, 0) == pytest.approx(lo0, rel=1e-15)
+    assert step_next(1.0, np.inf, 0) == pytest.approx(hi0, rel=1e-15)
+    assert step_next(1.0, 1.0, 0) == pytest.approx(lo0, rel=1e-15)
     # as k grows the cap on growth shrinks to 1 and the shrink factor to 1
-    assert oracle_mod.step_next(1.0, np.inf, 10**8) == pytest.approx(1.0, abs=2e-5)
-    assert oracle_mod.step_next(1.0, 1.0, 10**8) == pytest.approx(1.0, abs=5e-3)
+    assert step_next(1.0, np.inf, 10**8) == pytest.approx(1.0, abs=2e-5)
+    assert step_next(1.0, 1.0, 10**8) == pytest.approx(1.0, abs=5e-3)
 
 
 # ---------------------------------------------------------------- invariants
