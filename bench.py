@@ -71,6 +71,79 @@ def counter_traffic(kernel, workload):
     return e.get("traffic_bytes")
 
 
+def _kernel_short(name):
+    base = name.split("(")[0]
+    if base.startswith("void "):
+        base = base[5:]
+    return base[len("pdlp::"):] if base.startswith("pdlp::") else base
+
+
+def _counter_avgs(db, counter):
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = con.execute("select kernel_name, count(*), avg(value) from counters_collection "
+                       "where counter_name = ? group by kernel_name", (counter,)).fetchall()
+    con.close()
+    return {_kernel_short(k): (cnt, avg) for k, cnt, avg in rows}
+
+
+def _durations(db):
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, count(*), avg(duration), sum(duration) from kernels group by name").fetchall()
+    con.close()
+    return {_kernel_short(k): (cnt, avg, tot) for k, cnt, avg, tot in rows}
+
+
+def traffic_from(dirpath, precision, workload, copy_bytes):
+    """Per-launch HBM traffic of the two fused SpMV kernel pairs from rocprofv3
+    FETCH_SIZE / WRITE_SIZE runs (KiB per dispatch), each scaled by what the
+    same counter reads for a device-to-device copy of `copy_bytes`; written to
+    profiles/traffic.json under the current kernel source hash.  Prints a
+    markdown summary of durations and counters."""
+    db = lambda sub: os.path.join(dirpath, sub, "run_results.db")
+    fetch, write = _counter_avgs(db("fetch"), "FETCH_SIZE"), _counter_avgs(db("write"), "WRITE_SIZE")
+    cf, cw = _counter_avgs(db("copy_fetch"), "FETCH_SIZE"), _counter_avgs(db("copy_write"), "WRITE_SIZE")
+    copy = "__amd_rocclr_copyBuffer"
+    ff = copy_bytes / (cf[copy][1] * 1024.0)
+    wf = copy_bytes / (cw[copy][1] * 1024.0)
+    stats = _durations(db("stats")) if os.path.exists(db("stats")) else {}
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    d = json.load(open(path)) if os.path.exists(path) else {}
+    d[workload] = {}
+    sha = kernel_source_sha()
+    lines = [f"copy calibration ({copy_bytes} B per copy): FETCH_SIZE x{ff:.4f}, WRITE_SIZE x{wf:.4f}", "",
+             "| kernel | launches | avg us | FETCH KiB | WRITE KiB | scaled MB/launch |", "|---|---|---|---|---|---|"]
+    def find(table, label):
+        # 'k_dual<double>' names every instantiation 'k_dual<double, S>'
+        stem = label[:-1]
+        hits = [k for k in table if k == label or k.startswith(stem + ",")]
+        assert len(hits) == 1, (label, hits)
+        return table[hits[0]], hits[0]
+
+    for pair in kernel_names(precision).values():
+        e = {"source_sha": sha, "fetch_factor": ff, "write_factor": wf, "parts": {}}
+        tot = 0.0
+        for k in pair.split("+"):
+            (_, fk), full = find(fetch, k)
+            (_, wk), _ = find(write, k)
+            b = fk * 1024.0 * ff + wk * 1024.0 * wf
+            tot += b
+            e["parts"][k] = {"fetch_kib": fk, "write_kib": wk, "traffic_bytes": b}
+            cnt, avg, _ = stats.get(full, (0, float("nan"), 0))
+            lines.append(f"| {full} | {cnt} | {avg / 1e3:.1f} | {fk:.0f} | {wk:.0f} | {b / 1e6:.0f} |")
+        e["traffic_bytes"] = tot
+        d[workload][pair] = e
+    with open(path, "w") as f:
+        json.dump(d, f, indent=1)
+        f.write("\n")
+    if stats:
+        lines += ["", "| kernel (all) | launches | avg us | total ms |", "|---|---|---|---|"]
+        for k, (cnt, avg, tot) in sorted(stats.items(), key=lambda kv: -kv[1][2])[:12]:
+            lines.append(f"| {k} | {cnt} | {avg / 1e3:.1f} | {tot / 1e6:.2f} |")
+    print("\n".join(lines))
+
+
 def cpu_baseline(data, iters):
     from oracle.oracle import Oracle
     o = Oracle(data)
@@ -104,7 +177,14 @@ def main():
                     help="batch workload: instances solved one by one for the sequential comparison")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run 5 plain device-to-device copies of this many MiB (counter calibration)")
+    ap.add_argument("--traffic-from", default=None,
+                    help="no GPU: read rocprofv3 databases under DIR/{stats,fetch,write,copy_fetch,copy_write} "
+                         "and write profiles/traffic.json for the default workload")
+    ap.add_argument("--copy-mib", type=int, default=1024, help="size of the calibration copy for --traffic-from")
     args = ap.parse_args()
+    if args.traffic_from:
+        wl = f"large_powerlaw_lp_n{args.n}" + ("" if args.precision == "fp64" else "_mixed")
+        return traffic_from(args.traffic_from, args.precision, wl, args.copy_mib << 20)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               f"(the multi-GPU sharding is a design, not part of this build)", file=sys.stderr)
@@ -174,6 +254,8 @@ def main():
           file=sys.stderr, flush=True)
 
     prob_layout = prob.layout()
+    blocks = {name: dict(zip(("slices", "nnz_per_block", "rows_per_block"), prob.layout_blocks(w)))
+              for w, name in ((0, "K"), (1, "KT"))}
     ttt = None
     if not args.no_ttt:
         t0 = time.perf_counter()
@@ -208,7 +290,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload, "n": n, "m1": m1, "m2": m2, "nnz": data.nnz, "seed": args.seed,
                    "precision": args.precision, "iters_per_step": ITERS_PER_STEP,
-                   "column_slices": list(prob_layout),
+                   "column_slices": list(prob_layout), "row_blocks": blocks,
                    "generator": "power-law column counts 1..200 (mean 10), N(0,1)*10^U(-3,3) per row, "
                                 "certificate-feasible"},
         "roofline": roofline,

@@ -167,6 +167,12 @@ int lp_device_bytes(const lp_problem *P, int64_t *bytes);
 /* Column slices chosen for K (over x) and K' (over y); either may be NULL. */
 int lp_layout(const lp_problem *P, int *slices_K, int *slices_KT);
 
+/* The full layout of one product (which = 0: K, 1: K'): column slices, the
+ * most nonzeros and the most rows of one row block (a single longer row
+ * forms a block of its own).  Any output may be NULL; LP_ERR_ARG for a bad
+ * `which`. */
+int lp_layout_blocks(const lp_problem *P, int which, int *slices, int *nnz_per_block, int *rows_per_block);
+
 void lp_free(lp_problem *P);
 
 /* ------------------------------------------------------------------------

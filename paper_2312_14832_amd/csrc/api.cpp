@@ -38,7 +38,7 @@ int slices_for(int64_t bytes, int64_t slice_bytes)
 // Host side of a Sliced product: per-slice CSR (slice-major), the position
 // of every sliced entry in the source CSR, and the row blocks.
 struct HostSliced {
-    int S = 1, rows = 0, cols = 0, nb = kStreamNB;
+    int S = 1, rows = 0, cols = 0, nb = kStreamNB, rb = kStreamRB;
     std::vector<int> rp, ci, src, brow, boff;
     int max_blocks = 0;
 };
@@ -46,10 +46,11 @@ struct HostSliced {
 // Rows of the source CSR must have their columns sorted, so that each
 // slice's part of a row is one contiguous run.
 void build_sliced(HostSliced &H, int rows, int cols, const std::vector<int> &rp, const std::vector<int> &ci, int S,
-                  int nb = kStreamNB)
+                  int nb = kStreamNB, int rb = kStreamRB)
 {
     H.S = S;
     H.nb = nb;
+    H.rb = rb;
     H.rows = rows;
     H.cols = cols;
     const int64_t nnz = rp[rows];
@@ -79,12 +80,17 @@ void build_sliced(HostSliced &H, int rows, int cols, const std::vector<int> &rp,
         r[rows] = (int)pos;
         H.brow.push_back(0);
         const size_t before = H.brow.size();
-        row_blocks(r, 0, rows, H.brow, H.nb);
+        row_blocks(r, 0, rows, H.brow, H.nb, H.rb);
         const int nb = (int)(H.brow.size() - before);
         H.boff[s + 1] = H.boff[s] + nb;
         H.max_blocks = std::max(H.max_blocks, nb);
     }
 }
+
+struct TuneTrial {
+    int S, nb, rb;
+    float ms;
+};
 
 // workgroups of a partial pass: enough for every row block of the busiest
 // slice, a multiple of 8 (XCDs) and of S, at most 4096
@@ -125,7 +131,8 @@ struct lp_problem {
     bool graph_timed = false, graph_events_failed = false;
     bool own_stream = false;
     int slices_K = 1, slices_KT = 1;
-    std::vector<std::pair<int, float>> tune_log_K, tune_log_KT;   // (slices, ms) tried by the autotuner
+    int shape_K[3] = {1, kStreamNB, kStreamRB}, shape_KT[3] = {1, kStreamNB, kStreamRB};  // S, nnz, rows per block
+    std::vector<TuneTrial> tune_log_K, tune_log_KT;   // layouts tried by the autotuner
     std::vector<hipEvent_t> ev;
     int64_t t_count[2] = {0, 0};
     double t_ms[2] = {0, 0};
@@ -255,33 +262,40 @@ float time_product(lp_problem *P, const Sliced<T> &q, T *in, T *out, int64_t in_
     return ms / reps;
 }
 
-// Autotuner for one product: times the default slice count, its neighbours
-// (halved, doubled) and smaller row blocks on the actual matrix and keeps
-// the fastest layout.
+// Autotuner for one product: times the default layout, its neighbours in
+// slice count (halved, doubled), in nonzeros per row block (halved) and in
+// rows per row block (256) on the actual matrix and keeps the fastest.
 template <typename T>
 Sliced<T> tuned_sliced(lp_problem *P, const HostSliced &H0, const std::vector<int> &rp, const std::vector<int> &ci,
-                       const double *vals, T *in, T *out, int64_t in_len, std::vector<std::pair<int, float>> &log)
+                       const double *vals, T *in, T *out, int64_t in_len, std::vector<TuneTrial> &log, int *shape)
 {
     Sliced<T> best = upload_sliced<T>(P, H0, vals);
     float best_ms = time_product<T>(P, best, in, out, in_len);
-    log.emplace_back(H0.S * 100000 + H0.nb, best_ms);
-    const std::pair<int, int> cands[] = {{H0.S / 2, kStreamNB}, {H0.S * 2, kStreamNB}, {H0.S, kStreamNB / 2}};
+    log.push_back({H0.S, H0.nb, H0.rb, best_ms});
+    shape[0] = H0.S; shape[1] = H0.nb; shape[2] = H0.rb;
+    const int cands[][3] = {{H0.S / 2, H0.nb, H0.rb}, {H0.S * 2, H0.nb, H0.rb}, {H0.S, H0.nb / 2, H0.rb},
+                            {H0.S, H0.nb, 256}};
     for (const auto &cand : cands) {
-        const int S = cand.first, nb = cand.second;
-        if (S < 1 || S > 32) continue;
+        const int S = cand[0], nb = cand[1], rb = cand[2];
+        if (S < 1 || S > 32 || (S == H0.S && nb == H0.nb && rb == H0.rb)) continue;
         HostSliced H;
-        build_sliced(H, H0.rows, H0.cols, rp, ci, S, nb);
+        build_sliced(H, H0.rows, H0.cols, rp, ci, S, nb, rb);
         Sliced<T> q = upload_sliced<T>(P, H, vals);
         const float ms = time_product<T>(P, q, in, out, in_len);
-        log.emplace_back(S * 100000 + nb, ms);
+        log.push_back({S, nb, rb, ms});
         if (ms < best_ms) {
             free_sliced<T>(P, best);
             best = q;
             best_ms = ms;
+            shape[0] = S; shape[1] = nb; shape[2] = rb;
         } else {
             free_sliced<T>(P, q);
         }
     }
+    if (P->opt.verbose)
+        for (const auto &t : log)
+            std::fprintf(stderr, "[lp] layout %s S=%d nnz/block=%d rows/block=%d: %.3f ms\n",
+                         &log == &P->tune_log_K ? "K" : "K'", t.S, t.nb, t.rb, t.ms);
     return best;
 }
 
@@ -301,11 +315,13 @@ void setup_typed(lp_problem *P, const HostSliced &HK, const HostSliced &HT, cons
     P->tmp_n = tvec(n);
     P->tmp_m = tvec(m);
     if (P->opt.autotune) {
-        d.K = tuned_sliced<T>(P, HK, rp, ci, kv64, (T *)P->tmp_n, (T *)P->tmp_m, n, P->tune_log_K);
-        d.KT = tuned_sliced<T>(P, HT, tp, ti, tv64, (T *)P->tmp_m, (T *)P->tmp_n, m, P->tune_log_KT);
+        d.K = tuned_sliced<T>(P, HK, rp, ci, kv64, (T *)P->tmp_n, (T *)P->tmp_m, n, P->tune_log_K, P->shape_K);
+        d.KT = tuned_sliced<T>(P, HT, tp, ti, tv64, (T *)P->tmp_m, (T *)P->tmp_n, m, P->tune_log_KT, P->shape_KT);
     } else {
         d.K = upload_sliced<T>(P, HK, kv64);
         d.KT = upload_sliced<T>(P, HT, tv64);
+        P->shape_K[0] = HK.S; P->shape_K[1] = HK.nb; P->shape_K[2] = HK.rb;
+        P->shape_KT[0] = HT.S; P->shape_KT[1] = HT.nb; P->shape_KT[2] = HT.rb;
     }
     P->slices_K = d.K.S;
     P->slices_KT = d.KT.S;
@@ -952,6 +968,16 @@ int lp_layout(const lp_problem *P, int *slices_K, int *slices_KT)
     if (!P) return LP_ERR_ARG;
     if (slices_K) *slices_K = P->slices_K;
     if (slices_KT) *slices_KT = P->slices_KT;
+    return LP_OK;
+}
+
+int lp_layout_blocks(const lp_problem *P, int which, int *slices, int *nnz_per_block, int *rows_per_block)
+{
+    if (!P || (which != 0 && which != 1)) return LP_ERR_ARG;
+    const int *s = which ? P->shape_KT : P->shape_K;
+    if (slices) *slices = s[0];
+    if (nnz_per_block) *nnz_per_block = s[1];
+    if (rows_per_block) *rows_per_block = s[2];
     return LP_OK;
 }
 

@@ -106,13 +106,25 @@ __device__ __forceinline__ void block_sum_partials(const double *part, int np, d
 // column-sliced CSR-Stream partial products
 // ----------------------------------------------------------------------------
 
-// row i of the product: the slices' partials added in slice order
-template <typename T>
+// row i of the product: the slices' partials added in slice order.  With
+// the slice count NS known at compile time every load is issued before the
+// first add; NS = 0 reads the count at run time.
+template <int NS, typename T>
 __device__ __forceinline__ T sum_slices(const Sliced<T> &P, int i)
 {
-    T a = P.part[i];
-    for (int s = 1; s < P.S; ++s) a += P.part[(size_t)s * P.rows + i];
-    return a;
+    if constexpr (NS > 0) {
+        T p[NS];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) p[s] = P.part[(size_t)s * P.rows + i];
+        T a = p[0];
+#pragma unroll
+        for (int s = 1; s < NS; ++s) a += p[s];
+        return a;
+    } else {
+        T a = P.part[i];
+        for (int s = 1; s < P.S; ++s) a += P.part[(size_t)s * P.rows + i];
+        return a;
+    }
 }
 
 // ----------------------------------------------------------------------------
@@ -430,15 +442,30 @@ __device__ __forceinline__ void stream_block(const int *__restrict__ rp, const i
     const int cnt = e - b;
     // a multi-row block never exceeds kStreamNB nonzeros, only a single row can
     if (cnt <= kStreamNB) {
-#pragma unroll 4
-        for (int t = (int)threadIdx.x; t < cnt; t += kBlock) {
-            const int col = __builtin_nontemporal_load(ci + b + t);
-            const T a = __builtin_nontemporal_load(v + b + t);
-            prod[t] = a * x[col];
+        // Three straight-line phases so that a thread's loads overlap: every
+        // value and column it owns, then every gather, then the products.
+        // Slots past the block's end re-read its last entry (same cache
+        // line) rather than branch, which would serialise the gathers.
+        constexpr int U = kStreamNB / kBlock;
+        if (cnt > 0) {
+            int col[U];
+            T a[U], g[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = min((int)threadIdx.x + u * kBlock, cnt - 1);
+                col[u] = __builtin_nontemporal_load(ci + b + t);
+                a[u] = __builtin_nontemporal_load(v + b + t);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) g[u] = x[col[u]];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int t = (int)threadIdx.x + u * kBlock;
+                if (t < cnt) prod[t] = a[u] * g[u];
+            }
         }
         __syncthreads();
-        const int r = r0 + (int)threadIdx.x;
-        if (r < r1) {
+        for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) {
             T acc = T(0);
             const int je = rp[r + 1] - b;
             for (int j = rp[r] - b; j < je; ++j) acc += prod[j];

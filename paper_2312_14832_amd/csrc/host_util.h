@@ -91,6 +91,7 @@ void transpose_csr(int rows, int cols, const std::vector<int> &rp, const std::ve
 // CSR-Stream row blocks of rows [r_begin, r_end): at most kStreamRB rows and
 // nb_max (<= kStreamNB) nonzeros each (a longer single row is a block of its
 // own).  Appends block end rows to `ends` (the first block starts at r_begin).
-void row_blocks(const int *rp, int r_begin, int r_end, std::vector<int> &ends, int nb_max = kStreamNB);
+void row_blocks(const int *rp, int r_begin, int r_end, std::vector<int> &ends, int nb_max = kStreamNB,
+                int rb_max = kStreamRB);
 
 }  // namespace pdlp

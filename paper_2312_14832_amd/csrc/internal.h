@@ -13,7 +13,7 @@ constexpr int kMaxGrid = 2048;   // workgroups of an elementwise solver kernel =
 constexpr int kCheckSums = 18;   // 9 sums for the current and 9 for the averaged iterate
 constexpr int kXcds = 8;         // MI355X: 8 XCDs, workgroups dealt to them round-robin
 constexpr int kStreamNB = 2048;  // nonzeros staged in LDS per row block
-constexpr int kStreamRB = 256;   // rows per row block (one thread per row in the row sums)
+constexpr int kStreamRB = 1024;  // most rows per row block (each thread sums every 256th row)
 
 // One sparse product y = A x split by COLUMNS into S contiguous slices.  The
 // slice of x a workgroup gathers from is small enough to stay in one XCD's

@@ -53,7 +53,7 @@ __global__ __launch_bounds__(kBlock) void k_partial_KT(Dev<T> d)
     sliced_partial(d.KT, (const T *)pick(d.yb, ctl->cur));
 }
 
-template <typename T>
+template <typename T, int NS>
 __global__ __launch_bounds__(kBlock) void k_dual(Dev<T> d, int vb_m)
 {
     const Ctl *ctl = d.ctl;
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(kBlock) void k_dual(Dev<T> d, int vb_m)
     DualEpi<T> epi{pick(d.yb, c), pick(d.Kxb, c), d.qs, pick(d.yb, c ^ 1), pick(d.Kxb, c ^ 1), d.m1, sigma, 0.0, 0.0};
     for (int vb = blockIdx.x; vb < vb_m; vb += gridDim.x) {
         const int i = vb * kBlock + (int)threadIdx.x;
-        if (i < d.m) epi(i, sum_slices(d.K, i));
+        if (i < d.m) epi(i, sum_slices<NS>(d.K, i));
     }
     double v[2] = {epi.dy2, epi.inter};
     block_store_partials<2>(v, d.part_dual);
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(kBlock) void k_step_decide(Ctl *ctl, const double *
     step_decision(ctl, a[0], b[0], b[1]);
 }
 
-template <typename T>
+template <typename T, int NS>
 __global__ __launch_bounds__(kBlock) void k_update(Dev<T> d, int vb_n, int vb_m)
 {
     const Ctl *ctl = d.ctl;
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_update(Dev<T> d, int vb_n, int vb_m)
         for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
             if (vb < vb_n) {
                 const int j = vb * kBlock + (int)threadIdx.x;
-                if (j < d.n) epi(j, sum_slices(d.KT, j));
+                if (j < d.n) epi(j, sum_slices<NS>(d.KT, j));
             } else {
                 const int i = (vb - vb_n) * kBlock + (int)threadIdx.x;
                 if (i < d.m) average_row(d, i, c, epi.w);
@@ -174,7 +174,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_sum_slices(Sliced<T> P, T *__restrict__ out)
 {
     const int i = blockIdx.x * kBlock + (int)threadIdx.x;
-    if (i < P.rows) out[i] = sum_slices(P, i);
+    if (i < P.rows) out[i] = sum_slices<0>(P, i);
 }
 
 // values into the sliced layout: dst[p] = src_vals[src_pos[p]]
@@ -359,7 +359,14 @@ hipError_t launch_partial_KT(const Dev<T> &d, hipStream_t s)
 template <typename T>
 hipError_t launch_dual(const Dev<T> &d, const Geo &g, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_dual<T>, dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_m);
+    switch (d.K.S) {
+    case 1: hipLaunchKernelGGL((k_dual<T, 1>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_m); break;
+    case 2: hipLaunchKernelGGL((k_dual<T, 2>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_m); break;
+    case 4: hipLaunchKernelGGL((k_dual<T, 4>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_m); break;
+    case 8: hipLaunchKernelGGL((k_dual<T, 8>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_m); break;
+    case 16: hipLaunchKernelGGL((k_dual<T, 16>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_m); break;
+    default: hipLaunchKernelGGL((k_dual<T, 0>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_m); break;
+    }
     return hipGetLastError();
 }
 
@@ -374,7 +381,14 @@ hipError_t launch_step_decide(const Dev<T> &d, const Geo &g, hipStream_t s)
 template <typename T>
 hipError_t launch_update(const Dev<T> &d, const Geo &g, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_update<T>, dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_n, g.vb_m);
+    switch (d.KT.S) {
+    case 1: hipLaunchKernelGGL((k_update<T, 1>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_n, g.vb_m); break;
+    case 2: hipLaunchKernelGGL((k_update<T, 2>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_n, g.vb_m); break;
+    case 4: hipLaunchKernelGGL((k_update<T, 4>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_n, g.vb_m); break;
+    case 8: hipLaunchKernelGGL((k_update<T, 8>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_n, g.vb_m); break;
+    case 16: hipLaunchKernelGGL((k_update<T, 16>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_n, g.vb_m); break;
+    default: hipLaunchKernelGGL((k_update<T, 0>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_n, g.vb_m); break;
+    }
     return hipGetLastError();
 }
 

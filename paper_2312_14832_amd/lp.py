@@ -22,7 +22,8 @@ NSCALARS = 16
 
 # every symbol include/lp.h declares
 EXPORTS = ["lp_default_options", "lp_load", "lp_set_start", "lp_set_start_weight", "lp_solve", "lp_result", "lp_get_state",
-           "lp_set_state", "lp_get_scaling", "lp_spmv", "lp_kernel_time", "lp_device_bytes", "lp_layout", "lp_free",
+           "lp_set_state", "lp_get_scaling", "lp_spmv", "lp_kernel_time", "lp_device_bytes", "lp_layout",
+           "lp_layout_blocks", "lp_free",
            "lp_strerror", "lp_last_error", "lp_batch_load", "lp_batch_solve", "lp_batch_result",
            "lp_batch_get_state", "lp_batch_set_state", "lp_batch_device_bytes", "lp_batch_free",
            "lp_batch_last_error"]
@@ -75,6 +76,8 @@ def library():
         L.lp_kernel_time.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.lp_device_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
         L.lp_layout.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.lp_layout_blocks.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                       C.POINTER(C.c_int)]
         L.lp_free.argtypes = [C.c_void_p]
         L.lp_free.restype = None
         L.lp_strerror.argtypes = [C.c_int]
@@ -211,6 +214,12 @@ class Problem:
         a = C.c_int(); b = C.c_int()
         self._check(library().lp_layout(self.h, C.byref(a), C.byref(b)))
         return a.value, b.value
+
+    def layout_blocks(self, which):
+        """(slices, most nonzeros, most rows) of one row block of K (0) or K' (1)."""
+        s, nb, rb = C.c_int(), C.c_int(), C.c_int()
+        self._check(library().lp_layout_blocks(self.h, which, C.byref(s), C.byref(nb), C.byref(rb)))
+        return s.value, nb.value, rb.value
 
     def device_bytes(self):
         b = C.c_int64()
