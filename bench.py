@@ -175,6 +175,9 @@ def main():
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--seq-sample", type=int, default=32,
                     help="batch workload: instances solved one by one for the sequential comparison")
+    ap.add_argument("--kernel-timing", type=int, default=1, choices=[0, 1],
+                    help="1: HIP events around the two fused products in the timed region (roofline); "
+                         "0: no events (the window runs as one captured graph)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run 5 plain device-to-device copies of this many MiB (counter calibration)")
     ap.add_argument("--traffic-from", default=None,
@@ -217,7 +220,7 @@ def main():
 
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
-    prob = lp.Problem(data, precision=args.precision, stream=stream, kernel_timing=1, autotune=1)
+    prob = lp.Problem(data, precision=args.precision, stream=stream, kernel_timing=args.kernel_timing, autotune=1)
     torch.cuda.synchronize()
     load_s = time.perf_counter() - t0
     print(f"[bench] loaded in {load_s:.1f}s ({prob.device_bytes() / 2**30:.2f} GiB on device), "
@@ -250,7 +253,7 @@ def main():
                 "frac": d["GB_s"] / HBM_PEAK_GBS if d["GB_s"] else None,
                 "traffic": counter_traffic(dom, workload), "alg_bytes_per_launch": d["alg_bytes"]}
     print(f"[bench] {K} windows in {dt:.3f}s -> {iters / dt:.0f} it/s; "
-          + "; ".join(f"{k} {v['avg_us']:.1f}us {v['GB_s']:.0f}GB/s" for k, v in spmv.items()),
+          + "; ".join(f"{k} {v['avg_us']:.1f}us {v['GB_s'] or 0:.0f}GB/s" for k, v in spmv.items()),
           file=sys.stderr, flush=True)
 
     prob_layout = prob.layout()

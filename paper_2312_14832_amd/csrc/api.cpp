@@ -609,15 +609,34 @@ int do_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit)
         get_ctl(P, d.ctl);
         if (timed && !P->hctl->done) {
             // every slot of a window that ended unfinished did real work
-            for (int s = 0; s < W; ++s) {
+            double ta = 0.0, tb = 0.0;
+            bool read = true;
+            for (int s = 0; s < W && read; ++s) {
                 float a = 0, b = 0;
-                HIPT(hipEventElapsedTime(&a, P->ev[4 * s + 0], P->ev[4 * s + 1]));
-                HIPT(hipEventElapsedTime(&b, P->ev[4 * s + 2], P->ev[4 * s + 3]));
-                P->t_ms[0] += a;
-                P->t_ms[1] += b;
+                const hipError_t ea = hipEventElapsedTime(&a, P->ev[4 * s + 0], P->ev[4 * s + 1]);
+                const hipError_t eb = hipEventElapsedTime(&b, P->ev[4 * s + 2], P->ev[4 * s + 3]);
+                if (ea != hipSuccess || eb != hipSuccess) {
+                    // events recorded by graph nodes carry no timestamps on
+                    // this runtime: time the next windows with plain launches
+                    (void)hipGetLastError();
+                    if (!use_graph) HIPT(ea != hipSuccess ? ea : eb);
+                    read = false;
+                    break;
+                }
+                ta += a;
+                tb += b;
             }
-            P->t_count[0] += W;
-            P->t_count[1] += W;
+            if (read) {
+                P->t_ms[0] += ta;
+                P->t_ms[1] += tb;
+                P->t_count[0] += W;
+                P->t_count[1] += W;
+            } else {
+                P->graph_events_failed = true;
+                (void)hipGraphExecDestroy(P->graph);
+                P->graph = nullptr;
+                use_graph = false;
+            }
         }
         (void)k_before;
         if (P->hctl->done) break;
