@@ -51,7 +51,7 @@ def kernel_bytes(which, n, m, nnz, s=8):
 
 def kernel_source_sha():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "internal.h"):
+    for f in ("kernels.hip", "device.h", "internal.h"):
         with open(os.path.join(ROOT, "paper_2312_14832_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -129,7 +129,7 @@ def traffic_from(dirpath, precision, workload, copy_bytes):
             (_, wk), _ = find(write, k)
             b = fk * 1024.0 * ff + wk * 1024.0 * wf
             tot += b
-            e["parts"][k] = {"fetch_kib": fk, "write_kib": wk, "traffic_bytes": b}
+            e["parts"][full] = {"fetch_kib": fk, "write_kib": wk, "traffic_bytes": b}
             cnt, avg, _ = stats.get(full, (0, float("nan"), 0))
             lines.append(f"| {full} | {cnt} | {avg / 1e3:.1f} | {fk:.0f} | {wk:.0f} | {b / 1e6:.0f} |")
         e["traffic_bytes"] = tot
@@ -178,6 +178,8 @@ def main():
     ap.add_argument("--kernel-timing", type=int, default=1, choices=[0, 1],
                     help="1: HIP events around the two fused products in the timed region (roofline); "
                          "0: no events (the window runs as one captured graph)")
+    ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
+                    help="1: time neighbouring layouts at load and keep the fastest; 0: the default layout")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run 5 plain device-to-device copies of this many MiB (counter calibration)")
     ap.add_argument("--traffic-from", default=None,
@@ -220,7 +222,8 @@ def main():
 
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
-    prob = lp.Problem(data, precision=args.precision, stream=stream, kernel_timing=args.kernel_timing, autotune=1)
+    prob = lp.Problem(data, precision=args.precision, stream=stream, kernel_timing=args.kernel_timing,
+                      autotune=args.autotune)
     torch.cuda.synchronize()
     load_s = time.perf_counter() - t0
     print(f"[bench] loaded in {load_s:.1f}s ({prob.device_bytes() / 2**30:.2f} GiB on device), "
@@ -245,7 +248,9 @@ def main():
         avg_us = 1e3 * ms / max(cnt, 1)
         b = kernel_bytes(w, n, m1 + m2, data.nnz, s)
         spmv[kernel_names(args.precision)[w]] = {"launches": cnt, "avg_us": avg_us, "alg_bytes": b,
-                                 "GB_s": b / (avg_us * 1e-6) / 1e9 if avg_us > 0 else None}
+                                 "GB_s": b / (avg_us * 1e-6) / 1e9 if avg_us > 0 else None,
+                                 "gathers": data.nnz,
+                                 "G_gathers_s": data.nnz / (avg_us * 1e-6) / 1e9 if avg_us > 0 else None}
     dom = max(spmv, key=lambda k: spmv[k]["avg_us"] * spmv[k]["launches"])
     d = spmv[dom]
     workload = f"large_powerlaw_lp_n{n}" + ("" if args.precision == "fp64" else "_mixed")

@@ -40,6 +40,7 @@ int slices_for(int64_t bytes, int64_t slice_bytes)
 struct HostSliced {
     int S = 1, rows = 0, cols = 0, nb = kStreamNB, rb = kStreamRB;
     std::vector<int> rp, ci, src, brow, boff;
+    std::vector<int4> blk;   // per row block: first row, end row, first entry, end entry
     int max_blocks = 0;
 };
 
@@ -58,6 +59,7 @@ void build_sliced(HostSliced &H, int rows, int cols, const std::vector<int> &rp,
     H.ci.resize((size_t)std::max<int64_t>(nnz, 1));
     H.src.resize((size_t)std::max<int64_t>(nnz, 1));
     H.brow.clear();
+    H.blk.clear();
     H.boff.assign(S + 1, 0);
     std::vector<int> cur(rp.begin(), rp.end() - 1);
     int64_t pos = 0;
@@ -82,6 +84,10 @@ void build_sliced(HostSliced &H, int rows, int cols, const std::vector<int> &rp,
         const size_t before = H.brow.size();
         row_blocks(r, 0, rows, H.brow, H.nb, H.rb);
         const int nb = (int)(H.brow.size() - before);
+        for (int k = 0; k < nb; ++k) {
+            const int r0 = H.brow[before - 1 + k], r1 = H.brow[before + k];
+            H.blk.push_back(make_int4(r0, r1, r[r0], r[r1]));
+        }
         H.boff[s + 1] = H.boff[s] + nb;
         H.max_blocks = std::max(H.max_blocks, nb);
     }
@@ -214,27 +220,27 @@ Sliced<T> upload_sliced(lp_problem *P, const HostSliced &H, const double *scaled
     q.grid = partial_grid(H.S, H.max_blocks);
     int *rp = (int *)P->dalloc(sizeof(int) * H.rp.size());
     int *ci = (int *)P->dalloc(sizeof(int) * (size_t)std::max<int64_t>(nnz, 1));
-    int *brow = (int *)P->dalloc(sizeof(int) * H.brow.size());
+    int4 *blk = (int4 *)P->dalloc(sizeof(int4) * std::max<size_t>(H.blk.size(), 1));
     int *boff = (int *)P->dalloc(sizeof(int) * H.boff.size());
     T *v = (T *)P->dalloc(sizeof(T) * (size_t)std::max<int64_t>(nnz, 1));
     T *part = (T *)P->dalloc(sizeof(T) * (size_t)H.S * (size_t)std::max(H.rows, 1));
     int *src = (int *)P->dalloc(sizeof(int) * (size_t)std::max<int64_t>(nnz, 1));
     upload(P, rp, H.rp.data(), (int64_t)H.rp.size());
     upload(P, ci, H.ci.data(), nnz);
-    upload(P, brow, H.brow.data(), (int64_t)H.brow.size());
+    upload(P, blk, H.blk.data(), (int64_t)H.blk.size());
     upload(P, boff, H.boff.data(), (int64_t)H.boff.size());
     upload(P, src, H.src.data(), nnz);
     HIPT(launch_gather_values<T>(scaled_csr_vals, src, v, nnz, P->stream));
     sync(P);
     P->dfree(src);
-    q.rp = rp; q.ci = ci; q.brow = brow; q.boff = boff; q.v = v; q.part = part;
+    q.rp = rp; q.ci = ci; q.blk = blk; q.boff = boff; q.v = v; q.part = part;
     return q;
 }
 
 template <typename T>
 void free_sliced(lp_problem *P, Sliced<T> &q)
 {
-    for (const void *p : {(const void *)q.rp, (const void *)q.ci, (const void *)q.brow, (const void *)q.boff,
+    for (const void *p : {(const void *)q.rp, (const void *)q.ci, (const void *)q.blk, (const void *)q.boff,
                           (const void *)q.v, (const void *)q.part})
         P->dfree(const_cast<void *>(p));
     q = Sliced<T>{};

@@ -23,11 +23,11 @@ __global__ __launch_bounds__(kBlock) void bk_product(BDev<T> b)
         const Ctl *c = b.ctl + L.inst[blk];
         if (c->done || (WHICH == 1 && !c->accepted)) continue;
         if (WHICH == 0)
-            stream_block(b.krp, b.kci, b.kv, (const T *)pick(b.d.xb, c->cur ^ 1), L.r0[blk], L.r1[blk], b.prodK, prod,
-                         red);
+            stream_block(b.krp, b.kci, b.kv, (const T *)pick(b.d.xb, c->cur ^ 1), L.r0[blk], L.r1[blk],
+                         b.krp[L.r0[blk]], b.krp[L.r1[blk]], b.prodK, prod, red);
         else
-            stream_block(b.trp, b.tci, b.tv, (const T *)pick(b.d.yb, c->cur), L.r0[blk], L.r1[blk], b.prodKT, prod,
-                         red);
+            stream_block(b.trp, b.tci, b.tv, (const T *)pick(b.d.yb, c->cur), L.r0[blk], L.r1[blk],
+                         b.trp[L.r0[blk]], b.trp[L.r1[blk]], b.prodKT, prod, red);
     }
 }
 
@@ -41,8 +41,12 @@ __global__ __launch_bounds__(kBlock) void bk_product_plain(BDev<T> b, const T *_
     const int per = (int)gridDim.x / kXcds;
     for (int k = L.xoff[xcd] + (int)blockIdx.x / kXcds; k < L.xoff[xcd + 1]; k += per) {
         const int blk = L.order[k];
-        if (WHICH == 0) stream_block(b.krp, b.kci, b.kv, in, L.r0[blk], L.r1[blk], out, prod, red);
-        else stream_block(b.trp, b.tci, b.tv, in, L.r0[blk], L.r1[blk], out, prod, red);
+        if (WHICH == 0)
+            stream_block(b.krp, b.kci, b.kv, in, L.r0[blk], L.r1[blk], b.krp[L.r0[blk]], b.krp[L.r1[blk]], out, prod,
+                         red);
+        else
+            stream_block(b.trp, b.tci, b.tv, in, L.r0[blk], L.r1[blk], b.trp[L.r0[blk]], b.trp[L.r1[blk]], out, prod,
+                         red);
     }
 }
 

@@ -429,33 +429,41 @@ __device__ __forceinline__ void average_row(const Dev<T> &d, int i, int c, T w)
     d.Kxa[i] = b + w * (kx[i] - b);
 }
 
-// CSR-Stream sums of one row block [r0, r1) of a CSR (global row pointers rp,
-// at most kStreamRB rows): products staged in LDS, one thread per row sums
-// them in index order.  A block of one row longer than kStreamNB is summed
-// by the whole workgroup.  Every thread of the workgroup must call it.
+// CSR-Stream sums of one row block: rows [r0, r1) (at most kStreamRB) whose
+// entries are [b, e) of a CSR with global row pointers rp.  Products are
+// staged in LDS and each thread sums every kBlock-th row in index order.  A
+// block of one row longer than kStreamNB is summed by the whole workgroup.
+// Every thread of the workgroup must call it.
 template <typename T>
 __device__ __forceinline__ void stream_block(const int *__restrict__ rp, const int *__restrict__ ci,
                                              const T *__restrict__ v, const T *__restrict__ x, int r0, int r1,
-                                             T *__restrict__ out, T *prod, double *red)
+                                             int b, int e, T *__restrict__ out, T *prod, double *red)
 {
-    const int b = rp[r0], e = rp[r1];
     const int cnt = e - b;
     // a multi-row block never exceeds kStreamNB nonzeros, only a single row can
     if (cnt <= kStreamNB) {
-        // Three straight-line phases so that a thread's loads overlap: every
-        // value and column it owns, then every gather, then the products.
-        // Slots past the block's end re-read its last entry (same cache
-        // line) rather than branch, which would serialise the gathers.
-        constexpr int U = kStreamNB / kBlock;
+        // Straight-line phases so that a thread's loads overlap: every value,
+        // column and row pointer it owns, then every gather, then the
+        // products.  Slots past the block's end re-read its last entry or row
+        // (same cache line) rather than branch, which would serialise them.
+        constexpr int U = kStreamNB / kBlock, RU = kStreamRB / kBlock;
+        int col[U], rs[RU], re[RU];
+        T a[U], g[U];
         if (cnt > 0) {
-            int col[U];
-            T a[U], g[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int t = min((int)threadIdx.x + u * kBlock, cnt - 1);
                 col[u] = __builtin_nontemporal_load(ci + b + t);
                 a[u] = __builtin_nontemporal_load(v + b + t);
             }
+        }
+#pragma unroll
+        for (int j = 0; j < RU; ++j) {
+            const int r = min(r0 + (int)threadIdx.x + j * kBlock, r1 - 1);
+            rs[j] = rp[r];
+            re[j] = rp[r + 1];
+        }
+        if (cnt > 0) {
 #pragma unroll
             for (int u = 0; u < U; ++u) g[u] = x[col[u]];
 #pragma unroll
@@ -465,11 +473,14 @@ __device__ __forceinline__ void stream_block(const int *__restrict__ rp, const i
             }
         }
         __syncthreads();
-        for (int r = r0 + (int)threadIdx.x; r < r1; r += kBlock) {
-            T acc = T(0);
-            const int je = rp[r + 1] - b;
-            for (int j = rp[r] - b; j < je; ++j) acc += prod[j];
-            out[r] = acc;
+#pragma unroll
+        for (int j = 0; j < RU; ++j) {
+            const int r = r0 + (int)threadIdx.x + j * kBlock;
+            if (r < r1) {
+                T acc = T(0);
+                for (int p = rs[j] - b; p < re[j] - b; ++p) acc += prod[p];
+                out[r] = acc;
+            }
         }
         __syncthreads();
     } else {
@@ -524,8 +535,11 @@ __device__ __forceinline__ void sliced_partial(const Sliced<T> &P, const T *__re
     const int *rp = P.rp + (size_t)s * (P.rows + 1);
     T *out = P.part + (size_t)s * P.rows;
     const int nblk = P.boff[s + 1] - P.boff[s];
-    const int *bro = P.brow + P.boff[s] + s;
-    for (int k = chunk0; k < nblk; k += stride) stream_block(rp, P.ci, P.v, x, bro[k], bro[k + 1], out, prod, red);
+    const int4 *bd = P.blk + P.boff[s];
+    for (int k = chunk0; k < nblk; k += stride) {
+        const int4 q = bd[k];
+        stream_block(rp, P.ci, P.v, x, q.x, q.y, q.z, q.w, out, prod, red);
+    }
 }
 
 }  // namespace pdlp

@@ -31,7 +31,7 @@ struct Sliced {
     const int *rp;    // [S*(rows+1)] per-slice row pointers into ci / v
     const int *ci;    // column indices, slice-major
     const T *v;       // values, same layout
-    const int *brow;  // row-block boundaries; slice s owns brow[boff[s]+s .. boff[s+1]+s]
+    const int4 *blk;  // row blocks {first row, end row, first entry, end entry}; slice s owns blk[boff[s] .. boff[s+1])
     const int *boff;  // [S+1] prefix counts of row blocks
     T *part;          // [S*rows] partial products
 };
