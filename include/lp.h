@@ -21,13 +21,17 @@
  *     solve outcome is lp_info.status.
  *   - Indices are int32 and 0-based; values are IEEE binary64.  Absent bounds
  *     are -INFINITY in l and +INFINITY in u.
- *   - Input pointers are HOST pointers.  Inputs are copied during the call;
- *     the library keeps no caller pointer.  Outputs go to caller-allocated
- *     host buffers.
- *   - Device memory is allocated by the library at lp_load and released by
- *     lp_free.  All GPU work is ordered on lp_options.stream (a hipStream_t;
- *     NULL = a non-blocking stream the library creates) and every call
- *     returns after that work is done.
+ *   - The arrays of lp_load, lp_set_start and lp_result are host pointers, or
+ *     device pointers when lp_options.ptr_kind = LP_DEVICE (every other call
+ *     takes host pointers).  Inputs are copied during the call; the library
+ *     keeps no caller pointer.  Outputs go to caller-allocated buffers.
+ *   - Device memory: by default the library allocates it at lp_load and
+ *     releases it at lp_free.  With lp_options.workspace set, every byte comes
+ *     from that caller-owned device buffer instead (lp_workspace_size tells
+ *     how many bytes) and the library calls no device allocator.  All GPU work
+ *     is ordered on lp_options.stream (a hipStream_t; NULL = a non-blocking
+ *     stream the library creates) and every call returns after that work is
+ *     done.
  *   - A handle is not thread-safe; separate handles are independent.
  */
 #ifndef PDLP_AMD_LP_H
@@ -50,6 +54,10 @@ extern "C" {
 #define LP_ERR_STATE (-6)      /* lp_result before any lp_solve; state buffer of the wrong size */
 #define LP_ERR_HIP (-7)        /* a HIP runtime call failed; lp_last_error() has the message */
 #define LP_ERR_NOMEM (-8)      /* host or device allocation failed */
+
+/* lp_options.ptr_kind */
+#define LP_HOST 0              /* array arguments are host pointers */
+#define LP_DEVICE 1            /* array arguments of lp_load, lp_set_start, lp_result are device pointers */
 
 /* lp_options.precision */
 #define LP_FP64 0              /* FP64 values, iterates and reductions */
@@ -87,8 +95,13 @@ typedef struct {
     int kernel_timing;      /* 1: bracket the two SpMV kernels with hipEvents (see lp_kernel_time) */
     int slice_kib;          /* target KiB of a gathered vector per column slice of K and K' (2048 = half an XCD's L2) */
     int autotune;           /* 1: at lp_load, time the slice count from slice_kib and its halved/doubled
-                               neighbours on the actual matrix and keep the fastest, per product (0) */
+                               neighbours on the actual matrix and keep the fastest, per product (0);
+                               ignored when a workspace is given */
     int verbose;
+    int ptr_kind;           /* LP_HOST (default) or LP_DEVICE */
+    void *workspace;        /* NULL, or device memory of workspace_bytes bytes, 256-byte aligned, owned by
+                               the caller, untouched by it until lp_free */
+    size_t workspace_bytes;
 } lp_options;
 
 typedef struct {
@@ -105,11 +118,20 @@ typedef struct {
 /* Fill *opt with the defaults listed above. */
 void lp_default_options(lp_options *opt);
 
+/* Bytes of device workspace lp_load needs for K under *opt (the layout,
+ * vectors, scratch and the load-time copies used by the scaling).  Host-side
+ * only: sorts and slices the pattern of K as lp_load does, no GPU work (with
+ * ptr_kind = LP_DEVICE it copies K to the host first).  opt may be NULL
+ * (defaults).  Errors: LP_ERR_ARG, _DIM, _TOO_LARGE. */
+int lp_workspace_size(const lp_csr *K, const lp_options *opt, size_t *bytes);
+
 /* Validate, build the CSR of K' (counting sort, so the K' product needs no
  * atomics), cut both products into column slices sized to stay resident in
  * one XCD's L2, copy to the GPU and apply the diagonal scaling there.  The scaling is
  * the diagonal preconditioning the paper's experiments apply before PDHG
- * (Sec. 3.1).  On success *P owns all device memory; on error *P = NULL.
+ * (Sec. 3.1).  On success *P owns all device memory (or its part of the
+ * caller's workspace); on error *P = NULL.  A workspace smaller than
+ * lp_workspace_size reports LP_ERR_NOMEM; one not 256-byte aligned LP_ERR_ARG.
  * Errors: LP_ERR_ARG, _DIM, _NAN, _BOUNDS, _TOO_LARGE, _HIP, _NOMEM. */
 int lp_load(lp_problem **P, const lp_csr *K, const double *c, const double *q,
             const double *l, const double *u, int64_t m1, const lp_options *opt);
@@ -132,9 +154,10 @@ int lp_set_start_weight(lp_problem *P, double omega);
  * the limit is hit; see lp_info.status.  Errors: LP_ERR_ARG, LP_ERR_HIP. */
 int lp_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit_s);
 
-/* Copy the returned point to host buffers x[n], y[m], lambda[n] (each may be
- * NULL), unscaled and in the original order; lambda = proj_Lambda(c - K'y).
- * info may be NULL.  Errors: LP_ERR_STATE before the first lp_solve. */
+/* Copy the returned point to buffers x[n], y[m], lambda[n] (each may be
+ * NULL; device buffers when ptr_kind = LP_DEVICE), unscaled and in the
+ * original order; lambda = proj_Lambda(c - K'y).  info may be NULL.
+ * Errors: LP_ERR_STATE before the first lp_solve. */
 int lp_result(const lp_problem *P, double *x, double *y, double *lambda, lp_info *info);
 
 /* Solver state for checkpoint/resume and per-step comparison, as doubles in
@@ -185,7 +208,9 @@ typedef struct lp_batch lp_batch;   /* opaque; owned by the library */
 
 /* count instances: K[i], c[i], q[i], l[i], u[i], m1[i] as in lp_load (host
  * pointers, copied).  Options apply to every instance.  Same error codes as
- * lp_load (the first failing instance decides). */
+ * lp_load (the first failing instance decides).  A batch takes host pointers
+ * and allocates its own device memory: ptr_kind = LP_DEVICE or a workspace
+ * is LP_ERR_ARG. */
 int lp_batch_load(lp_batch **B, int32_t count, const lp_csr *K, const double *const *c, const double *const *q,
                   const double *const *l, const double *const *u, const int64_t *m1, const lp_options *opt);
 /* Solve every instance (cold start, or resume when lp_batch_set_state was

@@ -93,6 +93,13 @@ void build_sliced(HostSliced &H, int rows, int cols, const std::vector<int> &rp,
     }
 }
 
+// size of one device allocation as the handle makes it
+size_t dev_round(size_t bytes)
+{
+    if (bytes == 0) bytes = 8;
+    return (bytes + 255) & ~(size_t)255;
+}
+
 struct TuneTrial {
     int S, nb, rb;
     float ms;
@@ -127,6 +134,8 @@ struct lp_problem {
     std::vector<void *> allocs;     // device allocations owned by the handle
     std::vector<int64_t> alloc_bytes;
     int64_t dev_bytes = 0;
+    char *ws = nullptr;             // caller's workspace: bump-allocated, never returned before lp_free
+    size_t ws_size = 0, ws_used = 0;
     bool mixed = false;
     Dev<double> d64{};
     Dev<float> d32{};
@@ -148,9 +157,15 @@ struct lp_problem {
 
     void *dalloc(size_t bytes)
     {
+        bytes = dev_round(bytes);
+        if (ws) {
+            if (bytes > ws_size - ws_used) throw HipError{hipErrorOutOfMemory, "workspace too small for lp_load"};
+            void *p = ws + ws_used;
+            ws_used += bytes;
+            dev_bytes = (int64_t)ws_used;
+            return p;
+        }
         void *p = nullptr;
-        if (bytes == 0) bytes = 8;
-        bytes = (bytes + 255) & ~(size_t)255;
         HIPT(hipMalloc(&p, bytes));
         allocs.push_back(p);
         alloc_bytes.push_back((int64_t)bytes);
@@ -159,6 +174,7 @@ struct lp_problem {
     }
     void dfree(void *p)
     {
+        if (ws) return;   // workspace memory goes back to the caller at lp_free
         for (size_t i = 0; i < allocs.size(); ++i)
             if (allocs[i] == p) {
                 (void)hipFree(p);
@@ -320,7 +336,7 @@ void setup_typed(lp_problem *P, const HostSliced &HK, const HostSliced &HT, cons
     auto tvec = [&](int64_t len) { return (T *)P->dalloc(sizeof(T) * (size_t)std::max<int64_t>(len, 1)); };
     P->tmp_n = tvec(n);
     P->tmp_m = tvec(m);
-    if (P->opt.autotune) {
+    if (P->opt.autotune && !P->ws) {
         d.K = tuned_sliced<T>(P, HK, rp, ci, kv64, (T *)P->tmp_n, (T *)P->tmp_m, n, P->tune_log_K, P->shape_K);
         d.KT = tuned_sliced<T>(P, HT, tp, ti, tv64, (T *)P->tmp_m, (T *)P->tmp_n, m, P->tune_log_KT, P->shape_KT);
     } else {
@@ -353,6 +369,104 @@ void setup_typed(lp_problem *P, const HostSliced &HK, const HostSliced &HT, cons
     d.ctl = (Ctl *)P->dalloc(sizeof(Ctl));
 }
 
+// Host copies of lp_load's arrays when the caller passed device pointers.
+struct HostLP {
+    std::vector<int32_t> rp, ci;
+    std::vector<double> v, c, q, l, u;
+    lp_csr K{};
+};
+
+template <typename T>
+void fetch(std::vector<T> &dst, const T *src, int64_t count, hipStream_t st)
+{
+    dst.resize((size_t)std::max<int64_t>(count, 0));
+    if (count > 0 && src) HIPT(hipMemcpyAsync(dst.data(), src, sizeof(T) * (size_t)count, hipMemcpyDeviceToHost, st));
+}
+
+// Copies the device arrays (pattern only when c is NULL) and points H.K at
+// them; sizes are checked first so no copy reads past the caller's arrays.
+int fetch_lp(const lp_csr *K, const double *c, const double *q, const double *l, const double *u, hipStream_t st,
+             HostLP &H)
+{
+    int rc = validate_dims(K);
+    if (rc != LP_OK) return rc;
+    fetch(H.rp, K->row_ptr, K->m + 1, st);
+    fetch(H.ci, K->col, K->nnz, st);
+    if (c) {
+        if ((K->nnz > 0 && !K->val) || (K->n > 0 && (!l || !u)) || (K->m > 0 && !q)) return LP_ERR_ARG;
+        fetch(H.v, K->val, K->nnz, st);
+        fetch(H.c, c, K->n, st);
+        fetch(H.l, l, K->n, st);
+        fetch(H.u, u, K->n, st);
+        fetch(H.q, q, K->m, st);
+    }
+    HIPT(hipStreamSynchronize(st));
+    H.K = *K;
+    H.K.row_ptr = H.rp.data();
+    H.K.col = H.ci.data();
+    H.K.val = c ? H.v.data() : nullptr;
+    return LP_OK;
+}
+
+int check_options(const lp_options &o)
+{
+    if ((o.precision != LP_FP64 && o.precision != LP_MIXED) || o.check_every <= 0 || o.ruiz_iters < 0 ||
+        (o.fixed_step && !(o.fixed_eta > 0.0)) || o.window <= 0 || o.slice_kib <= 0 ||
+        (o.ptr_kind != LP_HOST && o.ptr_kind != LP_DEVICE) ||
+        (o.workspace && (reinterpret_cast<uintptr_t>(o.workspace) % 256 != 0)))
+        return LP_ERR_ARG;
+    return LP_OK;
+}
+
+// The host layout lp_load builds for K (sorted rows, transpose, slices).
+void host_layout(const lp_csr *K, bool mixed, int slice_kib, std::vector<int> &rp, std::vector<int> &ci,
+                 std::vector<double> &kv, std::vector<int> &tp, std::vector<int> &ti, std::vector<double> &tv,
+                 HostSliced &HK, HostSliced &HT)
+{
+    const int64_t m = K->m, n = K->n;
+    append_sorted_rows(K, 0, rp, ci, kv);
+    transpose_csr((int)m, (int)n, rp, ci, kv, tp, ti, tv);
+    // column slices sized so a slice of the gathered vector stays in one XCD's L2
+    const int64_t tsz = mixed ? 4 : 8;
+    const int64_t slice_bytes = (int64_t)slice_kib * 1024;
+    build_sliced(HK, (int)m, (int)n, rp, ci, slices_for(n * tsz, slice_bytes));
+    build_sliced(HT, (int)n, (int)m, tp, ti, slices_for(m * tsz, slice_bytes));
+}
+
+// Every device allocation do_load and setup_typed make, in bytes as dalloc
+// rounds them, for the default layout: the size of a caller's workspace.
+// Kept next to the code it mirrors; a GPU test checks the two agree.
+size_t load_plan_bytes(int64_t m, int64_t n, int64_t nnz, const HostSliced &HK, const HostSliced &HT, bool mixed)
+{
+    const size_t T = mixed ? sizeof(float) : sizeof(double);
+    auto one = [](int64_t v) { return (size_t)std::max<int64_t>(v, 1); };
+    size_t b = 0;
+    auto add = [&](size_t bytes) { b += dev_round(bytes); };
+    // do_load: CSR pair and vectors for the scaling, norms, staging
+    add(4 * one(m + 1)); add(4 * one(nnz)); add(4 * one(n + 1)); add(4 * one(nnz));
+    add(8 * one(nnz)); add(8 * one(nnz));
+    for (int64_t len : {n, n, n, m, m, n, m, n, n, n, n, m}) add(8 * one(len));   // c l u q Dr Dc r s cs ls us qs
+    add(8 * kMaxGrid); add(8 * 8);
+    add(8 * one(n)); add(8 * one(n)); add(8 * one(m));
+    // setup_typed: lp_spmv scratch, the two sliced products, vectors, partials, controller
+    add(T * one(n)); add(T * one(m));
+    for (const HostSliced *H : {&HK, &HT}) {
+        add(sizeof(int) * H->rp.size());
+        add(4 * one(nnz));
+        add(sizeof(int4) * std::max<size_t>(H->blk.size(), 1));
+        add(sizeof(int) * H->boff.size());
+        add(T * one(nnz));
+        add(T * (size_t)H->S * (size_t)std::max(H->rows, 1));
+        add(4 * one(nnz));
+    }
+    if (mixed) for (int64_t len : {n, n, n, m}) add(T * one(len));
+    for (int k = 0; k < 2; ++k) for (int64_t len : {n, m, m, n}) add(T * one(len));
+    for (int64_t len : {n, m, m, n, n, m, n, m, n}) add(T * one(len));   // averages, anchor, output
+    add(8 * kMaxGrid); add(8 * kMaxGrid * 2); add(8 * kMaxGrid * kCheckSums);
+    add(sizeof(Ctl));
+    return b;
+}
+
 int do_load(lp_problem *P, const lp_csr *K, const double *c, const double *q, const double *l, const double *u)
 {
     const int64_t m = P->m, n = P->n, nnz = P->nnz;
@@ -364,19 +478,20 @@ int do_load(lp_problem *P, const lp_csr *K, const double *c, const double *q, co
     P->inv_r = P->perm_r;
     P->inv_c = P->perm_c;
 
-    // K with the columns of each row sorted, and K' by a counting sort
+    // K with the columns of each row sorted, K' by a counting sort, both sliced
     std::vector<int> rp, ci, tp, ti;
     std::vector<double> kv, tv;
-    append_sorted_rows(K, 0, rp, ci, kv);
-    transpose_csr((int)m, (int)n, rp, ci, kv, tp, ti, tv);
-    // column slices sized so a slice of the gathered vector stays in one XCD's L2
-    const int64_t tsz = P->mixed ? 4 : 8;
-    const int64_t slice_bytes = (int64_t)P->opt.slice_kib * 1024;
     HostSliced HK, HT;
-    build_sliced(HK, (int)m, (int)n, rp, ci, slices_for(n * tsz, slice_bytes));
-    build_sliced(HT, (int)n, (int)m, tp, ti, slices_for(m * tsz, slice_bytes));
+    host_layout(K, P->mixed, P->opt.slice_kib, rp, ci, kv, tp, ti, tv, HK, HT);
     P->slices_K = HK.S;
     P->slices_KT = HT.S;
+    if (P->ws && P->ws_size < load_plan_bytes(m, n, nnz, HK, HT, P->mixed)) {
+        char buf[160];
+        snprintf(buf, sizeof(buf), "workspace of %zu bytes, lp_load needs %zu", P->ws_size,
+                 load_plan_bytes(m, n, nnz, HK, HT, P->mixed));
+        P->err = buf;
+        return LP_ERR_NOMEM;
+    }
 
     // device copies of the CSR pair (for the scaling) and the vectors
     auto ialloc = [&](int64_t len) { return (int *)P->dalloc(sizeof(int) * (size_t)std::max<int64_t>(len, 1)); };
@@ -671,7 +786,15 @@ int do_result(const lp_problem *Pc, double *x, double *y, double *lam, lp_info *
     lp_problem *P = const_cast<lp_problem *>(Pc);
     Dev<T> &d = P->dev<T>();
     const int64_t m = P->m, n = P->n;
-    if (x || y || lam) {
+    if ((x || y || lam) && P->opt.ptr_kind == LP_DEVICE) {
+        // vectors keep the caller's order, so the staged results copy as they are
+        HIPT(launch_result<T>(d, P->stage_n0, P->stage_m, P->stage_n1, P->stream));
+        const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+        if (x && n) HIPT(hipMemcpyAsync(x, P->stage_n0, sizeof(double) * (size_t)n, k, P->stream));
+        if (lam && n) HIPT(hipMemcpyAsync(lam, P->stage_n1, sizeof(double) * (size_t)n, k, P->stream));
+        if (y && m) HIPT(hipMemcpyAsync(y, P->stage_m, sizeof(double) * (size_t)m, k, P->stream));
+        sync(P);
+    } else if (x || y || lam) {
         HIPT(launch_result<T>(d, P->stage_n0, P->stage_m, P->stage_n1, P->stream));
         std::vector<double> hx((size_t)n), hy((size_t)m), hl((size_t)n);
         download(P, hx.data(), P->stage_n0, n);
@@ -833,19 +956,66 @@ void lp_default_options(lp_options *o)
     o->verbose = 0;
 }
 
+int lp_workspace_size(const lp_csr *K, const lp_options *opt, size_t *bytes)
+{
+    if (!K || !bytes) return LP_ERR_ARG;
+    lp_options o;
+    if (opt) o = *opt;
+    else lp_default_options(&o);
+    int rc = check_options(o);
+    if (rc != LP_OK) return rc;
+    try {
+        HostLP H;
+        if (o.ptr_kind == LP_DEVICE) {
+            rc = fetch_lp(K, nullptr, nullptr, nullptr, nullptr, (hipStream_t)o.stream, H);
+            if (rc != LP_OK) return rc;
+            K = &H.K;
+        }
+        rc = validate_pattern(K);
+        if (rc != LP_OK) return rc;
+        // the layout depends on the pattern only: zeros stand in for the values
+        std::vector<double> zeros((size_t)std::max<int64_t>(K->nnz, 1), 0.0);
+        lp_csr P = *K;
+        P.val = zeros.data();
+        std::vector<int> rp, ci, tp, ti;
+        std::vector<double> kv, tv;
+        HostSliced HK, HT;
+        host_layout(&P, o.precision == LP_MIXED, o.slice_kib, rp, ci, kv, tp, ti, tv, HK, HT);
+        *bytes = load_plan_bytes(K->m, K->n, K->nnz, HK, HT, o.precision == LP_MIXED);
+    } catch (const HipError &) {
+        return LP_ERR_HIP;
+    } catch (const std::bad_alloc &) {
+        return LP_ERR_NOMEM;
+    }
+    return LP_OK;
+}
+
 int lp_load(lp_problem **out, const lp_csr *K, const double *c, const double *q, const double *l, const double *u,
             int64_t m1, const lp_options *opt)
 {
     if (!out) return LP_ERR_ARG;
     *out = nullptr;
-    int rc = validate_lp(K, c, q, l, u, m1);
-    if (rc != LP_OK) return rc;
     lp_options o;
     if (opt) o = *opt;
     else lp_default_options(&o);
-    if ((o.precision != LP_FP64 && o.precision != LP_MIXED) || o.check_every <= 0 || o.ruiz_iters < 0 ||
-        (o.fixed_step && !(o.fixed_eta > 0.0)) || o.window <= 0 || o.slice_kib <= 0)
-        return LP_ERR_ARG;
+    int rc = check_options(o);
+    if (rc != LP_OK) return rc;
+    HostLP H;
+    if (o.ptr_kind == LP_DEVICE) {
+        if (!K || (K->n > 0 && !c)) return LP_ERR_ARG;
+        try {
+            rc = fetch_lp(K, c, q, l, u, (hipStream_t)o.stream, H);
+        } catch (const HipError &) {
+            return LP_ERR_HIP;
+        } catch (const std::bad_alloc &) {
+            return LP_ERR_NOMEM;
+        }
+        if (rc != LP_OK) return rc;
+        K = &H.K;
+        c = H.c.data(); q = H.q.data(); l = H.l.data(); u = H.u.data();
+    }
+    rc = validate_lp(K, c, q, l, u, m1);
+    if (rc != LP_OK) return rc;
     std::unique_ptr<lp_problem> P;
     try {
         P.reset(new lp_problem());
@@ -856,6 +1026,8 @@ int lp_load(lp_problem **out, const lp_csr *K, const double *c, const double *q,
     P->opt = o;
     P->mixed = o.precision == LP_MIXED;
     P->stream = (hipStream_t)o.stream;
+    P->ws = (char *)o.workspace;
+    P->ws_size = o.workspace ? o.workspace_bytes : 0;
     try {
         if (!P->stream) {
             // a stream of our own (default priority) so the window can be graph-captured
@@ -871,7 +1043,10 @@ int lp_load(lp_problem **out, const lp_csr *K, const double *c, const double *q,
     } catch (const std::bad_alloc &) {
         rc = LP_ERR_NOMEM;
     }
-    if (rc != LP_OK) return rc;
+    if (rc != LP_OK) {
+        if (o.verbose && !P->err.empty()) fprintf(stderr, "lp_load: %s\n", P->err.c_str());
+        return rc;
+    }
     *out = P.release();
     return LP_OK;
 }
@@ -881,8 +1056,18 @@ int lp_set_start(lp_problem *P, const double *x0, const double *y0)
     if (!P) return LP_ERR_ARG;
     P->has_xs = x0 != nullptr;
     P->has_ys = y0 != nullptr;
-    if (x0) P->xs.assign(x0, x0 + P->n);
-    if (y0) P->ys.assign(y0, y0 + P->m);
+    if (P->opt.ptr_kind == LP_DEVICE) {
+        try {
+            if (x0) fetch(P->xs, x0, P->n, P->stream);
+            if (y0) fetch(P->ys, y0, P->m, P->stream);
+            HIPT(hipStreamSynchronize(P->stream));
+        } catch (const HipError &h) {
+            return fail_hip(P, h);
+        }
+    } else {
+        if (x0) P->xs.assign(x0, x0 + P->n);
+        if (y0) P->ys.assign(y0, y0 + P->m);
+    }
     P->state_ready = false;
     return LP_OK;
 }

@@ -3,6 +3,34 @@
 
 namespace pdlp {
 
+int validate_dims(const lp_csr *K)
+{
+    if (!K) return LP_ERR_ARG;
+    const int64_t m = K->m, n = K->n, nnz = K->nnz;
+    if (m < 0 || n < 0 || nnz < 0) return LP_ERR_DIM;
+    if (m >= (int64_t(1) << 31) || n >= (int64_t(1) << 31) || nnz >= (int64_t(1) << 31)) return LP_ERR_TOO_LARGE;
+    if (!K->row_ptr || (nnz > 0 && !K->col)) return LP_ERR_ARG;
+    return LP_OK;
+}
+
+int validate_pattern(const lp_csr *K)
+{
+    int rc = validate_dims(K);
+    if (rc != LP_OK) return rc;
+    const int64_t m = K->m, n = K->n, nnz = K->nnz;
+    if (K->row_ptr[0] != 0 || K->row_ptr[m] != nnz) return LP_ERR_DIM;
+    for (int64_t i = 0; i < m; ++i)
+        if (K->row_ptr[i + 1] < K->row_ptr[i]) return LP_ERR_DIM;
+    std::vector<int64_t> seen((size_t)std::max<int64_t>(n, 1), -1);
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t p = K->row_ptr[i]; p < K->row_ptr[i + 1]; ++p) {
+            const int64_t j = K->col[p];
+            if (j < 0 || j >= n || seen[j] == i) return LP_ERR_DIM;
+            seen[j] = i;
+        }
+    return LP_OK;
+}
+
 int validate_lp(const lp_csr *K, const double *c, const double *q, const double *l, const double *u, int64_t m1)
 {
     if (!K) return LP_ERR_ARG;

@@ -77,6 +77,9 @@ inline void d2d(hipStream_t st, T *dst, const T *src, int64_t count)
 
 // The input rules of lp_load (LP_ERR_* codes of lp.h).
 int validate_lp(const lp_csr *K, const double *c, const double *q, const double *l, const double *u, int64_t m1);
+// Sizes and pointers of a CSR only; then its structure (no values).
+int validate_dims(const lp_csr *K);
+int validate_pattern(const lp_csr *K);
 
 // Append the rows of K (columns sorted inside each row, columns shifted by
 // col_off) to a CSR under construction.

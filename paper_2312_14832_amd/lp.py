@@ -15,13 +15,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpdlp_amd.so")
 
 LP_FP64, LP_MIXED = 0, 1
+LP_HOST, LP_DEVICE = 0, 1
 STATUS = {0: "NOT_SOLVED", 1: "OPTIMAL", 2: "ITERATION_LIMIT", 3: "TIME_LIMIT", 4: "NUMERICAL"}
 ERRORS = {-1: "LP_ERR_ARG", -2: "LP_ERR_DIM", -3: "LP_ERR_NAN", -4: "LP_ERR_BOUNDS",
           -5: "LP_ERR_TOO_LARGE", -6: "LP_ERR_STATE", -7: "LP_ERR_HIP", -8: "LP_ERR_NOMEM"}
 NSCALARS = 16
 
 # every symbol include/lp.h declares
-EXPORTS = ["lp_default_options", "lp_load", "lp_set_start", "lp_set_start_weight", "lp_solve", "lp_result", "lp_get_state",
+EXPORTS = ["lp_default_options", "lp_workspace_size", "lp_load", "lp_set_start", "lp_set_start_weight", "lp_solve", "lp_result", "lp_get_state",
            "lp_set_state", "lp_get_scaling", "lp_spmv", "lp_kernel_time", "lp_device_bytes", "lp_layout",
            "lp_layout_blocks", "lp_free",
            "lp_strerror", "lp_last_error", "lp_batch_load", "lp_batch_solve", "lp_batch_result",
@@ -40,7 +41,8 @@ class LPOptions(C.Structure):
                 ("pc_alpha", C.c_double), ("check_every", C.c_int), ("kkt_omega_power", C.c_double),
                 ("fixed_step", C.c_int), ("fixed_eta", C.c_double), ("use_graph", C.c_int),
                 ("window", C.c_int), ("kernel_timing", C.c_int), ("slice_kib", C.c_int),
-                ("autotune", C.c_int), ("verbose", C.c_int)]
+                ("autotune", C.c_int), ("verbose", C.c_int), ("ptr_kind", C.c_int),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
 
 
 class LPInfo(C.Structure):
@@ -63,6 +65,7 @@ def library():
         dp = C.POINTER(C.c_double)
         L.lp_default_options.argtypes = [C.POINTER(LPOptions)]
         L.lp_default_options.restype = None
+        L.lp_workspace_size.argtypes = [C.POINTER(LPCsr), C.POINTER(LPOptions), C.POINTER(C.c_size_t)]
         L.lp_load.argtypes = [C.POINTER(C.c_void_p), C.POINTER(LPCsr), dp, dp, dp, dp, C.c_int64,
                               C.POINTER(LPOptions)]
         L.lp_set_start.argtypes = [C.c_void_p, dp, dp]
@@ -115,32 +118,78 @@ def _f64(a):
 
 
 def default_options(**kw) -> LPOptions:
+    """lp_options with the library defaults and the given fields.  precision
+    and ptr_kind accept "fp64"/"mixed" and "host"/"device"; stream a
+    torch.cuda.Stream; workspace a contiguous torch uint8 CUDA tensor."""
     o = LPOptions()
     library().lp_default_options(C.byref(o))
     for k, v in kw.items():
         if k == "precision" and isinstance(v, str):
             v = {"fp64": LP_FP64, "mixed": LP_MIXED}[v]
+        if k == "ptr_kind" and isinstance(v, str):
+            v = {"host": LP_HOST, "device": LP_DEVICE}[v]
         if k == "stream" and v is not None and not isinstance(v, int):
             v = int(v.cuda_stream)  # a torch.cuda.Stream
+        if k == "workspace" and v is not None and not isinstance(v, int):
+            assert v.is_cuda and v.is_contiguous()
+            o.workspace_bytes = v.numel() * v.element_size()
+            v = v.data_ptr()
         setattr(o, k, v)
     return o
+
+
+def _ptr(a, ctype):
+    """Host numpy array or device torch tensor -> typed pointer."""
+    if a is None:
+        return None
+    if hasattr(a, "data_ptr"):
+        assert a.is_cuda and a.is_contiguous()
+        return C.cast(C.c_void_p(a.data_ptr()), C.POINTER(ctype))
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _csr(lp, device):
+    """LPCsr of lp.row_ptr / col / val (numpy, or torch CUDA tensors when device)."""
+    if device:
+        rp, ci, v = lp.row_ptr, lp.col, lp.val
+        nnz = int(rp[-1].item())
+    else:
+        rp = np.ascontiguousarray(lp.row_ptr, np.int32)
+        ci = np.ascontiguousarray(lp.col, np.int32)
+        v = None if getattr(lp, "val", None) is None else _f64(lp.val)
+        nnz = int(rp[-1])
+    return LPCsr(int(lp.m), int(lp.n), nnz, _ptr(rp, C.c_int32), _ptr(ci, C.c_int32), _ptr(v, C.c_double)), (rp, ci, v)
+
+
+def workspace_size(lp, **options):
+    """Device bytes lp_load needs from a caller workspace (lp_workspace_size);
+    runs on the host only."""
+    o = default_options(**options)
+    K, keep = _csr(lp, o.ptr_kind == LP_DEVICE)
+    b = C.c_size_t()
+    rc = library().lp_workspace_size(C.byref(K), C.byref(o), C.byref(b))
+    if rc != 0:
+        raise LPError(rc, library().lp_strerror(rc).decode())
+    return b.value
 
 
 class Problem:
     """One LP loaded on the GPU (lp_load); see include/lp.h for semantics."""
 
     def __init__(self, lp, **options):
+        """options as default_options.  With ptr_kind="device" the arrays of lp
+        (row_ptr, col int32; val, c, q, l, u float64) are torch CUDA tensors,
+        and set_start / result take and fill torch CUDA tensors."""
         L = library()
         self.m, self.n, self.m1 = int(lp.m), int(lp.n), int(lp.m1)
+        self.workspace = options.get("workspace")   # kept alive as long as the handle
         self.opt = default_options(**options)
-        rp = np.ascontiguousarray(lp.row_ptr, np.int32)
-        ci = np.ascontiguousarray(lp.col, np.int32)
-        v = _f64(lp.val)
-        K = LPCsr(self.m, self.n, int(rp[-1]), rp.ctypes.data_as(C.POINTER(C.c_int32)),
-                  ci.ctypes.data_as(C.POINTER(C.c_int32)), _dp(v))
-        c, q, l, u = _f64(lp.c), _f64(lp.q), _f64(lp.l), _f64(lp.u)
+        self.device = self.opt.ptr_kind == LP_DEVICE
+        K, keep = _csr(lp, self.device)
+        vecs = [lp.c, lp.q, lp.l, lp.u] if self.device else [_f64(a) for a in (lp.c, lp.q, lp.l, lp.u)]
+        c, q, l, u = (_ptr(a, C.c_double) for a in vecs)
         h = C.c_void_p()
-        rc = L.lp_load(C.byref(h), C.byref(K), _dp(c), _dp(q), _dp(l), _dp(u), self.m1, C.byref(self.opt))
+        rc = L.lp_load(C.byref(h), C.byref(K), c, q, l, u, self.m1, C.byref(self.opt))
         if rc != 0:
             raise LPError(rc, L.lp_strerror(rc).decode())
         self.h = h
@@ -158,6 +207,9 @@ class Problem:
         self.close()
 
     def set_start(self, x=None, y=None):
+        if self.device:
+            self._check(library().lp_set_start(self.h, _ptr(x, C.c_double), _ptr(y, C.c_double)))
+            return
         xs = None if x is None else _f64(x)
         ys = None if y is None else _f64(y)
         self._check(library().lp_set_start(self.h, _dp(xs), _dp(ys)))
@@ -178,6 +230,14 @@ class Problem:
         return d
 
     def result(self):
+        if self.device:
+            import torch
+            x = torch.empty(self.n, dtype=torch.float64, device="cuda")
+            y = torch.empty(self.m, dtype=torch.float64, device="cuda")
+            lam = torch.empty(self.n, dtype=torch.float64, device="cuda")
+            self._check(library().lp_result(self.h, _ptr(x, C.c_double), _ptr(y, C.c_double),
+                                            _ptr(lam, C.c_double), None))
+            return x, y, lam, self.info()
         x = np.empty(self.n); y = np.empty(self.m); lam = np.empty(self.n)
         inf = LPInfo()
         self._check(library().lp_result(self.h, _dp(x), _dp(y), _dp(lam), C.byref(inf)))

@@ -88,7 +88,8 @@ def test_validation_codes_match_oracle(oracle_mod, mut, code):
 
 def test_bad_options_rejected():
     lp = _lib()
-    for kw in [dict(precision=7), dict(check_every=0), dict(window=0), dict(fixed_step=1, fixed_eta=0.0)]:
+    for kw in [dict(precision=7), dict(check_every=0), dict(window=0), dict(fixed_step=1, fixed_eta=0.0),
+               dict(ptr_kind=5), dict(workspace=8, workspace_bytes=1 << 20)]:
         with pytest.raises(lp.LPError) as ei:
             lp.Problem(gen.tiny_lp(0), **kw)
         assert ei.value.code == -1
@@ -103,3 +104,35 @@ def test_null_arguments():
     assert L.lp_solve(None, 1e-4, 10, 0.0) == -1
     assert L.lp_result(None, None, None, None, None) == -1
     L.lp_free(None)
+
+
+def test_workspace_size_is_host_only_and_sane():
+    """lp_workspace_size runs without a GPU.  The size covers at least the
+    matrix twice (solver layout and the scaling's CSR pair, values and int32
+    columns) and ten vectors per row and column; FP32 mode needs less, a
+    larger LP more."""
+    lp = _lib()
+    small, big = gen.tiny_lp(0), gen.large_lp(seed=2, n=20000, m1=5000, m2=5000)
+    for data in (small, big):
+        nnz, n, m = data.nnz, data.n, data.m
+        b64 = lp.workspace_size(data)
+        b32 = lp.workspace_size(data, precision="mixed")
+        assert b64 >= 2 * nnz * (8 + 4) * 2 + 8 * 10 * (n + m)
+        assert b64 <= 4 * (2 * nnz * (8 + 4) * 2 + 8 * 40 * (n + m)) + (4 << 20)
+        assert b32 < b64
+        assert b64 % 256 == 0 and b32 % 256 == 0
+    assert lp.workspace_size(big) > lp.workspace_size(small)
+
+
+def test_workspace_size_rejects_bad_input():
+    lp = _lib()
+    for mut in ("col_oob", "dup", "rp_bad"):
+        with pytest.raises(lp.LPError) as ei:
+            lp.workspace_size(_mutate(gen.tiny_lp(0), mut))
+        assert ei.value.code == -2
+    with pytest.raises(lp.LPError) as ei:
+        lp.workspace_size(gen.tiny_lp(0), ptr_kind=9)
+    assert ei.value.code == -1
+    L = lp.library()
+    b = C.c_size_t()
+    assert L.lp_workspace_size(None, None, C.byref(b)) == -1

@@ -1,0 +1,100 @@
+"""The C ABI's memory boundary on the GPU: a handle carved from a caller's
+workspace (lp_workspace_size bytes, no device allocation by the library) and
+device-pointer arguments (ptr_kind = LP_DEVICE) give the same results, bit
+for bit, as the default host-pointer handle that allocates its own memory."""
+import numpy as np
+import pytest
+
+from paper_2312_14832_amd import gen
+from gpu_helpers import say
+
+pytestmark = pytest.mark.gpu
+
+
+def _tol(precision):
+    return 1e-6 if precision == "fp64" else 1e-4   # FP32 iterates stall above 1e-6
+
+
+def _solve_host(lpmod, data, precision, **kw):
+    p = lpmod.Problem(data, precision=precision, **kw)
+    p.solve(_tol(precision), 200_000)
+    x, y, lam, info = p.result()
+    st = p.get_state()
+    p.close()
+    return x, y, lam, info, st
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("which", ["tiny", "mid"])
+def test_workspace_handle_matches_default(lpmod, precision, which):
+    import torch
+    data = gen.tiny_lp(3) if which == "tiny" else gen.large_lp(seed=5, n=60000, m1=15000, m2=15000)
+    say(f"case workspace {which} {precision}")
+    need = lpmod.workspace_size(data, precision=precision)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    ws.fill_(0xFF)   # NaN bytes everywhere: nothing may be read before it is written
+    p = lpmod.Problem(data, precision=precision, workspace=ws)
+    assert p.device_bytes() == need
+    p.solve(_tol(precision), 200_000)
+    x, y, lam, info = p.result()
+    st = p.get_state()
+    p.close()
+    x0, y0, lam0, info0, st0 = _solve_host(lpmod, data, precision)
+    assert info["status"] == info0["status"] == "OPTIMAL"
+    assert info["iterations"] == info0["iterations"]
+    for a, b in ((x, x0), (y, y0), (lam, lam0), (st, st0)):
+        assert np.array_equal(a, b)
+
+
+def test_workspace_too_small_or_misaligned(lpmod):
+    import torch
+    data = gen.tiny_lp(1)
+    need = lpmod.workspace_size(data)
+    ws = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    with pytest.raises(lpmod.LPError) as ei:
+        lpmod.Problem(data, workspace=ws[:need - 256])
+    assert ei.value.code == -8
+    with pytest.raises(lpmod.LPError) as ei:
+        lpmod.Problem(data, workspace=ws[8:8 + need])
+    assert ei.value.code == -1
+    # a workspace with room to spare works and uses exactly what was asked for
+    p = lpmod.Problem(data, workspace=ws)
+    assert p.device_bytes() == need
+    assert p.solve(1e-6, 200_000)["status"] == "OPTIMAL"
+    p.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_device_pointers_match_host_pointers(lpmod, precision):
+    import torch
+    say(f"case device pointers {precision}")
+    data = gen.tiny_lp(2)
+    rng = np.random.Generator(np.random.PCG64(7))
+    xs = rng.uniform(0, 3, data.n)
+    ys = rng.normal(size=data.m)
+
+    dev = lambda a, dt=torch.float64: torch.from_numpy(np.ascontiguousarray(a)).to(dtype=dt, device="cuda")
+
+    class DevLP:
+        m, n, m1 = data.m, data.n, data.m1
+        row_ptr = dev(data.row_ptr, torch.int32)
+        col = dev(data.col, torch.int32)
+        val, c, q, l, u = dev(data.val), dev(data.c), dev(data.q), dev(data.l), dev(data.u)
+
+    assert lpmod.workspace_size(DevLP, ptr_kind="device", precision=precision) == \
+        lpmod.workspace_size(data, precision=precision)
+    pd = lpmod.Problem(DevLP, ptr_kind="device", precision=precision)
+    pd.set_start(dev(xs), dev(ys))
+    pd.solve(_tol(precision), 200_000)
+    xd, yd, ld, infod = pd.result()
+    pd.close()
+    ph = lpmod.Problem(data, precision=precision)
+    ph.set_start(xs, ys)
+    ph.solve(_tol(precision), 200_000)
+    xh, yh, lh, infoh = ph.result()
+    ph.close()
+    assert infod["status"] == infoh["status"] == "OPTIMAL"
+    assert infod["iterations"] == infoh["iterations"]
+    assert np.array_equal(xd.cpu().numpy(), xh)
+    assert np.array_equal(yd.cpu().numpy(), yh)
+    assert np.array_equal(ld.cpu().numpy(), lh)
