@@ -170,7 +170,7 @@ def main():
     ap.add_argument("--ws-train", type=int, default=512, help="warmstart: training instances")
     ap.add_argument("--ws-eval", type=int, default=128, help="warmstart: held-out instances")
     ap.add_argument("--ws-epochs", type=int, default=120)
-    ap.add_argument("--workload", choices=["large", "batch", "warmstart"], default="large",
+    ap.add_argument("--workload", choices=["large", "tiny", "batch", "warmstart"], default="large",
                     help="large: one 2e6x1e6 LP (default); batch: 512 uneven LPs solved together")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--seq-sample", type=int, default=32,
@@ -211,6 +211,8 @@ def main():
         return
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "tiny":
+        return bench_tiny(args)
     if args.workload == "warmstart":
         return bench_warmstart(args)
     n = args.n
@@ -307,6 +309,62 @@ def main():
         "cpu_baseline": cpu,
         "load_s": load_s,
         "gen_s": gen_s,
+    }
+    print(json.dumps(out))
+
+
+def bench_tiny(args):
+    """The tiny LP (n=1000, m1=200, m2=300, 5 nonzeros per column; seeds
+    0..9).  Its data (about 0.2 MB) sits in L2, so the rate is set by kernel
+    launch and synchronisation latency, not by memory: the iteration rate of
+    captured graph windows, the time to rel KKT 1e-6 per instance (fresh
+    handle, load excluded), and the oracle's time to 1e-6 on one host core."""
+    import numpy as np
+    import torch
+    from paper_2312_14832_amd import gen, lp
+
+    lps = [gen.tiny_lp(s) for s in range(10)]
+    st = torch.cuda.current_stream()
+    p = lp.Problem(lps[0], stream=st)
+    p.solve(1e-30, ITERS_PER_STEP * max(args.warmup, 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = p.solve(1e-30, ITERS_PER_STEP * args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    iters = info["iterations"]
+    p.close()
+    print(f"[bench] tiny: {iters / dt:.0f} it/s", file=sys.stderr, flush=True)
+    ttt, ora = [], []
+    for s, data in enumerate(lps):
+        q = lp.Problem(data, stream=st)
+        t0 = time.perf_counter()
+        inf = q.solve(1e-6, 10**6)
+        torch.cuda.synchronize()
+        ttt.append({"seed": s, "seconds": time.perf_counter() - t0, "iterations": inf["iterations"],
+                    "status": inf["status"]})
+        q.close()
+        if not args.no_cpu:
+            from oracle.oracle import Oracle
+            o = Oracle(data)
+            t0 = time.perf_counter()
+            _, _, _, oi = o.solve(1e-6, 10**6)
+            ora.append({"seed": s, "seconds": time.perf_counter() - t0, "iterations": oi["iterations"]})
+    med = float(np.median([t["seconds"] for t in ttt]))
+    print(f"[bench] tiny: median time to 1e-6 {med * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    out = {
+        "metric": "PDHG iters/sec", "value": iters / dt, "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "tiny_lp_n1000", "n": 1000, "m1": 200, "m2": 300, "nnz": lps[0].nnz,
+                   "seeds": list(range(10)), "iters_per_step": ITERS_PER_STEP},
+        "roofline": {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None,
+                     "traffic": None,
+                     "note": "0.2 MB of data per iteration, resident in L2: launch and sync latency bound"},
+        "time_to_tol": {"tol": 1e-6, "median_s": med, "runs": ttt},
+        "cpu_baseline": ({"kind": "oracle", "cores": 1, "unit": "s to 1e-6",
+                          "median_s": float(np.median([o["seconds"] for o in ora])), "runs": ora}
+                         if ora else None),
     }
     print(json.dumps(out))
 
