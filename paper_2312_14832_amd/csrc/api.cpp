@@ -721,7 +721,7 @@ int do_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit)
         if (g) (void)hipGraphDestroy(g);
     }
     while (!P->hctl->done) {
-        const long long k_before = P->hctl->k;
+        const long long k_before = P->hctl->k, a_before = P->hctl->attempts;
         if (use_graph) {
             HIPT(hipGraphLaunch(P->graph, st));
         } else {
@@ -759,8 +759,12 @@ int do_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit)
                 use_graph = false;
             }
         }
-        (void)k_before;
         if (P->hctl->done) break;
+        if (P->hctl->k == k_before && P->hctl->attempts == a_before) {
+            // every slot takes a step decision, so a window always moves the counters
+            P->err = "no step decision in a whole window (controller stalled)";
+            return LP_ERR_HIP;
+        }
         if (time_limit > 0.0) {
             const double el = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
             if (el > time_limit) {
