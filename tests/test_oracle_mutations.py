@@ -20,6 +20,7 @@ MUTATIONS = {
 
 CHECKS = [
     ("two PDHG steps by hand", pins.check_two_steps_golden),
+    ("exact rational replay", pins.check_rational_replay),
     ("KKT_omega by hand", pins.check_kkt_omega_golden),
     ("termination quantities by hand", pins.check_termination_golden),
     ("scaling by hand", pins.check_scaling_golden),

@@ -381,3 +381,62 @@ def test_sketch_matrix_structure():
     assert np.all(cols == 8)
     rows = np.repeat(np.arange(64), np.diff(rp))
     assert len(set(zip(rows.tolist(), ci.tolist()))) == 8000   # distinct rows per column
+
+
+def test_exact_rational_replay_of_constant_step_pdhg(oracle_mod):
+    check_rational_replay(oracle_mod)
+
+
+def check_rational_replay(om, libpath=None):
+    """With a constant rational step, a rational primal weight and no scaling,
+    every PDHG quantity is rational (projections are clamps), so exact
+    arithmetic (fractions.Fraction) reproduces the iteration of Sec. 2
+    exactly.  50 steps of the FP64 oracle stay within 1e-14 relative of it,
+    averages included; the LP has a free, an upper-bounded, a boxed and a
+    lower-bounded column, one equality and two inequality rows."""
+    from fractions import Fraction as F
+    Kd = [[1, 2, 0, -1], [0, 1, 1, 1], [2, -1, 1, 0]]
+    c = [F(1), F(-2), F(3, 2), F(1, 2)]
+    q = [F(1), F(1, 2), F(-1)]
+    l = [-np.inf, -np.inf, 0.0, -1.0]
+    u = [np.inf, 3.0, 2.0, np.inf]
+    m1, m, n = 1, 3, 4
+    eta, omega = F(1, 8), F(1, 2)
+    tau, sigma = eta / omega, eta * omega
+
+    def clamp(v, lo, hi):
+        if lo != -np.inf and v < F(lo):
+            return F(lo)
+        if hi != np.inf and v > F(hi):
+            return F(hi)
+        return v
+
+    Kx = lambda x: [sum(F(Kd[i][j]) * x[j] for j in range(n)) for i in range(m)]
+    KTy = lambda y: [sum(F(Kd[i][j]) * y[i] for i in range(m)) for j in range(n)]
+    x = [clamp(F(0), l[j], u[j]) for j in range(n)]
+    y = [F(0)] * m
+    xbar, ybar, W = list(x), list(y), F(0)
+    exact = []
+    for k in range(50):
+        g = KTy(y)
+        xn = [clamp(x[j] - tau * (c[j] - g[j]), l[j], u[j]) for j in range(n)]
+        kxn, kx = Kx(xn), Kx(x)
+        yn = [y[i] + sigma * (q[i] - 2 * kxn[i] + kx[i]) for i in range(m)]
+        yn = [v if i < m1 else max(v, F(0)) for i, v in enumerate(yn)]
+        W += eta
+        xbar = [a + (eta / W) * (b - a) for a, b in zip(xbar, xn)]
+        ybar = [a + (eta / W) * (b - a) for a, b in zip(ybar, yn)]
+        x, y = xn, yn
+        exact.append((list(x), list(y), list(xbar), list(ybar)))
+
+    lp = gen.from_dense(np.array(Kd, float), [float(v) for v in c], [float(v) for v in q], l, u, m1)
+    o = om.Oracle(lp, ruiz_iters=0, pc_alpha=-1.0, fixed_step=True, fixed_eta=float(eta), libpath=libpath)
+    o.set_start_weight(float(omega))
+    for k in (1, 2, 7, 25, 50):
+        o.solve(1e-30, k)
+        st = o.get_state()
+        for key, ex in zip(("x", "y", "xbar", "ybar"), exact[k - 1]):
+            want = np.array([float(v) for v in ex])
+            scale = max(1.0, np.abs(want).max())
+            assert np.abs(st[key] - want).max() <= 1e-14 * scale, (k, key)
+    assert any(float(v) in (0.0, 2.0, 3.0, -1.0) for v in exact[-1][0])   # some bound is active
