@@ -144,6 +144,42 @@ def traffic_from(dirpath, precision, workload, copy_bytes):
     print("\n".join(lines))
 
 
+def compare_with_fp64(lp, data, prob, ttt, stream, args):
+    """Error of the mixed-precision result against FP64: its KKT quantities
+    evaluated in FP64 on the GPU (an FP64 handle started at the mixed point,
+    zero iterations), and the objective against an FP64 solve to the same
+    tolerance."""
+    import numpy as np
+    import torch
+    x, y, _, _ = prob.result()
+    p64 = lp.Problem(data, precision="fp64", stream=stream)
+    p64.set_start(x, y)
+    ev = p64.solve(1e-4, 0)
+    t0 = time.perf_counter()
+    p64.set_start(None, None)
+    ref = p64.solve(1e-4, 10**7, args.ttt_limit)
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t0
+    p64.close()
+    out = {"fp64_eval_of_mixed_point": {"rel_primal": ev["rel_primal"], "rel_dual": ev["rel_dual"],
+                                        "rel_gap": ev["rel_gap"], "rel_kkt": ev["rel_kkt"], "pobj": ev["pobj"]},
+           "fp64_solve": {"status": ref["status"], "iterations": ref["iterations"], "seconds": t64,
+                          "pobj": ref["pobj"], "rel_kkt": ref["rel_kkt"]},
+           "objective_rel_diff": abs(ttt["pobj"] - ref["pobj"]) / max(1.0, abs(ref["pobj"]))}
+    # how far apart the objectives of two points meeting the criteria at eps
+    # can be, to first order (value-function sensitivity to the residuals)
+    eps = 1e-4
+    band = 2.0 * (eps * (1 + abs(ev["pobj"]) + abs(ev["dobj"]))
+                  + np.linalg.norm(y) * eps * (1 + np.linalg.norm(data.q))
+                  + np.linalg.norm(x) * eps * (1 + np.linalg.norm(data.c)))
+    out["objective_band_rel"] = band / max(1.0, abs(ref["pobj"]))
+    print(f"[bench] mixed point in FP64: rel KKT {ev['rel_kkt']:.3e}; objective vs FP64 solve "
+          f"{out['objective_rel_diff']:.2e}, first-order band {out['objective_band_rel']:.2e} "
+          f"(FP64 solve {t64:.2f}s, {ref['iterations']} it)",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline(data, iters):
     from oracle.oracle import Oracle
     o = Oracle(data)
@@ -277,6 +313,9 @@ def main():
                "pobj": tinfo["pobj"], "time_limit_s": args.ttt_limit}
         print(f"[bench] time to 1e-4: {tt:.2f}s {tinfo['status']} after {tinfo['iterations']} iterations",
               file=sys.stderr, flush=True)
+    mixed_vs_fp64 = None
+    if not args.no_ttt and args.precision == "mixed":
+        mixed_vs_fp64 = compare_with_fp64(lp, data, prob, ttt, stream, args)
     prob.close()
 
     cpu = None
@@ -306,6 +345,7 @@ def main():
         "roofline": roofline,
         "spmv": spmv,
         "time_to_tol": ttt,
+        "mixed_vs_fp64": mixed_vs_fp64,
         "cpu_baseline": cpu,
         "load_s": load_s,
         "gen_s": gen_s,
