@@ -430,9 +430,11 @@ def bench_batch(args):
     print(f"[bench] generated {len(lps)} LPs, sum n={sum(p.n for p in lps)}, sum nnz={nnz} in {gen_s:.1f}s",
           file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    bt = lp.Batch(lps, precision=args.precision, stream=torch.cuda.current_stream())
+    bt = lp.Batch(lps, precision=args.precision, stream=torch.cuda.current_stream(), autotune=args.autotune)
     load_s = time.perf_counter() - t0
-    print(f"[bench] batch loaded in {load_s:.1f}s ({bt.device_bytes() / 2**30:.2f} GiB)", file=sys.stderr, flush=True)
+    shapes = {"K": bt.layout_blocks(0), "KT": bt.layout_blocks(1)}
+    print(f"[bench] batch loaded in {load_s:.1f}s ({bt.device_bytes() / 2**30:.2f} GiB), row blocks "
+          f"(nonzeros, rows) {shapes}", file=sys.stderr, flush=True)
     # warm-up: a short solve (graph capture, caches)
     bt.solve(1e-30, 64 * max(args.warmup, 1))
     torch.cuda.synchronize()
@@ -476,6 +478,7 @@ def bench_batch(args):
         "dtype": "f64" if args.precision == "fp64" else "f32+f64acc",
         "data": "synthetic",
         "config": {"workload": f"batch_{len(lps)}_uneven_lps", "count": len(lps), "sum_nnz": nnz,
+                   "row_blocks": {k: {"nnz_per_block": v[0], "rows_per_block": v[1]} for k, v in shapes.items()},
                    "seeds": [1000, 1000 + len(lps) - 1], "precision": args.precision, "tol": 1e-4},
         "batch_seconds": batch_s,
         "solved": solved,

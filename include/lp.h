@@ -95,8 +95,9 @@ typedef struct {
     int kernel_timing;      /* 1: bracket the two SpMV kernels with hipEvents (see lp_kernel_time) */
     int slice_kib;          /* target KiB of a gathered vector per column slice of K and K' (2048 = half an XCD's L2) */
     int autotune;           /* 1: at lp_load, time the slice count from slice_kib and its halved/doubled
-                               neighbours on the actual matrix and keep the fastest, per product (0);
-                               ignored when a workspace is given */
+                               neighbours and smaller row blocks on the actual matrix and keep the fastest,
+                               per product (0); ignored when a workspace is given.  At lp_batch_load: the
+                               row-block shape (lp_batch_layout_blocks) */
     int verbose;
     int ptr_kind;           /* LP_HOST (default) or LP_DEVICE */
     void *workspace;        /* NULL, or device memory of workspace_bytes bytes, 256-byte aligned, owned by
@@ -224,6 +225,12 @@ int lp_batch_result(const lp_batch *B, int32_t i, double *x, double *y, double *
 int lp_batch_get_state(const lp_batch *B, int32_t i, double *buf, int64_t *len);
 int lp_batch_set_state(lp_batch *B, int32_t i, const double *buf, int64_t len);
 int lp_batch_device_bytes(const lp_batch *B, int64_t *bytes);
+/* Row-block shape of the batch's products (which = 0: K, 1: K'): the most
+ * nonzeros and rows of one block.  With lp_options.autotune set, lp_batch_load
+ * times four shapes per product (2048 or 1024 nonzeros, 1024 or 256 rows) on
+ * the block-diagonal matrix and keeps the fastest; otherwise 2048 and 1024.
+ * Errors: LP_ERR_ARG for a bad `which`. */
+int lp_batch_layout_blocks(const lp_batch *B, int which, int *nnz_per_block, int *rows_per_block);
 void lp_batch_free(lp_batch *B);
 const char *lp_batch_last_error(const lp_batch *B);
 const char *lp_strerror(int code);

@@ -49,6 +49,7 @@ struct lp_batch {
     bool has_result = false;
     std::vector<char> state_set;
     std::vector<double> finish_s;   // per instance: seconds into the last solve when it finished
+    int shape[2][2] = {{kStreamNB, kStreamRB}, {kStreamNB, kStreamRB}};   // K, K': most nonzeros, rows per block
     double seconds = 0;
     std::string err;
 
@@ -68,6 +69,12 @@ namespace {
 
 void bsync(lp_batch *P) { HIPT(hipStreamSynchronize(P->stream)); }
 
+void release_blocks(lp_batch *P, const BlockList &L)
+{
+    for (const void *p : {(const void *)L.r0, (const void *)L.r1, (const void *)L.inst, (const void *)L.order})
+        P->arena.release(const_cast<void *>(p));
+}
+
 int fail(lp_batch *P, const HipError &h)
 {
     char buf[512];
@@ -76,15 +83,17 @@ int fail(lp_batch *P, const HipError &h)
     return h.e == hipErrorOutOfMemory ? LP_ERR_NOMEM : LP_ERR_HIP;
 }
 
-// row blocks of every instance's padded row range, dealt to XCDs
+// row blocks (at most nb nonzeros and rb rows) of every instance's padded
+// row range, dealt to XCDs
 BlockList make_blocks(lp_batch *P, const std::vector<int> &rp, const std::vector<int64_t> &off,
-                      const std::vector<int64_t> &len_pad, const std::vector<int> &xcd_of)
+                      const std::vector<int64_t> &len_pad, const std::vector<int> &xcd_of, int nb = kStreamNB,
+                      int rb = kStreamRB)
 {
     const int B = P->B;
     std::vector<int> r0, r1, inst;
     for (int i = 0; i < B; ++i) {
         std::vector<int> ends;
-        row_blocks(rp.data(), (int)off[i], (int)(off[i] + len_pad[i]), ends);
+        row_blocks(rp.data(), (int)off[i], (int)(off[i] + len_pad[i]), ends, nb, rb);
         int start = (int)off[i];
         for (int e : ends) {
             r0.push_back(start);
@@ -291,6 +300,56 @@ int do_batch_load(lp_batch *P, const lp_csr *K, const double *const *c, const do
         b.LK = make_blocks(P, rp, P->moff, mpad, xcd_of);
         b.LT = make_blocks(P, tp, P->noff, npad, xcd_of);
         bsync(P);
+        if (P->opt.autotune) {
+            // row-block shapes timed on the actual block-diagonal matrix, per
+            // product: the default and smaller nonzero and row limits
+            const int cand[][2] = {{kStreamNB, kStreamRB}, {kStreamNB / 2, kStreamRB}, {kStreamNB, 256},
+                                   {kStreamNB / 2, 256}};
+            // vectors of ones in the trial buffers (overwritten by every solve's start)
+            HIPT(launch_fill(P->stage_n0, 1.0, N, st));
+            HIPT(launch_fill(P->stage_m, 1.0, M, st));
+            HIPT(launch_from_double<T>(P->stage_n0, d.xb[1], N, st));
+            HIPT(launch_from_double<T>(P->stage_m, d.yb[1], M, st));
+            hipEvent_t e0, e1;
+            HIPT(hipEventCreate(&e0));
+            HIPT(hipEventCreate(&e1));
+            for (int which = 0; which < 2; ++which) {
+                BlockList &cur = which ? b.LT : b.LK;
+                float best_ms = 0;
+                int best = 0;
+                for (int k = 0; k < 4; ++k) {
+                    const BlockList L = k == 0 ? cur
+                                               : make_blocks(P, which ? tp : rp, which ? P->noff : P->moff,
+                                                             which ? npad : mpad, xcd_of, cand[k][0], cand[k][1]);
+                    BDev<T> t = b;
+                    (which ? t.LT : t.LK) = L;
+                    const T *in = which ? d.yb[1] : d.xb[1];
+                    T *out = which ? b.prodKT : b.prodK;
+                    for (int r = 0; r < 2; ++r) HIPT(launch_batch_product_plain<T>(t, which, in, out, st));
+                    HIPT(hipEventRecord(e0, st));
+                    for (int r = 0; r < 5; ++r) HIPT(launch_batch_product_plain<T>(t, which, in, out, st));
+                    HIPT(hipEventRecord(e1, st));
+                    HIPT(hipEventSynchronize(e1));
+                    float ms = 0;
+                    HIPT(hipEventElapsedTime(&ms, e0, e1));
+                    if (P->opt.verbose)
+                        fprintf(stderr, "[lp_batch] product %d: blocks of <= %d nonzeros, <= %d rows: %.3f ms\n",
+                                which, cand[k][0], cand[k][1], ms / 5);
+                    if (k == 0 || ms < best_ms) {
+                        if (k > 0) release_blocks(P, cur);
+                        cur = L;
+                        best_ms = ms;
+                        best = k;
+                    } else {
+                        release_blocks(P, L);
+                    }
+                }
+                P->shape[which][0] = cand[best][0];
+                P->shape[which][1] = cand[best][1];
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+        }
     };
     if (P->mixed) setup(float{});
     else setup(double{});
@@ -648,6 +707,14 @@ int lp_batch_set_state(lp_batch *P, int32_t i, const double *buf, int64_t len)
     } catch (const HipError &h) {
         return fail(P, h);
     }
+}
+
+int lp_batch_layout_blocks(const lp_batch *P, int which, int *nnz_per_block, int *rows_per_block)
+{
+    if (!P || (which != 0 && which != 1)) return LP_ERR_ARG;
+    if (nnz_per_block) *nnz_per_block = P->shape[which][0];
+    if (rows_per_block) *rows_per_block = P->shape[which][1];
+    return LP_OK;
 }
 
 int lp_batch_device_bytes(const lp_batch *P, int64_t *bytes)

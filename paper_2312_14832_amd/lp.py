@@ -26,7 +26,8 @@ EXPORTS = ["lp_default_options", "lp_workspace_size", "lp_load", "lp_set_start",
            "lp_set_state", "lp_get_scaling", "lp_spmv", "lp_kernel_time", "lp_device_bytes", "lp_layout",
            "lp_layout_blocks", "lp_free",
            "lp_strerror", "lp_last_error", "lp_batch_load", "lp_batch_solve", "lp_batch_result",
-           "lp_batch_get_state", "lp_batch_set_state", "lp_batch_device_bytes", "lp_batch_free",
+           "lp_batch_get_state", "lp_batch_set_state", "lp_batch_device_bytes", "lp_batch_layout_blocks",
+           "lp_batch_free",
            "lp_batch_last_error"]
 
 
@@ -95,6 +96,7 @@ def library():
         L.lp_batch_get_state.argtypes = [C.c_void_p, C.c_int32, dp, C.POINTER(C.c_int64)]
         L.lp_batch_set_state.argtypes = [C.c_void_p, C.c_int32, dp, C.c_int64]
         L.lp_batch_device_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+        L.lp_batch_layout_blocks.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.lp_batch_free.argtypes = [C.c_void_p]
         L.lp_batch_free.restype = None
         L.lp_batch_last_error.argtypes = [C.c_void_p]
@@ -378,6 +380,12 @@ class Batch:
     def set_state(self, i, buf):
         buf = _f64(buf)
         self._check(library().lp_batch_set_state(self.h, int(i), _dp(buf), buf.size))
+
+    def layout_blocks(self, which):
+        """(most nonzeros, most rows) of one row block of K (0) or K' (1)."""
+        nb, rb = C.c_int(), C.c_int()
+        self._check(library().lp_batch_layout_blocks(self.h, which, C.byref(nb), C.byref(rb)))
+        return nb.value, rb.value
 
     def device_bytes(self):
         b = C.c_int64()

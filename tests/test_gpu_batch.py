@@ -111,3 +111,28 @@ def test_batch_resume_bitwise(lpmod):
         if full[i][5] < 256:
             continue  # met rel KKT <= 1e-30 exactly before 256 steps: its state stopped there
         assert np.array_equal(bt.get_state(i)[16:], full[i][16:]), i
+
+
+def test_batch_autotuned_layout(lpmod):
+    """With autotune the batch keeps one of the four timed row-block shapes
+    per product, and the method is unchanged: one step from the same state
+    matches the untuned batch to 1e-10 (only the summation order of rows
+    longer than a block can differ; 40 steps stay inside the first check
+    window), and every instance still solves to 1e-4."""
+    say("case batch autotune")
+    lps = small_batch(8, seed0=4000)
+    tuned = lpmod.Batch(lps, autotune=1)
+    plain = lpmod.Batch(lps)
+    shapes = {(2048, 1024), (1024, 1024), (2048, 256), (1024, 256)}
+    assert tuned.layout_blocks(0) in shapes and tuned.layout_blocks(1) in shapes
+    assert plain.layout_blocks(0) == (2048, 1024) == plain.layout_blocks(1)
+    tuned.solve(1e-30, 40)
+    plain.solve(1e-30, 40)
+    for i, p in enumerate(lps):
+        st, sp = (lpmod.unpack_state(b.get_state(i), p.n, p.m) for b in (tuned, plain))
+        assert ints_equal(st, sp), i
+        wv, vv = vec_diff(st, sp)
+        assert wv < PER_STEP_TOL, (i, vv, wv)
+    tuned.solve(1e-4, 200000, 120.0)
+    for i in range(len(lps)):
+        assert tuned.info(i)["status"] == "OPTIMAL", i
