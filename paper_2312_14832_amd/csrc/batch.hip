@@ -50,10 +50,13 @@ __global__ __launch_bounds__(kBlock) void bk_product_plain(BDev<T> b, const T *_
     }
 }
 
-// one workgroup per m-chunk
+// one workgroup per m-chunk; workgroup 0 also lowers the check gate, which
+// the step decisions of this slot raise again if an instance checks
 template <typename T>
 __global__ __launch_bounds__(kBlock) void bk_dual(BDev<T> b)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *b.gate = 0;
+    if ((int)blockIdx.x >= b.ncm) return;
     const int inst = b.cinst_m[blockIdx.x];
     const Ctl *ctl = b.ctl + inst;
     if (ctl->done) return;
@@ -79,7 +82,10 @@ __global__ __launch_bounds__(kBlock) void bk_step_decide(BDev<T> b)
     double a[1], c2[2];
     block_sum_partials<1>(b.d.part_primal + b.nc0[blockIdx.x], b.ncc[blockIdx.x], a);
     block_sum_partials<2>(b.d.part_dual + 2 * (size_t)b.mc0[blockIdx.x], b.mcc[blockIdx.x], c2);
-    if (threadIdx.x == 0) step_decision(ctl, a[0], c2[0], c2[1]);
+    if (threadIdx.x == 0) {
+        step_decision(ctl, a[0], c2[0], c2[1]);
+        if (ctl->mode != MODE_NONE) atomicExch(b.gate, 1);
+    }
 }
 
 // one workgroup per n-chunk, then one per m-chunk
@@ -112,33 +118,42 @@ __global__ __launch_bounds__(kBlock) void bk_update(BDev<T> b)
     }
 }
 
+// The check kernels walk 256-element chunks (each inside one instance) with
+// a grid stride, each chunk's partial in its own slot.  Inside the solve
+// loop (gated) they return at once unless this slot's step decisions put
+// some instance into a check; the host-driven start, resume and final checks
+// run ungated.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void bk_check_reduce(BDev<T> b)
+__global__ __launch_bounds__(kBlock) void bk_check_reduce(BDev<T> b, int gated)
 {
-    const bool nside = (int)blockIdx.x < b.ncn;
-    const int chunk = nside ? (int)blockIdx.x : (int)blockIdx.x - b.ncn;
-    const int inst = nside ? b.cinst_n[chunk] : b.cinst_m[chunk];
-    const Ctl *ctl = b.ctl + inst;
-    if (ctl->mode == MODE_NONE || ctl->done) return;
-    const Dev<T> &d = b.d;
-    const int c = ctl->cur;
-    const int e = chunk * kBlock + (int)threadIdx.x;
-    double s[kCheckSums];
+    if (gated && *b.gate == 0) return;
+    for (int ch = blockIdx.x; ch < b.ncn + b.ncm; ch += gridDim.x) {
+        const bool nside = ch < b.ncn;
+        const int chunk = nside ? ch : ch - b.ncn;
+        const int inst = nside ? b.cinst_n[chunk] : b.cinst_m[chunk];
+        const Ctl *ctl = b.ctl + inst;
+        if (ctl->mode == MODE_NONE || ctl->done) continue;
+        const Dev<T> &d = b.d;
+        const int c = ctl->cur;
+        const int e = chunk * kBlock + (int)threadIdx.x;
+        double s[kCheckSums];
 #pragma unroll
-    for (int i = 0; i < kCheckSums; ++i) s[i] = 0.0;
-    if (nside) {
-        col_sums(d, e, (const T *)pick(d.xb, c), (const T *)pick(d.KTyb, c), s);
-        col_sums(d, e, (const T *)d.xa, (const T *)d.KTya, s + 9);
-    } else {
-        row_sums(d, e, b.m1g[inst], (const T *)pick(d.yb, c), (const T *)pick(d.Kxb, c), s);
-        row_sums(d, e, b.m1g[inst], (const T *)d.ya, (const T *)d.Kxa, s + 9);
+        for (int i = 0; i < kCheckSums; ++i) s[i] = 0.0;
+        if (nside) {
+            col_sums(d, e, (const T *)pick(d.xb, c), (const T *)pick(d.KTyb, c), s);
+            col_sums(d, e, (const T *)d.xa, (const T *)d.KTya, s + 9);
+        } else {
+            row_sums(d, e, b.m1g[inst], (const T *)pick(d.yb, c), (const T *)pick(d.Kxb, c), s);
+            row_sums(d, e, b.m1g[inst], (const T *)d.ya, (const T *)d.Kxa, s + 9);
+        }
+        block_store_partials<kCheckSums>(s, d.part_check, ch);
     }
-    block_store_partials<kCheckSums>(s, d.part_check);
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void bk_check_decide(BDev<T> b)
+__global__ __launch_bounds__(kBlock) void bk_check_decide(BDev<T> b, int gated)
 {
+    if (gated && *b.gate == 0) return;
     Ctl *ctl = b.ctl + blockIdx.x;
     if (ctl->mode == MODE_NONE || ctl->done) return;
     double Sn[kCheckSums], Sm[kCheckSums];
@@ -152,23 +167,27 @@ __global__ __launch_bounds__(kBlock) void bk_check_decide(BDev<T> b)
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void bk_check_apply(BDev<T> b)
+__global__ __launch_bounds__(kBlock) void bk_check_apply(BDev<T> b, int gated)
 {
-    const bool nside = (int)blockIdx.x < b.ncn;
-    const int chunk = nside ? (int)blockIdx.x : (int)blockIdx.x - b.ncn;
-    const int inst = nside ? b.cinst_n[chunk] : b.cinst_m[chunk];
-    const Ctl *ctl = b.ctl + inst;
-    if (ctl->mode == MODE_NONE) return;
-    const Dev<T> &d = b.d;
-    const int c = ctl->cur, rt = ctl->restart_to, co = ctl->copy_out, sel = ctl->out_sel, np = ctl->need_primal;
-    const int e = chunk * kBlock + (int)threadIdx.x;
-    double dx2 = 0.0;
-    if (nside) {
-        apply_col(d, e, c, rt, co, sel, np, (T)(ctl->eta / ctl->omega), dx2);
-        double v[1] = {dx2};
-        block_store_partials<1>(v, d.part_primal);
-    } else {
-        apply_row(d, e, c, rt, co, sel);
+    if (gated && *b.gate == 0) return;
+    for (int ch = blockIdx.x; ch < b.ncn + b.ncm; ch += gridDim.x) {
+        const bool nside = ch < b.ncn;
+        const int chunk = nside ? ch : ch - b.ncn;
+        const int inst = nside ? b.cinst_n[chunk] : b.cinst_m[chunk];
+        const Ctl *ctl = b.ctl + inst;
+        if (ctl->mode == MODE_NONE) continue;
+        const Dev<T> &d = b.d;
+        const int c = ctl->cur, rt = ctl->restart_to, co = ctl->copy_out, sel = ctl->out_sel;
+        const int np = ctl->need_primal;
+        const int e = chunk * kBlock + (int)threadIdx.x;
+        double dx2 = 0.0;
+        if (nside) {
+            apply_col(d, e, c, rt, co, sel, np, (T)(ctl->eta / ctl->omega), dx2);
+            double v[1] = {dx2};
+            block_store_partials<1>(v, d.part_primal, chunk);
+        } else {
+            apply_row(d, e, c, rt, co, sel);
+        }
     }
 }
 
@@ -218,6 +237,9 @@ __global__ void k_seg_absmax(const double *a, const int64_t *off, double *out)
 
 // ----------------------------------------------------------------------------
 
+// workgroups of a chunk-striding batch kernel: every chunk, at most 4096
+inline int chunk_grid(int chunks) { return chunks < 1 ? 1 : (chunks < 4096 ? chunks : 4096); }
+
 template <typename T>
 hipError_t launch_batch_product(const BDev<T> &b, int which, hipStream_t s)
 {
@@ -237,7 +259,7 @@ hipError_t launch_batch_product_plain(const BDev<T> &b, int which, const T *in, 
 template <typename T>
 hipError_t launch_batch_dual(const BDev<T> &b, hipStream_t s)
 {
-    hipLaunchKernelGGL(bk_dual<T>, dim3(b.ncm), dim3(kBlock), 0, s, b);
+    hipLaunchKernelGGL(bk_dual<T>, dim3(b.ncm > 0 ? b.ncm : 1), dim3(kBlock), 0, s, b);
     return hipGetLastError();
 }
 
@@ -256,18 +278,18 @@ hipError_t launch_batch_update(const BDev<T> &b, hipStream_t s)
 }
 
 template <typename T>
-hipError_t launch_batch_check(const BDev<T> &b, hipStream_t s)
+hipError_t launch_batch_check(const BDev<T> &b, int gated, hipStream_t s)
 {
-    hipLaunchKernelGGL(bk_check_reduce<T>, dim3(b.ncn + b.ncm), dim3(kBlock), 0, s, b);
-    hipLaunchKernelGGL(bk_check_decide<T>, dim3(b.B), dim3(kBlock), 0, s, b);
-    hipLaunchKernelGGL(bk_check_apply<T>, dim3(b.ncn + b.ncm), dim3(kBlock), 0, s, b);
+    hipLaunchKernelGGL(bk_check_reduce<T>, dim3(chunk_grid(b.ncn + b.ncm)), dim3(kBlock), 0, s, b, gated);
+    hipLaunchKernelGGL(bk_check_decide<T>, dim3(b.B), dim3(kBlock), 0, s, b, gated);
+    hipLaunchKernelGGL(bk_check_apply<T>, dim3(chunk_grid(b.ncn + b.ncm)), dim3(kBlock), 0, s, b, gated);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_batch_apply(const BDev<T> &b, hipStream_t s)
 {
-    hipLaunchKernelGGL(bk_check_apply<T>, dim3(b.ncn + b.ncm), dim3(kBlock), 0, s, b);
+    hipLaunchKernelGGL(bk_check_apply<T>, dim3(chunk_grid(b.ncn + b.ncm)), dim3(kBlock), 0, s, b, 0);
     return hipGetLastError();
 }
 
@@ -303,7 +325,7 @@ hipError_t launch_seg_absmax(const double *a, const int64_t *off, int B, double 
     template hipError_t launch_batch_dual<T>(const BDev<T> &, hipStream_t);                                        \
     template hipError_t launch_batch_step_decide<T>(const BDev<T> &, hipStream_t);                                 \
     template hipError_t launch_batch_update<T>(const BDev<T> &, hipStream_t);                                      \
-    template hipError_t launch_batch_check<T>(const BDev<T> &, hipStream_t);                                       \
+    template hipError_t launch_batch_check<T>(const BDev<T> &, int, hipStream_t);                                  \
     template hipError_t launch_batch_apply<T>(const BDev<T> &, hipStream_t);                                       \
     template hipError_t launch_batch_start<T>(const BDev<T> &, hipStream_t);
 

@@ -281,6 +281,8 @@ int do_batch_load(lp_batch *P, const lp_csr *K, const double *const *c, const do
         d.part_check = A.make<double>((int64_t)kCheckSums * (b.ncn + b.ncm));
         b.ctl = A.make<Ctl>(B);
         d.ctl = b.ctl;
+        b.gate = A.make<int>(1);
+        HIPT(hipMemsetAsync(b.gate, 0, sizeof(int), st));
         int *d_cin = A.make<int>(b.ncn), *d_cim = A.make<int>(b.ncm);
         int *d_nc0 = A.make<int>(B), *d_ncc = A.make<int>(B), *d_mc0 = A.make<int>(B), *d_mcc = A.make<int>(B);
         int *d_m1g = A.make<int>(B);
@@ -373,7 +375,7 @@ void batch_slot(lp_batch *P)
     HIPT(launch_batch_step_decide<T>(b, st));
     HIPT(launch_batch_product<T>(b, 1, st));
     HIPT(launch_batch_update<T>(b, st));
-    HIPT(launch_batch_check<T>(b, st));
+    HIPT(launch_batch_check<T>(b, 1, st));
 }
 
 void put_ctls(lp_batch *P, Ctl *d)
@@ -430,7 +432,7 @@ int do_batch_solve(lp_batch *P, double tol, int64_t max_iters, double time_limit
         d2d(st, d.ya, (const T *)d.yb[0], M);
         d2d(st, d.y0, (const T *)d.yb[0], M);
         d2d(st, d.Kxa, (const T *)d.Kxb[0], M);
-        HIPT(launch_batch_check<T>(b, st));
+        HIPT(launch_batch_check<T>(b, 0, st));
     } else {
         for (int i = 0; i < B; ++i) {
             Ctl &c = P->hctl[i];
@@ -459,7 +461,7 @@ int do_batch_solve(lp_batch *P, double tol, int64_t max_iters, double time_limit
         if (!P->hctl[i].done && P->hctl[i].k >= max_iters) any_at_limit = true;
     if (any_at_limit) {
         HIPT(launch_batch_set_final(b.ctl, B, LP_ITERATION_LIMIT, st));
-        HIPT(launch_batch_check<T>(b, st));
+        HIPT(launch_batch_check<T>(b, 0, st));
         get_ctls(P, b.ctl);
     }
     P->finish_s.assign(B, -1.0);
@@ -495,7 +497,7 @@ int do_batch_solve(lp_batch *P, double tol, int64_t max_iters, double time_limit
         left = note_finished();
         if (left > 0 && time_limit > 0.0 && elapsed() > time_limit) {
             HIPT(launch_batch_set_final(b.ctl, B, LP_TIME_LIMIT, st));
-            HIPT(launch_batch_check<T>(b, st));
+            HIPT(launch_batch_check<T>(b, 0, st));
             get_ctls(P, b.ctl);
             left = note_finished();
             break;

@@ -38,7 +38,7 @@ __device__ __forceinline__ double proj_lambda(double g, bool lf, bool uf)
 // One FP64 partial per workgroup and value: wave64 butterfly, then the four
 // wave results added in a fixed order.
 template <int NV>
-__device__ __forceinline__ void block_store_partials(double (&v)[NV], double *out)
+__device__ __forceinline__ void block_store_partials(double (&v)[NV], double *out, int slot = -1)
 {
     __shared__ double sh[kBlock / 64][NV];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -56,8 +56,10 @@ __device__ __forceinline__ void block_store_partials(double (&v)[NV], double *ou
     __syncthreads();
     if (threadIdx.x < NV) {
         const int i = threadIdx.x;
-        out[(size_t)blockIdx.x * NV + i] = ((sh[0][i] + sh[1][i]) + sh[2][i]) + sh[3][i];
+        const size_t at = slot < 0 ? (size_t)blockIdx.x : (size_t)slot;
+        out[at * NV + i] = ((sh[0][i] + sh[1][i]) + sh[2][i]) + sh[3][i];
     }
+    if (slot >= 0) __syncthreads();   // the caller loops: sh is written again next round
 }
 
 // Sum np partials of NV values each inside one workgroup; every thread gets

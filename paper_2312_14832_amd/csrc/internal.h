@@ -125,6 +125,7 @@ struct BDev {
     const int *m1g;           // per instance: first inequality row (global index)
     const double *Nq, *Nc;    // per instance: |q|, |c| of the unscaled data
     Ctl *ctl;                 // [B]
+    int *gate;                // 1 while some instance is in a check this slot
 };
 
 template <typename T> hipError_t launch_batch_product(const BDev<T> &b, int which, hipStream_t s);
@@ -133,7 +134,9 @@ template <typename T> hipError_t launch_batch_product_plain(const BDev<T> &b, in
 template <typename T> hipError_t launch_batch_dual(const BDev<T> &b, hipStream_t s);
 template <typename T> hipError_t launch_batch_step_decide(const BDev<T> &b, hipStream_t s);
 template <typename T> hipError_t launch_batch_update(const BDev<T> &b, hipStream_t s);
-template <typename T> hipError_t launch_batch_check(const BDev<T> &b, hipStream_t s);
+// gated = 1 inside the solve loop: the check kernels return at once unless
+// this slot's step decisions raised the gate
+template <typename T> hipError_t launch_batch_check(const BDev<T> &b, int gated, hipStream_t s);
 template <typename T> hipError_t launch_batch_apply(const BDev<T> &b, hipStream_t s);
 template <typename T> hipError_t launch_batch_start(const BDev<T> &b, hipStream_t s);
 hipError_t launch_batch_set_final(Ctl *ctl, int B, int status, hipStream_t s);
