@@ -82,11 +82,12 @@ void build_sliced(HostSliced &H, int rows, int cols, const std::vector<int> &rp,
         r[rows] = (int)pos;
         H.brow.push_back(0);
         const size_t before = H.brow.size();
-        row_blocks(r, 0, rows, H.brow, H.nb, H.rb);
+        std::vector<char> wave;
+        row_blocks(r, 0, rows, H.brow, wave, H.nb, H.rb);
         const int nb = (int)(H.brow.size() - before);
         for (int k = 0; k < nb; ++k) {
             const int r0 = H.brow[before - 1 + k], r1 = H.brow[before + k];
-            H.blk.push_back(make_int4(r0, r1, r[r0], r[r1]));
+            H.blk.push_back(make_int4(r0, wave[k] ? ~r1 : r1, r[r0], r[r1]));
         }
         H.boff[s + 1] = H.boff[s] + nb;
         H.max_blocks = std::max(H.max_blocks, nb);

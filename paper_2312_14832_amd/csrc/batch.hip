@@ -10,6 +10,17 @@
 
 namespace pdlp {
 
+// row block blk of a batch product (end row complemented for long rows)
+template <typename T>
+__device__ __forceinline__ void batch_block(const int *rp, const int *ci, const T *v, const T *x, const BlockList &L,
+                                            int blk, T *out, T *prod, double *red)
+{
+    const int r0 = L.r0[blk], r1e = L.r1[blk];
+    const bool wave = r1e < 0;
+    const int r1 = wave ? ~r1e : r1e;
+    stream_block(rp, ci, v, x, r0, r1, wave, rp[r0], rp[r1], out, prod, red);
+}
+
 template <typename T, int WHICH>
 __global__ __launch_bounds__(kBlock) void bk_product(BDev<T> b)
 {
@@ -23,11 +34,9 @@ __global__ __launch_bounds__(kBlock) void bk_product(BDev<T> b)
         const Ctl *c = b.ctl + L.inst[blk];
         if (c->done || (WHICH == 1 && !c->accepted)) continue;
         if (WHICH == 0)
-            stream_block(b.krp, b.kci, b.kv, (const T *)pick(b.d.xb, c->cur ^ 1), L.r0[blk], L.r1[blk],
-                         b.krp[L.r0[blk]], b.krp[L.r1[blk]], b.prodK, prod, red);
+            batch_block(b.krp, b.kci, b.kv, (const T *)pick(b.d.xb, c->cur ^ 1), L, blk, b.prodK, prod, red);
         else
-            stream_block(b.trp, b.tci, b.tv, (const T *)pick(b.d.yb, c->cur), L.r0[blk], L.r1[blk],
-                         b.trp[L.r0[blk]], b.trp[L.r1[blk]], b.prodKT, prod, red);
+            batch_block(b.trp, b.tci, b.tv, (const T *)pick(b.d.yb, c->cur), L, blk, b.prodKT, prod, red);
     }
 }
 
@@ -41,12 +50,8 @@ __global__ __launch_bounds__(kBlock) void bk_product_plain(BDev<T> b, const T *_
     const int per = (int)gridDim.x / kXcds;
     for (int k = L.xoff[xcd] + (int)blockIdx.x / kXcds; k < L.xoff[xcd + 1]; k += per) {
         const int blk = L.order[k];
-        if (WHICH == 0)
-            stream_block(b.krp, b.kci, b.kv, in, L.r0[blk], L.r1[blk], b.krp[L.r0[blk]], b.krp[L.r1[blk]], out, prod,
-                         red);
-        else
-            stream_block(b.trp, b.tci, b.tv, in, L.r0[blk], L.r1[blk], b.trp[L.r0[blk]], b.trp[L.r1[blk]], out, prod,
-                         red);
+        if (WHICH == 0) batch_block(b.krp, b.kci, b.kv, in, L, blk, out, prod, red);
+        else batch_block(b.trp, b.tci, b.tv, in, L, blk, out, prod, red);
     }
 }
 

@@ -93,13 +93,14 @@ BlockList make_blocks(lp_batch *P, const std::vector<int> &rp, const std::vector
     std::vector<int> r0, r1, inst;
     for (int i = 0; i < B; ++i) {
         std::vector<int> ends;
-        row_blocks(rp.data(), (int)off[i], (int)(off[i] + len_pad[i]), ends, nb, rb);
+        std::vector<char> wave;
+        row_blocks(rp.data(), (int)off[i], (int)(off[i] + len_pad[i]), ends, wave, nb, rb);
         int start = (int)off[i];
-        for (int e : ends) {
+        for (size_t k = 0; k < ends.size(); ++k) {
             r0.push_back(start);
-            r1.push_back(e);
+            r1.push_back(wave[k] ? ~ends[k] : ends[k]);
             inst.push_back(i);
-            start = e;
+            start = ends[k];
         }
     }
     BlockList L{};

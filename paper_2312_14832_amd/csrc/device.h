@@ -431,15 +431,17 @@ __device__ __forceinline__ void average_row(const Dev<T> &d, int i, int c, T w)
     d.Kxa[i] = b + w * (kx[i] - b);
 }
 
-// CSR-Stream sums of one row block: rows [r0, r1) (at most kStreamRB) whose
-// entries are [b, e) of a CSR with global row pointers rp.  Products are
-// staged in LDS and each thread sums every kBlock-th row in index order.  A
-// block of one row longer than kStreamNB is summed by the whole workgroup.
+// CSR-Stream sums of one row block: rows [r0, r1) whose entries are [b, e)
+// of a CSR with global row pointers rp.  Products are staged in LDS; in a
+// block of short rows (at most kStreamRB) each thread sums every kBlock-th
+// row in index order, in a block of long rows (wave set, at most kBlock/64)
+// each wavefront sums one row, lanes striding and a butterfly combining them.
+// A block of one row longer than kStreamNB is summed by the whole workgroup.
 // Every thread of the workgroup must call it.
 template <typename T>
 __device__ __forceinline__ void stream_block(const int *__restrict__ rp, const int *__restrict__ ci,
                                              const T *__restrict__ v, const T *__restrict__ x, int r0, int r1,
-                                             int b, int e, T *__restrict__ out, T *prod, double *red)
+                                             bool wave, int b, int e, T *__restrict__ out, T *prod, double *red)
 {
     const int cnt = e - b;
     // a multi-row block never exceeds kStreamNB nonzeros, only a single row can
@@ -475,13 +477,25 @@ __device__ __forceinline__ void stream_block(const int *__restrict__ rp, const i
             }
         }
         __syncthreads();
+        if (!wave) {
 #pragma unroll
-        for (int j = 0; j < RU; ++j) {
-            const int r = r0 + (int)threadIdx.x + j * kBlock;
-            if (r < r1) {
+            for (int j = 0; j < RU; ++j) {
+                const int r = r0 + (int)threadIdx.x + j * kBlock;
+                if (r < r1) {
+                    T acc = T(0);
+                    for (int p = rs[j] - b; p < re[j] - b; ++p) acc += prod[p];
+                    out[r] = acc;
+                }
+            }
+        } else {
+            const int r = r0 + ((int)threadIdx.x >> 6), lane = (int)threadIdx.x & 63;
+            if (r < r1) {   // uniform over the wavefront
+                const int p1 = rp[r + 1] - b;
                 T acc = T(0);
-                for (int p = rs[j] - b; p < re[j] - b; ++p) acc += prod[p];
-                out[r] = acc;
+                for (int p = rp[r] - b + lane; p < p1; p += 64) acc += prod[p];
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+                if (lane == 0) out[r] = acc;
             }
         }
         __syncthreads();
@@ -540,7 +554,8 @@ __device__ __forceinline__ void sliced_partial(const Sliced<T> &P, const T *__re
     const int4 *bd = P.blk + P.boff[s];
     for (int k = chunk0; k < nblk; k += stride) {
         const int4 q = bd[k];
-        stream_block(rp, P.ci, P.v, x, q.x, q.y, q.z, q.w, out, prod, red);
+        const bool wave = q.y < 0;
+        stream_block(rp, P.ci, P.v, x, q.x, wave ? ~q.y : q.y, wave, q.z, q.w, out, prod, red);
     }
 }
 

@@ -96,15 +96,21 @@ void transpose_csr(int rows, int cols, const std::vector<int> &rp, const std::ve
         }
 }
 
-void row_blocks(const int *rp, int r_begin, int r_end, std::vector<int> &ends, int nb_max, int rb_max)
+void row_blocks(const int *rp, int r_begin, int r_end, std::vector<int> &ends, std::vector<char> &wave, int nb_max,
+                int rb_max)
 {
     if (nb_max > kStreamNB || nb_max < 1) nb_max = kStreamNB;
     if (rb_max > kStreamRB || rb_max < 1) rb_max = kStreamRB;
+    auto len = [&](int r) { return rp[r + 1] - rp[r]; };
     int start = r_begin;
     while (start < r_end) {
+        const bool lng = len(start) > kWaveRow;
+        const int most = lng ? kBlock / 64 : rb_max;
         int end = start + 1;
-        while (end < r_end && end - start < rb_max && rp[end + 1] - rp[start] <= nb_max) ++end;
+        while (end < r_end && end - start < most && (len(end) > kWaveRow) == lng && rp[end + 1] - rp[start] <= nb_max)
+            ++end;
         ends.push_back(end);
+        wave.push_back(lng ? 1 : 0);
         start = end;
     }
 }

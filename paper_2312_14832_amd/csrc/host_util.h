@@ -94,7 +94,12 @@ void transpose_csr(int rows, int cols, const std::vector<int> &rp, const std::ve
 // CSR-Stream row blocks of rows [r_begin, r_end): at most kStreamRB rows and
 // nb_max (<= kStreamNB) nonzeros each (a longer single row is a block of its
 // own).  Appends block end rows to `ends` (the first block starts at r_begin).
-void row_blocks(const int *rp, int r_begin, int r_end, std::vector<int> &ends, int nb_max = kStreamNB,
-                int rb_max = kStreamRB);
+// Row blocks of rows [r_begin, r_end): runs of rows of at most kWaveRow
+// entries (at most rb_max rows and nb_max entries), and groups of up to
+// kBlock/64 longer rows (at most nb_max entries; a row longer than that is a
+// block of its own).  ends[k] is the end row of block k; wave[k] = 1 marks a
+// group of long rows.
+void row_blocks(const int *rp, int r_begin, int r_end, std::vector<int> &ends, std::vector<char> &wave,
+                int nb_max = kStreamNB, int rb_max = kStreamRB);
 
 }  // namespace pdlp

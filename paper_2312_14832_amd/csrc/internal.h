@@ -14,6 +14,10 @@ constexpr int kCheckSums = 18;   // 9 sums for the current and 9 for the average
 constexpr int kXcds = 8;         // MI355X: 8 XCDs, workgroups dealt to them round-robin
 constexpr int kStreamNB = 2048;  // nonzeros staged in LDS per row block
 constexpr int kStreamRB = 1024;  // most rows per row block (each thread sums every 256th row)
+constexpr int kWaveRow = 64;     // rows longer than this are summed by a whole wavefront
+// A row block is either a run of rows of at most kWaveRow entries (thread per
+// row) or up to kBlock/64 longer rows (wavefront per row); a wavefront block's
+// end row is stored complemented (~end) in the block descriptor.
 
 // One sparse product y = A x split by COLUMNS into S contiguous slices.  The
 // slice of x a workgroup gathers from is small enough to stay in one XCD's
@@ -31,7 +35,8 @@ struct Sliced {
     const int *rp;    // [S*(rows+1)] per-slice row pointers into ci / v
     const int *ci;    // column indices, slice-major
     const T *v;       // values, same layout
-    const int4 *blk;  // row blocks {first row, end row, first entry, end entry}; slice s owns blk[boff[s] .. boff[s+1])
+    const int4 *blk;  // row blocks {first row, end row (~end: wavefront rows), first entry, end entry};
+                      // slice s owns blk[boff[s] .. boff[s+1])
     const int *boff;  // [S+1] prefix counts of row blocks
     T *part;          // [S*rows] partial products
 };
@@ -100,7 +105,7 @@ struct Geo {
 // [r0[k], r1[k]) of instance inst[k].
 struct BlockList {
     int nblk;
-    const int *r0, *r1, *inst, *order;
+    const int *r0, *r1, *inst, *order;   // r1 complemented for wavefront-row blocks
     int xoff[kXcds + 1];
     int grid;                 // workgroups of the product kernel (a multiple of 8)
 };
