@@ -228,7 +228,7 @@ def main():
         return traffic_from(args.traffic_from, args.precision, wl, args.copy_mib << 20)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              f"(the multi-GPU sharding is a design, not part of this build)", file=sys.stderr)
+              f"(sharding over several GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
