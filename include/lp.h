@@ -98,7 +98,8 @@ typedef struct {
                                neighbours and smaller row blocks on the actual matrix and keep the fastest,
                                per product (0); ignored when a workspace is given.  At lp_batch_load: the
                                row-block shape (lp_batch_layout_blocks) */
-    int verbose;
+    int verbose;            /* 1: messages on stderr, and one trace line per window of the solve (k, attempts,
+                               restarts, eta, omega, and rel_p, rel_d, rel_gap, KKT_omega of the last check) */
     int ptr_kind;           /* LP_HOST (default) or LP_DEVICE */
     void *workspace;        /* NULL, or device memory of workspace_bytes bytes, 256-byte aligned, owned by
                                the caller, untouched by it until lp_free */

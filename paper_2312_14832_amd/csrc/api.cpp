@@ -588,6 +588,17 @@ void run_check(lp_problem *P)
     HIPT(launch_check_apply<T>(d, P->geo, P->stream));
 }
 
+// One line per window (verbose): counters, step size, primal weight, and the
+// quantities of the latest check (current iterate, then average).
+void trace_window(const Ctl &c)
+{
+    fprintf(stderr,
+            "[lp] k=%lld attempts=%lld restarts=%lld eta=%.6g omega=%.6g | last check: rel_p %.3e/%.3e "
+            "rel_d %.3e/%.3e rel_gap %.3e/%.3e KKT_omega %.4e/%.4e KKT0 %.4e%s\n",
+            c.k, c.attempts, c.restarts, c.eta, c.omega, c.rel_p[0], c.rel_p[1], c.rel_d[0], c.rel_d[1], c.rel_g[0],
+            c.rel_g[1], c.kkt[0], c.kkt[1], c.KKT0, c.done ? " (done)" : "");
+}
+
 void put_ctl(lp_problem *P, const Ctl &c, Ctl *dctl)
 {
     *P->hctl = c;
@@ -729,6 +740,7 @@ int do_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit)
             for (int s = 0; s < W; ++s) launch_slot<T>(P, s, timed);
         }
         get_ctl(P, d.ctl);
+        if (P->opt.verbose) trace_window(*P->hctl);
         if (timed && !P->hctl->done) {
             // every slot of a window that ended unfinished did real work
             double ta = 0.0, tb = 0.0;
