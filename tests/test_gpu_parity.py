@@ -87,19 +87,26 @@ def long_rows_lp(seed):
 LOCKSTEP_POINTS = [0, 1, 2, 7, 62, 63, 64, 65, 100, 126, 127, 128, 191, 255, 300, 383, 511, 640, 767, 900, 1023]
 
 
-@pytest.mark.parametrize("seed,slice_kib", [(0, 2048), (1, 2048), (2, 1)])
-def test_lockstep_one_step_fp64(lpmod, oracle_mod, seed, slice_kib):
+@pytest.mark.parametrize("seed,slice_kib,n", [(0, 2048, 0), (1, 2048, 0), (2, 1, 0), (4, 1, 2000), (5, 1, 20000)])
+def test_lockstep_one_step_fp64(lpmod, oracle_mod, seed, slice_kib, n):
     """Per-iteration parity: from the oracle's state after k accepted steps,
     one more accepted step on the GPU (including the check and restart that
-    fall on k+1) equals the oracle's next state."""
-    data = gen.tiny_lp(seed)
+    fall on k+1) equals the oracle's next state.  n > 0 takes a power-law LP
+    of that size: with 1 KiB slices, 16 and 32 column slices (the epilogue's
+    compile-time and run-time slice-count paths)."""
+    data = gen.tiny_lp(seed) if n == 0 else gen.large_lp(seed=seed, n=n, m1=n // 4, m2=n // 4)
     p = lpmod.Problem(data, slice_kib=slice_kib)
+    if n == 2000:
+        assert p.layout()[0] == 16
+    if n == 20000:
+        assert p.layout() == (32, 32)
     o = oracle_mod.Oracle(data)
     Dr, Dc, _ = o.scaling()
-    o.solve(1e-30, max(LOCKSTEP_POINTS) + 1)
+    points = LOCKSTEP_POINTS if n == 0 else [0, 1, 63, 64, 65, 127, 128]
+    o.solve(1e-30, max(points) + 1)
     total = o.get_state()
     rows = []
-    for k in LOCKSTEP_POINTS:
+    for k in points:
         if k >= total["k"]:
             break
         say(f"case lockstep seed={seed} k={k}")
