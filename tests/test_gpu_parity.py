@@ -284,12 +284,24 @@ def test_warm_start_matches_oracle(lpmod, oracle_mod, omega):
     assert_states_close(gpu_state(lpmod, p), so, step_condition(o.get_state(), so), "warm")
 
 
-@pytest.mark.parametrize("case", ["box_only", "long_rows", "simplex", "fixed_step"])
+@pytest.mark.parametrize("case", ["box_only", "long_rows", "simplex", "fixed_step", "zero_matrix", "one_by_one",
+                                  "empty_rows_cols"])
 def test_edge_cases(lpmod, oracle_mod, case):
     say(f"case edge {case}")
     kw = {}
     if case == "box_only":
         data = gen.box_only_lp(3, n=700)
+    elif case == "zero_matrix":
+        # K has rows but no nonzeros: 0 = 0 and 0 >= -1, -2; the bounds decide x
+        c = np.random.default_rng(5).standard_normal(5)
+        data = gen.from_dense(np.zeros((3, 5)), c, [0.0, -1.0, -2.0], np.zeros(5), np.full(5, 10.0), 1)
+    elif case == "one_by_one":
+        data = gen.from_dense(np.array([[2.0]]), [1.0], [1.0], [0.0], [10.0], 0)   # min x, 2x >= 1
+    elif case == "empty_rows_cols":
+        rng = np.random.Generator(np.random.PCG64(11))
+        counts = rng.integers(0, 3, size=400).astype(np.int64)   # many empty columns, and rows no column hits
+        data = gen.certificate_lp(rng, 120, 180, counts)
+        assert np.any(np.diff(data.row_ptr) == 0) and np.any(counts == 0)
     elif case == "long_rows":
         data = long_rows_lp(7)
     elif case == "simplex":
