@@ -136,3 +136,45 @@ def test_batch_autotuned_layout(lpmod):
     tuned.solve(1e-4, 200000, 120.0)
     for i in range(len(lps)):
         assert tuned.info(i)["status"] == "OPTIMAL", i
+
+
+def test_batch_full_size_sampled(lpmod, oracle_mod):
+    """The 512-member batch the bench times (1.2e8 nonzeros), in its launch
+    configuration (FP32 iterates, autotuned row blocks): every instance is
+    set to the oracle's state of its own LP, one step is taken for all at
+    once, and sampled instances (smallest, largest, spread between) are
+    held to the FP32 one-step bound against the oracle's next state; every
+    other instance must have advanced exactly one accepted step."""
+    say("case batch full size: generate")
+    lps = [gen.batch_member(1000 + i) for i in range(512)]
+    say("case batch full size: load")
+    bt = lpmod.Batch(lps, precision="mixed", autotune=1)
+    sizes = np.array([p.nnz for p in lps])
+    order = np.argsort(sizes)
+    sample = sorted(set(int(i) for i in order[[0, 1, 128, 256, 384, 510, 511]]))
+    k = 63   # the step that closes the first check window
+    oracles = {}
+    for i in sample:
+        say(f"case batch full size: oracle {i} (nnz {sizes[i]})")
+        o = oracle_mod.Oracle(lps[i])
+        o.solve(1e-30, k)
+        raw = o.get_state_raw()
+        prev = o.get_state()
+        o.solve(1e-30, k + 1)
+        oracles[i] = (raw, prev, o.get_state())
+    bt.solve(1e-30, k)   # every instance at k accepted steps of its own run
+    for i, (raw, _, _) in oracles.items():
+        bt.set_state(i, raw)
+    others = [i for i in range(512) if i not in oracles]
+    for i in others:
+        bt.set_state(i, bt.get_state(i))
+    say("case batch full size: one step for all 512")
+    bt.solve(1e-30, k + 1)
+    for i, (raw, prev, so) in oracles.items():
+        p = lps[i]
+        sg = lpmod.unpack_state(bt.get_state(i), p.n, p.m)
+        assert ints_equal(sg, so), i
+        wv, vv = vec_diff(sg, so)
+        assert wv < 64 * 2.0 ** -24, (i, vv, wv)
+    for i in others[::37]:
+        assert bt.info(i)["iterations"] == k + 1, i
