@@ -153,6 +153,139 @@ __global__ __launch_bounds__(256) void k_gemm(const void *A, int lda, const void
     }
 }
 
+// BF16 GEMM for large outputs: a 128x128 tile per 256-thread workgroup,
+// each wave64 owning 64x64 as 2x2 v_mfma_f32_32x32x16_bf16 tiles, K in
+// stages of 32.  Operands are staged in LDS as [row][k] (k contiguous, rows
+// padded to 40 so a wave's 16-byte operand reads hit distinct banks); a
+// thread moves 16-byte vectors (8 bf16) and, for an operand stored with the
+// other index contiguous, scatters each vector across 8 LDS rows.  The next
+// stage's vectors are loaded into registers while the current one is
+// multiplied.  Edges (and unaligned operands, vec == false) take guarded
+// per-element loads with zero fill.  Same split and epilogue contract as
+// k_gemm.
+constexpr int BT = 128;   // output tile
+constexpr int BK = 32;    // K per stage
+constexpr int BP = 40;    // padded LDS row (bf16 elements)
+
+// Vector v (0..511) of an operand's stage: rows r0.. of op(X) (R x Kdim),
+// k in [k0, ke).  KC: stored with k contiguous (row-major in k); else the
+// row index is contiguous.  Returns 8 bf16 in k order (KC) or in row order.
+template <bool KC>
+__device__ __forceinline__ uint4 stage_load(const uint16_t *X, int ld, int R, int r0, int k0, int ke, int v, bool vec)
+{
+    int r, k;
+    if (KC) { r = v >> 2; k = (v & 3) * 8; }   // 128 rows x 4 vectors of k
+    else { k = v >> 4; r = (v & 15) * 8; }      // 32 k x 16 vectors of rows
+    const int gr = r0 + r, gk = k0 + k;
+    uint4 out;
+    if (KC) {
+        if (vec && gr < R && gk + 8 <= ke) return *(const uint4 *)(X + (size_t)gr * ld + gk);
+        uint16_t e[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) e[i] = (gr < R && gk + i < ke) ? X[(size_t)gr * ld + gk + i] : 0;
+        __builtin_memcpy(&out, e, 16);
+    } else {
+        if (vec && gk < ke && gr + 8 <= R) return *(const uint4 *)(X + (size_t)gk * ld + gr);
+        uint16_t e[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) e[i] = (gk < ke && gr + i < R) ? X[(size_t)gk * ld + gr + i] : 0;
+        __builtin_memcpy(&out, e, 16);
+    }
+    return out;
+}
+
+template <bool KC>
+__device__ __forceinline__ void stage_store(uint16_t (*S)[BP], int v, uint4 val)
+{
+    if (KC) {
+        *(uint4 *)&S[v >> 2][(v & 3) * 8] = val;
+    } else {
+        uint16_t e[8];
+        __builtin_memcpy(e, &val, 16);
+        const int k = v >> 4, r = (v & 15) * 8;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) S[r + i][k] = e[i];
+    }
+}
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm_bf16_big(const uint16_t *A, int lda, const uint16_t *B, int ldb, float *C,
+                                                       int ldc, int M, int N, int K, int kps, const float *bias,
+                                                       int relu, uint16_t *Cb, int vec)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t As[BT][BP];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[BT][BP];
+    const int m0 = blockIdx.y * BT, n0 = blockIdx.x * BT;
+    const int kb = blockIdx.z * kps, ke = min(K, kb + kps);
+    float *Cout = C + (size_t)blockIdx.z * (size_t)M * ldc;
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+    // op(A) is M x K: stored [M][K] (k contiguous) unless TA; op(B)' is N x K:
+    // stored [N][K] (k contiguous) when TB, else [K][N]
+    constexpr bool AK = !TA, BKC = TB;
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+    uint4 ra[2], rb[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        ra[h] = stage_load<AK>(A, lda, M, m0, kb, ke, t + 256 * h, vec);
+        rb[h] = stage_load<BKC>(B, ldb, N, n0, kb, ke, t + 256 * h, vec);
+    }
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            stage_store<AK>(As, t + 256 * h, ra[h]);
+            stage_store<BKC>(Bs, t + 256 * h, rb[h]);
+        }
+        __syncthreads();
+        if (k0 + BK < ke) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                ra[h] = stage_load<AK>(A, lda, M, m0, k0 + BK, ke, t + 256 * h, vec);
+                rb[h] = stage_load<BKC>(B, ldb, N, n0, k0 + BK, ke, t + 256 * h, vec);
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 16) {
+            const int kofs = kk + 8 * (lane >> 5);
+            bf16x8 a[2], b[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                __builtin_memcpy(&a[i], &As[wm + 32 * i + (lane & 31)][kofs], 16);
+                __builtin_memcpy(&b[i], &Bs[wn + 32 * i + (lane & 31)][kofs], 16);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int row = m0 + wm + 32 * i + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                const int col = n0 + wn + 32 * j + (lane & 31);
+                if (row < M && col < N) {
+                    float o = acc[i][j][v];
+                    if (gridDim.z == 1) {
+                        if (bias) o += bias[col];
+                        if (relu && o < 0.0f) o = 0.0f;
+                        if (Cb) Cb[(size_t)row * ldc + col] = f2bf(o);
+                    }
+                    Cout[(size_t)row * ldc + col] = o;
+                }
+            }
+}
+
 // C = sum over splits of the partial tiles, in split order
 __global__ void k_split_sum(const float *part, int splits, int64_t len, float *C)
 {
@@ -273,6 +406,26 @@ void gemm(hipStream_t st, bool bf, bool ta, bool tb, int M, int N, int K, const 
     dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT, splits);
     float *out = splits > 1 ? scratch : C;
     const int ldo = splits > 1 ? N : ldc;
+    const int64_t big_tiles = (int64_t)((N + BT - 1) / BT) * ((M + BT - 1) / BT) * splits;
+    if (bf && big_tiles >= 128) {
+        // enough 128x128 tiles to fill the GPU: the large-tile MFMA kernel
+        const bool vec = lda % 8 == 0 && ldb % 8 == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0 &&
+                         (reinterpret_cast<uintptr_t>(B) & 15) == 0;
+        dim3 g2((N + BT - 1) / BT, (M + BT - 1) / BT, splits);
+        const float *bs = splits > 1 ? nullptr : bias;
+        const int rl = splits > 1 ? 0 : (int)relu;
+        uint16_t *cb = splits > 1 ? nullptr : Cb;
+        const uint16_t *Ah = (const uint16_t *)A, *Bh = (const uint16_t *)B;
+        if (!ta && !tb) hipLaunchKernelGGL((k_gemm_bf16_big<false, false>), g2, dim3(256), 0, st, Ah, lda, Bh, ldb, out, ldo, M, N, K, kps, bs, rl, cb, (int)vec);
+        else if (ta && !tb) hipLaunchKernelGGL((k_gemm_bf16_big<true, false>), g2, dim3(256), 0, st, Ah, lda, Bh, ldb, out, ldo, M, N, K, kps, bs, rl, cb, (int)vec);
+        else if (!ta && tb) hipLaunchKernelGGL((k_gemm_bf16_big<false, true>), g2, dim3(256), 0, st, Ah, lda, Bh, ldb, out, ldo, M, N, K, kps, bs, rl, cb, (int)vec);
+        else hipLaunchKernelGGL((k_gemm_bf16_big<true, true>), g2, dim3(256), 0, st, Ah, lda, Bh, ldb, out, ldo, M, N, K, kps, bs, rl, cb, (int)vec);
+        if (splits > 1)
+            hipLaunchKernelGGL(k_split_sum, dim3(nblk((int64_t)M * N)), dim3(256), 0, st, (const float *)scratch,
+                               splits, (int64_t)M * N, C);
+        HIPT(hipGetLastError());
+        return;
+    }
 #define PDLP_GEMM_LAUNCH(BFV, TAV, TBV)                                                                            \
     hipLaunchKernelGGL((k_gemm<BFV, TAV, TBV>), grid, dim3(256), 0, st, A, lda, B, ldb, out, ldo, M, N, K, kps,     \
                        splits > 1 ? nullptr : bias, splits > 1 ? 0 : (int)relu, splits > 1 ? nullptr : Cb)
