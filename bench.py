@@ -206,7 +206,7 @@ def main():
     ap.add_argument("--ws-train", type=int, default=512, help="warmstart: training instances")
     ap.add_argument("--ws-eval", type=int, default=128, help="warmstart: held-out instances")
     ap.add_argument("--ws-epochs", type=int, default=120)
-    ap.add_argument("--workload", choices=["large", "tiny", "batch", "warmstart"], default="large",
+    ap.add_argument("--workload", choices=["large", "tiny", "batch", "warmstart", "gemm"], default="large",
                     help="large: one 2e6x1e6 LP (default); batch: 512 uneven LPs solved together")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--seq-sample", type=int, default=32,
@@ -249,6 +249,8 @@ def main():
         return bench_batch(args)
     if args.workload == "tiny":
         return bench_tiny(args)
+    if args.workload == "gemm":
+        return bench_gemm(args)
     if args.workload == "warmstart":
         return bench_warmstart(args)
     n = args.n
@@ -406,6 +408,53 @@ def bench_tiny(args):
                           "median_s": float(np.median([o["seconds"] for o in ora])), "runs": ora}
                          if ora else None),
     }
+    print(json.dumps(out))
+
+
+def bench_gemm(args):
+    """The network's GEMM kernels (lpw_gemm) at large square sizes and at the
+    network's own shapes, timed with HIP events on the current stream:
+    TFLOP/s against the MFMA BF16 (2.5 PFLOP/s) and FP32 vector (157.3
+    TFLOP/s) dense peaks, and the relative error against an FP32 product of
+    the same rounded operands."""
+    import torch
+    from paper_2312_14832_amd import warmstart as ws
+    peak = {"bf16": 2500.0, "fp32": 157.3}
+    cases = [(4096, 4096, 4096, False, False, 20), (8192, 8192, 8192, False, False, 5),
+             (256, 1024, 1024, False, False, 20), (1024, 1024, 256, True, False, 20),
+             (256, 300000, 64, False, False, 20)]
+    gen_ = torch.Generator(device="cuda").manual_seed(0)
+    rows = []
+    for prec in ("bf16", "fp32"):
+        dt = torch.bfloat16 if prec == "bf16" else torch.float32
+        for M, N, K, ta, tb, reps in cases:
+            A = torch.randn((K, M) if ta else (M, K), device="cuda", generator=gen_).to(dt).contiguous()
+            B = torch.randn((N, K) if tb else (K, N), device="cuda", generator=gen_).to(dt).contiguous()
+            for _ in range(3):
+                C = ws.gemm(A, B, ta, tb, prec)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                C = ws.gemm(A, B, ta, tb, prec)
+            e1.record()
+            torch.cuda.synchronize()
+            us = 1e3 * e0.elapsed_time(e1) / reps
+            tf = 2.0 * M * N * K / (us * 1e-6) / 1e12
+            ref = (A.float().t() if ta else A.float()) @ (B.float().t() if tb else B.float())
+            err = float((C - ref).norm() / ref.norm())
+            rows.append({"precision": prec, "M": M, "N": N, "K": K, "trans_a": ta, "trans_b": tb, "us": us,
+                         "TFLOP_s": tf, "frac_of_peak": tf / peak[prec], "relerr": err})
+            print(f"[bench] gemm {prec} {M}x{N}x{K} ta={ta}: {us:.1f} us {tf:.1f} TFLOP/s relerr {err:.1e}",
+                  file=sys.stderr, flush=True)
+    big = rows[0]
+    out = {"metric": "GEMM TFLOP/s (network kernels)", "value": big["TFLOP_s"], "unit": "TFLOP/s", "n_gpus": 1,
+           "steps": 20, "warmup": 3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "bf16 x bf16 -> f32", "data": "synthetic",
+           "config": {"workload": "gemm_4096_bf16"},
+           "roofline": {"bound": "mfma", "achieved": big["TFLOP_s"], "peak": peak["bf16"], "unit": "TFLOP/s",
+                        "frac": big["frac_of_peak"], "traffic": None},
+           "cases": rows}
     print(json.dumps(out))
 
 

@@ -29,7 +29,10 @@ def cosine(a, b):
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
 @pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
-@pytest.mark.parametrize("M,N,K", [(64, 64, 32), (100, 70, 45), (3, 130, 300), (257, 65, 1000)])
+@pytest.mark.parametrize("M,N,K", [(64, 64, 32), (100, 70, 45), (3, 130, 300), (257, 65, 1000),
+                                   # >= 128 tiles of 128x128: the large-tile MFMA kernel in BF16, with ragged
+                                   # M, N, K edges, and an odd leading dimension (per-element staging)
+                                   (1030, 2100, 300), (1031, 2049, 301)])
 def test_gemm_matches_numpy(ws, precision, ta, tb, M, N, K):
     import torch
     say(f"case gemm {precision} ta={ta} tb={tb} {M}x{N}x{K}")
