@@ -175,7 +175,7 @@ __device__ __forceinline__ uint4 stage_load(const uint16_t *X, int ld, int R, in
 {
     int r, k;
     if (KC) { r = v >> 2; k = (v & 3) * 8; }   // 128 rows x 4 vectors of k
-    else { k = v >> 4; r = (v & 15) * 8; }      // 32 k x 16 vectors of rows
+    else { k = v & 31; r = (v >> 5) * 8; }      // 16 vectors of rows x 32 k (k fastest: see stage_store)
     const int gr = r0 + r, gk = k0 + k;
     uint4 out;
     if (KC) {
@@ -200,9 +200,12 @@ __device__ __forceinline__ void stage_store(uint16_t (*S)[BP], int v, uint4 val)
     if (KC) {
         *(uint4 *)&S[v >> 2][(v & 3) * 8] = val;
     } else {
+        // consecutive lanes take consecutive k, so each of the 8 scattered
+        // 2-byte writes of a wave covers whole LDS rows rather than piling
+        // onto a few banks
         uint16_t e[8];
         __builtin_memcpy(e, &val, 16);
-        const int k = v >> 4, r = (v & 15) * 8;
+        const int k = v & 31, r = (v >> 5) * 8;
 #pragma unroll
         for (int i = 0; i < 8; ++i) S[r + i][k] = e[i];
     }
