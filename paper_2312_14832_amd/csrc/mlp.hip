@@ -164,18 +164,19 @@ __global__ __launch_bounds__(256) void k_gemm(const void *A, int lda, const void
 // per-element loads with zero fill.  Same split and epilogue contract as
 // k_gemm.
 constexpr int BT = 128;   // output tile
-constexpr int BK = 32;    // K per stage
-constexpr int BP = 40;    // padded LDS row (bf16 elements)
+constexpr int BK = 64;    // K per stage
+constexpr int BP = 72;    // padded LDS row (bf16 elements): 144-byte rows put a wave's 16-byte reads on distinct banks
+constexpr int BV = BT * BK / 8 / 256;   // 16-byte vectors per thread per operand and stage
 
-// Vector v (0..511) of an operand's stage: rows r0.. of op(X) (R x Kdim),
+// Vector v (0..BT*BK/8-1) of an operand's stage: rows r0.. of op(X) (R x Kdim),
 // k in [k0, ke).  KC: stored with k contiguous (row-major in k); else the
 // row index is contiguous.  Returns 8 bf16 in k order (KC) or in row order.
 template <bool KC>
 __device__ __forceinline__ uint4 stage_load(const uint16_t *X, int ld, int R, int r0, int k0, int ke, int v, bool vec)
 {
     int r, k;
-    if (KC) { r = v >> 2; k = (v & 3) * 8; }   // 128 rows x 4 vectors of k
-    else { k = v & 31; r = (v >> 5) * 8; }      // 16 vectors of rows x 32 k (k fastest: see stage_store)
+    if (KC) { r = v / (BK / 8); k = (v % (BK / 8)) * 8; }   // 128 rows x BK/8 vectors of k
+    else { k = v % BK; r = (v / BK) * 8; }                   // 16 vectors of rows x BK k (k fastest: see stage_store)
     const int gr = r0 + r, gk = k0 + k;
     uint4 out;
     if (KC) {
@@ -198,14 +199,14 @@ template <bool KC>
 __device__ __forceinline__ void stage_store(uint16_t (*S)[BP], int v, uint4 val)
 {
     if (KC) {
-        *(uint4 *)&S[v >> 2][(v & 3) * 8] = val;
+        *(uint4 *)&S[v / (BK / 8)][(v % (BK / 8)) * 8] = val;
     } else {
         // consecutive lanes take consecutive k, so each of the 8 scattered
         // 2-byte writes of a wave covers whole LDS rows rather than piling
         // onto a few banks
         uint16_t e[8];
         __builtin_memcpy(e, &val, 16);
-        const int k = v & 31, r = (v >> 5) * 8;
+        const int k = v % BK, r = (v / BK) * 8;
 #pragma unroll
         for (int i = 0; i < 8; ++i) S[r + i][k] = e[i];
     }
@@ -233,22 +234,22 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_big(const uint16_t *A, int ld
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
-    uint4 ra[2], rb[2];
+    uint4 ra[BV], rb[BV];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < BV; ++h) {
         ra[h] = stage_load<AK>(A, lda, M, m0, kb, ke, t + 256 * h, vec);
         rb[h] = stage_load<BKC>(B, ldb, N, n0, kb, ke, t + 256 * h, vec);
     }
     for (int k0 = kb; k0 < ke; k0 += BK) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int h = 0; h < BV; ++h) {
             stage_store<AK>(As, t + 256 * h, ra[h]);
             stage_store<BKC>(Bs, t + 256 * h, rb[h]);
         }
         __syncthreads();
         if (k0 + BK < ke) {
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < BV; ++h) {
                 ra[h] = stage_load<AK>(A, lda, M, m0, k0 + BK, ke, t + 256 * h, vec);
                 rb[h] = stage_load<BKC>(B, ldb, N, n0, k0 + BK, ke, t + 256 * h, vec);
             }
