@@ -420,7 +420,9 @@ def bench_gemm(args):
     import torch
     from paper_2312_14832_amd import warmstart as ws
     peak = {"bf16": 2500.0, "fp32": 157.3}
-    cases = [(4096, 4096, 4096, False, False, 20), (8192, 8192, 8192, False, False, 5),
+    cases = [(4096, 4096, 4096, False, False, 20), (4096, 4096, 4096, False, True, 20),
+             (4096, 4096, 4096, True, False, 20), (4096, 4096, 4096, True, True, 20),
+             (8192, 8192, 8192, False, False, 5),
              (256, 1024, 1024, False, False, 20), (1024, 1024, 256, True, False, 20),
              (256, 300000, 64, False, False, 20)]
     gen_ = torch.Generator(device="cuda").manual_seed(0)
