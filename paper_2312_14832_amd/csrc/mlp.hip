@@ -8,10 +8,12 @@
 // primal-dual point z = (x, y) that seeds the solver.  Shapes are row-major
 // with the batch as the leading dimension: Y[B x N] = X[B x K] W[K x N] + b.
 //
-// GEMMs: one LDS-tiled kernel, 64x64 output tile per 256-thread workgroup.
+// GEMMs: LDS-tiled kernels.
 //   BF16 mode: operands rounded to bfloat16, products on MFMA
-//     (v_mfma_f32_32x32x16_bf16, gfx950), FP32 accumulation; each wave64 owns
-//     a 32x32 quarter of the tile.
+//     (v_mfma_f32_32x32x16_bf16, gfx950), FP32 accumulation: a 128x128 tile
+//     per workgroup when the output has enough tiles to fill the GPU
+//     (k_gemm_bf16_big), else a 64x64 tile with each wave64 owning a 32x32
+//     quarter.
 //   FP32 mode: the same tiling with FP32 FMA (every thread a 4x4 block); used
 //     to check gradients against the FP64 reference at FP32 accuracy.
 // Long reductions (dL/dalpha contracts over out_dim) are split over
@@ -155,8 +157,8 @@ __global__ __launch_bounds__(256) void k_gemm(const void *A, int lda, const void
 
 // BF16 GEMM for large outputs: a 128x128 tile per 256-thread workgroup,
 // each wave64 owning 64x64 as 2x2 v_mfma_f32_32x32x16_bf16 tiles, K in
-// stages of 32.  Operands are staged in LDS as [row][k] (k contiguous, rows
-// padded to 40 so a wave's 16-byte operand reads hit distinct banks); a
+// stages of 64.  Operands are staged in LDS as [row][k] (k contiguous, rows
+// padded to 72 so a wave's 16-byte operand reads hit distinct banks); a
 // thread moves 16-byte vectors (8 bf16) and, for an operand stored with the
 // other index contiguous, scatters each vector across 8 LDS rows.  The next
 // stage's vectors are loaded into registers while the current one is
