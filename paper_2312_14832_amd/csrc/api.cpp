@@ -123,7 +123,6 @@ struct lp_problem {
     int64_t m = 0, n = 0, nnz = 0, m1 = 0;
     lp_options opt{};
     hipStream_t stream = nullptr;
-    std::vector<int> perm_r, inv_r, perm_c, inv_c;  // perm: new -> old, inv: old -> new
     Geo geo{};
     std::string err;
     double Nq = 0, Nc = 0, omega0 = 1, eta0 = 1;
@@ -471,14 +470,6 @@ size_t load_plan_bytes(int64_t m, int64_t n, int64_t nnz, const HostSliced &HK, 
 int do_load(lp_problem *P, const lp_csr *K, const double *c, const double *q, const double *l, const double *u)
 {
     const int64_t m = P->m, n = P->n, nnz = P->nnz;
-    // vectors keep the caller's order (the permutation hooks stay identity)
-    P->perm_r.resize((size_t)m);
-    P->perm_c.resize((size_t)n);
-    for (int64_t i = 0; i < m; ++i) P->perm_r[i] = (int)i;
-    for (int64_t j = 0; j < n; ++j) P->perm_c[j] = (int)j;
-    P->inv_r = P->perm_r;
-    P->inv_c = P->perm_c;
-
     // K with the columns of each row sorted, K' by a counting sort, both sliced
     std::vector<int> rp, ci, tp, ti;
     std::vector<double> kv, tv;
@@ -631,16 +622,12 @@ int do_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit)
         // start point, products, averages/anchor = start, KKT0, first primal trial
         const double *xs = nullptr, *ys = nullptr;
         if (P->has_xs) {
-            std::vector<double> tmp((size_t)n);
-            for (int64_t j = 0; j < n; ++j) tmp[j] = P->xs[P->perm_c[j]];
-            upload(P, P->stage_n0, tmp.data(), n);
+            upload(P, P->stage_n0, P->xs.data(), n);
             sync(P);
             xs = P->stage_n0;
         }
         if (P->has_ys) {
-            std::vector<double> tmp((size_t)m);
-            for (int64_t i = 0; i < m; ++i) tmp[i] = P->ys[P->perm_r[i]];
-            upload(P, P->stage_m, tmp.data(), m);
+            upload(P, P->stage_m, P->ys.data(), m);
             sync(P);
             ys = P->stage_m;
         }
@@ -804,7 +791,6 @@ int do_result(const lp_problem *Pc, double *x, double *y, double *lam, lp_info *
     Dev<T> &d = P->dev<T>();
     const int64_t m = P->m, n = P->n;
     if ((x || y || lam) && P->opt.ptr_kind == LP_DEVICE) {
-        // vectors keep the caller's order, so the staged results copy as they are
         HIPT(launch_result<T>(d, P->stage_n0, P->stage_m, P->stage_n1, P->stream));
         const hipMemcpyKind k = hipMemcpyDeviceToDevice;
         if (x && n) HIPT(hipMemcpyAsync(x, P->stage_n0, sizeof(double) * (size_t)n, k, P->stream));
@@ -813,18 +799,10 @@ int do_result(const lp_problem *Pc, double *x, double *y, double *lam, lp_info *
         sync(P);
     } else if (x || y || lam) {
         HIPT(launch_result<T>(d, P->stage_n0, P->stage_m, P->stage_n1, P->stream));
-        std::vector<double> hx((size_t)n), hy((size_t)m), hl((size_t)n);
-        download(P, hx.data(), P->stage_n0, n);
-        download(P, hy.data(), P->stage_m, m);
-        download(P, hl.data(), P->stage_n1, n);
+        if (x) download(P, x, P->stage_n0, n);
+        if (y) download(P, y, P->stage_m, m);
+        if (lam) download(P, lam, P->stage_n1, n);
         sync(P);
-        for (int64_t j = 0; j < n; ++j) {
-            const int o = P->perm_c[j];
-            if (x) x[o] = hx[j];
-            if (lam) lam[o] = hl[j];
-        }
-        if (y)
-            for (int64_t i = 0; i < m; ++i) y[P->perm_r[i]] = hy[i];
     }
     if (info) {
         get_ctl(P, d.ctl);
@@ -874,15 +852,12 @@ int do_get_state(const lp_problem *Pc, double *buf)
     bool is_n[10];
     state_vectors<T>(P, v, is_n);
     double *p = buf + kNScalars;
-    std::vector<double> tmp((size_t)std::max(P->m, P->n));
     for (int i = 0; i < 10; ++i) {
         const int64_t len = is_n[i] ? P->n : P->m;
         double *stage = is_n[i] ? P->stage_n0 : P->stage_m;
         HIPT(launch_to_double<T>(v[i], stage, len, P->stream));
-        download(P, tmp.data(), stage, len);
+        download(P, p, stage, len);
         sync(P);
-        const std::vector<int> &perm = is_n[i] ? P->perm_c : P->perm_r;
-        for (int64_t t = 0; t < len; ++t) p[perm[t]] = tmp[t];
         p += len;
     }
     return LP_OK;
@@ -902,13 +877,10 @@ int do_set_state(lp_problem *P, const double *buf)
     bool is_n[10];
     state_vectors<T>(P, v, is_n);
     const double *p = buf + kNScalars;
-    std::vector<double> tmp((size_t)std::max(P->m, P->n));
     for (int i = 0; i < 10; ++i) {
         const int64_t len = is_n[i] ? P->n : P->m;
         double *stage = is_n[i] ? P->stage_n0 : P->stage_m;
-        const std::vector<int> &perm = is_n[i] ? P->perm_c : P->perm_r;
-        for (int64_t t = 0; t < len; ++t) tmp[t] = p[perm[t]];
-        upload(P, stage, tmp.data(), len);
+        upload(P, stage, p, len);
         HIPT(launch_from_double<T>(stage, v[i], len, P->stream));
         sync(P);
         p += len;
@@ -924,24 +896,19 @@ int do_spmv(lp_problem *P, int transpose, const double *in, double *out)
 {
     Dev<T> &d = P->dev<T>();
     const int64_t lin = transpose ? P->m : P->n, lout = transpose ? P->n : P->m;
-    const std::vector<int> &pin = transpose ? P->perm_r : P->perm_c;
-    const std::vector<int> &pout = transpose ? P->perm_c : P->perm_r;
     double *sin = transpose ? P->stage_m : P->stage_n0;
     double *sout = transpose ? P->stage_n0 : P->stage_m;
     T *tin = (T *)(transpose ? P->tmp_m : P->tmp_n);
     T *tout = (T *)(transpose ? P->tmp_n : P->tmp_m);
-    std::vector<double> tmp((size_t)std::max(lin, lout));
-    for (int64_t t = 0; t < lin; ++t) tmp[t] = in[pin[t]];
-    upload(P, sin, tmp.data(), lin);
+    upload(P, sin, in, lin);
     HIPT(launch_from_double<T>(sin, tin, lin, P->stream));
     if (transpose)
         HIPT(launch_spmv<T>(d.KT, tin, tout, P->stream));
     else
         HIPT(launch_spmv<T>(d.K, tin, tout, P->stream));
     HIPT(launch_to_double<T>(tout, sout, lout, P->stream));
-    download(P, tmp.data(), sout, lout);
+    download(P, out, sout, lout);
     sync(P);
-    for (int64_t t = 0; t < lout; ++t) out[pout[t]] = tmp[t];
     return LP_OK;
 }
 
@@ -1151,14 +1118,9 @@ int lp_get_scaling(const lp_problem *Pc, double *Dr, double *Dc)
     try {
         const double *dDr = P->mixed ? P->d32.Dr : P->d64.Dr;
         const double *dDc = P->mixed ? P->d32.Dc : P->d64.Dc;
-        std::vector<double> tr((size_t)P->m), tc((size_t)P->n);
-        download(P, tr.data(), dDr, P->m);
-        download(P, tc.data(), dDc, P->n);
+        if (Dr) download(P, Dr, dDr, P->m);
+        if (Dc) download(P, Dc, dDc, P->n);
         sync(P);
-        if (Dr)
-            for (int64_t i = 0; i < P->m; ++i) Dr[P->perm_r[i]] = tr[i];
-        if (Dc)
-            for (int64_t j = 0; j < P->n; ++j) Dc[P->perm_c[j]] = tc[j];
     } catch (const HipError &h) {
         return fail_hip(P, h);
     }
