@@ -268,20 +268,14 @@ float time_product(lp_problem *P, const Sliced<T> &q, T *in, T *out, int64_t in_
 {
     std::vector<T> ones((size_t)std::max<int64_t>(in_len, 1), T(1));
     upload(P, in, ones.data(), in_len);
-    hipEvent_t a, b;
-    HIPT(hipEventCreate(&a));
-    HIPT(hipEventCreate(&b));
+    EventPair ev;
     for (int r = 0; r < 2; ++r) HIPT(launch_spmv<T>(q, in, out, P->stream));
-    HIPT(hipEventRecord(a, P->stream));
+    HIPT(hipEventRecord(ev.a, P->stream));
     const int reps = 5;
     for (int r = 0; r < reps; ++r) HIPT(launch_spmv<T>(q, in, out, P->stream));
-    HIPT(hipEventRecord(b, P->stream));
-    HIPT(hipEventSynchronize(b));
-    float ms = 0;
-    HIPT(hipEventElapsedTime(&ms, a, b));
-    (void)hipEventDestroy(a);
-    (void)hipEventDestroy(b);
-    return ms / reps;
+    HIPT(hipEventRecord(ev.b, P->stream));
+    HIPT(hipEventSynchronize(ev.b));
+    return ev.ms() / reps;
 }
 
 // Autotuner for one product: times the default layout, its neighbours in

@@ -313,9 +313,7 @@ int do_batch_load(lp_batch *P, const lp_csr *K, const double *const *c, const do
             HIPT(launch_fill(P->stage_m, 1.0, M, st));
             HIPT(launch_from_double<T>(P->stage_n0, d.xb[1], N, st));
             HIPT(launch_from_double<T>(P->stage_m, d.yb[1], M, st));
-            hipEvent_t e0, e1;
-            HIPT(hipEventCreate(&e0));
-            HIPT(hipEventCreate(&e1));
+            EventPair ev;
             for (int which = 0; which < 2; ++which) {
                 BlockList &cur = which ? b.LT : b.LK;
                 float best_ms = 0;
@@ -329,12 +327,11 @@ int do_batch_load(lp_batch *P, const lp_csr *K, const double *const *c, const do
                     const T *in = which ? d.yb[1] : d.xb[1];
                     T *out = which ? b.prodKT : b.prodK;
                     for (int r = 0; r < 2; ++r) HIPT(launch_batch_product_plain<T>(t, which, in, out, st));
-                    HIPT(hipEventRecord(e0, st));
+                    HIPT(hipEventRecord(ev.a, st));
                     for (int r = 0; r < 5; ++r) HIPT(launch_batch_product_plain<T>(t, which, in, out, st));
-                    HIPT(hipEventRecord(e1, st));
-                    HIPT(hipEventSynchronize(e1));
-                    float ms = 0;
-                    HIPT(hipEventElapsedTime(&ms, e0, e1));
+                    HIPT(hipEventRecord(ev.b, st));
+                    HIPT(hipEventSynchronize(ev.b));
+                    const float ms = ev.ms();
                     if (P->opt.verbose)
                         fprintf(stderr, "[lp_batch] product %d: blocks of <= %d nonzeros, <= %d rows: %.3f ms\n",
                                 which, cand[k][0], cand[k][1], ms / 5);
@@ -350,8 +347,6 @@ int do_batch_load(lp_batch *P, const lp_csr *K, const double *const *c, const do
                 P->shape[which][0] = cand[best][0];
                 P->shape[which][1] = cand[best][1];
             }
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
         }
     };
     if (P->mixed) setup(float{});

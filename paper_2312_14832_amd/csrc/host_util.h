@@ -57,6 +57,34 @@ struct Arena {
     }
 };
 
+// Two timing events, destroyed with the object (also when a call between
+// them throws).
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    EventPair()
+    {
+        HIPT(hipEventCreate(&a));
+        const hipError_t e = hipEventCreate(&b);
+        if (e != hipSuccess) {
+            (void)hipEventDestroy(a);
+            throw HipError{e, "hipEventCreate"};
+        }
+    }
+    ~EventPair()
+    {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+    EventPair(const EventPair &) = delete;
+    EventPair &operator=(const EventPair &) = delete;
+    float ms() const
+    {
+        float t = 0;
+        HIPT(hipEventElapsedTime(&t, a, b));
+        return t;
+    }
+};
+
 template <typename T>
 inline void h2d(hipStream_t st, T *dst, const T *src, int64_t count)
 {
