@@ -192,12 +192,19 @@ def cpu_baseline(data, iters):
             "seconds": dt}
 
 
+def workload_name(args):
+    """Key of a single-LP workload in the bench line and in traffic.json."""
+    base = f"pagerank_lp_n{args.n}" if args.workload == "pagerank" else f"large_powerlaw_lp_n{args.n}"
+    return base + ("" if args.precision == "fp64" else "_mixed")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=2_000_000)
+    ap.add_argument("--n", type=int, default=None,
+                    help="variables (large: 2,000,000; pagerank: 1,000,000 graph nodes)")
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
@@ -206,8 +213,10 @@ def main():
     ap.add_argument("--ws-train", type=int, default=512, help="warmstart: training instances")
     ap.add_argument("--ws-eval", type=int, default=128, help="warmstart: held-out instances")
     ap.add_argument("--ws-epochs", type=int, default=120)
-    ap.add_argument("--workload", choices=["large", "tiny", "batch", "warmstart", "gemm"], default="large",
-                    help="large: one 2e6x1e6 LP (default); batch: 512 uneven LPs solved together")
+    ap.add_argument("--workload", choices=["large", "pagerank", "tiny", "batch", "warmstart", "gemm"],
+                    default="large",
+                    help="large: one 2e6x1e6 LP (default); pagerank: the LP of a random graph's PageRank "
+                         "vector; batch: 512 uneven LPs solved together")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--seq-sample", type=int, default=32,
                     help="batch workload: instances solved one by one for the sequential comparison")
@@ -220,12 +229,13 @@ def main():
                     help="only run 5 plain device-to-device copies of this many MiB (counter calibration)")
     ap.add_argument("--traffic-from", default=None,
                     help="no GPU: read rocprofv3 databases under DIR/{stats,fetch,write,copy_fetch,copy_write} "
-                         "and write profiles/traffic.json for the default workload")
+                         "and write profiles/traffic.json for the chosen single-LP workload")
     ap.add_argument("--copy-mib", type=int, default=1024, help="size of the calibration copy for --traffic-from")
     args = ap.parse_args()
+    if args.n is None:
+        args.n = 1_000_000 if args.workload == "pagerank" else 2_000_000
     if args.traffic_from:
-        wl = f"large_powerlaw_lp_n{args.n}" + ("" if args.precision == "fp64" else "_mixed")
-        return traffic_from(args.traffic_from, args.precision, wl, args.copy_mib << 20)
+        return traffic_from(args.traffic_from, args.precision, workload_name(args), args.copy_mib << 20)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               f"(sharding over several GPUs is not implemented)", file=sys.stderr)
@@ -254,9 +264,17 @@ def main():
     if args.workload == "warmstart":
         return bench_warmstart(args)
     n = args.n
-    m1 = m2 = n // 4
     t0 = time.perf_counter()
-    data = gen.large_lp(seed=args.seed, n=n, m1=m1, m2=m2)
+    if args.workload == "pagerank":
+        data = gen.pagerank_lp(seed=args.seed, n=n)
+        recipe = ("random graph, 1 + Poisson(5) links per node (repeats collapsed), damping 0.85; "
+                  "row 0: sum(x) = 1, rows 1..n: x - 0.85 A x >= 0.15/n, x >= 0, c = 0")
+    else:
+        data = gen.large_lp(seed=args.seed, n=n, m1=n // 4, m2=n // 4)
+        recipe = ("power-law column counts 1..200 (mean 10), N(0,1)*10^U(-3,3) per row, "
+                  "certificate-feasible")
+    workload = workload_name(args)
+    m1, m2 = data.m1, data.m - data.m1
     gen_s = time.perf_counter() - t0
     print(f"[bench] generated n={n} m={m1 + m2} nnz={data.nnz} in {gen_s:.1f}s", file=sys.stderr, flush=True)
 
@@ -293,7 +311,6 @@ def main():
                                  "G_gathers_s": data.nnz / (avg_us * 1e-6) / 1e9 if avg_us > 0 else None}
     dom = max(spmv, key=lambda k: spmv[k]["avg_us"] * spmv[k]["launches"])
     d = spmv[dom]
-    workload = f"large_powerlaw_lp_n{n}" + ("" if args.precision == "fp64" else "_mixed")
     roofline = {"kernel": dom, "bound": "hbm", "achieved": d["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": d["GB_s"] / HBM_PEAK_GBS if d["GB_s"] else None,
                 "traffic": counter_traffic(dom, workload), "alg_bytes_per_launch": d["alg_bytes"]}
@@ -342,8 +359,7 @@ def main():
         "config": {"workload": workload, "n": n, "m1": m1, "m2": m2, "nnz": data.nnz, "seed": args.seed,
                    "precision": args.precision, "iters_per_step": ITERS_PER_STEP,
                    "column_slices": list(prob_layout), "row_blocks": blocks,
-                   "generator": "power-law column counts 1..200 (mean 10), N(0,1)*10^U(-3,3) per row, "
-                                "certificate-feasible"},
+                   "generator": recipe},
         "roofline": roofline,
         "spmv": spmv,
         "time_to_tol": ttt,

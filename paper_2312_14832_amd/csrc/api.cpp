@@ -36,11 +36,13 @@ int slices_for(int64_t bytes, int64_t slice_bytes)
 }
 
 // Host side of a Sliced product: per-slice CSR (slice-major), the position
-// of every sliced entry in the source CSR, and the row blocks.
+// of every sliced entry in the source CSR, the row blocks, and the long rows
+// with the chunk slots of each.
 struct HostSliced {
     int S = 1, rows = 0, cols = 0, nb = kStreamNB, rb = kStreamRB;
     std::vector<int> rp, ci, src, brow, boff;
     std::vector<int4> blk;   // per row block: first row, end row, first entry, end entry
+    std::vector<int> lrow, loff{0};   // long rows and their slot offsets
     int max_blocks = 0;
 };
 
@@ -49,6 +51,8 @@ struct HostSliced {
 void build_sliced(HostSliced &H, int rows, int cols, const std::vector<int> &rp, const std::vector<int> &ci, int S,
                   int nb = kStreamNB, int rb = kStreamRB)
 {
+    if (nb > kStreamNB || nb < 1) nb = kStreamNB;   // a chunk is at most one staged block
+    if (rb > kStreamRB || rb < 1) rb = kStreamRB;
     H.S = S;
     H.nb = nb;
     H.rb = rb;
@@ -63,7 +67,6 @@ void build_sliced(HostSliced &H, int rows, int cols, const std::vector<int> &rp,
     H.boff.assign(S + 1, 0);
     std::vector<int> cur(rp.begin(), rp.end() - 1);
     int64_t pos = 0;
-    H.max_blocks = 0;
     for (int s = 0; s < S; ++s) {
         const int hi = (int)((int64_t)cols * (s + 1) / S);
         int *r = &H.rp[(size_t)s * (rows + 1)];
@@ -80,17 +83,47 @@ void build_sliced(HostSliced &H, int rows, int cols, const std::vector<int> &rp,
             cur[i] = p;
         }
         r[rows] = (int)pos;
-        H.brow.push_back(0);
-        const size_t before = H.brow.size();
-        std::vector<char> wave;
-        row_blocks(r, 0, rows, H.brow, wave, H.nb, H.rb);
-        const int nb = (int)(H.brow.size() - before);
-        for (int k = 0; k < nb; ++k) {
-            const int r0 = H.brow[before - 1 + k], r1 = H.brow[before + k];
-            H.blk.push_back(make_int4(r0, wave[k] ? ~r1 : r1, r[r0], r[r1]));
+    }
+    // long rows: slots slice-major, one per chunk of at most nb entries
+    H.lrow.clear();
+    H.loff.assign(1, 0);
+    for (int i = 0; i < rows; ++i)
+        if (rp[i + 1] - rp[i] > kLongRow) H.lrow.push_back(i);
+    std::vector<int> slot0(H.lrow.size());   // next free slot of each long row
+    for (size_t k = 0; k < H.lrow.size(); ++k) {
+        int chunks = 0;
+        for (int s = 0; s < S; ++s) {
+            const int *r = &H.rp[(size_t)s * (rows + 1)];
+            chunks += (r[H.lrow[k] + 1] - r[H.lrow[k]] + nb - 1) / nb;
         }
-        H.boff[s + 1] = H.boff[s] + nb;
-        H.max_blocks = std::max(H.max_blocks, nb);
+        slot0[k] = H.loff.back();
+        H.loff.push_back(H.loff.back() + chunks);
+    }
+    H.max_blocks = 0;
+    for (int s = 0; s < S; ++s) {
+        const int *r = &H.rp[(size_t)s * (rows + 1)];
+        const size_t first = H.blk.size();
+        auto plain = [&](int r_begin, int r_end) {
+            H.brow.assign(1, r_begin);
+            std::vector<char> wave;
+            row_blocks(r, r_begin, r_end, H.brow, wave, H.nb, H.rb);
+            for (size_t k = 0; k + 1 < H.brow.size(); ++k) {
+                const int r0 = H.brow[k], r1 = H.brow[k + 1];
+                H.blk.push_back(make_int4(r0, wave[k] ? ~r1 : r1, r[r0], r[r1]));
+            }
+        };
+        int start = 0;
+        for (size_t k = 0; k < H.lrow.size(); ++k) {
+            const int lr = H.lrow[k];
+            plain(start, lr);
+            for (int b = r[lr]; b < r[lr + 1]; b += nb)
+                H.blk.push_back(make_int4(~slot0[k]++, 0, b, std::min(b + nb, r[lr + 1])));
+            start = lr + 1;
+        }
+        plain(start, rows);
+        const int cnt = (int)(H.blk.size() - first);
+        H.boff[s + 1] = H.boff[s] + cnt;
+        H.max_blocks = std::max(H.max_blocks, cnt);
     }
 }
 
@@ -240,7 +273,13 @@ Sliced<T> upload_sliced(lp_problem *P, const HostSliced &H, const double *scaled
     int *boff = (int *)P->dalloc(sizeof(int) * H.boff.size());
     T *v = (T *)P->dalloc(sizeof(T) * (size_t)std::max<int64_t>(nnz, 1));
     T *part = (T *)P->dalloc(sizeof(T) * (size_t)H.S * (size_t)std::max(H.rows, 1));
+    const int nlong = (int)H.lrow.size();
+    int *lrow = (int *)P->dalloc(sizeof(int) * (size_t)std::max(nlong, 1));
+    int *loff = (int *)P->dalloc(sizeof(int) * H.loff.size());
+    T *lpart = (T *)P->dalloc(sizeof(T) * (size_t)std::max(H.loff.back(), 1));
     int *src = (int *)P->dalloc(sizeof(int) * (size_t)std::max<int64_t>(nnz, 1));
+    upload(P, lrow, H.lrow.data(), nlong);
+    upload(P, loff, H.loff.data(), (int64_t)H.loff.size());
     upload(P, rp, H.rp.data(), (int64_t)H.rp.size());
     upload(P, ci, H.ci.data(), nnz);
     upload(P, blk, H.blk.data(), (int64_t)H.blk.size());
@@ -250,6 +289,7 @@ Sliced<T> upload_sliced(lp_problem *P, const HostSliced &H, const double *scaled
     sync(P);
     P->dfree(src);
     q.rp = rp; q.ci = ci; q.blk = blk; q.boff = boff; q.v = v; q.part = part;
+    q.nlong = nlong; q.lrow = lrow; q.loff = loff; q.lpart = lpart;
     return q;
 }
 
@@ -257,7 +297,8 @@ template <typename T>
 void free_sliced(lp_problem *P, Sliced<T> &q)
 {
     for (const void *p : {(const void *)q.rp, (const void *)q.ci, (const void *)q.blk, (const void *)q.boff,
-                          (const void *)q.v, (const void *)q.part})
+                          (const void *)q.v, (const void *)q.part, (const void *)q.lrow, (const void *)q.loff,
+                          (const void *)q.lpart})
         P->dfree(const_cast<void *>(p));
     q = Sliced<T>{};
 }
@@ -451,6 +492,7 @@ size_t load_plan_bytes(int64_t m, int64_t n, int64_t nnz, const HostSliced &HK, 
         add(sizeof(int) * H->boff.size());
         add(T * one(nnz));
         add(T * (size_t)H->S * (size_t)std::max(H->rows, 1));
+        add(4 * one((int64_t)H->lrow.size())); add(4 * H->loff.size()); add(T * one(H->loff.back()));
         add(4 * one(nnz));
     }
     if (mixed) for (int64_t len : {n, n, n, m}) add(T * one(len));

@@ -129,6 +129,42 @@ __device__ __forceinline__ T sum_slices(const Sliced<T> &P, int i)
     }
 }
 
+// The total of every long row (more than kLongRow entries) inside rows
+// [vb*kBlock, (vb+1)*kBlock): the whole workgroup adds the row's chunk dot
+// products in a fixed order, and the thread of that row gets it in `val`
+// (returns true for that thread only).  Every thread of the workgroup must
+// call it with the same vb.  LONG = false (a product without long rows)
+// compiles to nothing.
+template <bool LONG, typename T>
+__device__ __forceinline__ bool long_row_total(const Sliced<T> &P, int vb, T &val)
+{
+    if constexpr (!LONG) return false;
+    if (P.nlong == 0) return false;
+    __shared__ double sh[kBlock / 64];
+    const int lo = vb * kBlock, hi = lo + kBlock;
+    int a = 0, b = P.nlong;   // first long row >= lo
+    while (a < b) {
+        const int mid = (a + b) >> 1;
+        if (P.lrow[mid] < lo) a = mid + 1;
+        else b = mid;
+    }
+    bool have = false;
+    for (int k = a; k < P.nlong && P.lrow[k] < hi; ++k) {
+        double acc = 0.0;
+        for (int p = P.loff[k] + (int)threadIdx.x; p < P.loff[k + 1]; p += kBlock) acc += (double)P.lpart[p];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (P.lrow[k] - lo == (int)threadIdx.x) {
+            val = (T)(((sh[0] + sh[1]) + sh[2]) + sh[3]);
+            have = true;
+        }
+        __syncthreads();
+    }
+    return have;
+}
+
 // ----------------------------------------------------------------------------
 // epilogues
 // ----------------------------------------------------------------------------
@@ -511,6 +547,39 @@ __device__ __forceinline__ void stream_block(const int *__restrict__ rp, const i
     }
 }
 
+// Dot product of entries [b, e) of one slice (1 <= e - b <= kStreamNB): a
+// chunk of a long row.  Same load / gather / product phases as stream_block,
+// products added in registers, then across the workgroup in a fixed order;
+// every thread gets the result.  Every thread of the workgroup must call it.
+template <typename T>
+__device__ __forceinline__ T chunk_dot(const int *__restrict__ ci, const T *__restrict__ v, const T *__restrict__ x,
+                                       int b, int e, double *red)
+{
+    constexpr int U = kStreamNB / kBlock;
+    const int cnt = e - b;
+    int col[U];
+    T a[U], g[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int t = min((int)threadIdx.x + u * kBlock, cnt - 1);
+        col[u] = __builtin_nontemporal_load(ci + b + t);
+        a[u] = __builtin_nontemporal_load(v + b + t);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) g[u] = x[col[u]];
+    T acc = T(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if ((int)threadIdx.x + u * kBlock < cnt) acc += a[u] * g[u];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = (double)acc;
+    __syncthreads();
+    const T r = (T)(((red[0] + red[1]) + red[2]) + red[3]);
+    __syncthreads();
+    return r;
+}
+
 // The 18 check sums of the current and the averaged iterate over the
 // elements this workgroup owns in a grid-stride walk of the n-chunks then the
 // m-chunks (the same walk as the elementwise solver kernels, so a thread
@@ -539,8 +608,9 @@ __device__ __forceinline__ void check_sums_pass(const Dev<T> &d, int c, int vb_n
 }
 
 // One column slice's partial products (see Sliced): workgroup b takes slice
-// b % S and walks that slice's row blocks with stride gridDim / S.
-template <typename T>
+// b % S and walks that slice's row blocks with stride gridDim / S.  LONG:
+// the product has long rows, so some blocks are chunks of one.
+template <bool LONG, typename T>
 __device__ __forceinline__ void sliced_partial(const Sliced<T> &P, const T *__restrict__ x)
 {
     __shared__ T prod[kStreamNB];
@@ -554,6 +624,13 @@ __device__ __forceinline__ void sliced_partial(const Sliced<T> &P, const T *__re
     const int4 *bd = P.blk + P.boff[s];
     for (int k = chunk0; k < nblk; k += stride) {
         const int4 q = bd[k];
+        if constexpr (LONG) {
+            if (q.x < 0) {   // a chunk of a long row
+                const T r = chunk_dot(P.ci, P.v, x, q.z, q.w, red);
+                if (threadIdx.x == 0) P.lpart[~q.x] = r;
+                continue;
+            }
+        }
         const bool wave = q.y < 0;
         stream_block(rp, P.ci, P.v, x, q.x, wave ? ~q.y : q.y, wave, q.z, q.w, out, prod, red);
     }

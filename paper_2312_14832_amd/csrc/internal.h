@@ -15,9 +15,15 @@ constexpr int kXcds = 8;         // MI355X: 8 XCDs, workgroups dealt to them rou
 constexpr int kStreamNB = 2048;  // nonzeros staged in LDS per row block
 constexpr int kStreamRB = 1024;  // most rows per row block (each thread sums every 256th row)
 constexpr int kWaveRow = 64;     // rows longer than this are summed by a whole wavefront
+constexpr int kLongRow = 4 * kStreamNB;  // rows longer than this are cut into chunks
 // A row block is either a run of rows of at most kWaveRow entries (thread per
 // row) or up to kBlock/64 longer rows (wavefront per row); a wavefront block's
-// end row is stored complemented (~end) in the block descriptor.
+// end row is stored complemented (~end) in the block descriptor.  A row of
+// more than kLongRow entries (a dense row, e.g. a sum-to-one constraint) is
+// instead cut, in every slice, into chunks of at most one block's nonzeros;
+// each chunk is a block of its own whose descriptor holds ~slot (negative)
+// in place of the first row, and its workgroup writes the chunk's dot
+// product to lpart[slot].  The epilogue adds a long row's slots.
 
 // One sparse product y = A x split by COLUMNS into S contiguous slices.  The
 // slice of x a workgroup gathers from is small enough to stay in one XCD's
@@ -38,7 +44,11 @@ struct Sliced {
     const int4 *blk;  // row blocks {first row, end row (~end: wavefront rows), first entry, end entry};
                       // slice s owns blk[boff[s] .. boff[s+1])
     const int *boff;  // [S+1] prefix counts of row blocks
-    T *part;          // [S*rows] partial products
+    T *part;          // [S*rows] partial products (slots of long rows unused)
+    int nlong;        // rows longer than kLongRow
+    const int *lrow;  // [nlong] those rows, ascending
+    const int *loff;  // [nlong+1] long row k owns lpart[loff[k] .. loff[k+1]), slice-major
+    T *lpart;         // chunk dot products of the long rows
 };
 
 // check modes

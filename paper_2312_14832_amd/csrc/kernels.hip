@@ -35,25 +35,26 @@ namespace pdlp {
 // the iteration kernels
 // ----------------------------------------------------------------------------
 
-// K x' partial products (x' = the primal trial)
-template <typename T>
+// K x' partial products (x' = the primal trial).  LONG (here and below): the
+// product has rows cut into chunks.
+template <typename T, bool LONG>
 __global__ __launch_bounds__(kBlock) void k_partial_K(Dev<T> d)
 {
     const Ctl *ctl = d.ctl;
     if (ctl->done) return;
-    sliced_partial(d.K, (const T *)pick(d.xb, ctl->cur ^ 1));
+    sliced_partial<LONG>(d.K, (const T *)pick(d.xb, ctl->cur ^ 1));
 }
 
 // K' y' partial products, only after an accepted step
-template <typename T>
+template <typename T, bool LONG>
 __global__ __launch_bounds__(kBlock) void k_partial_KT(Dev<T> d)
 {
     const Ctl *ctl = d.ctl;
     if (ctl->done || !ctl->accepted) return;
-    sliced_partial(d.KT, (const T *)pick(d.yb, ctl->cur));
+    sliced_partial<LONG>(d.KT, (const T *)pick(d.yb, ctl->cur));
 }
 
-template <typename T, int NS>
+template <typename T, int NS, bool LONG>
 __global__ __launch_bounds__(kBlock) void k_dual(Dev<T> d, int vb_m)
 {
     const Ctl *ctl = d.ctl;
@@ -63,7 +64,9 @@ __global__ __launch_bounds__(kBlock) void k_dual(Dev<T> d, int vb_m)
     DualEpi<T> epi{pick(d.yb, c), pick(d.Kxb, c), d.qs, pick(d.yb, c ^ 1), pick(d.Kxb, c ^ 1), d.m1, sigma, 0.0, 0.0};
     for (int vb = blockIdx.x; vb < vb_m; vb += gridDim.x) {
         const int i = vb * kBlock + (int)threadIdx.x;
-        if (i < d.m) epi(i, sum_slices<NS>(d.K, i));
+        T lt;
+        const bool lng = long_row_total<LONG>(d.K, vb, lt);
+        if (i < d.m) epi(i, lng ? lt : sum_slices<NS>(d.K, i));
     }
     double v[2] = {epi.dy2, epi.inter};
     block_store_partials<2>(v, d.part_dual);
@@ -84,7 +87,7 @@ __global__ __launch_bounds__(kBlock) void k_step_decide(Ctl *ctl, const double *
     step_decision(ctl, a[0], b[0], b[1]);
 }
 
-template <typename T, int NS>
+template <typename T, int NS, bool LONG>
 __global__ __launch_bounds__(kBlock) void k_update(Dev<T> d, int vb_n, int vb_m)
 {
     const Ctl *ctl = d.ctl;
@@ -105,7 +108,9 @@ __global__ __launch_bounds__(kBlock) void k_update(Dev<T> d, int vb_n, int vb_m)
         for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
             if (vb < vb_n) {
                 const int j = vb * kBlock + (int)threadIdx.x;
-                if (j < d.n) epi(j, sum_slices<NS>(d.KT, j));
+                T lt;
+                const bool lng = long_row_total<LONG>(d.KT, vb, lt);
+                if (j < d.n) epi(j, lng ? lt : sum_slices<NS>(d.KT, j));
             } else {
                 const int i = (vb - vb_n) * kBlock + (int)threadIdx.x;
                 if (i < d.m) average_row(d, i, c, epi.w);
@@ -164,17 +169,19 @@ __global__ __launch_bounds__(kBlock) void k_check_apply(Dev<T> d, int vb_n, int 
     block_store_partials<1>(v, d.part_primal);
 }
 
-template <typename T>
+template <typename T, bool LONG>
 __global__ __launch_bounds__(kBlock) void k_partial_plain(Sliced<T> P, const T *__restrict__ x)
 {
-    sliced_partial(P, x);
+    sliced_partial<LONG>(P, x);
 }
 
-template <typename T>
+template <typename T, bool LONG>
 __global__ __launch_bounds__(kBlock) void k_sum_slices(Sliced<T> P, T *__restrict__ out)
 {
     const int i = blockIdx.x * kBlock + (int)threadIdx.x;
-    if (i < P.rows) out[i] = sum_slices<0>(P, i);
+    T lt;
+    const bool lng = long_row_total<LONG>(P, (int)blockIdx.x, lt);
+    if (i < P.rows) out[i] = lng ? lt : sum_slices<0>(P, i);
 }
 
 // values into the sliced layout: dst[p] = src_vals[src_pos[p]]
@@ -345,28 +352,37 @@ static inline int blocks_for(int64_t len) { return (int)((len + kBlock - 1) / kB
 template <typename T>
 hipError_t launch_partial_K(const Dev<T> &d, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_partial_K<T>, dim3(d.K.grid), dim3(kBlock), 0, s, d);
+    if (d.K.nlong) hipLaunchKernelGGL((k_partial_K<T, true>), dim3(d.K.grid), dim3(kBlock), 0, s, d);
+    else hipLaunchKernelGGL((k_partial_K<T, false>), dim3(d.K.grid), dim3(kBlock), 0, s, d);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_partial_KT(const Dev<T> &d, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_partial_KT<T>, dim3(d.KT.grid), dim3(kBlock), 0, s, d);
+    if (d.KT.nlong) hipLaunchKernelGGL((k_partial_KT<T, true>), dim3(d.KT.grid), dim3(kBlock), 0, s, d);
+    else hipLaunchKernelGGL((k_partial_KT<T, false>), dim3(d.KT.grid), dim3(kBlock), 0, s, d);
     return hipGetLastError();
+}
+
+template <typename T, bool LONG>
+void launch_dual_t(const Dev<T> &d, const Geo &g, hipStream_t s)
+{
+    switch (d.K.S) {
+    case 1: hipLaunchKernelGGL((k_dual<T, 1, LONG>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_m); break;
+    case 2: hipLaunchKernelGGL((k_dual<T, 2, LONG>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_m); break;
+    case 4: hipLaunchKernelGGL((k_dual<T, 4, LONG>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_m); break;
+    case 8: hipLaunchKernelGGL((k_dual<T, 8, LONG>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_m); break;
+    case 16: hipLaunchKernelGGL((k_dual<T, 16, LONG>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_m); break;
+    default: hipLaunchKernelGGL((k_dual<T, 0, LONG>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_m); break;
+    }
 }
 
 template <typename T>
 hipError_t launch_dual(const Dev<T> &d, const Geo &g, hipStream_t s)
 {
-    switch (d.K.S) {
-    case 1: hipLaunchKernelGGL((k_dual<T, 1>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_m); break;
-    case 2: hipLaunchKernelGGL((k_dual<T, 2>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_m); break;
-    case 4: hipLaunchKernelGGL((k_dual<T, 4>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_m); break;
-    case 8: hipLaunchKernelGGL((k_dual<T, 8>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_m); break;
-    case 16: hipLaunchKernelGGL((k_dual<T, 16>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_m); break;
-    default: hipLaunchKernelGGL((k_dual<T, 0>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_m); break;
-    }
+    if (d.K.nlong) launch_dual_t<T, true>(d, g, s);
+    else launch_dual_t<T, false>(d, g, s);
     return hipGetLastError();
 }
 
@@ -378,17 +394,25 @@ hipError_t launch_step_decide(const Dev<T> &d, const Geo &g, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename T, bool LONG>
+void launch_update_t(const Dev<T> &d, const Geo &g, hipStream_t s)
+{
+    switch (d.KT.S) {
+    case 1: hipLaunchKernelGGL((k_update<T, 1, LONG>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_n, g.vb_m); break;
+    case 2: hipLaunchKernelGGL((k_update<T, 2, LONG>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_n, g.vb_m); break;
+    case 4: hipLaunchKernelGGL((k_update<T, 4, LONG>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_n, g.vb_m); break;
+    case 8: hipLaunchKernelGGL((k_update<T, 8, LONG>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_n, g.vb_m); break;
+    case 16: hipLaunchKernelGGL((k_update<T, 16, LONG>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_n, g.vb_m);
+        break;
+    default: hipLaunchKernelGGL((k_update<T, 0, LONG>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_n, g.vb_m); break;
+    }
+}
+
 template <typename T>
 hipError_t launch_update(const Dev<T> &d, const Geo &g, hipStream_t s)
 {
-    switch (d.KT.S) {
-    case 1: hipLaunchKernelGGL((k_update<T, 1>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_n, g.vb_m); break;
-    case 2: hipLaunchKernelGGL((k_update<T, 2>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_n, g.vb_m); break;
-    case 4: hipLaunchKernelGGL((k_update<T, 4>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_n, g.vb_m); break;
-    case 8: hipLaunchKernelGGL((k_update<T, 8>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_n, g.vb_m); break;
-    case 16: hipLaunchKernelGGL((k_update<T, 16>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_n, g.vb_m); break;
-    default: hipLaunchKernelGGL((k_update<T, 0>), dim3(g.grid), dim3(kBlock), 0, s, d, g.vb_n, g.vb_m); break;
-    }
+    if (d.KT.nlong) launch_update_t<T, true>(d, g, s);
+    else launch_update_t<T, false>(d, g, s);
     return hipGetLastError();
 }
 
@@ -418,8 +442,13 @@ template <typename T>
 hipError_t launch_spmv(const Sliced<T> &P, const T *in, T *out, hipStream_t s)
 {
     if (P.rows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_partial_plain<T>, dim3(P.grid), dim3(kBlock), 0, s, P, in);
-    hipLaunchKernelGGL(k_sum_slices<T>, dim3(blocks_for(P.rows)), dim3(kBlock), 0, s, P, out);
+    if (P.nlong) {
+        hipLaunchKernelGGL((k_partial_plain<T, true>), dim3(P.grid), dim3(kBlock), 0, s, P, in);
+        hipLaunchKernelGGL((k_sum_slices<T, true>), dim3(blocks_for(P.rows)), dim3(kBlock), 0, s, P, out);
+    } else {
+        hipLaunchKernelGGL((k_partial_plain<T, false>), dim3(P.grid), dim3(kBlock), 0, s, P, in);
+        hipLaunchKernelGGL((k_sum_slices<T, false>), dim3(blocks_for(P.rows)), dim3(kBlock), 0, s, P, out);
+    }
     return hipGetLastError();
 }
 

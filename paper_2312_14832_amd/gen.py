@@ -291,3 +291,40 @@ def sketch_matrix(dim: int, rows: int = 256, per_col: int = 8, seed: int = 4242)
     rr = r.ravel().astype(np.int64)
     rp, ci, v = _to_csr(rr, cols, sign.ravel(), rows, dim)
     return rp, ci, v.astype(np.float32)
+
+
+# ----------------------------------------------------------------------------
+# PageRank-style LP (a second workload with structured sparsity)
+# ----------------------------------------------------------------------------
+
+def pagerank_lp(seed: int, n: int, avg_out: float = 6.0, damping: float = 0.85) -> LPData:
+    """LP whose unique feasible point is the PageRank vector of a random graph.
+
+    Graph: node j draws 1 + Poisson(avg_out - 1) links to other nodes, uniformly
+    with repeats collapsed (so every node links somewhere); A is its
+    column-stochastic transition matrix (A_ij = 1/outdeg_j for each link j -> i).  The LP has n variables x >= 0, zero cost, one
+    equality row sum(x) = 1 (row 0) and n inequality rows
+    ``x_i - damping * (A x)_i >= (1 - damping)/n``.  Summing the inequality
+    rows gives (1 - damping) sum(x) >= 1 - damping, so with sum(x) = 1 every
+    row is tight and x is the solution of (I - damping A) x = (1 - damping)/n.
+    Shape: m = n + 1, nnz = n (row 0) + n (diagonal) + sum of out-degrees.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if n < 2:
+        raise ValueError("pagerank_lp needs n >= 2")
+    draws = np.minimum(1 + rng.poisson(avg_out - 1.0, size=n), n - 1)
+    src = np.repeat(np.arange(n, dtype=np.int64), draws)
+    dst = rng.integers(0, n - 1, size=src.size, dtype=np.int64)
+    dst += dst >= src                     # uniform over the other n - 1 nodes
+    key = np.unique(src * n + dst)        # repeated links collapse to one
+    src, dst = key // n, key % n
+    deg = np.bincount(src, minlength=n)   # >= 1: a node's first link is never a repeat
+    w = -damping / deg[src]
+    rows = np.concatenate([np.zeros(n, np.int64), 1 + np.arange(n, dtype=np.int64), 1 + dst])
+    cols = np.concatenate([np.arange(n, dtype=np.int64), np.arange(n, dtype=np.int64), src])
+    vals = np.concatenate([np.ones(n), np.ones(n), w])
+    row_ptr, col, val = _to_csr(rows, cols, vals, n + 1, n)
+    q = np.concatenate([[1.0], np.full(n, (1.0 - damping) / n)])
+    return LPData(m=n + 1, n=n, m1=1, row_ptr=row_ptr, col=col, val=val, c=np.zeros(n), q=q,
+                  l=np.zeros(n), u=np.full(n, np.inf),
+                  meta={"workload": "pagerank", "seed": seed, "n": n, "avg_out": avg_out, "damping": damping})

@@ -440,3 +440,46 @@ def check_rational_replay(om, libpath=None):
             scale = max(1.0, np.abs(want).max())
             assert np.abs(st[key] - want).max() <= 1e-14 * scale, (k, key)
     assert any(float(v) in (0.0, 2.0, 3.0, -1.0) for v in exact[-1][0])   # some bound is active
+
+
+# ---------------------------------------------------------------- PageRank LP
+
+def pagerank_vector(lp, iters=250):
+    """The PageRank vector as the fixed point of x = (1-d)/n + d A x (the
+    inequality rows of the LP taken as equations, with d A = I - K[1:]).  The
+    map contracts by d in the 1-norm (A is column-stochastic), so from the
+    uniform start the error after 250 steps is at most 2 * 0.85^250 < 1e-17."""
+    K1 = lp.csr()[1:]
+    x = np.full(lp.n, 1.0 / lp.n)
+    for _ in range(iters):
+        x = lp.q[1:] + x - K1 @ x
+    return x
+
+
+def test_pagerank_lp_structure():
+    """The generator's LP: row 0 is sum(x) = 1; the inequality block is
+    I - d A with A column-stochastic, so each of its columns sums to 1 - d;
+    the PageRank vector is positive, sums to one and meets every row."""
+    lp = gen.pagerank_lp(5, 3000)
+    d = lp.meta["damping"]
+    K = lp.csr()
+    assert lp.m == lp.n + 1 and lp.m1 == 1
+    assert np.array_equal(K[0].toarray().ravel(), np.ones(lp.n))
+    assert np.allclose(np.asarray(K[1:].sum(axis=0)).ravel(), 1.0 - d, rtol=0, atol=1e-14)
+    assert np.array_equal(K[1:].diagonal(), np.ones(lp.n))
+    x = pagerank_vector(lp)
+    assert x.min() > 0 and abs(x.sum() - 1.0) < 1e-12
+    assert np.all(K[1:] @ x >= lp.q[1:] - 1e-15)
+
+
+def test_pagerank_solution_is_the_pagerank_vector(oracle_mod):
+    """The LP's only feasible point is the PageRank vector, so the oracle at
+    rel KKT 1e-8 lands on it: 1e-5 relative in the 2-norm (it reaches about
+    4e-7), with zero objective and x >= 0."""
+    lp = gen.pagerank_lp(11, 20000)
+    xs = pagerank_vector(lp)
+    o = oracle_mod.Oracle(lp)
+    x, y, lam, info = o.solve(1e-8, 100_000)
+    assert info["status"] == "OPTIMAL"
+    assert np.linalg.norm(x - xs) <= 1e-5 * np.linalg.norm(xs)
+    assert info["pobj"] == 0.0 and x.min() >= 0.0
