@@ -94,10 +94,11 @@ typedef struct {
     int window;             /* attempt slots launched between host polls of the done flag (64) */
     int kernel_timing;      /* 1: bracket the two SpMV kernels with hipEvents (see lp_kernel_time) */
     int slice_kib;          /* target KiB of a gathered vector per column slice of K and K' (2048 = half an XCD's L2) */
-    int autotune;           /* 1: at lp_load, time the slice count from slice_kib and its halved/doubled
-                               neighbours and smaller row blocks on the actual matrix and keep the fastest,
-                               per product (0); ignored when a workspace is given.  At lp_batch_load: the
-                               row-block shape (lp_batch_layout_blocks) */
+    int autotune;           /* 1: at lp_load, time the slice count from slice_kib, then halve it (else
+                               double it, to at most 32) while that keeps helping, then smaller row blocks,
+                               on the actual matrix, and keep the fastest, per product (0); ignored when a
+                               workspace is given.  At lp_batch_load: the row-block shape
+                               (lp_batch_layout_blocks) */
     int verbose;            /* 1: messages on stderr, and one trace line per window of the solve (k, attempts,
                                restarts, eta, omega, and rel_p, rel_d, rel_gap, KKT_omega of the last check) */
     int ptr_kind;           /* LP_HOST (default) or LP_DEVICE */

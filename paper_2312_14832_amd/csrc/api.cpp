@@ -319,9 +319,12 @@ float time_product(lp_problem *P, const Sliced<T> &q, T *in, T *out, int64_t in_
     return ev.ms() / reps;
 }
 
-// Autotuner for one product: times the default layout, its neighbours in
-// slice count (halved, doubled), in nonzeros per row block (halved) and in
-// rows per row block (256) on the actual matrix and keeps the fastest.
+// Autotuner for one product: times the default layout, then walks the slice
+// count down by halving while that keeps helping (else up by doubling, to at
+// most 32), then tries halved nonzeros per row block and 256 rows per block at
+// the best slice count, on the actual matrix, and keeps the fastest.  The walk
+// matters on very sparse matrices with many rows: each slice adds a row
+// pointer and a partial per row, which can outweigh the L2 locality it buys.
 template <typename T>
 Sliced<T> tuned_sliced(lp_problem *P, const HostSliced &H0, const std::vector<int> &rp, const std::vector<int> &ci,
                        const double *vals, T *in, T *out, int64_t in_len, std::vector<TuneTrial> &log, int *shape)
@@ -330,11 +333,8 @@ Sliced<T> tuned_sliced(lp_problem *P, const HostSliced &H0, const std::vector<in
     float best_ms = time_product<T>(P, best, in, out, in_len);
     log.push_back({H0.S, H0.nb, H0.rb, best_ms});
     shape[0] = H0.S; shape[1] = H0.nb; shape[2] = H0.rb;
-    const int cands[][3] = {{H0.S / 2, H0.nb, H0.rb}, {H0.S * 2, H0.nb, H0.rb}, {H0.S, H0.nb / 2, H0.rb},
-                            {H0.S, H0.nb, 256}};
-    for (const auto &cand : cands) {
-        const int S = cand[0], nb = cand[1], rb = cand[2];
-        if (S < 1 || S > 32 || (S == H0.S && nb == H0.nb && rb == H0.rb)) continue;
+    // time one layout; keep it if it is the fastest so far
+    auto trial = [&](int S, int nb, int rb) {
         HostSliced H;
         build_sliced(H, H0.rows, H0.cols, rp, ci, S, nb, rb);
         Sliced<T> q = upload_sliced<T>(P, H, vals);
@@ -345,10 +345,18 @@ Sliced<T> tuned_sliced(lp_problem *P, const HostSliced &H0, const std::vector<in
             best = q;
             best_ms = ms;
             shape[0] = S; shape[1] = nb; shape[2] = rb;
-        } else {
-            free_sliced<T>(P, q);
+            return true;
         }
-    }
+        free_sliced<T>(P, q);
+        return false;
+    };
+    bool down = false;
+    for (int S = H0.S / 2; S >= 1 && trial(S, H0.nb, H0.rb); S /= 2) down = true;
+    if (!down)
+        for (int S = H0.S * 2; S <= 32 && trial(S, H0.nb, H0.rb); S *= 2) {}
+    const int S = shape[0];
+    if (H0.nb / 2 >= 1) trial(S, H0.nb / 2, H0.rb);
+    if (H0.rb != 256) trial(S, shape[1], 256);
     if (P->opt.verbose)
         for (const auto &t : log)
             std::fprintf(stderr, "[lp] layout %s S=%d nnz/block=%d rows/block=%d: %.3f ms\n",
