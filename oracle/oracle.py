@@ -10,14 +10,16 @@ import numpy as np
 from . import build as _build
 
 NSCALARS = 16
-STATUS = {0: "NOT_SOLVED", 1: "OPTIMAL", 2: "ITERATION_LIMIT", 3: "TIME_LIMIT", 4: "NUMERICAL"}
+STATUS = {0: "NOT_SOLVED", 1: "OPTIMAL", 2: "ITERATION_LIMIT", 3: "TIME_LIMIT", 4: "NUMERICAL",
+          5: "PRIMAL_INFEASIBLE", 6: "DUAL_INFEASIBLE"}
 SCALAR_NAMES = ["eta_hat", "omega", "W", "KKT0", "KKT_prev", "k", "t", "attempts", "restarts",
                 "status", "eta_last"]
 
 
 class _Opts(C.Structure):
     _fields_ = [("ruiz_iters", C.c_int), ("pc_alpha", C.c_double), ("check_every", C.c_int),
-                ("kkt_p", C.c_double), ("fixed_step", C.c_int), ("fixed_eta", C.c_double)]
+                ("kkt_p", C.c_double), ("fixed_step", C.c_int), ("fixed_eta", C.c_double),
+                ("infeas_tol", C.c_double)]
 
 
 _lib = None
@@ -90,11 +92,11 @@ class Oracle:
     """One LP loaded into the oracle."""
 
     def __init__(self, lp, ruiz_iters=10, pc_alpha=1.0, check_every=64, kkt_p=2.0,
-                 fixed_step=False, fixed_eta=0.0, libpath=None):
+                 fixed_step=False, fixed_eta=0.0, infeas_tol=1e-8, libpath=None):
         L = lib(libpath)
         self.L = L
         self.m, self.n, self.m1 = int(lp.m), int(lp.n), int(lp.m1)
-        o = _Opts(ruiz_iters, pc_alpha, check_every, kkt_p, int(bool(fixed_step)), fixed_eta)
+        o = _Opts(ruiz_iters, pc_alpha, check_every, kkt_p, int(bool(fixed_step)), fixed_eta, infeas_tol)
         self._keep = [np.ascontiguousarray(lp.row_ptr, np.int32), np.ascontiguousarray(lp.col, np.int32),
                       _f64(lp.val), _f64(lp.c), _f64(lp.q), _f64(lp.l), _f64(lp.u)]
         rp, ci, v, c, q, l, u = self._keep

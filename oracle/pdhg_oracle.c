@@ -29,7 +29,10 @@
  *   - termination and restart are checked every `check_every` accepted steps;
  *     termination on the unscaled problem, restart KKT on the scaled one,
  *     with omega raised to `kkt_p` (2 as printed);
- *   - projections propagate NaN.
+ *   - projections propagate NaN;
+ *   - infeasibility (the paper is silent): at each check the differences of
+ *     the current iterate from the restart anchor are tested as Farkas rays
+ *     on the unscaled problem (see ray_status).
  *
  * Plain loops, sequential left-to-right sums, no blocking or reordering.
  * Build with -ffp-contract=off and no fast-math.
@@ -54,6 +57,8 @@
 #define ORC_ITERATION_LIMIT 2
 #define ORC_TIME_LIMIT 3
 #define ORC_NUMERICAL 4
+#define ORC_PRIMAL_INFEASIBLE 5
+#define ORC_DUAL_INFEASIBLE 6
 
 #define ORC_NSCALARS 16
 
@@ -70,6 +75,7 @@ typedef struct {
     double kkt_p;       /* exponent of omega in KKT_omega (2) */
     int fixed_step;     /* 1: constant eta = fixed_eta, every step accepted */
     double fixed_eta;
+    double infeas_tol;  /* ray certificates accepted at this relative residual (1e-8); 0: no detection */
 } orc_opts;
 
 typedef struct {
@@ -137,6 +143,23 @@ static void spmv_KT(const orc_t *P, const double *y, double *out)
         for (int64_t p = P->rp[i]; p < P->rp[i + 1]; ++p) out[P->ci[p]] += P->kv[p] * y[i];
 }
 
+/* products with the unscaled K (same pattern, original values) */
+static void spmv_K_unscaled(const orc_t *P, const double *x, double *out)
+{
+    for (int64_t i = 0; i < P->m; ++i) {
+        double s = 0.0;
+        for (int64_t p = P->rp[i]; p < P->rp[i + 1]; ++p) s += P->v[p] * x[P->ci[p]];
+        out[i] = s;
+    }
+}
+
+static void spmv_KT_unscaled(const orc_t *P, const double *y, double *out)
+{
+    for (int64_t j = 0; j < P->n; ++j) out[j] = 0.0;
+    for (int64_t i = 0; i < P->m; ++i)
+        for (int64_t p = P->rp[i]; p < P->rp[i + 1]; ++p) out[P->ci[p]] += P->v[p] * y[i];
+}
+
 static double norm2(const double *a, int64_t len)
 {
     double s = 0.0;
@@ -200,6 +223,7 @@ void orc_default_opts(orc_opts *o)
     o->kkt_p = 2.0;
     o->fixed_step = 0;
     o->fixed_eta = 0.0;
+    o->infeas_tol = 1e-8;
 }
 
 static void scale_problem(orc_t *P)
@@ -501,6 +525,67 @@ static int pdhg_step(orc_t *P)
     return 0;
 }
 
+/* Infeasibility certificates (Farkas' lemma for the LP pair), on the
+ * unscaled problem.  Candidate rays are the differences of the current
+ * iterate from the restart anchor: when the LP has no primal-dual solution
+ * the iterates drift along a ray and these differences grow with it.
+ *   Dual ray w = (y - y0)/Dr proves the primal infeasible when
+ *     dobj = q'w + sum_j (l_j lam_j+ - u_j lam_j-) > 0, with lam = proj_Lambda(-K'w),
+ *     and ||(-K'w - lam, min(w_G, 0))||_2 <= eps * dobj.
+ *   Primal ray d = (x - x0)/Dc proves the dual infeasible (the primal
+ *     unbounded, if feasible) when c'd < 0 and
+ *     ||(A d, max(-G d, 0), v)||_2 <= eps * |c'd|, v_j = min(d_j, 0) if l_j is
+ *     finite, plus max(d_j, 0) if u_j is finite (d must lie in the bounds'
+ *     recession cone).
+ * Returns the status (primal infeasibility first) or 0; on a certificate the
+ * output holds the rays (x: d, y: w, and K'yo such that the returned lam is
+ * proj_Lambda(-K'w)), with pobj = c'd and dobj as above. */
+static int ray_status(orc_t *P, const orc_eval_t *ec)
+{
+    int64_t m = P->m, n = P->n;
+    double eps = P->o.infeas_tol;
+    double *d = xalloc(n, sizeof(double)), *w = xalloc(m, sizeof(double));
+    double *Ad = xalloc(m, sizeof(double)), *KTw = xalloc(n, sizeof(double));
+    for (int64_t j = 0; j < n; ++j) d[j] = (P->x[j] - P->x0[j]) / P->Dc[j];
+    for (int64_t i = 0; i < m; ++i) w[i] = (P->y[i] - P->y0[i]) / P->Dr[i];
+    spmv_K_unscaled(P, d, Ad);
+    spmv_KT_unscaled(P, w, KTw);
+    double cd = 0.0, pres2 = 0.0, qw = 0.0, bnd = 0.0, dres2 = 0.0;
+    for (int64_t i = 0; i < m; ++i) {
+        double r = Ad[i];
+        if (i >= P->m1) r = -Ad[i] > 0.0 ? -Ad[i] : 0.0;
+        pres2 += r * r;
+        qw += P->q[i] * w[i];
+        if (i >= P->m1 && w[i] < 0.0) dres2 += w[i] * w[i];
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        int lf = isfinite(P->l[j]), uf = isfinite(P->u[j]);
+        cd += P->c[j] * d[j];
+        if (lf && d[j] < 0.0) pres2 += d[j] * d[j];
+        if (uf && d[j] > 0.0) pres2 += d[j] * d[j];
+        double g = -KTw[j];
+        double lam = proj_lambda(g, lf, uf);
+        dres2 += (g - lam) * (g - lam);
+        if (lf && lam > 0.0) bnd += P->l[j] * lam;
+        if (uf && lam < 0.0) bnd += P->u[j] * lam;
+    }
+    double dobj = qw + bnd;
+    int st = 0;
+    if (dobj > 0.0 && sqrt(dres2) <= eps * dobj) st = ORC_PRIMAL_INFEASIBLE;
+    else if (cd < 0.0 && sqrt(pres2) <= eps * -cd) st = ORC_DUAL_INFEASIBLE;
+    if (st) {
+        for (int64_t j = 0; j < n; ++j) P->xo[j] = P->x[j] - P->x0[j];
+        for (int64_t i = 0; i < m; ++i) P->yo[i] = P->y[i] - P->y0[i];
+        spmv_KT(P, P->yo, P->KTyo);   /* scaled K'(y - y0) */
+        for (int64_t j = 0; j < n; ++j) P->KTyo[j] += P->cs[j];
+        P->out_rel_p = ec->rel_p; P->out_rel_d = ec->rel_d; P->out_rel_g = ec->rel_g;
+        P->out_pobj = cd; P->out_dobj = dobj;
+        P->has_output = 1;
+    }
+    free(d); free(w); free(Ad); free(KTw);
+    return st;
+}
+
 /* Termination test on current and average; restart test when `restart_ok`.
  * Returns 1 when the run must stop (status set). */
 static int check(orc_t *P, double tol, int restart_ok, int at_limit)
@@ -520,6 +605,13 @@ static int check(orc_t *P, double tol, int restart_ok, int at_limit)
         else set_output(P, P->x, P->y, P->KTy, &ec);
         P->status = ORC_OPTIMAL;
         return 1;
+    }
+    if (P->o.infeas_tol > 0.0) {
+        int st = ray_status(P, &ec);
+        if (st) {
+            P->status = st;
+            return 1;
+        }
     }
     if (at_limit) {
         if (use_avg) set_output(P, P->xa, P->ya, P->KTya, &ea);

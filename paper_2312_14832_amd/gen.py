@@ -328,3 +328,48 @@ def pagerank_lp(seed: int, n: int, avg_out: float = 6.0, damping: float = 0.85) 
     return LPData(m=n + 1, n=n, m1=1, row_ptr=row_ptr, col=col, val=val, c=np.zeros(n), q=q,
                   l=np.zeros(n), u=np.full(n, np.inf),
                   meta={"workload": "pagerank", "seed": seed, "n": n, "avg_out": avg_out, "damping": damping})
+
+
+# ----------------------------------------------------------------------------
+# LPs without a solution (for infeasibility detection)
+# ----------------------------------------------------------------------------
+
+def _with_rows_cols(lp: LPData, K: sp.csr_matrix, m1: int, c, q, l, u, meta) -> LPData:
+    K = sp.csr_matrix(K)
+    K.sort_indices()
+    if K.nnz >= 2**31:
+        raise ValueError("nnz does not fit int32")
+    return LPData(m=K.shape[0], n=K.shape[1], m1=m1, row_ptr=K.indptr.astype(np.int32),
+                  col=K.indices.astype(np.int32), val=np.ascontiguousarray(K.data, dtype=np.float64),
+                  c=np.asarray(c, float), q=np.asarray(q, float), l=np.asarray(l, float),
+                  u=np.asarray(u, float), meta=meta)
+
+
+def infeasible_lp(seed: int, kind: str) -> LPData:
+    """A tiny random LP made to have no primal-dual solution.
+
+    kind "primal": one more equality row asks the boxed variables ([0, 10])
+    of a random set of 20 to sum to 10 * 20 + 5, more than their bounds allow.
+    kind "dual": one more variable with cost -1, bounds [0, inf), entering only
+    inequality rows, with positive coefficients, so x_new -> inf stays feasible
+    and lowers the cost without bound (the base LP is feasible).
+    """
+    base = tiny_lp(seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 7919))
+    K = base.csr()
+    A, G = K[:base.m1], K[base.m1:]
+    if kind == "primal":
+        boxed = np.flatnonzero(np.isfinite(base.l) & np.isfinite(base.u))
+        S = rng.choice(boxed, 20, replace=False)
+        row = sp.csr_matrix((np.ones(20), (np.zeros(20, int), S)), shape=(1, base.n))
+        K2 = sp.vstack([A, row, G])
+        q = np.concatenate([base.q[:base.m1], [float(base.u[S].sum()) + 5.0], base.q[base.m1:]])
+        return _with_rows_cols(base, K2, base.m1 + 1, base.c, q, base.l, base.u,
+                               {"workload": "infeasible_primal", "seed": seed})
+    if kind == "dual":
+        rows = rng.choice(G.shape[0], 4, replace=False)
+        col = sp.csr_matrix((rng.uniform(0.5, 2.0, 4), (rows, np.zeros(4, int))), shape=(G.shape[0], 1))
+        K2 = sp.vstack([sp.hstack([A, sp.csr_matrix((base.m1, 1))]), sp.hstack([G, col])])
+        return _with_rows_cols(base, K2, base.m1, np.append(base.c, -1.0), base.q, np.append(base.l, 0.0),
+                               np.append(base.u, np.inf), {"workload": "infeasible_dual", "seed": seed})
+    raise ValueError(kind)

@@ -47,6 +47,41 @@ def highs(lp):
     return res.fun, res.x, y
 
 
+def highs_status(lp):
+    """scipy linprog (HiGHS) status of the LP: 0 optimal, 2 infeasible, 3 unbounded."""
+    K = lp.csr()
+    m1 = lp.m1
+    bounds = [(None if np.isinf(a) else a, None if np.isinf(b) else b) for a, b in zip(lp.l, lp.u)]
+    kw = {}
+    if m1 > 0:
+        kw["A_eq"], kw["b_eq"] = K[:m1], lp.q[:m1]
+    if lp.m - m1 > 0:
+        kw["A_ub"], kw["b_ub"] = -K[m1:], -lp.q[m1:]
+    return so.linprog(lp.c, bounds=bounds, method="highs", **kw).status
+
+
+def farkas_ratios(lp, x_ray, y_ray):
+    """The two Farkas certificates of an LP without a solution, computed from
+    the unscaled data.  Dual ray w: objective q'w + sum(l lam+ - u lam-) with
+    lam = proj_Lambda(-K'w), residual |(-K'w - lam, min(w_G, 0))|.  Primal ray
+    d: objective c'd, residual |(A d, max(-G d, 0), recession-cone violation)|.
+    Returns (dual_obj, dual_res, primal_obj, primal_res)."""
+    K = lp.csr()
+    m1 = lp.m1
+    lf, uf = np.isfinite(lp.l), np.isfinite(lp.u)
+    w, d = y_ray, x_ray
+    g = -(K.T @ w)
+    lam = np.where(lf & uf, g, np.where(lf, np.maximum(g, 0), np.where(uf, np.minimum(g, 0), 0.0)))
+    lo, hi = np.where(lf, lp.l, 0.0), np.where(uf, lp.u, 0.0)
+    dobj = lp.q @ w + np.sum(np.where(lf & (lam > 0), lo * lam, 0.0)) \
+        + np.sum(np.where(uf & (lam < 0), hi * lam, 0.0))
+    dres = np.linalg.norm(np.concatenate([g - lam, np.minimum(w[m1:], 0.0)]))
+    Kd = K @ d
+    cone = np.where(lf, np.minimum(d, 0.0), 0.0) + np.where(uf, np.maximum(d, 0.0), 0.0)
+    pres = np.linalg.norm(np.concatenate([Kd[:m1], np.maximum(-Kd[m1:], 0.0), cone]))
+    return dobj, dres, lp.c @ d, pres
+
+
 def brute_force_vertices(Kd, q, m1, l, u, c):
     """Minimum of c'x over the vertices of {Ax=b, Gx>=h, l<=x<=u} (all bounds finite).
 

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from paper_2312_14832_amd import gen
-from lp_helpers import brute_force_vertices, fnum, highs, load_golden
+from lp_helpers import brute_force_vertices, farkas_ratios, fnum, highs, highs_status, load_golden
 
 
 # ---------------------------------------------------------------- end results
@@ -483,3 +483,61 @@ def test_pagerank_solution_is_the_pagerank_vector(oracle_mod):
     assert info["status"] == "OPTIMAL"
     assert np.linalg.norm(x - xs) <= 1e-5 * np.linalg.norm(xs)
     assert info["pobj"] == 0.0 and x.min() >= 0.0
+
+
+# ------------------------------------------------- infeasibility certificates
+
+def _lp_from_dense(Kd, m1, c, q, l, u):
+    import scipy.sparse as sp
+    K = sp.csr_matrix(np.asarray(Kd, float))
+    return gen.LPData(m=K.shape[0], n=K.shape[1], m1=m1, row_ptr=K.indptr.astype(np.int32),
+                      col=K.indices.astype(np.int32), val=K.data.astype(float), c=np.asarray(c, float),
+                      q=np.asarray(q, float), l=np.asarray(l, float), u=np.asarray(u, float))
+
+
+def test_primal_infeasible_closed_form(oracle_mod):
+    """x1 + x2 = -1 with x >= 0: Farkas' dual ray is y < 0 (q'y = -y > 0,
+    -K'y = (-y, -y) >= 0 absorbed by lam in R+), the only direction there is."""
+    lp = _lp_from_dense([[1.0, 1.0]], 1, [1.0, 2.0], [-1.0], [0.0, 0.0], [np.inf, np.inf])
+    x, y, lam, info = oracle_mod.Oracle(lp).solve(1e-8, 200_000)
+    assert info["status"] == "PRIMAL_INFEASIBLE"
+    assert y[0] < 0
+    dobj, dres, _, _ = farkas_ratios(lp, x, y)
+    assert dobj > 0 and dres <= 1e-8 * dobj
+    assert info["dobj"] == pytest.approx(dobj, rel=1e-9)
+    assert np.allclose(lam, -(lp.csr().T @ y), rtol=1e-9)   # lam = proj(-K'y), here inside R+
+
+
+def test_dual_infeasible_closed_form(oracle_mod):
+    """min -x1 s.t. x1 - x2 = 0, x >= 0: unbounded along d = (1, 1)/sqrt(2),
+    the only ray with c'd < 0 in the feasible cone."""
+    lp = _lp_from_dense([[1.0, -1.0]], 1, [-1.0, 0.0], [0.0], [0.0, 0.0], [np.inf, np.inf])
+    x, y, lam, info = oracle_mod.Oracle(lp).solve(1e-8, 200_000)
+    assert info["status"] == "DUAL_INFEASIBLE"
+    assert np.allclose(x / np.linalg.norm(x), [2 ** -0.5, 2 ** -0.5], atol=1e-6)
+    _, _, pobj, pres = farkas_ratios(lp, x, y)
+    assert pobj < 0 and pres <= 1e-8 * -pobj
+    assert info["pobj"] == pytest.approx(pobj, rel=1e-9)
+
+
+@pytest.mark.parametrize("kind,want,hs", [("primal", "PRIMAL_INFEASIBLE", 2), ("dual", "DUAL_INFEASIBLE", 3)])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_infeasible_lps_get_certificates(oracle_mod, kind, want, hs, seed):
+    """HiGHS confirms the LP has no solution; the oracle reports it and its
+    ray meets Farkas' conditions when recomputed from the unscaled data."""
+    lp = gen.infeasible_lp(seed, kind)
+    assert highs_status(lp) == hs
+    x, y, lam, info = oracle_mod.Oracle(lp).solve(1e-8, 400_000)
+    assert info["status"] == want
+    dobj, dres, pobj, pres = farkas_ratios(lp, x, y)
+    if kind == "primal":
+        assert dobj > 0 and dres <= 1e-8 * dobj * (1 + 1e-6)
+    else:
+        assert pobj < 0 and pres <= 1e-8 * -pobj * (1 + 1e-6)
+
+
+def test_detection_off_runs_to_the_limit(oracle_mod):
+    """infeas_tol = 0 disables the ray tests: the same LP ends at the limit."""
+    lp = gen.infeasible_lp(0, "primal")
+    _, _, _, info = oracle_mod.Oracle(lp, infeas_tol=0.0).solve(1e-8, 30_000)
+    assert info["status"] == "ITERATION_LIMIT"
