@@ -69,6 +69,9 @@ extern "C" {
 #define LP_ITERATION_LIMIT 2
 #define LP_TIME_LIMIT 3
 #define LP_NUMERICAL 4         /* NaN in a step-size or KKT quantity */
+#define LP_PRIMAL_INFEASIBLE 5 /* a dual ray certifies that no x meets the constraints (see lp_result) */
+#define LP_DUAL_INFEASIBLE 6   /* a primal ray certifies that the dual has no feasible point: the LP is
+                                  unbounded if it is feasible (see lp_result) */
 
 typedef struct lp_problem lp_problem;   /* opaque; owned by the library */
 
@@ -105,6 +108,14 @@ typedef struct {
     void *workspace;        /* NULL, or device memory of workspace_bytes bytes, 256-byte aligned, owned by
                                the caller, untouched by it until lp_free */
     size_t workspace_bytes;
+    double infeas_tol;      /* relative residual at which a ray certifies infeasibility (1e-8; 0 disables
+                               the test).  At each check the differences of the current iterate from the
+                               restart anchor are tested as Farkas rays on the unscaled problem: a dual ray
+                               w (y_G part >= 0) with q'w + l'lam+ - u'lam- > 0, lam = proj_Lambda(-K'w),
+                               and |(-K'w - lam, min(w_G,0))| <= infeas_tol times that objective proves
+                               primal infeasibility; a primal ray d with c'd < 0 and
+                               |(A d, max(-G d,0), bound-cone violation of d)| <= infeas_tol |c'd| proves
+                               dual infeasibility.  The paper does not specify detection. */
 } lp_options;
 
 typedef struct {
@@ -160,6 +171,10 @@ int lp_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit_s);
 /* Copy the returned point to buffers x[n], y[m], lambda[n] (each may be
  * NULL; device buffers when ptr_kind = LP_DEVICE), unscaled and in the
  * original order; lambda = proj_Lambda(c - K'y).  info may be NULL.
+ * After LP_PRIMAL_INFEASIBLE or LP_DUAL_INFEASIBLE the point is the pair of
+ * rays (x = d, y = w, lambda = proj_Lambda(-K'w); see infeas_tol), with
+ * info->pobj = c'd and info->dobj = q'w + l'lam+ - u'lam-; the rel_* fields
+ * are those of the current iterate.
  * Errors: LP_ERR_STATE before the first lp_solve. */
 int lp_result(const lp_problem *P, double *x, double *y, double *lambda, lp_info *info);
 

@@ -404,11 +404,12 @@ void setup_typed(lp_problem *P, const HostSliced &HK, const HostSliced &HT, cons
         d.xb[b] = tvec(n); d.yb[b] = tvec(m); d.Kxb[b] = tvec(m); d.KTyb[b] = tvec(n);
     }
     d.xa = tvec(n); d.ya = tvec(m); d.Kxa = tvec(m); d.KTya = tvec(n);
-    d.x0 = tvec(n); d.y0 = tvec(m);
+    d.x0 = tvec(n); d.y0 = tvec(m); d.Kx0 = tvec(m); d.KTy0 = tvec(n);
     d.xo = tvec(n); d.yo = tvec(m); d.KTyo = tvec(n);
     d.part_primal = (double *)P->dalloc(sizeof(double) * kMaxGrid);
     d.part_dual = (double *)P->dalloc(sizeof(double) * kMaxGrid * 2);
     d.part_check = (double *)P->dalloc(sizeof(double) * kMaxGrid * kCheckSums);
+    d.part_ray = (double *)P->dalloc(sizeof(double) * kMaxGrid * kRaySums);
     d.ctl = (Ctl *)P->dalloc(sizeof(Ctl));
 }
 
@@ -455,7 +456,7 @@ int check_options(const lp_options &o)
 {
     if ((o.precision != LP_FP64 && o.precision != LP_MIXED) || o.check_every <= 0 || o.ruiz_iters < 0 ||
         (o.fixed_step && !(o.fixed_eta > 0.0)) || o.window <= 0 || o.slice_kib <= 0 ||
-        (o.ptr_kind != LP_HOST && o.ptr_kind != LP_DEVICE) ||
+        (o.ptr_kind != LP_HOST && o.ptr_kind != LP_DEVICE) || !(o.infeas_tol >= 0.0) || std::isinf(o.infeas_tol) ||
         (o.workspace && (reinterpret_cast<uintptr_t>(o.workspace) % 256 != 0)))
         return LP_ERR_ARG;
     return LP_OK;
@@ -505,8 +506,8 @@ size_t load_plan_bytes(int64_t m, int64_t n, int64_t nnz, const HostSliced &HK, 
     }
     if (mixed) for (int64_t len : {n, n, n, m}) add(T * one(len));
     for (int k = 0; k < 2; ++k) for (int64_t len : {n, m, m, n}) add(T * one(len));
-    for (int64_t len : {n, m, m, n, n, m, n, m, n}) add(T * one(len));   // averages, anchor, output
-    add(8 * kMaxGrid); add(8 * kMaxGrid * 2); add(8 * kMaxGrid * kCheckSums);
+    for (int64_t len : {n, m, m, n, n, m, m, n, n, m, n}) add(T * one(len));   // averages, anchor (+ products), output
+    add(8 * kMaxGrid); add(8 * kMaxGrid * 2); add(8 * kMaxGrid * kCheckSums); add(8 * kMaxGrid * kRaySums);
     add(sizeof(Ctl));
     return b;
 }
@@ -682,6 +683,7 @@ int do_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit)
         c.KKT_prev = INFINITY;
         c.mode = MODE_INIT;
         c.tol = tol;
+        c.infeas_tol = P->opt.infeas_tol;
         c.kkt_p = P->opt.kkt_omega_power;
         c.fixed_eta = P->opt.fixed_eta;
         c.max_iters = max_iters;
@@ -697,6 +699,8 @@ int do_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit)
         copy_dev(P, d.ya, d.yb[0], m);
         copy_dev(P, d.y0, d.yb[0], m);
         copy_dev(P, d.Kxa, d.Kxb[0], m);
+        copy_dev(P, d.Kx0, d.Kxb[0], m);
+        copy_dev(P, d.KTy0, d.KTyb[0], n);
         run_check<T>(P);
     } else {
         Ctl c = *P->hctl;   // set by lp_set_state
@@ -708,12 +712,16 @@ int do_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit)
         c.copy_out = 0;
         c.need_primal = 1;
         c.tol = tol;
+        c.infeas_tol = P->opt.infeas_tol;
         c.max_iters = max_iters;
         c.kkt_p = P->opt.kkt_omega_power;
         c.check_every = P->opt.check_every;
         c.fixed_step = P->opt.fixed_step;
         c.fixed_eta = P->opt.fixed_eta;
         put_ctl(P, c, d.ctl);
+        // the anchor's products (the state holds the anchor, not its products)
+        HIPT(launch_spmv<T>(d.K, d.x0, d.Kx0, st));
+        HIPT(launch_spmv<T>(d.KT, d.y0, d.KTy0, st));
         HIPT(launch_check_apply<T>(d, P->geo, st));
     }
     P->state_ready = false;
@@ -982,6 +990,7 @@ void lp_default_options(lp_options *o)
     o->slice_kib = 2048;
     o->autotune = 0;
     o->verbose = 0;
+    o->infeas_tol = 1e-8;
 }
 
 int lp_workspace_size(const lp_csr *K, const lp_options *opt, size_t *bytes)

@@ -152,6 +152,10 @@ __global__ __launch_bounds__(kBlock) void bk_check_reduce(BDev<T> b, int gated)
             row_sums(d, e, b.m1g[inst], (const T *)d.ya, (const T *)d.Kxa, s + 9);
         }
         block_store_partials<kCheckSums>(s, d.part_check, ch);
+        double r[kRaySums] = {0.0, 0.0, 0.0, 0.0};
+        if (nside) ray_col_sums(d, e, (const T *)pick(d.xb, c), (const T *)pick(d.KTyb, c), r);
+        else ray_row_sums(d, e, b.m1g[inst], (const T *)pick(d.yb, c), (const T *)pick(d.Kxb, c), r);
+        block_store_partials<kRaySums>(r, d.part_ray, ch);
     }
 }
 
@@ -161,14 +165,18 @@ __global__ __launch_bounds__(kBlock) void bk_check_decide(BDev<T> b, int gated)
     if (gated && *b.gate == 0) return;
     Ctl *ctl = b.ctl + blockIdx.x;
     if (ctl->mode == MODE_NONE || ctl->done) return;
-    double Sn[kCheckSums], Sm[kCheckSums];
+    double Sn[kCheckSums], Sm[kCheckSums], Rn[kRaySums], Rm[kRaySums];
     block_sum_partials<kCheckSums>(b.d.part_check + (size_t)kCheckSums * b.nc0[blockIdx.x], b.ncc[blockIdx.x], Sn);
     block_sum_partials<kCheckSums>(b.d.part_check + (size_t)kCheckSums * (b.ncn + b.mc0[blockIdx.x]),
                                    b.mcc[blockIdx.x], Sm);
+    block_sum_partials<kRaySums>(b.d.part_ray + (size_t)kRaySums * b.nc0[blockIdx.x], b.ncc[blockIdx.x], Rn);
+    block_sum_partials<kRaySums>(b.d.part_ray + (size_t)kRaySums * (b.ncn + b.mc0[blockIdx.x]), b.mcc[blockIdx.x],
+                                 Rm);
     if (threadIdx.x != 0) return;
-    double S[kCheckSums];
+    double S[kCheckSums], R[kRaySums];
     for (int i = 0; i < kCheckSums; ++i) S[i] = Sn[i] + Sm[i];
-    check_decision(ctl, S, b.Nq[blockIdx.x], b.Nc[blockIdx.x]);
+    for (int i = 0; i < kRaySums; ++i) R[i] = Rn[i] + Rm[i];
+    check_decision(ctl, S, R, b.Nq[blockIdx.x], b.Nc[blockIdx.x]);
 }
 
 template <typename T>

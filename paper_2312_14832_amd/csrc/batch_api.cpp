@@ -273,13 +273,14 @@ int do_batch_load(lp_batch *P, const lp_csr *K, const double *const *c, const do
             d.xb[k] = A.make<T>(N); d.yb[k] = A.make<T>(M); d.Kxb[k] = A.make<T>(M); d.KTyb[k] = A.make<T>(N);
         }
         d.xa = A.make<T>(N); d.ya = A.make<T>(M); d.Kxa = A.make<T>(M); d.KTya = A.make<T>(N);
-        d.x0 = A.make<T>(N); d.y0 = A.make<T>(M);
+        d.x0 = A.make<T>(N); d.y0 = A.make<T>(M); d.Kx0 = A.make<T>(M); d.KTy0 = A.make<T>(N);
         d.xo = A.make<T>(N); d.yo = A.make<T>(M); d.KTyo = A.make<T>(N);
         b.prodK = A.make<T>(M);
         b.prodKT = A.make<T>(N);
         d.part_primal = A.make<double>(b.ncn);
         d.part_dual = A.make<double>(2 * (int64_t)b.ncm);
         d.part_check = A.make<double>((int64_t)kCheckSums * (b.ncn + b.ncm));
+        d.part_ray = A.make<double>((int64_t)kRaySums * (b.ncn + b.ncm));
         b.ctl = A.make<Ctl>(B);
         d.ctl = b.ctl;
         b.gate = A.make<int>(1);
@@ -393,6 +394,7 @@ Ctl fresh_ctl(const lp_batch *P, int i, double tol, int64_t max_iters)
     c.omega = P->omega0[i];
     c.KKT_prev = INFINITY;
     c.tol = tol;
+    c.infeas_tol = P->opt.infeas_tol;
     c.kkt_p = P->opt.kkt_omega_power;
     c.fixed_eta = P->opt.fixed_eta;
     c.max_iters = max_iters;
@@ -428,6 +430,8 @@ int do_batch_solve(lp_batch *P, double tol, int64_t max_iters, double time_limit
         d2d(st, d.ya, (const T *)d.yb[0], M);
         d2d(st, d.y0, (const T *)d.yb[0], M);
         d2d(st, d.Kxa, (const T *)d.Kxb[0], M);
+        d2d(st, d.Kx0, (const T *)d.Kxb[0], M);
+        d2d(st, d.KTy0, (const T *)d.KTyb[0], N);
         HIPT(launch_batch_check<T>(b, 0, st));
     } else {
         for (int i = 0; i < B; ++i) {
@@ -440,6 +444,7 @@ int do_batch_solve(lp_batch *P, double tol, int64_t max_iters, double time_limit
             c.copy_out = 0;
             c.need_primal = 1;
             c.tol = tol;
+            c.infeas_tol = P->opt.infeas_tol;
             c.max_iters = max_iters;
             c.kkt_p = P->opt.kkt_omega_power;
             c.check_every = P->opt.check_every;
@@ -447,6 +452,9 @@ int do_batch_solve(lp_batch *P, double tol, int64_t max_iters, double time_limit
             c.fixed_eta = P->opt.fixed_eta;
         }
         put_ctls(P, b.ctl);
+        // the anchor's products (the state holds the anchor, not its products)
+        HIPT(launch_batch_product_plain<T>(b, 0, d.x0, d.Kx0, st));
+        HIPT(launch_batch_product_plain<T>(b, 1, d.y0, d.KTy0, st));
         // resume only needs the first primal trial: the apply step alone
         HIPT(launch_batch_apply<T>(b, st));
     }
@@ -627,7 +635,8 @@ int lp_batch_load(lp_batch **out, int32_t count, const lp_csr *K, const double *
     if (opt) o = *opt;
     else lp_default_options(&o);
     if ((o.precision != LP_FP64 && o.precision != LP_MIXED) || o.check_every <= 0 || o.ruiz_iters < 0 ||
-        (o.fixed_step && !(o.fixed_eta > 0.0)) || o.window <= 0)
+        (o.fixed_step && !(o.fixed_eta > 0.0)) || o.window <= 0 || !(o.infeas_tol >= 0.0) ||
+        std::isinf(o.infeas_tol))
         return LP_ERR_ARG;
     std::unique_ptr<lp_batch> P(new lp_batch());
     P->B = count;

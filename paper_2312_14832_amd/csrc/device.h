@@ -280,6 +280,42 @@ __device__ __forceinline__ void col_sums(const Dev<T> &d, int j, const T *x, con
     s[8] += dd * dd;
 }
 
+// The 4 ray sums of the current iterate (difference from the anchor, taken
+// as a Farkas ray on the unscaled problem; scalings cancel in the
+// objectives): s[0] c'd, s[1] |(A d, max(-G d, 0), bound-cone violation)|^2,
+// s[2] q'w + l'lam+ - u'lam- with lam = proj_Lambda(-K'w),
+// s[3] |(-K'w - lam, min(w_G, 0))|^2; d = (x - x0)/Dc, w = (y - y0)/Dr.
+template <typename T>
+__device__ __forceinline__ void ray_row_sums(const Dev<T> &d, int i, int m1, const T *y, const T *kx, double *s)
+{
+    const double kd = ((double)kx[i] - (double)d.Kx0[i]) * d.Dr[i];
+    double r = kd;
+    if (i >= m1) r = -kd > 0.0 ? -kd : 0.0;
+    s[1] += r * r;
+    const double dy = (double)y[i] - (double)d.y0[i];
+    s[2] += (double)d.qs[i] * dy;
+    if (i >= m1) {
+        const double w = dy / d.Dr[i];
+        if (w < 0.0) s[3] += w * w;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void ray_col_sums(const Dev<T> &d, int j, const T *x, const T *kty, double *s)
+{
+    const double lj = (double)d.ls[j], uj = (double)d.us[j];
+    const bool lf = isfinite(lj), uf = isfinite(uj);
+    const double dx = (double)x[j] - (double)d.x0[j];
+    s[0] += (double)d.cs[j] * dx;
+    const double dj = dx / d.Dc[j];
+    if ((lf && dj < 0.0) || (uf && dj > 0.0)) s[1] += dj * dj;
+    const double g = (double)d.KTy0[j] - (double)kty[j];
+    const double lam = proj_lambda(g, lf, uf);
+    const double r = (g - lam) * d.Dc[j];
+    s[3] += r * r;
+    if (lf && lam > 0.0) s[2] += lj * lam;
+    if (uf && lam < 0.0) s[2] += uj * lam;
+}
 
 // Adaptive step-size test (PDLP's rule; the paper uses eta without stating
 // the rule): eta_bar = (omega|dx|^2 + |dy|^2/omega) / (2|dy.K dx|),
@@ -323,11 +359,12 @@ __device__ inline void step_decision(Ctl *ctl, double dx2, double dy2, double in
     ctl->eta = eta_new;
 }
 
-// Termination (the three relative criteria on the unscaled problem),
-// candidate choice and restart conditions 1-3 on KKT_omega (scaled problem),
-// primal-weight update.  S holds the 9 check sums of the current iterate then
-// the 9 of the average.  Called by one thread per LP.
-__device__ inline void check_decision(Ctl *ctl, const double *S, double Nq, double Nc)
+// Termination (the three relative criteria on the unscaled problem), then
+// the ray certificates of infeasibility, candidate choice and restart
+// conditions 1-3 on KKT_omega (scaled problem), primal-weight update.  S
+// holds the 9 check sums of the current iterate then the 9 of the average,
+// R the 4 ray sums.  Called by one thread per LP.
+__device__ inline void check_decision(Ctl *ctl, const double *S, const double *R, double Nq, double Nc)
 {
     const double wp = pow(ctl->omega, ctl->kkt_p);
     double rel[2], kkt[2];
@@ -380,6 +417,19 @@ __device__ inline void check_decision(Ctl *ctl, const double *S, double Nq, doub
         finish(LP_OPTIMAL, use_avg);
         return;
     }
+    if (ctl->infeas_tol > 0.0) {
+        const double *r = R;
+        int st = 0;
+        if (r[2] > 0.0 && sqrt(r[3]) <= ctl->infeas_tol * r[2]) st = LP_PRIMAL_INFEASIBLE;
+        else if (r[0] < 0.0 && sqrt(r[1]) <= ctl->infeas_tol * -r[0]) st = LP_DUAL_INFEASIBLE;
+        if (st) {
+            finish(st, 0);
+            ctl->out_sel = 2;   // the rays
+            ctl->out_pobj = r[0];
+            ctl->out_dobj = r[2];
+            return;
+        }
+    }
     int at_limit = 0;
     if (mode == MODE_FINAL) at_limit = ctl->final_status;
     else if (ctl->k >= ctl->max_iters) at_limit = LP_ITERATION_LIMIT;
@@ -412,28 +462,37 @@ __device__ inline void check_decision(Ctl *ctl, const double *S, double Nq, doub
 }
 
 // restart / output bookkeeping on column j (current buffer c):
-// rt = 2 restart to the average, 1 restart to the current point; co copies
-// the chosen point (sel: 0 current, 1 average) to the output buffers; np
-// computes the next primal trial with step tau
+// rt = 2 restart to the average, 1 restart to the current point (the anchor
+// and its product follow); co copies the chosen point (sel: 0 current,
+// 1 average, 2 the rays: differences from the anchor, with K'yo set so that
+// the result's lam is proj_Lambda(-K'w)) to the output buffers; np computes
+// the next primal trial with step tau
 template <typename T>
 __device__ __forceinline__ void apply_col(const Dev<T> &d, int j, int c, int rt, int co, int sel, int np, T tau,
                                           double &dx2)
 {
     T *x = pick(d.xb, c), *kty = pick(d.KTyb, c);
     if (co) {
-        d.xo[j] = sel ? d.xa[j] : x[j];
-        d.KTyo[j] = sel ? d.KTya[j] : kty[j];
+        if (sel == 2) {
+            d.xo[j] = x[j] - d.x0[j];
+            d.KTyo[j] = d.cs[j] + (kty[j] - d.KTy0[j]);
+        } else {
+            d.xo[j] = sel ? d.xa[j] : x[j];
+            d.KTyo[j] = sel ? d.KTya[j] : kty[j];
+        }
     }
     if (rt == 2) {
-        const T a = d.xa[j];
+        const T a = d.xa[j], b = d.KTya[j];
         x[j] = a;
         d.x0[j] = a;
-        kty[j] = d.KTya[j];
+        kty[j] = b;
+        d.KTy0[j] = b;
     } else if (rt == 1) {
-        const T a = x[j];
+        const T a = x[j], b = kty[j];
         d.xa[j] = a;
         d.x0[j] = a;
-        d.KTya[j] = kty[j];
+        d.KTya[j] = b;
+        d.KTy0[j] = b;
     }
     if (np) primal_elem(d, c, tau, j, dx2);
 }
@@ -442,17 +501,19 @@ template <typename T>
 __device__ __forceinline__ void apply_row(const Dev<T> &d, int i, int c, int rt, int co, int sel)
 {
     T *y = pick(d.yb, c), *kx = pick(d.Kxb, c);
-    if (co) d.yo[i] = sel ? d.ya[i] : y[i];
+    if (co) d.yo[i] = sel == 2 ? y[i] - d.y0[i] : (sel ? d.ya[i] : y[i]);
     if (rt == 2) {
-        const T a = d.ya[i];
+        const T a = d.ya[i], b = d.Kxa[i];
         y[i] = a;
         d.y0[i] = a;
-        kx[i] = d.Kxa[i];
+        kx[i] = b;
+        d.Kx0[i] = b;
     } else if (rt == 1) {
-        const T a = y[i];
+        const T a = y[i], b = kx[i];
         d.ya[i] = a;
         d.y0[i] = a;
-        d.Kxa[i] = kx[i];
+        d.Kxa[i] = b;
+        d.Kx0[i] = b;
     }
 }
 
@@ -603,6 +664,24 @@ __device__ __forceinline__ void check_sums_pass(const Dev<T> &d, int c, int vb_n
                 row_sums(d, i, d.m1, y, kx, s);
                 row_sums(d, i, d.m1, (const T *)d.ya, (const T *)d.Kxa, s + 9);
             }
+        }
+    }
+}
+
+// The 4 ray sums over the same walk, after the check sums are stored.
+template <typename T>
+__device__ __forceinline__ void ray_sums_pass(const Dev<T> &d, int c, int vb_n, int vb_m, double (&s)[kRaySums])
+{
+#pragma unroll
+    for (int i = 0; i < kRaySums; ++i) s[i] = 0.0;
+    const T *x = pick(d.xb, c), *kty = pick(d.KTyb, c), *y = pick(d.yb, c), *kx = pick(d.Kxb, c);
+    for (int vb = blockIdx.x; vb < vb_n + vb_m; vb += gridDim.x) {
+        if (vb < vb_n) {
+            const int j = vb * kBlock + (int)threadIdx.x;
+            if (j < d.n) ray_col_sums(d, j, x, kty, s);
+        } else {
+            const int i = (vb - vb_n) * kBlock + (int)threadIdx.x;
+            if (i < d.m) ray_row_sums(d, i, d.m1, y, kx, s);
         }
     }
 }

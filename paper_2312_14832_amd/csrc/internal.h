@@ -11,6 +11,7 @@ namespace pdlp {
 constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
 constexpr int kMaxGrid = 2048;   // workgroups of an elementwise solver kernel = partial-sum slots
 constexpr int kCheckSums = 18;   // 9 sums for the current and 9 for the averaged iterate
+constexpr int kRaySums = 4;      // the current iterate's rays (difference from the anchor)
 constexpr int kXcds = 8;         // MI355X: 8 XCDs, workgroups dealt to them round-robin
 constexpr int kStreamNB = 2048;  // nonzeros staged in LDS per row block
 constexpr int kStreamRB = 1024;  // most rows per row block (each thread sums every 256th row)
@@ -66,6 +67,7 @@ struct Ctl {
     double eta_last;   // step size of the last accepted step
     double avg_w;      // eta_last / W, the averaging weight of that step
     double tol;
+    double infeas_tol; // ray certificate threshold; 0: no infeasibility test
     double kkt_p;
     double fixed_eta;
     double rel_p[2], rel_d[2], rel_g[2], pobj[2], dobj[2], kkt[2];
@@ -98,10 +100,12 @@ struct Dev {
     T *xb[2], *yb[2], *Kxb[2], *KTyb[2];   // current / trial buffers
     T *xa, *ya, *Kxa, *KTya;   // step-weighted averages
     T *x0, *y0;                // restart anchor
+    T *Kx0, *KTy0;             // K x0 and K' y0 (ray residuals are differences of products)
     T *xo, *yo, *KTyo;         // returned point
     double *part_primal;       // [kMaxGrid]      |x' - x|^2 partials
     double *part_dual;         // [kMaxGrid * 2]  |y' - y|^2, (y'-y).(Kx'-Kx)
     double *part_check;        // [kMaxGrid * kCheckSums]
+    double *part_ray;          // [kMaxGrid * kRaySums] (a pass of its own: fewer live registers)
     Ctl *ctl;
 };
 

@@ -125,6 +125,9 @@ __global__ __launch_bounds__(kBlock) void k_update(Dev<T> d, int vb_n, int vb_m)
         double cs[kCheckSums];
         check_sums_pass(d, c, vb_n, vb_m, cs);
         block_store_partials<kCheckSums>(cs, d.part_check);
+        double rs[kRaySums];
+        ray_sums_pass(d, c, vb_n, vb_m, rs);
+        block_store_partials<kRaySums>(rs, d.part_ray);
     }
 }
 
@@ -136,15 +139,20 @@ __global__ __launch_bounds__(kBlock) void k_check_reduce(Dev<T> d, int vb_n, int
     double s[kCheckSums];
     check_sums_pass(d, ctl->cur, vb_n, vb_m, s);
     block_store_partials<kCheckSums>(s, d.part_check);
+    double r[kRaySums];
+    ray_sums_pass(d, ctl->cur, vb_n, vb_m, r);
+    block_store_partials<kRaySums>(r, d.part_ray);
 }
 
-__global__ __launch_bounds__(kBlock) void k_check_decide(Ctl *ctl, const double *part, int np, double Nq, double Nc)
+__global__ __launch_bounds__(kBlock) void k_check_decide(Ctl *ctl, const double *part, const double *pray, int np,
+                                                         double Nq, double Nc)
 {
     if (ctl->mode == MODE_NONE || ctl->done) return;
-    double S[kCheckSums];
+    double S[kCheckSums], R[kRaySums];
     block_sum_partials<kCheckSums>(part, np, S);
+    block_sum_partials<kRaySums>(pray, np, R);
     if (threadIdx.x != 0) return;
-    check_decision(ctl, S, Nq, Nc);
+    check_decision(ctl, S, R, Nq, Nc);
 }
 
 template <typename T>
@@ -426,8 +434,8 @@ hipError_t launch_check_reduce(const Dev<T> &d, const Geo &g, hipStream_t s)
 template <typename T>
 hipError_t launch_check_decide(const Dev<T> &d, const Geo &g, double Nq, double Nc, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_check_decide, dim3(1), dim3(kBlock), 0, s, d.ctl, (const double *)d.part_check, g.grid,
-                       Nq, Nc);
+    hipLaunchKernelGGL(k_check_decide, dim3(1), dim3(kBlock), 0, s, d.ctl, (const double *)d.part_check,
+                       (const double *)d.part_ray, g.grid, Nq, Nc);
     return hipGetLastError();
 }
 

@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(HERE, "libpdlp_amd.so")
 
 LP_FP64, LP_MIXED = 0, 1
 LP_HOST, LP_DEVICE = 0, 1
-STATUS = {0: "NOT_SOLVED", 1: "OPTIMAL", 2: "ITERATION_LIMIT", 3: "TIME_LIMIT", 4: "NUMERICAL"}
+STATUS = {0: "NOT_SOLVED", 1: "OPTIMAL", 2: "ITERATION_LIMIT", 3: "TIME_LIMIT", 4: "NUMERICAL",
+          5: "PRIMAL_INFEASIBLE", 6: "DUAL_INFEASIBLE"}
 ERRORS = {-1: "LP_ERR_ARG", -2: "LP_ERR_DIM", -3: "LP_ERR_NAN", -4: "LP_ERR_BOUNDS",
           -5: "LP_ERR_TOO_LARGE", -6: "LP_ERR_STATE", -7: "LP_ERR_HIP", -8: "LP_ERR_NOMEM"}
 NSCALARS = 16
@@ -43,7 +44,7 @@ class LPOptions(C.Structure):
                 ("fixed_step", C.c_int), ("fixed_eta", C.c_double), ("use_graph", C.c_int),
                 ("window", C.c_int), ("kernel_timing", C.c_int), ("slice_kib", C.c_int),
                 ("autotune", C.c_int), ("verbose", C.c_int), ("ptr_kind", C.c_int),
-                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t)]
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t), ("infeas_tol", C.c_double)]
 
 
 class LPInfo(C.Structure):

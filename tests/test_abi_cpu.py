@@ -38,6 +38,7 @@ def test_default_options_and_strerror():
     lp = _lib()
     o = lp.default_options()
     assert (o.precision, o.ruiz_iters, o.pc_alpha, o.check_every, o.kkt_omega_power) == (0, 10, 1.0, 64, 2.0)
+    assert o.infeas_tol == 1e-8
     L = lp.library()
     for code in [0, -1, -2, -3, -4, -5, -6, -7, -8]:
         assert L.lp_strerror(code)
@@ -89,7 +90,8 @@ def test_validation_codes_match_oracle(oracle_mod, mut, code):
 def test_bad_options_rejected():
     lp = _lib()
     for kw in [dict(precision=7), dict(check_every=0), dict(window=0), dict(fixed_step=1, fixed_eta=0.0),
-               dict(ptr_kind=5), dict(workspace=8, workspace_bytes=1 << 20)]:
+               dict(ptr_kind=5), dict(workspace=8, workspace_bytes=1 << 20), dict(infeas_tol=-1.0),
+               dict(infeas_tol=float("nan")), dict(infeas_tol=float("inf"))]:
         with pytest.raises(lp.LPError) as ei:
             lp.Problem(gen.tiny_lp(0), **kw)
         assert ei.value.code == -1

@@ -44,17 +44,23 @@ def test_time_limit(lpmod):
     assert info2["rel_kkt"] == info["rel_kkt"] > 1e-12
 
 
-def test_infeasible_lp_runs_to_the_iteration_limit(lpmod, oracle_mod):
-    """x >= 0 with x1 + x2 = -1 has no feasible point; the method has no
-    infeasibility detection, so both paths stop at max_iters."""
+def test_infeasible_lp_detected_or_runs_to_the_limit(lpmod, oracle_mod):
+    """x >= 0 with x1 + x2 = -1 has no feasible point.  With the ray test
+    both paths report PRIMAL_INFEASIBLE with a dual ray y < 0; with
+    infeas_tol = 0 both stop at max_iters."""
     say("case infeasible")
     data = gen.from_dense(np.array([[1.0, 1.0]]), [1.0, 1.0], [-1.0], [0.0, 0.0], [np.inf, np.inf], 1)
     p = lpmod.Problem(data)
-    info = p.solve(1e-6, 2000)
+    info = p.solve(1e-6, 200_000)
+    _, _, _, io = oracle_mod.Oracle(data).solve(1e-6, 200_000)
+    assert info["status"] == io["status"] == "PRIMAL_INFEASIBLE"
+    _, y, _, _ = p.result()
+    assert y[0] < 0 and info["dobj"] > 0
+    p0 = lpmod.Problem(data, infeas_tol=0.0)
+    info = p0.solve(1e-6, 2000)
     assert info["status"] == "ITERATION_LIMIT" and info["iterations"] == 2000
     assert info["rel_primal"] > 1e-3
-    o = oracle_mod.Oracle(data)
-    _, _, _, io = o.solve(1e-6, 2000)
+    _, _, _, io = oracle_mod.Oracle(data, infeas_tol=0.0).solve(1e-6, 2000)
     assert io["status"] == "ITERATION_LIMIT"
 
 
