@@ -116,6 +116,16 @@ typedef struct {
                                primal infeasibility; a primal ray d with c'd < 0 and
                                |(A d, max(-G d,0), bound-cone violation of d)| <= infeas_tol |c'd| proves
                                dual infeasibility.  The paper does not specify detection. */
+    int presolve;           /* 1: reduce the LP on the host before loading it (0): fixed columns, empty
+                               columns, empty rows, singleton rows (an equality fixes its variable, an
+                               inequality tightens a bound), to a fixed point; a reduction that would prove
+                               infeasibility or unboundedness is left to the solve.  lp_set_start and
+                               lp_result keep the original index space (lp_result maps the point back, with
+                               the duals of removed rows, and reports the termination quantities of the
+                               original problem); the state, scaling, product and layout calls refer to the
+                               reduced problem (lp_presolved_size).  A stand-in for the presolvers the
+                               paper's experiments run first (Table 1).  Not with LP_DEVICE or a workspace
+                               (LP_ERR_ARG). */
 } lp_options;
 
 typedef struct {
@@ -177,6 +187,11 @@ int lp_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit_s);
  * are those of the current iterate.
  * Errors: LP_ERR_STATE before the first lp_solve. */
 int lp_result(const lp_problem *P, double *x, double *y, double *lambda, lp_info *info);
+
+/* Rows *m and columns *n of the problem on the GPU: the original ones, or
+ * the reduced ones when lp_options.presolve removed some.  Either pointer may
+ * be NULL.  Errors: LP_ERR_ARG. */
+int lp_presolved_size(const lp_problem *P, int64_t *m, int64_t *n);
 
 /* Solver state for checkpoint/resume and per-step comparison, as doubles in
  * the scaled space and the original order: 16 scalars

@@ -19,6 +19,7 @@
 
 #include "host_util.h"
 #include "internal.h"
+#include "presolve.h"
 
 using namespace pdlp;
 
@@ -153,7 +154,8 @@ int partial_grid(int S, int max_blocks)
 }  // namespace
 
 struct lp_problem {
-    int64_t m = 0, n = 0, nnz = 0, m1 = 0;
+    int64_t m = 0, n = 0, nnz = 0, m1 = 0;   // of the problem on the GPU (the reduced one after presolve)
+    std::unique_ptr<pdlp::Presolved> pre;   // set when presolve reduced the problem
     lp_options opt{};
     hipStream_t stream = nullptr;
     Geo geo{};
@@ -457,7 +459,8 @@ int check_options(const lp_options &o)
     if ((o.precision != LP_FP64 && o.precision != LP_MIXED) || o.check_every <= 0 || o.ruiz_iters < 0 ||
         (o.fixed_step && !(o.fixed_eta > 0.0)) || o.window <= 0 || o.slice_kib <= 0 ||
         (o.ptr_kind != LP_HOST && o.ptr_kind != LP_DEVICE) || !(o.infeas_tol >= 0.0) || std::isinf(o.infeas_tol) ||
-        (o.workspace && (reinterpret_cast<uintptr_t>(o.workspace) % 256 != 0)))
+        (o.workspace && (reinterpret_cast<uintptr_t>(o.workspace) % 256 != 0)) ||
+        (o.presolve != 0 && o.presolve != 1) || (o.presolve && (o.ptr_kind == LP_DEVICE || o.workspace)))
         return LP_ERR_ARG;
     return LP_OK;
 }
@@ -1001,6 +1004,7 @@ int lp_workspace_size(const lp_csr *K, const lp_options *opt, size_t *bytes)
     else lp_default_options(&o);
     int rc = check_options(o);
     if (rc != LP_OK) return rc;
+    if (o.presolve) return LP_ERR_ARG;   // the reduced size is only known with the data
     try {
         HostLP H;
         if (o.ptr_kind == LP_DEVICE) {
@@ -1056,6 +1060,15 @@ int lp_load(lp_problem **out, const lp_csr *K, const double *c, const double *q,
     std::unique_ptr<lp_problem> P;
     try {
         P.reset(new lp_problem());
+        if (o.presolve) {
+            std::unique_ptr<Presolved> R(new Presolved());
+            if (presolve(K, c, q, l, u, m1, *R)) {
+                K = &R->K;
+                c = R->c.data(); q = R->q.data(); l = R->l.data(); u = R->u.data();
+                m1 = R->m1;
+                P->pre = std::move(R);
+            }
+        }
     } catch (...) {
         return LP_ERR_NOMEM;
     }
@@ -1101,6 +1114,19 @@ int lp_set_start(lp_problem *P, const double *x0, const double *y0)
         } catch (const HipError &h) {
             return fail_hip(P, h);
         }
+    } else if (P->pre) {
+        // original-space start point: keep the entries of the reduced problem
+        const Presolved &R = *P->pre;
+        if (x0) {
+            P->xs.assign((size_t)P->n, 0.0);
+            for (int64_t j = 0; j < R.n0; ++j)
+                if (R.col_new[(size_t)j] >= 0) P->xs[(size_t)R.col_new[(size_t)j]] = x0[j];
+        }
+        if (y0) {
+            P->ys.assign((size_t)P->m, 0.0);
+            for (int64_t i = 0; i < R.m0; ++i)
+                if (R.row_new[(size_t)i] >= 0) P->ys[(size_t)R.row_new[(size_t)i]] = y0[i];
+        }
     } else {
         if (x0) P->xs.assign(x0, x0 + P->n);
         if (y0) P->ys.assign(y0, y0 + P->m);
@@ -1135,10 +1161,46 @@ int lp_result(const lp_problem *P, double *x, double *y, double *lambda, lp_info
     if (!P) return LP_ERR_ARG;
     if (!P->has_result) return LP_ERR_STATE;
     try {
-        return P->mixed ? do_result<float>(P, x, y, lambda, info) : do_result<double>(P, x, y, lambda, info);
+        if (!P->pre)
+            return P->mixed ? do_result<float>(P, x, y, lambda, info) : do_result<double>(P, x, y, lambda, info);
+        // presolved: the reduced point, mapped back and evaluated on the original problem
+        const Presolved &R = *P->pre;
+        std::vector<double> xr((size_t)std::max<int64_t>(P->n, 1)), yr((size_t)std::max<int64_t>(P->m, 1));
+        lp_info ri{};
+        const int rc = P->mixed ? do_result<float>(P, xr.data(), yr.data(), nullptr, &ri)
+                                : do_result<double>(P, xr.data(), yr.data(), nullptr, &ri);
+        if (rc != LP_OK) return rc;
+        if (ri.status == LP_PRIMAL_INFEASIBLE || ri.status == LP_DUAL_INFEASIBLE) {
+            // the rays of the reduced problem, zero on the removed rows and columns
+            for (int64_t j = 0; j < R.n0; ++j) {
+                const int k = R.col_new[(size_t)j];
+                if (x) x[j] = k >= 0 ? xr[(size_t)k] : 0.0;
+                if (lambda) lambda[j] = 0.0;
+            }
+            if (y)
+                for (int64_t i = 0; i < R.m0; ++i) {
+                    const int k = R.row_new[(size_t)i];
+                    y[i] = k >= 0 ? yr[(size_t)k] : 0.0;
+                }
+        } else {
+            postsolve(R, xr.data(), yr.data(), x, y, lambda, ri.pobj, ri.dobj, ri.rel_primal, ri.rel_dual,
+                      ri.rel_gap);
+        }
+        if (info) *info = ri;
+        return LP_OK;
     } catch (const HipError &h) {
         return fail_hip(const_cast<lp_problem *>(P), h);
+    } catch (const std::bad_alloc &) {
+        return LP_ERR_NOMEM;
     }
+}
+
+int lp_presolved_size(const lp_problem *P, int64_t *m, int64_t *n)
+{
+    if (!P) return LP_ERR_ARG;
+    if (m) *m = P->m;
+    if (n) *n = P->n;
+    return LP_OK;
 }
 
 int lp_get_state(const lp_problem *P, double *buf, int64_t *len)

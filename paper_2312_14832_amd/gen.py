@@ -373,3 +373,43 @@ def infeasible_lp(seed: int, kind: str) -> LPData:
         return _with_rows_cols(base, K2, base.m1, np.append(base.c, -1.0), base.q, np.append(base.l, 0.0),
                                np.append(base.u, np.inf), {"workload": "infeasible_dual", "seed": seed})
     raise ValueError(kind)
+
+
+def presolve_lp(seed: int) -> LPData:
+    """The tiny LP with every structure the presolve reduces, kept feasible
+    (by its certificate point x0) and bounded: 5 boxed variables fixed at
+    x0; 5 singleton equality rows a x_j = a x0_j; 5 singleton inequality rows
+    a x_j >= a (x0_j - 0.5) with a > 0 and 3 with a < 0 at x0_j + 0.5; an empty
+    equality row (0 = 0) and an empty inequality row (0 >= -1); three empty
+    columns (cost 1 on [0, inf), cost -1 on [0, 2], cost 0 and free)."""
+    base = tiny_lp(seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 104729))
+    n, m1 = base.n, base.m1
+    x0 = base.x0
+    K = base.csr()
+    l, u, c = base.l.copy(), base.u.copy(), base.c.copy()
+    boxed = np.flatnonzero(np.isfinite(l) & np.isfinite(u))
+    others = np.flatnonzero(~(np.isfinite(l) & np.isfinite(u)))
+    fixed = rng.choice(boxed, 5, replace=False)
+    l[fixed] = u[fixed] = x0[fixed]
+    pick = rng.choice(others, 13, replace=False)
+    eq_cols, ge_cols, le_cols = pick[:5], pick[5:10], pick[10:]
+    n2 = n + 3
+
+    def rows(cols, coef):
+        return sp.csr_matrix((coef, (np.arange(len(cols)), cols)), shape=(len(cols), n2))
+
+    a_eq = rng.uniform(0.5, 2.0, 5) * rng.choice([-1.0, 1.0], 5)
+    a_ge = rng.uniform(0.5, 2.0, 5)
+    a_le = -rng.uniform(0.5, 2.0, 3)
+    Kw = sp.hstack([K, sp.csr_matrix((base.m, 3))]).tocsr()
+    A = sp.vstack([Kw[:m1], rows(eq_cols, a_eq), sp.csr_matrix((1, n2))])
+    G = sp.vstack([Kw[m1:], rows(ge_cols, a_ge), rows(le_cols, a_le), sp.csr_matrix((1, n2))])
+    q = np.concatenate([base.q[:m1], a_eq * x0[eq_cols], [0.0], base.q[m1:], a_ge * (x0[ge_cols] - 0.5),
+                        a_le * (x0[le_cols] + 0.5), [-1.0]])
+    c = np.concatenate([c, [1.0, -1.0, 0.0]])
+    l = np.concatenate([l, [0.0, 0.0, -np.inf]])
+    u = np.concatenate([u, [np.inf, 2.0, np.inf]])
+    out = _with_rows_cols(base, sp.vstack([A, G]), m1 + 6, c, q, l, u, {"workload": "presolve_lp", "seed": seed})
+    out.x0 = np.concatenate([x0, [0.0, 2.0, 0.0]])
+    return out

@@ -25,7 +25,7 @@ NSCALARS = 16
 # every symbol include/lp.h declares
 EXPORTS = ["lp_default_options", "lp_workspace_size", "lp_load", "lp_set_start", "lp_set_start_weight", "lp_solve", "lp_result", "lp_get_state",
            "lp_set_state", "lp_get_scaling", "lp_spmv", "lp_kernel_time", "lp_device_bytes", "lp_layout",
-           "lp_layout_blocks", "lp_free",
+           "lp_layout_blocks", "lp_presolved_size", "lp_free",
            "lp_strerror", "lp_last_error", "lp_batch_load", "lp_batch_solve", "lp_batch_result",
            "lp_batch_get_state", "lp_batch_set_state", "lp_batch_device_bytes", "lp_batch_layout_blocks",
            "lp_batch_free",
@@ -44,7 +44,8 @@ class LPOptions(C.Structure):
                 ("fixed_step", C.c_int), ("fixed_eta", C.c_double), ("use_graph", C.c_int),
                 ("window", C.c_int), ("kernel_timing", C.c_int), ("slice_kib", C.c_int),
                 ("autotune", C.c_int), ("verbose", C.c_int), ("ptr_kind", C.c_int),
-                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t), ("infeas_tol", C.c_double)]
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t), ("infeas_tol", C.c_double),
+                ("presolve", C.c_int)]
 
 
 class LPInfo(C.Structure):
@@ -83,6 +84,7 @@ def library():
         L.lp_layout.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.lp_layout_blocks.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                        C.POINTER(C.c_int)]
+        L.lp_presolved_size.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.lp_free.argtypes = [C.c_void_p]
         L.lp_free.restype = None
         L.lp_strerror.argtypes = [C.c_int]
@@ -257,14 +259,22 @@ class Problem:
         buf = _f64(buf)
         self._check(library().lp_set_state(self.h, _dp(buf), buf.size))
 
+    def presolved_size(self):
+        """(rows, columns) of the problem on the GPU: the reduced one after presolve."""
+        m, n = C.c_int64(), C.c_int64()
+        self._check(library().lp_presolved_size(self.h, C.byref(m), C.byref(n)))
+        return m.value, n.value
+
     def scaling(self):
-        Dr = np.empty(self.m); Dc = np.empty(self.n)
+        m, n = self.presolved_size()
+        Dr = np.empty(m); Dc = np.empty(n)
         self._check(library().lp_get_scaling(self.h, _dp(Dr), _dp(Dc)))
         return Dr, Dc
 
     def spmv(self, v, transpose=False):
         v = _f64(v)
-        out = np.empty(self.n if transpose else self.m)
+        m, n = self.presolved_size()
+        out = np.empty(n if transpose else m)
         self._check(library().lp_spmv(self.h, int(bool(transpose)), _dp(v), _dp(out)))
         return out
 

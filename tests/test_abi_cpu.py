@@ -91,7 +91,8 @@ def test_bad_options_rejected():
     lp = _lib()
     for kw in [dict(precision=7), dict(check_every=0), dict(window=0), dict(fixed_step=1, fixed_eta=0.0),
                dict(ptr_kind=5), dict(workspace=8, workspace_bytes=1 << 20), dict(infeas_tol=-1.0),
-               dict(infeas_tol=float("nan")), dict(infeas_tol=float("inf"))]:
+               dict(infeas_tol=float("nan")), dict(infeas_tol=float("inf")), dict(presolve=2),
+               dict(presolve=1, ptr_kind=1), dict(presolve=1, workspace=256, workspace_bytes=1 << 20)]:
         with pytest.raises(lp.LPError) as ei:
             lp.Problem(gen.tiny_lp(0), **kw)
         assert ei.value.code == -1

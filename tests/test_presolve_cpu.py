@@ -1,0 +1,124 @@
+"""The library's presolve and postsolve (host code) checked exactly, without
+PDHG: the reduced LP is solved by HiGHS, its vertex solution mapped back, and
+the result must be an optimal primal-dual pair of the original LP."""
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_2312_14832_amd import gen
+from lp_helpers import highs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def shim(tmp_path_factory):
+    out = str(tmp_path_factory.mktemp("presolve") / "libpresolve_shim.so")
+    csrc = os.path.join(ROOT, "paper_2312_14832_amd", "csrc")
+    subprocess.run(["g++", "-O1", "-std=c++17", "-shared", "-fPIC", "-I", os.path.join(ROOT, "include"), "-I", csrc,
+                    os.path.join(csrc, "presolve.cpp"), os.path.join(ROOT, "tests", "presolve_shim.cpp"), "-o", out],
+                   check=True)
+    L = C.CDLL(out)
+    L.ps_presolve.restype = C.c_int
+    return L
+
+
+def _p(a, t=C.c_double):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+def run_presolve(L, lp):
+    rp, ci = np.ascontiguousarray(lp.row_ptr, np.int32), np.ascontiguousarray(lp.col, np.int32)
+    v, c, q, l, u = (np.ascontiguousarray(a, np.float64) for a in (lp.val, lp.c, lp.q, lp.l, lp.u))
+    dims = np.zeros(4, np.int64)
+    ok = L.ps_presolve(C.c_int64(lp.m), C.c_int64(lp.n), C.c_int64(lp.nnz), _p(rp, C.c_int32), _p(ci, C.c_int32),
+                       _p(v), _p(c), _p(q), _p(l), _p(u), C.c_int64(lp.m1), _p(dims, C.c_int64))
+    if not ok:
+        return None
+    m, n, m1, nnz = (int(t) for t in dims)
+    R = dict(rp=np.zeros(m + 1, np.int32), ci=np.zeros(max(nnz, 1), np.int32), v=np.zeros(max(nnz, 1)),
+             c=np.zeros(n), q=np.zeros(m), l=np.zeros(n), u=np.zeros(n), row_new=np.zeros(lp.m, np.int32),
+             col_new=np.zeros(lp.n, np.int32))
+    L.ps_reduced(*(_p(R[k], C.c_int32 if R[k].dtype == np.int32 else C.c_double)
+                   for k in ("rp", "ci", "v", "c", "q", "l", "u", "row_new", "col_new")))
+    red = gen.LPData(m=m, n=n, m1=m1, row_ptr=R["rp"], col=R["ci"][:nnz], val=R["v"][:nnz], c=R["c"], q=R["q"],
+                     l=R["l"], u=R["u"])
+    return red, R["row_new"], R["col_new"]
+
+
+def run_postsolve(L, lp, xr, yr):
+    x, y, lam, out = np.zeros(lp.n), np.zeros(lp.m), np.zeros(lp.n), np.zeros(5)
+    L.ps_postsolve(_p(np.ascontiguousarray(xr)), _p(np.ascontiguousarray(yr)), _p(x), _p(y), _p(lam), _p(out))
+    return x, y, lam, dict(zip(("pobj", "dobj", "rel_p", "rel_d", "rel_g"), out))
+
+
+def optimality(lp, x, y, lam):
+    """Primal and dual residuals and the gap of (x, y, lam) on lp, computed
+    here from the definitions (A3 of the paper's termination criteria)."""
+    K = lp.csr()
+    r = K @ x - lp.q
+    rp = np.concatenate([r[:lp.m1], np.maximum(-r[lp.m1:], 0.0)])
+    lf, uf = np.isfinite(lp.l), np.isfinite(lp.u)
+    g = lp.c - K.T @ y
+    dual_sign = np.minimum(y[lp.m1:], 0.0)
+    cone = np.where(lf & uf, 0.0, np.where(lf, np.minimum(lam, 0), np.where(uf, np.maximum(lam, 0), lam)))
+    bviol = np.maximum(lp.l - x, 0) + np.maximum(x - lp.u, 0)
+    pobj = lp.c @ x
+    dobj = lp.q @ y + np.sum(np.where(lf & (lam > 0), np.where(lf, lp.l, 0) * lam, 0)) \
+        + np.sum(np.where(uf & (lam < 0), np.where(uf, lp.u, 0) * lam, 0))
+    return (np.linalg.norm(rp), np.linalg.norm(g - lam), np.linalg.norm(dual_sign), np.linalg.norm(cone),
+            np.abs(bviol).max(), pobj, dobj)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_postsolve_of_exact_reduced_solution_is_optimal(shim, seed):
+    lp = gen.presolve_lp(seed)
+    red, row_new, col_new = run_presolve(shim, lp)
+    # at least the planted reductions: 13 singleton rows, 2 empty rows;
+    # 5 fixed, 5 fixed by singleton equalities, 3 empty columns
+    assert lp.m - red.m >= 15 and lp.n - red.n >= 13
+    assert red.m1 <= lp.m1 - 6 and np.all(red.l <= red.u)
+    opt, xr, yr = highs(red)
+    x, y, lam, info = run_postsolve(shim, lp, xr, yr)
+    ref, _, _ = highs(lp)
+    rp, rd, ysign, cone, bviol, pobj, dobj = optimality(lp, x, y, lam)
+    scale = 1 + np.abs(lp.q).max() + np.abs(lp.c).max()
+    assert rp <= 1e-8 * scale and rd <= 1e-8 * scale and ysign == 0 and cone == 0 and bviol <= 1e-12
+    assert pobj == pytest.approx(ref, rel=1e-9) and dobj == pytest.approx(ref, rel=1e-9)
+    # the postsolve's own report agrees with the definitions
+    assert info["pobj"] == pytest.approx(pobj, rel=1e-12) and info["dobj"] == pytest.approx(dobj, rel=1e-12)
+    assert max(info["rel_p"], info["rel_d"], info["rel_g"]) <= 1e-9
+    # kept entries come straight from the reduced solution
+    kc, kr = col_new >= 0, row_new >= 0
+    assert np.array_equal(x[kc], xr[col_new[kc]]) and np.array_equal(y[kr], yr[row_new[kr]])
+
+
+def test_nothing_to_reduce(shim):
+    """A dense LP (every row and column full, no fixed bounds) has no
+    reduction; tiny_lp(0) has one singleton inequality row (row 405), which
+    becomes a bound, and loses exactly that row."""
+    rng = np.random.default_rng(3)
+    K = sp.csr_matrix(rng.uniform(0.5, 1.5, (6, 9)))
+    lp = gen.LPData(m=6, n=9, m1=2, row_ptr=K.indptr.astype(np.int32), col=K.indices.astype(np.int32),
+                    val=K.data, c=rng.standard_normal(9), q=np.ones(6), l=np.zeros(9), u=np.full(9, 10.0))
+    assert run_presolve(shim, lp) is None
+    t = gen.tiny_lp(0)
+    red, row_new, col_new = run_presolve(shim, t)
+    single = np.flatnonzero(np.diff(t.row_ptr) == 1)
+    assert list(single) == [405] and (red.m, red.n) == (t.m - 1, t.n) and row_new[405] == -1
+
+
+def test_reductions_that_prove_infeasibility_are_left_alone(shim):
+    """A singleton equality outside its variable's box and an empty equality
+    row with a nonzero right-hand side stay in the reduced problem."""
+    Kd = np.array([[2.0, 0.0, 0.0], [0.0, 0.0, 0.0], [1.0, 1.0, 1.0]])
+    K = sp.csr_matrix(Kd)
+    K.eliminate_zeros()
+    lp = gen.LPData(m=3, n=3, m1=2, row_ptr=K.indptr.astype(np.int32), col=K.indices.astype(np.int32),
+                    val=K.data, c=np.ones(3), q=np.array([50.0, 1.0, 0.0]), l=np.zeros(3), u=np.full(3, 10.0))
+    out = run_presolve(shim, lp)
+    assert out is None
