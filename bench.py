@@ -12,9 +12,13 @@ paper's timings).
 
 Besides the JSON fields of the harness contract the line carries:
   roofline      the dominant kernel's algorithmic bytes per launch divided by
-                its mean hipEvent duration over the timed region, against the
-                8 TB/s HBM peak; `traffic` is the counter-measured HBM bytes per
-                launch from profiles/ (null when the kernel changed since)
+                its mean hipEvent duration, against the 8 TB/s HBM peak.  The
+                events bracket every launch of the timed region's first window
+                (64 launch pairs, plain launches); the other windows replay the
+                captured graph, as an untimed solve does (--kernel-timing 1:
+                events in every window).  `traffic` is the counter-measured HBM
+                bytes per launch from profiles/ (null when the kernel changed
+                since)
   spmv          the same figure for both SpMV kernels
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the same instance
   time_to_tol   wall time of a cold solve to relative KKT error 1e-4 (--ttt-tol)
@@ -231,9 +235,10 @@ def main():
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--seq-sample", type=int, default=32,
                     help="batch workload: instances solved one by one for the sequential comparison")
-    ap.add_argument("--kernel-timing", type=int, default=1, choices=[0, 1],
-                    help="1: HIP events around the two fused products in the timed region (roofline); "
-                         "0: no events (the window runs as one captured graph)")
+    ap.add_argument("--kernel-timing", type=int, default=2, choices=[0, 1, 2],
+                    help="2: HIP events around the two fused products in the first window of the timed "
+                         "region, the other windows replaying the captured graph (roofline; default); "
+                         "1: events in every window (plain launches); 0: no events")
     ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
                     help="1: time neighbouring layouts at load and keep the fastest; 0: the default layout")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -324,7 +329,8 @@ def main():
     d = spmv[dom]
     roofline = {"kernel": dom, "bound": "hbm", "achieved": d["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": d["GB_s"] / HBM_PEAK_GBS if d["GB_s"] else None,
-                "traffic": counter_traffic(dom, workload), "alg_bytes_per_launch": d["alg_bytes"]}
+                "traffic": counter_traffic(dom, workload), "alg_bytes_per_launch": d["alg_bytes"],
+                "timed_launches": d["launches"]}
     print(f"[bench] {K} windows in {dt:.3f}s -> {iters / dt:.0f} it/s; "
           + "; ".join(f"{k} {v['avg_us']:.1f}us {v['GB_s'] or 0:.0f}GB/s" for k, v in spmv.items()),
           file=sys.stderr, flush=True)

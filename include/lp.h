@@ -95,7 +95,11 @@ typedef struct {
     double fixed_eta;
     int use_graph;          /* 1: replay the iteration window as a captured hipGraph */
     int window;             /* attempt slots launched between host polls of the done flag (64) */
-    int kernel_timing;      /* 1: bracket the two SpMV kernels with hipEvents (see lp_kernel_time) */
+    int kernel_timing;      /* 1: bracket the two SpMV kernel pairs of every slot with hipEvents (see
+                               lp_kernel_time; the window then runs as plain launches on runtimes whose
+                               graph-recorded events carry no timestamps); 2: only in the first window of
+                               each lp_solve, launched plainly, the other windows replaying the untimed
+                               captured graph; 0: none */
     int slice_kib;          /* target KiB of a gathered vector per column slice of K and K' (2048 = half an XCD's L2) */
     int autotune;           /* 1: at lp_load, time the slice count from slice_kib, then halve it (else
                                double it, to at most 32) while that keeps helping, then smaller row blocks,
@@ -213,8 +217,8 @@ int lp_spmv(lp_problem *P, int transpose, const double *in, double *out);
 /* Launch statistics of the two products of the last lp_solve when
  * kernel_timing was set: which = 0 (K x' partial pass + fused dual step) or
  * 1 (K' y' partial pass + fused averages and next primal step); *count
- * launch pairs with *total_ms summed hipEvent time.  Zeros when timing was
- * off. */
+ * launch pairs with *total_ms summed hipEvent time (the first window's only
+ * with kernel_timing = 2).  Zeros when timing was off. */
 int lp_kernel_time(const lp_problem *P, int which, int64_t *count, double *total_ms);
 
 /* Device bytes held by the handle. */

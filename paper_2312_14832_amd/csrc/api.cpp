@@ -459,6 +459,7 @@ int check_options(const lp_options &o)
     if ((o.precision != LP_FP64 && o.precision != LP_MIXED) || o.check_every <= 0 || o.ruiz_iters < 0 ||
         (o.fixed_step && !(o.fixed_eta > 0.0)) || o.window <= 0 || o.slice_kib <= 0 ||
         (o.ptr_kind != LP_HOST && o.ptr_kind != LP_DEVICE) || !(o.infeas_tol >= 0.0) || std::isinf(o.infeas_tol) ||
+        o.kernel_timing < 0 || o.kernel_timing > 2 ||
         (o.workspace && (reinterpret_cast<uintptr_t>(o.workspace) % 256 != 0)) ||
         (o.presolve != 0 && o.presolve != 1) || (o.presolve && (o.ptr_kind == LP_DEVICE || o.workspace)))
         return LP_ERR_ARG;
@@ -738,17 +739,23 @@ int do_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit)
         get_ctl(P, d.ctl);
     }
     const int W = std::max(1, P->opt.window);
-    const bool timed = P->opt.kernel_timing != 0;
+    // kernel_timing: 0 none; 1 events around the products of every window;
+    // 2 only in the first window (plain launches), the rest replaying the
+    // untimed graph
+    const int tmode = P->opt.kernel_timing;
+    const bool timed = tmode != 0;
+    const bool timed_graph = tmode == 1;
     if (timed && (int)P->ev.size() < 4 * W) {
         for (auto e : P->ev) (void)hipEventDestroy(e);
         P->ev.assign(4 * W, nullptr);
         for (auto &e : P->ev) HIPT(hipEventCreate(&e));
     }
-    // the window is captured once per handle (with the timing events when
-    // kernel_timing is set, as event-record nodes); if the runtime refuses
-    // to capture event records, timed runs fall back to plain launches
-    bool use_graph = P->opt.use_graph && !(timed && P->graph_events_failed);
-    if (use_graph && (!P->graph || P->graph_window != W || P->graph_timed != timed)) {
+    // the window is captured once per handle (with the timing events as
+    // event-record nodes when kernel_timing = 1); if the runtime refuses to
+    // capture event records, or they carry no timestamps, those runs fall
+    // back to plain launches
+    bool use_graph = P->opt.use_graph && !(timed_graph && P->graph_events_failed);
+    if (use_graph && (!P->graph || P->graph_window != W || P->graph_timed != timed_graph)) {
         if (P->graph) {
             (void)hipGraphExecDestroy(P->graph);
             P->graph = nullptr;
@@ -757,33 +764,35 @@ int do_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit)
         HIPT(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
         bool ok = true;
         try {
-            for (int s = 0; s < W; ++s) launch_slot<T>(P, s, timed);
+            for (int s = 0; s < W; ++s) launch_slot<T>(P, s, timed_graph);
         } catch (const HipError &) {
             ok = false;
         }
         const hipError_t ec = hipStreamEndCapture(st, &g);
         if (ok && ec == hipSuccess && hipGraphInstantiate(&P->graph, g, nullptr, nullptr, 0) == hipSuccess) {
             P->graph_window = W;
-            P->graph_timed = timed;
+            P->graph_timed = timed_graph;
         } else {
             (void)hipGetLastError();
             P->graph = nullptr;
-            if (!timed) HIPT(ec != hipSuccess ? ec : hipErrorUnknown);
+            if (!timed_graph) HIPT(ec != hipSuccess ? ec : hipErrorUnknown);
             P->graph_events_failed = true;
             use_graph = false;
         }
         if (g) (void)hipGraphDestroy(g);
     }
-    while (!P->hctl->done) {
+    for (int widx = 0; !P->hctl->done; ++widx) {
         const long long k_before = P->hctl->k, a_before = P->hctl->attempts;
-        if (use_graph) {
+        const bool sampled = tmode == 2 && widx == 0;
+        const bool timed_now = tmode == 1 || sampled;
+        if (use_graph && !sampled) {
             HIPT(hipGraphLaunch(P->graph, st));
         } else {
-            for (int s = 0; s < W; ++s) launch_slot<T>(P, s, timed);
+            for (int s = 0; s < W; ++s) launch_slot<T>(P, s, timed_now);
         }
         get_ctl(P, d.ctl);
         if (P->opt.verbose) trace_window(*P->hctl);
-        if (timed && !P->hctl->done) {
+        if (timed_now && !P->hctl->done) {
             // every slot of a window that ended unfinished did real work
             double ta = 0.0, tb = 0.0;
             bool read = true;
@@ -795,7 +804,7 @@ int do_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit)
                     // events recorded by graph nodes carry no timestamps on
                     // this runtime: time the next windows with plain launches
                     (void)hipGetLastError();
-                    if (!use_graph) HIPT(ea != hipSuccess ? ea : eb);
+                    if (!use_graph || sampled) HIPT(ea != hipSuccess ? ea : eb);
                     read = false;
                     break;
                 }

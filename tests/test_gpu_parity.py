@@ -259,6 +259,24 @@ def test_deterministic_and_graph_equals_stream(lpmod):
     assert np.array_equal(s1, s3)
 
 
+def test_kernel_timing_modes_agree(lpmod):
+    """Event timing changes nothing computed: modes 0 (graph), 1 (events in
+    every window) and 2 (events in the first window, then the graph) give
+    bit-identical states; mode 2 counts the first window's launches only."""
+    say("case kernel timing modes")
+    data = gen.tiny_lp(6)
+    states, counts = [], []
+    for mode in (0, 1, 2):
+        p = lpmod.Problem(data, kernel_timing=mode)
+        p.solve(1e-30, 640)
+        states.append(p.get_state())
+        counts.append([p.kernel_time(w) for w in (0, 1)])
+    assert np.array_equal(states[0], states[1]) and np.array_equal(states[0], states[2])
+    assert counts[0] == [(0, 0.0), (0, 0.0)]
+    assert counts[1][0][0] >= 9 * 64 and counts[1][1][0] >= 9 * 64   # windows that ended unfinished
+    assert counts[2][0][0] == 64 and counts[2][1][0] == 64 and counts[2][0][1] > 0.0
+
+
 @pytest.mark.parametrize("omega", [0.0, 0.37])
 def test_warm_start_matches_oracle(lpmod, oracle_mod, omega):
     """Warm start (point, and with omega > 0 the primal weight) against the
