@@ -246,8 +246,9 @@ typedef struct lp_batch lp_batch;   /* opaque; owned by the library */
 /* count instances: K[i], c[i], q[i], l[i], u[i], m1[i] as in lp_load (host
  * pointers, copied).  Options apply to every instance.  Same error codes as
  * lp_load (the first failing instance decides).  A batch takes host pointers
- * and allocates its own device memory: ptr_kind = LP_DEVICE or a workspace
- * is LP_ERR_ARG. */
+ * and allocates its own device memory: ptr_kind = LP_DEVICE, a workspace or
+ * presolve is LP_ERR_ARG.  Rows longer than one row block (2048 entries) are
+ * summed by a whole workgroup, without the chunking of lp_load. */
 int lp_batch_load(lp_batch **B, int32_t count, const lp_csr *K, const double *const *c, const double *const *q,
                   const double *const *l, const double *const *u, const int64_t *m1, const lp_options *opt);
 /* Solve every instance (cold start, or resume when lp_batch_set_state was

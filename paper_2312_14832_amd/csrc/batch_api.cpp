@@ -626,7 +626,7 @@ int lp_batch_load(lp_batch **out, int32_t count, const lp_csr *K, const double *
     if (!out) return LP_ERR_ARG;
     *out = nullptr;
     if (count <= 0 || !K || !c || !q || !l || !u || !m1) return LP_ERR_ARG;
-    if (opt && (opt->ptr_kind != LP_HOST || opt->workspace)) return LP_ERR_ARG;
+    if (opt && (opt->ptr_kind != LP_HOST || opt->workspace || opt->presolve)) return LP_ERR_ARG;
     for (int i = 0; i < count; ++i) {
         const int rc = validate_lp(&K[i], c[i], q[i], l[i], u[i], m1[i]);
         if (rc != LP_OK) return rc;

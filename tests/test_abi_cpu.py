@@ -139,3 +139,13 @@ def test_workspace_size_rejects_bad_input():
     L = lp.library()
     b = C.c_size_t()
     assert L.lp_workspace_size(None, None, C.byref(b)) == -1
+
+
+def test_batch_rejects_unsupported_options():
+    """lp_batch_load checks its options before any GPU work: device pointers,
+    a workspace and presolve are not supported for batches."""
+    lp = _lib()
+    for kw in [dict(ptr_kind=1), dict(workspace=256, workspace_bytes=1 << 20), dict(presolve=1), dict(precision=3)]:
+        with pytest.raises(lp.LPError) as ei:
+            lp.Batch([gen.tiny_lp(0), gen.tiny_lp(1)], **kw)
+        assert ei.value.code == -1, kw

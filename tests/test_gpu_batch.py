@@ -178,3 +178,28 @@ def test_batch_full_size_sampled(lpmod, oracle_mod):
         assert wv < 64 * 2.0 ** -24, (i, vv, wv)
     for i in others[::37]:
         assert bt.info(i)["iterations"] == k + 1, i
+
+
+def test_batch_with_dense_rows(lpmod, oracle_mod):
+    """A batch holding PageRank LPs (a 20,000-entry row each, summed by one
+    workgroup in the batch path) next to small LPs: the first 40 steps match
+    the oracle's per instance, and every instance solves to 1e-6."""
+    lps = [gen.pagerank_lp(5, 20000), gen.tiny_lp(1), gen.pagerank_lp(6, 12000)]
+    bt = lpmod.Batch(lps)
+    bt.solve(1e-30, 40)
+    for i, p in enumerate(lps):
+        say(f"case batch dense rows i={i}")
+        o = oracle_mod.Oracle(p)
+        o.solve(1e-30, 40)
+        sg = lpmod.unpack_state(bt.get_state(i), p.n, p.m)
+        so = o.get_state()
+        assert ints_equal(sg, so), i
+        wv, vv = vec_diff(sg, so)
+        assert wv < PER_STEP_TOL * 1e3, (i, vv, wv)
+    bt2 = lpmod.Batch(lps)
+    bt2.solve(1e-6, 200_000)
+    for i, p in enumerate(lps):
+        x, y, lam, info = bt2.result(i)
+        assert info["status"] == "OPTIMAL", (i, info)
+        ev = oracle_mod.Oracle(p).eval_unscaled(x, y)
+        assert ev["rel_kkt"] <= 1e-6 * (1 + 1e-6), (i, ev)
