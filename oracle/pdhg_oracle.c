@@ -561,13 +561,13 @@ static int ray_status(orc_t *P, const orc_eval_t *ec)
     for (int64_t j = 0; j < n; ++j) {
         int lf = isfinite(P->l[j]), uf = isfinite(P->u[j]);
         cd += P->c[j] * d[j];
-        if (lf && d[j] < 0.0) pres2 += d[j] * d[j];
-        if (uf && d[j] > 0.0) pres2 += d[j] * d[j];
+        if (ORC_MUT != 10 && lf && d[j] < 0.0) pres2 += d[j] * d[j];
+        if (ORC_MUT != 10 && uf && d[j] > 0.0) pres2 += d[j] * d[j];
         double g = -KTw[j];
         double lam = proj_lambda(g, lf, uf);
         dres2 += (g - lam) * (g - lam);
         if (lf && lam > 0.0) bnd += P->l[j] * lam;
-        if (uf && lam < 0.0) bnd += P->u[j] * lam;
+        if (uf && lam < 0.0) bnd += (ORC_MUT == 9 ? -1.0 : 1.0) * P->u[j] * lam;
     }
     double dobj = qw + bnd;
     int st = 0;

@@ -2,10 +2,32 @@
 time (a flipped sign, a dropped term, a wrong exponent or index, a wrong
 averaging weight) and at least one pin must fail for each.  The planted
 builds live in a temporary directory and are used by this file only."""
+import os
+import subprocess
+import sys
+
 import pytest
 
 from oracle import build as obuild
 import test_oracle_pins as pins
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def check_infeasibility_bounded(om, libpath=None):
+    """The certificate pins; on a planted-mistake build in a child process
+    under a 20 s limit (it needs about 1 s), since a wrong step can loop on rejected steps
+    forever, and a pin that does not finish fails."""
+    if libpath is None:
+        return pins.check_infeasibility(om)
+    code = ("import sys; sys.path[:0] = [%r, %r]\n"
+            "from oracle import oracle as O\nimport test_oracle_pins as p\n"
+            "p.check_infeasibility(O, libpath=%r)\n") % (HERE, os.path.dirname(HERE), libpath)
+    try:
+        r = subprocess.run([sys.executable, "-c", code], timeout=20, capture_output=True)
+    except subprocess.TimeoutExpired:
+        raise AssertionError("infeasibility pins did not finish in 20 s")
+    assert r.returncode == 0, r.stderr.decode()[-400:]
 
 MUTATIONS = {
     1: "primal step uses c + K'y",
@@ -16,6 +38,8 @@ MUTATIONS = {
     6: "Ruiz column factor taken from the row maxima",
     7: "uniform instead of step-size weights in the averages",
     8: "KKT_omega uses omega instead of omega^2",
+    9: "dual ray objective adds +u lam- instead of -u lam-",
+    10: "primal ray test ignores the bounds' recession cone",
 }
 
 CHECKS = [
@@ -28,6 +52,7 @@ CHECKS = [
     ("step-weighted averages", pins.check_step_weighted_averages),
     ("vertex enumeration", lambda om, libpath=None: pins.check_vertex_objective(om, 11, 3, 1, 2, libpath,
                                                                                   max_iters=200_000)),
+    ("infeasibility certificates", check_infeasibility_bounded),
 ]
 
 

@@ -536,6 +536,34 @@ def test_infeasible_lps_get_certificates(oracle_mod, kind, want, hs, seed):
         assert pobj < 0 and pres <= 1e-8 * -pobj * (1 + 1e-6)
 
 
+def test_infeasibility_checks(oracle_mod):
+    check_infeasibility(oracle_mod)
+
+
+def check_infeasibility(om, libpath=None):
+    """The certificate pins in one function (for the planted-mistake builds,
+    with iteration caps a few times what the oracle needs): closed-form rays,
+    a reported ray objective against its recomputation on an LP whose
+    certificate uses finite upper bounds, and a bounded LP whose iterates
+    move along a direction with A d = 0 that only the box stops (it must not
+    be declared unbounded)."""
+    lp = _lp_from_dense([[1.0, 1.0]], 1, [1.0, 2.0], [-1.0], [0.0, 0.0], [np.inf, np.inf])
+    x, y, lam, info = om.Oracle(lp, libpath=libpath).solve(1e-8, 5_000)
+    assert info["status"] == "PRIMAL_INFEASIBLE" and y[0] < 0
+    lp = _lp_from_dense([[1.0, -1.0]], 1, [-1.0, 0.0], [0.0], [0.0, 0.0], [np.inf, np.inf])
+    x, y, lam, info = om.Oracle(lp, libpath=libpath).solve(1e-8, 5_000)
+    assert info["status"] == "DUAL_INFEASIBLE"
+    assert np.allclose(x / np.linalg.norm(x), [2 ** -0.5, 2 ** -0.5], atol=1e-6)
+    lp = gen.infeasible_lp(0, "primal")
+    x, y, lam, info = om.Oracle(lp, libpath=libpath).solve(1e-8, 60_000)
+    assert info["status"] == "PRIMAL_INFEASIBLE"
+    dobj, dres, _, _ = farkas_ratios(lp, x, y)
+    assert info["dobj"] == pytest.approx(dobj, rel=1e-9) and dres <= 1e-8 * dobj * (1 + 1e-6)
+    lp = _lp_from_dense([[1.0, -1.0]], 1, [-1.0, -1.0], [0.0], [0.0, 0.0], [1e6, 1e6])
+    _, _, _, info = om.Oracle(lp, libpath=libpath).solve(1e-8, 2_000)
+    assert info["status"] != "DUAL_INFEASIBLE"
+
+
 def test_detection_off_runs_to_the_limit(oracle_mod):
     """infeas_tol = 0 disables the ray tests: the same LP ends at the limit."""
     lp = gen.infeasible_lp(0, "primal")
