@@ -15,6 +15,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "host_util.h"
@@ -47,8 +48,20 @@ struct HostSliced {
     int max_blocks = 0;
 };
 
+// Run fn(t) for t in [0, T) on T threads (fn(0) on the caller's).
+template <typename F>
+void run_threads(int T, F &&fn)
+{
+    std::vector<std::thread> th;
+    for (int t = 1; t < T; ++t) th.emplace_back(fn, t);
+    fn(0);
+    for (auto &x : th) x.join();
+}
+
 // Rows of the source CSR must have their columns sorted, so that each
-// slice's part of a row is one contiguous run.
+// slice's part of a row is one contiguous run.  The split and the row blocks
+// run on host threads (by row chunks, then by slices); the result does not
+// depend on the thread count.
 void build_sliced(HostSliced &H, int rows, int cols, const std::vector<int> &rp, const std::vector<int> &ci, int S,
                   int nb = kStreamNB, int rb = kStreamRB)
 {
@@ -66,65 +79,107 @@ void build_sliced(HostSliced &H, int rows, int cols, const std::vector<int> &rp,
     H.brow.clear();
     H.blk.clear();
     H.boff.assign(S + 1, 0);
-    std::vector<int> cur(rp.begin(), rp.end() - 1);
-    int64_t pos = 0;
-    for (int s = 0; s < S; ++s) {
-        const int hi = (int)((int64_t)cols * (s + 1) / S);
-        int *r = &H.rp[(size_t)s * (rows + 1)];
-        for (int i = 0; i < rows; ++i) {
-            r[i] = (int)pos;
-            int p = cur[i];
-            const int e = rp[i + 1];
-            while (p < e && ci[p] < hi) {
-                H.ci[pos] = ci[p];
-                H.src[pos] = p;
-                ++pos;
-                ++p;
+    std::vector<int> bnd((size_t)S + 1);   // slice s holds columns [bnd[s], bnd[s+1])
+    for (int s = 0; s <= S; ++s) bnd[(size_t)s] = (int)((int64_t)cols * s / S);
+
+    // entries per (row chunk, slice), then each chunk's offset in every slice
+    // (slice-major, chunks in row order), then the entries themselves
+    const int T = std::max(1, std::min(host_threads(), rows / 16384 + 1));
+    auto chunk = [&](int t) {
+        return std::make_pair((int)((int64_t)rows * t / T), (int)((int64_t)rows * (t + 1) / T));
+    };
+    std::vector<int64_t> cnt((size_t)T * S, 0);
+    run_threads(T, [&](int t) {
+        const auto [r0, r1] = chunk(t);
+        int64_t *c = &cnt[(size_t)t * S];
+        for (int i = r0; i < r1; ++i) {
+            int sl = 0;
+            for (int p = rp[i]; p < rp[i + 1]; ++p) {
+                while (ci[p] >= bnd[(size_t)sl + 1]) ++sl;
+                ++c[sl];
             }
-            cur[i] = p;
         }
-        r[rows] = (int)pos;
+    });
+    std::vector<int64_t> off((size_t)T * S);
+    int64_t acc = 0;
+    for (int sl = 0; sl < S; ++sl)
+        for (int t = 0; t < T; ++t) {
+            off[(size_t)t * S + sl] = acc;
+            acc += cnt[(size_t)t * S + sl];
+        }
+    run_threads(T, [&](int t) {
+        const auto [r0, r1] = chunk(t);
+        std::vector<int64_t> cur(off.begin() + (size_t)t * S, off.begin() + (size_t)(t + 1) * S);
+        for (int i = r0; i < r1; ++i) {
+            for (int sl = 0; sl < S; ++sl) H.rp[(size_t)sl * (rows + 1) + i] = (int)cur[(size_t)sl];
+            int sl = 0;
+            for (int p = rp[i]; p < rp[i + 1]; ++p) {
+                while (ci[p] >= bnd[(size_t)sl + 1]) ++sl;
+                const int64_t at = cur[(size_t)sl]++;
+                H.ci[(size_t)at] = ci[p];
+                H.src[(size_t)at] = p;
+            }
+        }
+    });
+    acc = 0;
+    for (int sl = 0; sl < S; ++sl) {
+        for (int t = 0; t < T; ++t) acc += cnt[(size_t)t * S + sl];
+        H.rp[(size_t)sl * (rows + 1) + rows] = (int)acc;
     }
-    // long rows: slots slice-major, one per chunk of at most nb entries
+
+    // long rows: slots slice-major, one per chunk of at most nb entries;
+    // lslot[k*S + s] is the first slot of long row k in slice s
     H.lrow.clear();
     H.loff.assign(1, 0);
     for (int i = 0; i < rows; ++i)
         if (rp[i + 1] - rp[i] > kLongRow) H.lrow.push_back(i);
-    std::vector<int> slot0(H.lrow.size());   // next free slot of each long row
+    std::vector<int> lslot(H.lrow.size() * (size_t)S);
     for (size_t k = 0; k < H.lrow.size(); ++k) {
-        int chunks = 0;
-        for (int s = 0; s < S; ++s) {
-            const int *r = &H.rp[(size_t)s * (rows + 1)];
-            chunks += (r[H.lrow[k] + 1] - r[H.lrow[k]] + nb - 1) / nb;
+        int next = H.loff.back();
+        for (int sl = 0; sl < S; ++sl) {
+            const int *r = &H.rp[(size_t)sl * (rows + 1)];
+            lslot[k * S + sl] = next;
+            next += (r[H.lrow[k] + 1] - r[H.lrow[k]] + nb - 1) / nb;
         }
-        slot0[k] = H.loff.back();
-        H.loff.push_back(H.loff.back() + chunks);
+        H.loff.push_back(next);
     }
-    H.max_blocks = 0;
-    for (int s = 0; s < S; ++s) {
-        const int *r = &H.rp[(size_t)s * (rows + 1)];
-        const size_t first = H.blk.size();
-        auto plain = [&](int r_begin, int r_end) {
-            H.brow.assign(1, r_begin);
-            std::vector<char> wave;
-            row_blocks(r, r_begin, r_end, H.brow, wave, H.nb, H.rb);
-            for (size_t k = 0; k + 1 < H.brow.size(); ++k) {
-                const int r0 = H.brow[k], r1 = H.brow[k + 1];
-                H.blk.push_back(make_int4(r0, wave[k] ? ~r1 : r1, r[r0], r[r1]));
+
+    // row blocks, slice by slice
+    std::vector<std::vector<int4>> bs((size_t)S);
+    const int T2 = std::max(1, std::min(host_threads(), S));
+    run_threads(T2, [&](int t) {
+        std::vector<int> brow;
+        std::vector<char> wave;
+        for (int sl = t; sl < S; sl += T2) {
+            const int *r = &H.rp[(size_t)sl * (rows + 1)];
+            std::vector<int4> &out = bs[(size_t)sl];
+            auto plain = [&](int r_begin, int r_end) {
+                brow.assign(1, r_begin);
+                wave.clear();
+                row_blocks(r, r_begin, r_end, brow, wave, nb, rb);
+                for (size_t k = 0; k + 1 < brow.size(); ++k) {
+                    const int r0 = brow[k], r1 = brow[k + 1];
+                    out.push_back(make_int4(r0, wave[k] ? ~r1 : r1, r[r0], r[r1]));
+                }
+            };
+            int start = 0;
+            for (size_t k = 0; k < H.lrow.size(); ++k) {
+                const int lr = H.lrow[k];
+                plain(start, lr);
+                int slot = lslot[k * S + sl];
+                for (int b = r[lr]; b < r[lr + 1]; b += nb)
+                    out.push_back(make_int4(~slot++, 0, b, std::min(b + nb, r[lr + 1])));
+                start = lr + 1;
             }
-        };
-        int start = 0;
-        for (size_t k = 0; k < H.lrow.size(); ++k) {
-            const int lr = H.lrow[k];
-            plain(start, lr);
-            for (int b = r[lr]; b < r[lr + 1]; b += nb)
-                H.blk.push_back(make_int4(~slot0[k]++, 0, b, std::min(b + nb, r[lr + 1])));
-            start = lr + 1;
+            plain(start, rows);
         }
-        plain(start, rows);
-        const int cnt = (int)(H.blk.size() - first);
-        H.boff[s + 1] = H.boff[s] + cnt;
-        H.max_blocks = std::max(H.max_blocks, cnt);
+    });
+    H.max_blocks = 0;
+    for (int sl = 0; sl < S; ++sl) {
+        const int c = (int)bs[(size_t)sl].size();
+        H.blk.insert(H.blk.end(), bs[(size_t)sl].begin(), bs[(size_t)sl].end());
+        H.boff[(size_t)sl + 1] = H.boff[(size_t)sl] + c;
+        H.max_blocks = std::max(H.max_blocks, c);
     }
 }
 

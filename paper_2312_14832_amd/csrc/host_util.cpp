@@ -1,6 +1,8 @@
 // Host-side helpers shared by the single-LP and the batched C ABI.
 #include "host_util.h"
 
+#include <thread>
+
 namespace pdlp {
 
 int validate_dims(const lp_csr *K)
@@ -60,21 +62,41 @@ int validate_lp(const lp_csr *K, const double *c, const double *q, const double 
     return LP_OK;
 }
 
+int host_threads()
+{
+    const unsigned t = std::thread::hardware_concurrency();
+    return (int)std::min(16u, std::max(1u, t));
+}
+
 void append_sorted_rows(const lp_csr *K, int col_off, std::vector<int> &rp, std::vector<int> &ci,
                         std::vector<double> &v)
 {
     if (rp.empty()) rp.push_back(0);
+    const size_t base = ci.size();
+    ci.resize(base + (size_t)K->nnz);
+    v.resize(base + (size_t)K->nnz);
+    rp.reserve(rp.size() + (size_t)K->m);
     std::vector<std::pair<int, double>> row;
     for (int64_t i = 0; i < K->m; ++i) {
-        row.clear();
-        for (int64_t p = K->row_ptr[i]; p < K->row_ptr[i + 1]; ++p) row.emplace_back(K->col[p], K->val[p]);
-        std::sort(row.begin(), row.end(),
-                  [](const std::pair<int, double> &a, const std::pair<int, double> &b) { return a.first < b.first; });
-        for (const auto &e : row) {
-            ci.push_back(e.first + col_off);
-            v.push_back(e.second);
+        const int64_t b = K->row_ptr[i], e = K->row_ptr[i + 1];
+        int *co = ci.data() + base + b;
+        double *vo = v.data() + base + b;
+        if (std::is_sorted(K->col + b, K->col + e)) {
+            for (int64_t p = b; p < e; ++p) {
+                co[p - b] = K->col[p] + col_off;
+                vo[p - b] = K->val[p];
+            }
+        } else {
+            row.clear();
+            for (int64_t p = b; p < e; ++p) row.emplace_back(K->col[p], K->val[p]);
+            std::sort(row.begin(), row.end(),
+                      [](const std::pair<int, double> &x, const std::pair<int, double> &y) { return x.first < y.first; });
+            for (size_t k = 0; k < row.size(); ++k) {
+                co[k] = row[k].first + col_off;
+                vo[k] = row[k].second;
+            }
         }
-        rp.push_back((int)ci.size());
+        rp.push_back((int)(base + (size_t)e));
     }
 }
 
@@ -85,15 +107,39 @@ void transpose_csr(int rows, int cols, const std::vector<int> &rp, const std::ve
     tp.assign((size_t)cols + 1, 0);
     ti.assign((size_t)std::max<int64_t>(nnz, 1), 0);
     tv.assign((size_t)std::max<int64_t>(nnz, 1), 0.0);
-    for (int64_t p = 0; p < nnz; ++p) tp[ci[p] + 1]++;
-    for (int j = 0; j < cols; ++j) tp[j + 1] += tp[j];
-    std::vector<int> pos(tp.begin(), tp.end() - 1);
-    for (int i = 0; i < rows; ++i)
-        for (int p = rp[i]; p < rp[i + 1]; ++p) {
-            const int at = pos[ci[p]]++;
-            ti[at] = i;
-            tv[at] = v[p];
+    // Each thread owns a contiguous range of output rows (input columns):
+    // it scans every entry and counts, then places, only those in its range,
+    // in input-row order, so the result is that of the sequential counting
+    // sort whatever the thread count.
+    const int T = std::max(1, std::min(host_threads(), cols / 65536 + 1));
+    auto range = [&](int t) { return std::make_pair((int)((int64_t)cols * t / T), (int)((int64_t)cols * (t + 1) / T)); };
+    auto parallel = [&](auto &&fn) {
+        std::vector<std::thread> th;
+        for (int t = 1; t < T; ++t) th.emplace_back(fn, t);
+        fn(0);
+        for (auto &x : th) x.join();
+    };
+    parallel([&](int t) {
+        const auto [c0, c1] = range(t);
+        for (int64_t p = 0; p < nnz; ++p) {
+            const int j = ci[p];
+            if (j >= c0 && j < c1) tp[(size_t)j + 1]++;
         }
+    });
+    for (int j = 0; j < cols; ++j) tp[(size_t)j + 1] += tp[(size_t)j];
+    parallel([&](int t) {
+        const auto [c0, c1] = range(t);
+        std::vector<int> pos(tp.begin() + c0, tp.begin() + c1);
+        for (int i = 0; i < rows; ++i)
+            for (int p = rp[i]; p < rp[i + 1]; ++p) {
+                const int j = ci[p];
+                if (j >= c0 && j < c1) {
+                    const int at = pos[(size_t)(j - c0)]++;
+                    ti[(size_t)at] = i;
+                    tv[(size_t)at] = v[p];
+                }
+            }
+    });
 }
 
 void row_blocks(const int *rp, int r_begin, int r_end, std::vector<int> &ends, std::vector<char> &wave, int nb_max,

@@ -109,6 +109,9 @@ int validate_lp(const lp_csr *K, const double *c, const double *q, const double 
 int validate_dims(const lp_csr *K);
 int validate_pattern(const lp_csr *K);
 
+// Worker threads for host-side layout work (at most 16).
+int host_threads();
+
 // Append the rows of K (columns sorted inside each row, columns shifted by
 // col_off) to a CSR under construction.
 void append_sorted_rows(const lp_csr *K, int col_off, std::vector<int> &rp, std::vector<int> &ci,
