@@ -122,3 +122,67 @@ def test_reductions_that_prove_infeasibility_are_left_alone(shim):
                     val=K.data, c=np.ones(3), q=np.array([50.0, 1.0, 0.0]), l=np.zeros(3), u=np.full(3, 10.0))
     out = run_presolve(shim, lp)
     assert out is None
+
+
+# ------------------------------------------------------------ random instances
+
+from hypothesis import HealthCheck, assume, given, settings, strategies as st  # noqa: E402
+
+
+def _planted(seed, m1, m2, n, kmax, nfix, nsing):
+    """A small certificate LP (feasible and bounded by construction) with
+    planted reductions: some boxed variables fixed at the certificate point,
+    singleton equality rows through it and singleton inequality rows it
+    satisfies; the column counts 0..kmax leave empty columns and rows."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    m = m1 + m2
+    counts = rng.integers(0, min(kmax, m) + 1, size=n).astype(np.int64) if m else np.zeros(n, np.int64)
+    base = gen.certificate_lp(rng, m1, m2, counts)
+    l, u, x0 = base.l.copy(), base.u.copy(), base.x0
+    boxed = np.flatnonzero(np.isfinite(l) & np.isfinite(u))
+    for j in rng.choice(boxed, min(nfix, boxed.size), replace=False):
+        l[j] = u[j] = x0[j]
+    K = base.csr()
+
+    def single(j, a):
+        return sp.csr_matrix(([a], ([0], [j])), shape=(1, n))
+
+    eq_rows, eq_q, ge_rows, ge_q = [], [], [], []
+    for _ in range(nsing):
+        j = int(rng.integers(n))
+        a = float(rng.uniform(0.5, 2.0) * rng.choice([-1.0, 1.0]))
+        if rng.random() < 0.5:
+            eq_rows.append(single(j, a)); eq_q.append(a * x0[j])
+        else:
+            ge_rows.append(single(j, a)); ge_q.append(a * x0[j] - float(rng.uniform(0.0, 1.0)))
+    A = sp.vstack([K[:m1]] + eq_rows) if (m1 or eq_rows) else sp.csr_matrix((0, n))
+    G = sp.vstack([K[m1:]] + ge_rows) if (m2 or ge_rows) else sp.csr_matrix((0, n))
+    q = np.concatenate([base.q[:m1], eq_q, base.q[m1:], ge_q])
+    M = sp.vstack([A, G]).tocsr()
+    M.sort_indices()
+    return gen.LPData(m=M.shape[0], n=n, m1=A.shape[0], row_ptr=M.indptr.astype(np.int32),
+                      col=M.indices.astype(np.int32), val=M.data.astype(float), c=base.c, q=q, l=l, u=u)
+
+
+@settings(max_examples=150, deadline=None, suppress_health_check=[HealthCheck.too_slow,
+                                                                  HealthCheck.function_scoped_fixture])
+@given(seed=st.integers(0, 2**32 - 1), m1=st.integers(0, 10), m2=st.integers(0, 10), n=st.integers(1, 20),
+       kmax=st.integers(0, 4), nfix=st.integers(0, 3), nsing=st.integers(0, 5))
+def test_presolve_postsolve_random(shim, seed, m1, m2, n, kmax, nfix, nsing):
+    """On random LPs with planted reductions: the reduced LP's HiGHS optimum,
+    mapped back, is an optimal primal-dual pair of the original with
+    HiGHS's objective."""
+    lp = _planted(seed, m1, m2, n, kmax, nfix, nsing)
+    from lp_helpers import highs_status
+    assume(highs_status(lp) == 0)
+    out = run_presolve(shim, lp)
+    assume(out is not None)
+    red = out[0]
+    assert highs_status(red) == 0
+    _, xr, yr = highs(red)
+    x, y, lam, info = run_postsolve(shim, lp, xr, yr)
+    ref, _, _ = highs(lp)
+    rp, rd, ysign, cone, bviol, pobj, dobj = optimality(lp, x, y, lam)
+    scale = 1 + np.abs(lp.q).max(initial=0) + np.abs(lp.c).max() + np.abs(x).max()
+    assert rp <= 1e-7 * scale and rd <= 1e-7 * scale and ysign == 0 and cone == 0 and bviol <= 1e-9 * scale
+    assert abs(pobj - ref) <= 1e-7 * (1 + abs(ref)) and abs(dobj - ref) <= 1e-7 * (1 + abs(ref))
