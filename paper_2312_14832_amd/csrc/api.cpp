@@ -551,6 +551,7 @@ size_t load_plan_bytes(int64_t m, int64_t n, int64_t nnz, const HostSliced &HK, 
     for (int64_t len : {n, n, n, m, m, n, m, n, n, n, n, m}) add(8 * one(len));   // c l u q Dr Dc r s cs ls us qs
     add(8 * kMaxGrid); add(8 * 8);
     add(8 * one(n)); add(8 * one(n)); add(8 * one(m));
+    add(4 * one((int64_t)HK.lrow.size())); add(4 * one((int64_t)HT.lrow.size()));   // long rows for the scaling
     // setup_typed: lp_spmv scratch, the two sliced products, vectors, partials, controller
     add(T * one(n)); add(T * one(m));
     for (const HostSliced *H : {&HK, &HT}) {
@@ -615,7 +616,12 @@ int do_load(lp_problem *P, const lp_csr *K, const double *c, const double *q, co
     // column factors both come from the same current matrix
     const int M = (int)m, N = (int)n;
     hipStream_t st = P->stream;
-    HIPT(scale_csr_pair(d_rp, d_ci, d_kv, M, d_tp, d_ti, d_tv, N, Dr, Dc, r, s, P->opt.ruiz_iters, P->opt.pc_alpha, st));
+    // the rows longer than kLongRow (the same ones the products cut into chunks)
+    int *d_klong = ialloc((int64_t)HK.lrow.size()), *d_tlong = ialloc((int64_t)HT.lrow.size());
+    upload(P, d_klong, HK.lrow.data(), (int64_t)HK.lrow.size());
+    upload(P, d_tlong, HT.lrow.data(), (int64_t)HT.lrow.size());
+    HIPT(scale_csr_pair(d_rp, d_ci, d_kv, M, d_tp, d_ti, d_tv, N, Dr, Dc, r, s, P->opt.ruiz_iters, P->opt.pc_alpha, st,
+                        d_klong, (int)HK.lrow.size(), d_tlong, (int)HT.lrow.size()));
     HIPT(launch_scale_vectors(d_c, d_l, d_u, d_q, Dc, Dr, cs, ls, us, qs, N, M, st));
     double h[5] = {0, 0, 0, 0, 0};
     HIPT(launch_sumsq(d_q, m, P->red_part, P->red_out + 0, st));
@@ -637,7 +643,8 @@ int do_load(lp_problem *P, const lp_csr *K, const double *c, const double *q, co
     sync(P);
     // the CSR pair was only needed for the scaling
     for (void *pp : {(void *)d_rp, (void *)d_ci, (void *)d_kv, (void *)d_tp, (void *)d_ti, (void *)d_tv,
-                     (void *)r, (void *)s, (void *)d_c, (void *)d_l, (void *)d_u, (void *)d_q})
+                     (void *)r, (void *)s, (void *)d_c, (void *)d_l, (void *)d_u, (void *)d_q, (void *)d_klong,
+                     (void *)d_tlong})
         P->dfree(pp);
     if (P->mixed) {
         for (void *pp : {(void *)cs, (void *)ls, (void *)us, (void *)qs}) P->dfree(pp);

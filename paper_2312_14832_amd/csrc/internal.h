@@ -190,9 +190,12 @@ hipError_t launch_fill(double *a, double v, int len, hipStream_t s);
 hipError_t launch_scale_vectors(const double *c, const double *l, const double *u, const double *q,
                                 const double *Dc, const double *Dr, double *cs, double *ls, double *us,
                                 double *qs, int n, int m, hipStream_t s);
+// klong[nklong] / tlong[ntlong]: device lists of the rows of K / K' longer
+// than kLongRow, scaled on grids of their own (NULL, 0: every row one wave)
 hipError_t scale_csr_pair(const int *rp, const int *ci, double *kv, int m, const int *tp, const int *ti, double *tv,
                           int n, double *Dr, double *Dc, double *r, double *s, int ruiz_iters, double alpha,
-                          hipStream_t st);
+                          hipStream_t st, const int *klong = nullptr, int nklong = 0, const int *tlong = nullptr,
+                          int ntlong = 0);
 // deterministic sum of squares / max |.| over a vector: partials then one workgroup
 hipError_t launch_sumsq(const double *a, int64_t len, double *part, double *out, hipStream_t s);
 hipError_t launch_absmax(const double *a, int64_t len, double *part, double *out, hipStream_t s);

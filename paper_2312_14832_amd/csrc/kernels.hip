@@ -241,13 +241,16 @@ __global__ void k_convert(const A *in, B *out, int64_t len)
 // one-time scaling kernels (FP64, one wave64 per row)
 // ----------------------------------------------------------------------------
 
-__global__ void k_row_absmax(const int *rp, const double *v, int nrows, double *out)
+// skip_long: rows longer than kLongRow are left at 0 (k_row_absmax_long
+// then takes their maximum with many workgroups)
+__global__ void k_row_absmax(const int *rp, const double *v, int nrows, int skip_long, double *out)
 {
     const int row = blockIdx.x * (kBlock / 64) + ((int)threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= nrows) return;
     double a = 0.0;
-    for (int j = rp[row] + lane; j < rp[row + 1]; j += 64) a = fmax(a, fabs(v[j]));
+    if (!(skip_long && rp[row + 1] - rp[row] > kLongRow))
+        for (int j = rp[row] + lane; j < rp[row + 1]; j += 64) a = fmax(a, fabs(v[j]));
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) a = fmax(a, __shfl_xor(a, off));
     if (lane == 0) out[row] = a;
@@ -274,14 +277,46 @@ __global__ void k_finish_factor(double *f, int len)
     if (i < len) f[i] = f[i] > 0.0 ? sqrt(f[i]) : 1.0;
 }
 
-__global__ void k_rescale_rows(const int *rp, const int *ci, double *v, int nrows, const double *rowf,
+__global__ void k_rescale_rows(const int *rp, const int *ci, double *v, int nrows, int skip_long, const double *rowf,
                                const double *colf)
 {
     const int row = blockIdx.x * (kBlock / 64) + ((int)threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= nrows) return;
+    if (skip_long && rp[row + 1] - rp[row] > kLongRow) return;
     const double r = rowf[row];
     for (int j = rp[row] + lane; j < rp[row + 1]; j += 64) v[j] = v[j] / (r * colf[ci[j]]);
+}
+
+// The long rows listed in rows[0..nlong) (each more than kLongRow entries),
+// spread over gridDim.x workgroups per row (blockIdx.y picks the row).  The
+// maximum of |v| >= 0 is combined by an integer atomic max on the bit
+// pattern, which orders non-negative doubles exactly, so the result does not
+// depend on the order; the rescale is per entry, as in k_rescale_rows.
+__global__ void k_row_absmax_long(const int *rp, const double *v, const int *rows, double *out)
+{
+    __shared__ double sh[kBlock / 64];
+    const int r = rows[blockIdx.y];
+    double a = 0.0;
+    for (int j = rp[r] + (int)(blockIdx.x * kBlock + threadIdx.x); j < rp[r + 1]; j += (int)(gridDim.x * kBlock))
+        a = fmax(a, fabs(v[j]));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) a = fmax(a, __shfl_xor(a, off));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double b = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+        atomicMax(reinterpret_cast<unsigned long long *>(out + r), (unsigned long long)__double_as_longlong(b));
+    }
+}
+
+__global__ void k_rescale_long(const int *rp, const int *ci, double *v, const int *rows, const double *rowf,
+                               const double *colf)
+{
+    const int r = rows[blockIdx.y];
+    const double f = rowf[r];
+    for (int j = rp[r] + (int)(blockIdx.x * kBlock + threadIdx.x); j < rp[r + 1]; j += (int)(gridDim.x * kBlock))
+        v[j] = v[j] / (f * colf[ci[j]]);
 }
 
 __global__ void k_mul_inplace(double *a, const double *f, int len)
@@ -505,7 +540,7 @@ hipError_t launch_from_double(const double *in, T *out, int64_t len, hipStream_t
 hipError_t launch_row_absmax(const int *rp, const double *v, int nrows, double *out, hipStream_t s)
 {
     if (nrows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_row_absmax, dim3((nrows + 3) / 4), dim3(kBlock), 0, s, rp, v, nrows, out);
+    hipLaunchKernelGGL(k_row_absmax, dim3((nrows + 3) / 4), dim3(kBlock), 0, s, rp, v, nrows, 0, out);
     return hipGetLastError();
 }
 
@@ -527,7 +562,7 @@ hipError_t launch_rescale_rows(const int *rp, const int *ci, double *v, int nrow
                                const double *colf, hipStream_t s)
 {
     if (nrows <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_rescale_rows, dim3((nrows + 3) / 4), dim3(kBlock), 0, s, rp, ci, v, nrows, rowf, colf);
+    hipLaunchKernelGGL(k_rescale_rows, dim3((nrows + 3) / 4), dim3(kBlock), 0, s, rp, ci, v, nrows, 0, rowf, colf);
     return hipGetLastError();
 }
 
@@ -579,9 +614,29 @@ hipError_t launch_absmax(const double *a, int64_t len, double *part, double *out
 // of the inf-norm of each row of K and of K', both from the same current
 // matrix), then one Pock-Chambolle round with exponent alpha (skipped when
 // alpha < 0).  Scales both CSR copies in place and accumulates Dr, Dc.
+// One product's row maxima / rescale, its long rows (if listed) on their own grid.
+static void row_absmax_split(const int *rp, const double *v, int nrows, const int *lrows, int nlong, double *out,
+                             hipStream_t s)
+{
+    if (nrows <= 0) return;
+    const int skip = lrows && nlong > 0 && nlong <= 65535;   // gridDim.y limit
+    hipLaunchKernelGGL(k_row_absmax, dim3((nrows + 3) / 4), dim3(kBlock), 0, s, rp, v, nrows, skip, out);
+    if (skip) hipLaunchKernelGGL(k_row_absmax_long, dim3(256, nlong), dim3(kBlock), 0, s, rp, v, lrows, out);
+}
+
+static void rescale_split(const int *rp, const int *ci, double *v, int nrows, const int *lrows, int nlong,
+                          const double *rowf, const double *colf, hipStream_t s)
+{
+    if (nrows <= 0) return;
+    const int skip = lrows && nlong > 0 && nlong <= 65535;   // gridDim.y limit
+    hipLaunchKernelGGL(k_rescale_rows, dim3((nrows + 3) / 4), dim3(kBlock), 0, s, rp, ci, v, nrows, skip, rowf,
+                       colf);
+    if (skip) hipLaunchKernelGGL(k_rescale_long, dim3(256, nlong), dim3(kBlock), 0, s, rp, ci, v, lrows, rowf, colf);
+}
+
 hipError_t scale_csr_pair(const int *rp, const int *ci, double *kv, int m, const int *tp, const int *ti, double *tv,
                           int n, double *Dr, double *Dc, double *r, double *s, int ruiz_iters, double alpha,
-                          hipStream_t st)
+                          hipStream_t st, const int *klong, int nklong, const int *tlong, int ntlong)
 {
     hipError_t e;
     if ((e = launch_fill(Dr, 1.0, m, st)) != hipSuccess) return e;
@@ -590,16 +645,16 @@ hipError_t scale_csr_pair(const int *rp, const int *ci, double *kv, int m, const
     for (int it = 0; it < rounds; ++it) {
         const bool pc = it == ruiz_iters;
         if (!pc) {
-            (void)launch_row_absmax(rp, kv, m, r, st);
-            (void)launch_row_absmax(tp, tv, n, s, st);
+            row_absmax_split(rp, kv, m, klong, nklong, r, st);
+            row_absmax_split(tp, tv, n, tlong, ntlong, s, st);
         } else {
             (void)launch_row_abspow_sum(rp, kv, m, 2.0 - alpha, r, st);
             (void)launch_row_abspow_sum(tp, tv, n, alpha, s, st);
         }
         (void)launch_finish_factor(r, m, st);
         (void)launch_finish_factor(s, n, st);
-        (void)launch_rescale_rows(rp, ci, kv, m, r, s, st);
-        (void)launch_rescale_rows(tp, ti, tv, n, s, r, st);
+        rescale_split(rp, ci, kv, m, klong, nklong, r, s, st);
+        rescale_split(tp, ti, tv, n, tlong, ntlong, s, r, st);
         (void)launch_mul_inplace(Dr, r, m, st);
         if ((e = launch_mul_inplace(Dc, s, n, st)) != hipSuccess) return e;
     }
