@@ -64,3 +64,23 @@ def test_no_reduction_keeps_the_problem(lpmod, oracle_mod):
     ia, ib = a.solve(1e-6, 100_000), b.solve(1e-6, 100_000)
     assert ia["iterations"] == ib["iterations"]
     assert all(np.array_equal(u, v) for u, v in zip(a.result()[:3], b.result()[:3]))
+
+
+def test_everything_removable_solves_the_original(lpmod):
+    """Every row is a singleton and every column would then be fixed: the
+    presolve declines, the original LP is solved, and the answer is the
+    closed-form optimum x = (2, 5, 1), y = (1/2, 1, 2/3)."""
+    say("case presolve declines")
+    import scipy.sparse as sp
+    K = sp.csr_matrix(np.array([[2.0, 0.0, 0.0], [0.0, -1.0, 0.0], [0.0, 0.0, 3.0]]))
+    lp = gen.LPData(m=3, n=3, m1=1, row_ptr=K.indptr.astype(np.int32), col=K.indices.astype(np.int32),
+                    val=K.data, c=np.array([1.0, -1.0, 2.0]), q=np.array([4.0, -5.0, 3.0]),
+                    l=np.array([0.0, 0.0, 0.0]), u=np.array([10.0, np.inf, np.inf]))
+    p = lpmod.Problem(lp, presolve=1)
+    assert p.presolved_size() == (3, 3)
+    info = p.solve(1e-8, 100_000)
+    assert info["status"] == "OPTIMAL"
+    x, y, lam, info = p.result()
+    assert np.allclose(x, [2.0, 5.0, 1.0], atol=1e-6)
+    assert np.allclose(y, [0.5, 1.0, 2.0 / 3.0], atol=1e-6)
+    assert info["pobj"] == pytest.approx(-1.0, abs=1e-6)

@@ -186,3 +186,16 @@ def test_presolve_postsolve_random(shim, seed, m1, m2, n, kmax, nfix, nsing):
     scale = 1 + np.abs(lp.q).max(initial=0) + np.abs(lp.c).max() + np.abs(x).max()
     assert rp <= 1e-7 * scale and rd <= 1e-7 * scale and ysign == 0 and cone == 0 and bviol <= 1e-9 * scale
     assert abs(pobj - ref) <= 1e-7 * (1 + abs(ref)) and abs(dobj - ref) <= 1e-7 * (1 + abs(ref))
+
+
+def test_everything_removable_keeps_the_original(shim):
+    """Only singleton rows: once they are gone every column is empty and
+    would be fixed at its best bound, so nothing would remain to solve;
+    the presolve then declines and the original LP is loaded as it is."""
+    Kd = np.array([[2.0, 0.0, 0.0], [0.0, -1.0, 0.0], [0.0, 0.0, 3.0]])
+    K = sp.csr_matrix(Kd)
+    # 2 x0 = 4 (fixes x0 = 2), -x1 >= -5 (x1 <= 5), 3 x2 >= 3 (x2 >= 1)
+    lp = gen.LPData(m=3, n=3, m1=1, row_ptr=K.indptr.astype(np.int32), col=K.indices.astype(np.int32),
+                    val=K.data, c=np.array([1.0, -1.0, 2.0]), q=np.array([4.0, -5.0, 3.0]),
+                    l=np.array([0.0, 0.0, 0.0]), u=np.array([10.0, np.inf, np.inf]))
+    assert run_presolve(shim, lp) is None
