@@ -63,9 +63,10 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def counter_traffic(kernel, workload):
+def counter_traffic(kernel, workload, layout=None):
     """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source."""
+    taken on the current kernel source and on the same layout (column
+    slices, nonzeros and rows per row block of K and K')."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -74,7 +75,26 @@ def counter_traffic(kernel, workload):
     e = d.get(workload, {}).get(kernel)
     if not e or e.get("source_sha") != kernel_source_sha():
         return None
+    if layout is not None and e.get("layout") != layout:
+        return None
     return e.get("traffic_bytes")
+
+
+def profiled_layout(dirpath):
+    """Layout of a profiled run, from the bench's own line in DIR/stats.log
+    (the profile commands run with --autotune 0, so the row blocks are the
+    default 2048 nonzeros and 1024 rows unless the line names them)."""
+    import re
+    text = open(os.path.join(dirpath, "stats.log")).read()
+    m = re.search(r"layout K \(S, nnz/block, rows/block\) = \((\d+), (\d+), (\d+)\), "
+                  r"K' = \((\d+), (\d+), (\d+)\)", text)
+    if m:
+        v = [int(g) for g in m.groups()]
+        return {"K": v[:3], "KT": v[3:]}
+    m = re.search(r"column slices \(K, K'\) = \((\d+), (\d+)\)", text)
+    if not m:
+        return None
+    return {"K": [int(m.group(1)), 2048, 1024], "KT": [int(m.group(2)), 2048, 1024]}
 
 
 def _kernel_short(name):
@@ -127,8 +147,9 @@ def traffic_from(dirpath, precision, workload, copy_bytes):
         assert len(hits) == 1, (label, hits)
         return table[hits[0]], hits[0]
 
+    layout = profiled_layout(dirpath) if os.path.exists(os.path.join(dirpath, "stats.log")) else None
     for pair in kernel_names(precision).values():
-        e = {"source_sha": sha, "fetch_factor": ff, "write_factor": wf, "parts": {}}
+        e = {"source_sha": sha, "fetch_factor": ff, "write_factor": wf, "layout": layout, "parts": {}}
         tot = 0.0
         for k in pair.split("+"):
             (_, fk), full = find(fetch, k)
@@ -302,8 +323,10 @@ def main():
                       autotune=args.autotune)
     torch.cuda.synchronize()
     load_s = time.perf_counter() - t0
+    lk, lt = prob.layout_blocks(0), prob.layout_blocks(1)
     print(f"[bench] loaded in {load_s:.1f}s ({prob.device_bytes() / 2**30:.2f} GiB on device), "
-          f"column slices (K, K') = {prob.layout()}", file=sys.stderr, flush=True)
+          f"column slices (K, K') = {prob.layout()}; layout K (S, nnz/block, rows/block) = {lk}, K' = {lt}",
+          file=sys.stderr, flush=True)
 
     # warm-up windows (also compiles nothing: kernels are prebuilt)
     prob.solve(1e-30, ITERS_PER_STEP * max(args.warmup, 0))
@@ -331,7 +354,8 @@ def main():
     d = spmv[dom]
     roofline = {"kernel": dom, "bound": "hbm", "achieved": d["GB_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": d["GB_s"] / HBM_PEAK_GBS if d["GB_s"] else None,
-                "traffic": counter_traffic(dom, workload), "alg_bytes_per_launch": d["alg_bytes"],
+                "traffic": counter_traffic(dom, workload, {"K": list(lk), "KT": list(lt)}),
+                "alg_bytes_per_launch": d["alg_bytes"],
                 "timed_launches": d["launches"]}
     print(f"[bench] {K} windows in {dt:.3f}s -> {iters / dt:.0f} it/s; "
           + "; ".join(f"{k} {v['avg_us']:.1f}us {v['GB_s'] or 0:.0f}GB/s" for k, v in spmv.items()),
