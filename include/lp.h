@@ -103,7 +103,8 @@ typedef struct {
     int slice_kib;          /* target KiB of a gathered vector per column slice of K and K' (2048 = half an XCD's L2) */
     int autotune;           /* 1: at lp_load, time the slice count from slice_kib, then halve it (else
                                double it, to at most 32) while that keeps helping, then smaller row blocks,
-                               on the actual matrix, and keep the fastest, per product (0); ignored when a
+                               on the actual matrix, and keep the fastest, per product (0); a candidate
+                               replaces the current choice only when at least 3% faster.  Ignored when a
                                workspace is given.  At lp_batch_load: the row-block shape
                                (lp_batch_layout_blocks) */
     int verbose;            /* 1: messages on stderr, and one trace line per window of the solve (k, attempts,

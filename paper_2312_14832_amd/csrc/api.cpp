@@ -376,6 +376,11 @@ float time_product(lp_problem *P, const Sliced<T> &q, T *in, T *out, int64_t in_
     return ev.ms() / reps;
 }
 
+// A trial layout replaces the incumbent only when it is this much faster, so
+// that near-ties (timing noise) keep the earlier, default-side layout and
+// two processes rarely pick different layouts.
+constexpr float kTuneMargin = 0.97f;
+
 // Autotuner for one product: times the default layout, then walks the slice
 // count down by halving while that keeps helping (else up by doubling, to at
 // most 32), then tries halved nonzeros per row block and 256 rows per block at
@@ -397,7 +402,7 @@ Sliced<T> tuned_sliced(lp_problem *P, const HostSliced &H0, const std::vector<in
         Sliced<T> q = upload_sliced<T>(P, H, vals);
         const float ms = time_product<T>(P, q, in, out, in_len);
         log.push_back({S, nb, rb, ms});
-        if (ms < best_ms) {
+        if (ms < kTuneMargin * best_ms) {
             free_sliced<T>(P, best);
             best = q;
             best_ms = ms;

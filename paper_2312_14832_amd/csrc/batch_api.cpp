@@ -336,7 +336,7 @@ int do_batch_load(lp_batch *P, const lp_csr *K, const double *const *c, const do
                     if (P->opt.verbose)
                         fprintf(stderr, "[lp_batch] product %d: blocks of <= %d nonzeros, <= %d rows: %.3f ms\n",
                                 which, cand[k][0], cand[k][1], ms / 5);
-                    if (k == 0 || ms < best_ms) {
+                    if (k == 0 || ms < 0.97f * best_ms) {   // 3% margin: near-ties keep the default shape
                         if (k > 0) release_blocks(P, cur);
                         cur = L;
                         best_ms = ms;
