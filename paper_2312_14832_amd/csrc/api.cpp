@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <exception>
 #include <memory>
 #include <string>
 #include <thread>
@@ -48,14 +49,26 @@ struct HostSliced {
     int max_blocks = 0;
 };
 
-// Run fn(t) for t in [0, T) on T threads (fn(0) on the caller's).
+// Run fn(t) for t in [0, T) on T threads (fn(0) on the caller's); an
+// exception thrown by any of them (std::bad_alloc) is rethrown here after
+// all have joined.
 template <typename F>
 void run_threads(int T, F &&fn)
 {
+    std::vector<std::exception_ptr> err((size_t)T);
+    auto guarded = [&](int t) {
+        try {
+            fn(t);
+        } catch (...) {
+            err[(size_t)t] = std::current_exception();
+        }
+    };
     std::vector<std::thread> th;
-    for (int t = 1; t < T; ++t) th.emplace_back(fn, t);
-    fn(0);
+    for (int t = 1; t < T; ++t) th.emplace_back(guarded, t);
+    guarded(0);
     for (auto &x : th) x.join();
+    for (auto &e : err)
+        if (e) std::rethrow_exception(e);
 }
 
 // Rows of the source CSR must have their columns sorted, so that each

@@ -277,6 +277,20 @@ int do_batch_load(lp_batch *P, const lp_csr *K, const double *const *c, const do
         d.xo = A.make<T>(N); d.yo = A.make<T>(M); d.KTyo = A.make<T>(N);
         b.prodK = A.make<T>(M);
         b.prodKT = A.make<T>(N);
+        // Zero every iterate vector: lp_batch_set_state writes only each
+        // instance's own entries, and the chunk padding must read as the
+        // inert zeros a cold start writes (a resume's first primal trial
+        // sums |x' - x|^2 over whole chunks, padding included).
+        for (int k = 0; k < 2; ++k)
+            for (auto pv : {std::make_pair((void *)d.xb[k], N), std::make_pair((void *)d.yb[k], M),
+                            std::make_pair((void *)d.Kxb[k], M), std::make_pair((void *)d.KTyb[k], N)})
+                HIPT(hipMemsetAsync(pv.first, 0, sizeof(T) * (size_t)std::max<int64_t>(pv.second, 1), st));
+        for (auto pv : {std::make_pair((void *)d.xa, N), std::make_pair((void *)d.ya, M), std::make_pair((void *)d.Kxa, M),
+                        std::make_pair((void *)d.KTya, N), std::make_pair((void *)d.x0, N), std::make_pair((void *)d.y0, M),
+                        std::make_pair((void *)d.Kx0, M), std::make_pair((void *)d.KTy0, N), std::make_pair((void *)d.xo, N),
+                        std::make_pair((void *)d.yo, M), std::make_pair((void *)d.KTyo, N),
+                        std::make_pair((void *)b.prodK, M), std::make_pair((void *)b.prodKT, N)})
+            HIPT(hipMemsetAsync(pv.first, 0, sizeof(T) * (size_t)std::max<int64_t>(pv.second, 1), st));
         d.part_primal = A.make<double>(b.ncn);
         d.part_dual = A.make<double>(2 * (int64_t)b.ncm);
         d.part_check = A.make<double>((int64_t)kCheckSums * (b.ncn + b.ncm));

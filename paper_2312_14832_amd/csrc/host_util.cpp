@@ -1,6 +1,7 @@
 // Host-side helpers shared by the single-LP and the batched C ABI.
 #include "host_util.h"
 
+#include <exception>
 #include <thread>
 
 namespace pdlp {
@@ -113,11 +114,21 @@ void transpose_csr(int rows, int cols, const std::vector<int> &rp, const std::ve
     // sort whatever the thread count.
     const int T = std::max(1, std::min(host_threads(), cols / 65536 + 1));
     auto range = [&](int t) { return std::make_pair((int)((int64_t)cols * t / T), (int)((int64_t)cols * (t + 1) / T)); };
-    auto parallel = [&](auto &&fn) {
+    auto parallel = [&](auto &&fn) {   // exceptions of the workers are rethrown after the join
+        std::vector<std::exception_ptr> err((size_t)T);
+        auto guarded = [&](int t) {
+            try {
+                fn(t);
+            } catch (...) {
+                err[(size_t)t] = std::current_exception();
+            }
+        };
         std::vector<std::thread> th;
-        for (int t = 1; t < T; ++t) th.emplace_back(fn, t);
-        fn(0);
+        for (int t = 1; t < T; ++t) th.emplace_back(guarded, t);
+        guarded(0);
         for (auto &x : th) x.join();
+        for (auto &e : err)
+            if (e) std::rethrow_exception(e);
     };
     parallel([&](int t) {
         const auto [c0, c1] = range(t);

@@ -203,3 +203,31 @@ def test_batch_with_dense_rows(lpmod, oracle_mod):
         assert info["status"] == "OPTIMAL", (i, info)
         ev = oracle_mod.Oracle(p).eval_unscaled(x, y)
         assert ev["rel_kkt"] <= 1e-6 * (1 + 1e-6), (i, ev)
+
+
+def test_batch_resume_on_reused_memory(lpmod, oracle_mod):
+    """A batch loaded after another handle freed its device memory (which
+    then holds that handle's iterates) resumes exactly: the chunk padding
+    reads as zeros, not as what the memory held before."""
+    say("case batch resume on reused memory")
+    other = lpmod.Problem(gen.large_lp(seed=5, n=60000, m1=15000, m2=15000))
+    other.solve(1e-30, 640)
+    other.close()
+    lps = small_batch()
+    bt = lpmod.Batch(lps)
+    oracles = [oracle_mod.Oracle(p) for p in lps]
+    raws, nexts = [], []
+    for o in oracles:
+        o.solve(1e-30, 0)
+        raws.append(o.get_state_raw())
+        o.solve(1e-30, 1)
+        nexts.append(o.get_state())
+    for i, raw in enumerate(raws):
+        bt.set_state(i, raw)
+    bt.solve(1e-30, 1)
+    for i, p in enumerate(lps):
+        sg = lpmod.unpack_state(bt.get_state(i), p.n, p.m)
+        so = nexts[i]
+        assert ints_equal(sg, so), i
+        for name in ("eta_hat", "omega", "W", "eta_last"):
+            assert abs(sg[name] - so[name]) <= 1e-9 * abs(so[name]) + 1e-300, (i, name, sg[name], so[name])
