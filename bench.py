@@ -229,6 +229,18 @@ def cpu_baseline(data, max_windows=3, budget_s=13.0):
             "seconds": dt}
 
 
+def host_cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo; "unknown" elsewhere)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def workload_name(args):
     """Key of a single-LP workload in the bench line and in traffic.json."""
     base = f"pagerank_lp_n{args.n}" if args.workload == "pagerank" else f"large_powerlaw_lp_n{args.n}"
@@ -384,6 +396,7 @@ def main():
     if not args.no_cpu:
         cpu = cpu_baseline(data)   # about 13 s of one host core on the default workload
         cpu["threads_note"] = f"host has {os.cpu_count()} logical CPUs; the oracle is single-threaded"
+        cpu["cpu_model"] = host_cpu_model()
         print(f"[bench] cpu oracle {cpu['value']:.2f} it/s", file=sys.stderr, flush=True)
 
     out = {

@@ -620,11 +620,11 @@ static int check(orc_t *P, double tol, int restart_ok, int at_limit)
     }
     if (restart_ok) {
         double kc = kkt_omega(P, &ec, P->omega), ka = kkt_omega(P, &ea, P->omega);
-        int cand_cur = kc < ka;
+        int cand_cur = ORC_MUT == 11 ? 0 : kc < ka;
         double kz = cand_cur ? kc : ka;
         const orc_eval_t *ez = cand_cur ? &ec : &ea;
         int why = orc_restart_decision(kz, P->KKT0, P->KKT_prev, P->t, P->k);
-        P->KKT_prev = kz;
+        if (ORC_MUT != 12) P->KKT_prev = kz;
         if (why) {
             P->omega = orc_omega_update(P->omega, sqrt(ez->dx2), sqrt(ez->dy2));
             if (cand_cur) {

@@ -125,3 +125,45 @@ def objective_band(eps, data, x_ref, y_ref, pobj, dobj):
            + np.linalg.norm(y_ref) * eps * (1 + np.linalg.norm(data.q))
            + np.linalg.norm(x_ref) * eps * (1 + np.linalg.norm(data.c)))
     return 2.0 * per
+
+
+def restart_golden_lp(g):
+    """The LP of restart_candidate_1var.json (no rows)."""
+    from paper_2312_14832_amd import gen
+    n = int(g["n"])
+    return gen.from_dense(np.zeros((0, n)), g["c"], g["q"], [fnum(a) for a in g["l"]],
+                          [fnum(a) for a in g["u"]], g["m1"])
+
+
+RESTART_SCALARS = ["eta_hat", "omega", "W", "KKT0", "KKT_prev", "k", "t", "attempts", "restarts",
+                   "status", "eta_last"]
+
+
+def restart_golden_state(g, case):
+    """Flat solver state (16 scalars, then x, K'y, xbar, K'ybar, x0 for one
+    column and no rows) of one case of restart_candidate_1var.json."""
+    st = g["start"]
+    sc = dict(eta_hat=g["eta"], omega=g["omega"], W=case["W"], KKT0=case["KKT0"],
+              KKT_prev=fnum(st["KKT_prev"]), k=st["k"], t=st["t"], attempts=st["attempts"],
+              restarts=st["restarts"], status=0, eta_last=g["eta"])
+    buf = np.zeros(16 + 5)
+    for i, name in enumerate(RESTART_SCALARS):
+        buf[i] = sc[name]
+    buf[16:] = [case["x"], 0.0, case["xbar"], 0.0, st["x0"]]
+    return buf
+
+
+def check_restart_golden_state(st, want, label):
+    """Compare an unpacked state with one 'after' entry of the golden."""
+    for key in ("x", "xbar", "x0"):
+        assert st[key][0] == pytest_approx(fnum(want[key])), (label, key, st[key][0], want[key])
+    for key in ("W", "KKT0", "KKT_prev", "omega"):
+        w = fnum(want[key])
+        assert (st[key] == w) if np.isinf(w) else st[key] == pytest_approx(w), (label, key, st[key], w)
+    for key in ("t", "k", "restarts"):
+        assert int(st[key]) == int(want[key]), (label, key, st[key], want[key])
+
+
+def pytest_approx(v):
+    import pytest
+    return pytest.approx(v, rel=1e-15, abs=1e-300)

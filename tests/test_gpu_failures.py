@@ -1,8 +1,8 @@
 """Failure handling through the C ABI on the GPU, each case forced from the
 host with kernels that still exit normally: a NaN warm start (NaN-propagating
 projections -> NUMERICAL, then the cold-start fallback), a time limit, an
-infeasible LP (no infeasibility detection: ITERATION_LIMIT), and the
-per-window trace of verbose mode."""
+infeasible LP (a Farkas certificate: PRIMAL_INFEASIBLE, or ITERATION_LIMIT
+with the ray test off), and the per-window trace of verbose mode."""
 import numpy as np
 import pytest
 

@@ -5,7 +5,8 @@ import numpy as np
 import pytest
 
 from paper_2312_14832_amd import gen
-from lp_helpers import objective_band
+from lp_helpers import (check_restart_golden_state, load_golden, objective_band, restart_golden_lp,
+                        restart_golden_state)
 from gpu_helpers import (U64, gpu_state, ints_equal, kkt_scale, perturbed, say, scalar_diff, state_diff,
                          step_condition, vec_diff)
 
@@ -405,3 +406,21 @@ def test_full_size_large_lp(lpmod, oracle_mod):
         sg = gpu_state(lpmod, p)
         assert ints_equal(sg, so), k
         assert_states_close(sg, so, step_condition(prev, so), f"full k={k}", kkt_scale(so, Drs, Dcs, data))
+
+
+def test_restart_golden(lpmod, oracle_mod):
+    """The hand-traced restart cases (Sec. 2, "Restart criteria": the current
+    iterate as candidate only when its KKT_omega is strictly smaller;
+    condition 2 against the previous check's candidate) on the GPU's decision
+    kernels.  The batch runs the same device decision function per instance."""
+    say("case restart golden")
+    from oracle.oracle import unpack_state
+    g = load_golden("restart_candidate_1var.json")
+    lp = restart_golden_lp(g)
+    kw = dict(ruiz_iters=0, pc_alpha=-1.0, check_every=1, fixed_step=1, fixed_eta=g["eta"], infeas_tol=0.0)
+    for case in g["cases"]:
+        p = lpmod.Problem(lp, **kw)
+        for s, want in enumerate(case["after"], start=1):
+            p.set_state(restart_golden_state(g, case))
+            p.solve(1e-12, g["start"]["k"] + s)
+            check_restart_golden_state(unpack_state(p.get_state(), lp.n, lp.m), want, (case["name"], s))

@@ -40,6 +40,8 @@ MUTATIONS = {
     8: "KKT_omega uses omega instead of omega^2",
     9: "dual ray objective adds +u lam- instead of -u lam-",
     10: "primal ray test ignores the bounds' recession cone",
+    11: "restart candidate is always the average",
+    12: "KKT at the previous check never recorded (restart condition 2 cannot fire)",
 }
 
 CHECKS = [
@@ -49,6 +51,7 @@ CHECKS = [
     ("termination quantities by hand", pins.check_termination_golden),
     ("scaling by hand", pins.check_scaling_golden),
     ("step rule constants", pins.check_step_rule),
+    ("restart candidate and condition 2 by hand", pins.check_restart_golden),
     ("step-weighted averages", pins.check_step_weighted_averages),
     ("vertex enumeration", lambda om, libpath=None: pins.check_vertex_objective(om, 11, 3, 1, 2, libpath,
                                                                                   max_iters=200_000)),

@@ -9,7 +9,8 @@ import numpy as np
 import pytest
 
 from paper_2312_14832_amd import gen
-from lp_helpers import brute_force_vertices, farkas_ratios, fnum, highs, highs_status, load_golden
+from lp_helpers import (brute_force_vertices, check_restart_golden_state, farkas_ratios, fnum, highs, highs_status,
+                        load_golden, restart_golden_lp, restart_golden_state)
 
 
 # ---------------------------------------------------------------- end results
@@ -189,6 +190,26 @@ def check_two_steps_golden(om, libpath=None):
     assert np.array_equal(st["x"], e["x2"]) and np.array_equal(st["y"], e["y2"])
     assert np.array_equal(st["xbar"], e["xbar2"]) and np.array_equal(st["ybar"], e["ybar2"])
     assert st["k"] == 2 and st["W"] == 2 * g["eta"] and st["omega"] == g["omega"]
+
+
+def test_restart_candidate_and_condition_2_by_hand(oracle_mod):
+    check_restart_golden(oracle_mod)
+
+
+def check_restart_golden(om, libpath=None):
+    """The restart candidate (the current iterate only when its KKT_omega is
+    strictly smaller), condition 2 against the previous check's candidate,
+    and what a restart resets (Sec. 2, "Restart criteria"), traced by hand
+    on a one-variable LP from given states."""
+    g = load_golden("restart_candidate_1var.json")
+    lp = restart_golden_lp(g)
+    for case in g["cases"]:
+        o = om.Oracle(lp, ruiz_iters=0, pc_alpha=-1.0, check_every=1, fixed_step=True, fixed_eta=g["eta"],
+                      infeas_tol=0.0, libpath=libpath)
+        for s, want in enumerate(case["after"], start=1):
+            o.set_state_raw(restart_golden_state(g, case))
+            o.solve(1e-12, g["start"]["k"] + s)
+            check_restart_golden_state(o.get_state(), want, (case["name"], s))
 
 
 def test_averages_are_step_weighted(oracle_mod):
