@@ -215,6 +215,27 @@ int lp_get_scaling(const lp_problem *P, double *Dr, double *Dc);
  * buffers, original order.  Runs the same SpMV kernels as the solve. */
 int lp_spmv(lp_problem *P, int transpose, const double *in, double *out);
 
+/* lp_spmv for callers that cannot allocate device memory or synchronise:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same product, same kernels and the same result bit for bit as
+ * lp_spmv, but in[] and out[] are DEVICE pointers (double; in[n], out[m], or
+ * in[m], out[n] with transpose = 1, original order), and the intermediates
+ * (the per-slice partial vectors, the long-row chunk sums and, in LP_MIXED,
+ * FP32 copies of in and out) live in a fixed 64 MiB device array that the
+ * library holds on every GPU it runs on until the process ends.  It calls no
+ * allocator and does not wait: the work is only enqueued on the handle's
+ * stream (lp_options.stream), so the caller synchronises that stream before
+ * reading out.  Nothing in the array needs to start at zero.  Every call on
+ * one GPU shares that GPU's array, so calls that overlap on one GPU (other
+ * streams, other threads, other handles) race and must be serialised by the
+ * caller.  The handle's GPU must be the current device.
+ * Errors: LP_ERR_ARG (NULL pointer, wrong current device), LP_ERR_NOMEM (the
+ * product needs more than the 64 MiB array: S*rows*value size plus the
+ * long-row sums plus, in LP_MIXED, 4(n+m) bytes, each rounded up to 256;
+ * lp_last_error() states the size), LP_ERR_HIP (a launch failed or the array
+ * is not available). */
+int lp_spmv_noalloc(lp_problem *P, int transpose, const double *in, double *out);
+
 /* Launch statistics of the two products of the last lp_solve when
  * kernel_timing was set: which = 0 (K x' partial pass + fused dual step) or
  * 1 (K' y' partial pass + fused averages and next primal step); *count

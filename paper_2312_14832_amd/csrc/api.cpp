@@ -249,6 +249,8 @@ struct lp_problem {
     bool graph_timed = false, graph_events_failed = false;
     bool own_stream = false;
     int slices_K = 1, slices_KT = 1;
+    int device = -1;                // device current at lp_load (the handle's GPU)
+    void *nscratch = nullptr;       // that device's fixed scratch array (lp_spmv_noalloc); null if unavailable
     int shape_K[3] = {1, kStreamNB, kStreamRB}, shape_KT[3] = {1, kStreamNB, kStreamRB};  // S, nnz, rows per block
     std::vector<TuneTrial> tune_log_K, tune_log_KT;   // layouts tried by the autotuner
     std::vector<hipEvent_t> ev;
@@ -360,6 +362,7 @@ Sliced<T> upload_sliced(lp_problem *P, const HostSliced &H, const double *scaled
     P->dfree(src);
     q.rp = rp; q.ci = ci; q.blk = blk; q.boff = boff; q.v = v; q.part = part;
     q.nlong = nlong; q.lrow = lrow; q.loff = loff; q.lpart = lpart;
+    q.nlpart = H.loff.back();
     return q;
 }
 
@@ -1056,6 +1059,62 @@ int do_spmv(lp_problem *P, int transpose, const double *in, double *out)
     return LP_OK;
 }
 
+// Bytes of fixed scratch one product of lp_spmv_noalloc uses, laid out as
+// [S partial vectors][long-row chunk sums][mixed only: FP32 input, FP32 output],
+// each part 256-byte aligned.
+template <typename T>
+size_t noalloc_plan(const Sliced<T> &q, int64_t lin, int64_t lout, size_t off[4])
+{
+    size_t at = 0;
+    off[0] = at;
+    at += dev_round(sizeof(T) * (size_t)q.S * (size_t)std::max(q.rows, 1));
+    off[1] = at;
+    at += dev_round(sizeof(T) * (size_t)std::max(q.nlpart, 1));
+    off[2] = at;
+    if (sizeof(T) != sizeof(double)) {
+        at += dev_round(sizeof(T) * (size_t)std::max<int64_t>(lin, 1));
+        off[3] = at;
+        at += dev_round(sizeof(T) * (size_t)std::max<int64_t>(lout, 1));
+    } else {
+        off[3] = at;
+    }
+    return at;
+}
+
+// The product of lp_spmv on device buffers, with every intermediate in the
+// fixed scratch array: no allocation, no synchronisation.
+template <typename T>
+int do_spmv_noalloc(lp_problem *P, int transpose, const double *in, double *out)
+{
+    Dev<T> &d = P->dev<T>();
+    const int64_t lin = transpose ? P->m : P->n, lout = transpose ? P->n : P->m;
+    Sliced<T> q = transpose ? d.KT : d.K;
+    size_t off[4];
+    const size_t need = noalloc_plan(q, lin, lout, off);
+    if (need > kNoallocScratchBytes) {
+        char buf[200];
+        snprintf(buf, sizeof(buf), "lp_spmv_noalloc: this product needs %zu bytes of scratch, the fixed array holds %zu",
+                 need, kNoallocScratchBytes);
+        P->err = buf;
+        return LP_ERR_NOMEM;
+    }
+    unsigned char *base = (unsigned char *)P->nscratch;
+    q.part = (T *)(base + off[0]);
+    q.lpart = (T *)(base + off[1]);
+    // every partial slot the slice sums read is written by the partial pass
+    // (each slice's row blocks cover all rows; long rows use lpart, whose
+    // chunks are all written), so nothing in the scratch needs clearing
+    if constexpr (sizeof(T) == sizeof(double)) {
+        HIPT(launch_spmv<T>(q, (const T *)in, (T *)out, P->stream));
+    } else {
+        T *tin = (T *)(base + off[2]), *tout = (T *)(base + off[3]);
+        HIPT(launch_from_double<T>(in, tin, lin, P->stream));
+        HIPT(launch_spmv<T>(q, tin, tout, P->stream));
+        HIPT(launch_to_double<T>(tout, out, lout, P->stream));
+    }
+    return LP_OK;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1175,6 +1234,13 @@ int lp_load(lp_problem **out, const lp_csr *K, const double *c, const double *q,
         }
         HIPT(hipHostMalloc((void **)&P->hctl, sizeof(Ctl), hipHostMallocDefault));
         std::memset(P->hctl, 0, sizeof(Ctl));
+        HIPT(hipGetDevice(&P->device));
+        // set-up of lp_spmv_noalloc's scratch on this device (once per device);
+        // a failed lookup only disables that call
+        if (noalloc_scratch(&P->nscratch) != hipSuccess) {
+            P->nscratch = nullptr;
+            (void)hipGetLastError();
+        }
         rc = do_load(P.get(), K, c, q, l, u);
     } catch (const HipError &h) {
         rc = h.e == hipErrorOutOfMemory ? LP_ERR_NOMEM : LP_ERR_HIP;
@@ -1336,6 +1402,26 @@ int lp_spmv(lp_problem *P, int transpose, const double *in, double *out)
     if (!P || !in || !out) return LP_ERR_ARG;
     try {
         return P->mixed ? do_spmv<float>(P, transpose, in, out) : do_spmv<double>(P, transpose, in, out);
+    } catch (const HipError &h) {
+        return fail_hip(P, h);
+    }
+}
+
+int lp_spmv_noalloc(lp_problem *P, int transpose, const double *in, double *out)
+{
+    if (!P || !in || !out) return LP_ERR_ARG;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != P->device) {
+        P->err = "lp_spmv_noalloc: the handle's device is not the current device";
+        return LP_ERR_ARG;
+    }
+    if (!P->nscratch) {
+        P->err = "lp_spmv_noalloc: the fixed scratch array is not available on this device";
+        return LP_ERR_HIP;
+    }
+    try {
+        return P->mixed ? do_spmv_noalloc<float>(P, transpose, in, out)
+                        : do_spmv_noalloc<double>(P, transpose, in, out);
     } catch (const HipError &h) {
         return fail_hip(P, h);
     }

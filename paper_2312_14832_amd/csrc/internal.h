@@ -17,6 +17,7 @@ constexpr int kStreamNB = 2048;  // nonzeros staged in LDS per row block
 constexpr int kStreamRB = 1024;  // most rows per row block (each thread sums every 256th row)
 constexpr int kWaveRow = 64;     // rows longer than this are summed by a whole wavefront
 constexpr int kLongRow = 4 * kStreamNB;  // rows longer than this are cut into chunks
+constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;  // device scratch of lp_spmv_noalloc (64 MiB per GPU)
 // A row block is either a run of rows of at most kWaveRow entries (thread per
 // row) or up to kBlock/64 longer rows (wavefront per row); a wavefront block's
 // end row is stored complemented (~end) in the block descriptor.  A row of
@@ -50,6 +51,7 @@ struct Sliced {
     const int *lrow;  // [nlong] those rows, ascending
     const int *loff;  // [nlong+1] long row k owns lpart[loff[k] .. loff[k+1]), slice-major
     T *lpart;         // chunk dot products of the long rows
+    int nlpart;       // entries of lpart (loff[nlong])
 };
 
 // check modes
@@ -163,6 +165,8 @@ hipError_t launch_seg_sumsq(const double *a, const int64_t *off, int B, double *
 hipError_t launch_seg_absmax(const double *a, const int64_t *off, int B, double *out, hipStream_t s);
 
 // launchers (kernels.hip); each returns the hipError_t of the launch
+// per-device address of the fixed scratch array of lp_spmv_noalloc (noalloc.hip)
+hipError_t noalloc_scratch(void **ptr);
 template <typename T> hipError_t launch_partial_K(const Dev<T> &d, hipStream_t s);
 template <typename T> hipError_t launch_partial_KT(const Dev<T> &d, hipStream_t s);
 template <typename T> hipError_t launch_dual(const Dev<T> &d, const Geo &g, hipStream_t s);

@@ -24,7 +24,7 @@ NSCALARS = 16
 
 # every symbol include/lp.h declares
 EXPORTS = ["lp_default_options", "lp_workspace_size", "lp_load", "lp_set_start", "lp_set_start_weight", "lp_solve", "lp_result", "lp_get_state",
-           "lp_set_state", "lp_get_scaling", "lp_spmv", "lp_kernel_time", "lp_device_bytes", "lp_layout",
+           "lp_set_state", "lp_get_scaling", "lp_spmv", "lp_spmv_noalloc", "lp_kernel_time", "lp_device_bytes", "lp_layout",
            "lp_layout_blocks", "lp_presolved_size", "lp_free",
            "lp_strerror", "lp_last_error", "lp_batch_load", "lp_batch_solve", "lp_batch_result",
            "lp_batch_get_state", "lp_batch_set_state", "lp_batch_device_bytes", "lp_batch_layout_blocks",
@@ -79,6 +79,7 @@ def library():
         L.lp_set_state.argtypes = [C.c_void_p, dp, C.c_int64]
         L.lp_get_scaling.argtypes = [C.c_void_p, dp, dp]
         L.lp_spmv.argtypes = [C.c_void_p, C.c_int, dp, dp]
+        L.lp_spmv_noalloc.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.lp_kernel_time.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.lp_device_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
         L.lp_layout.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]
@@ -277,6 +278,13 @@ class Problem:
         out = np.empty(n if transpose else m)
         self._check(library().lp_spmv(self.h, int(bool(transpose)), _dp(v), _dp(out)))
         return out
+
+    def spmv_noalloc(self, d_in, d_out, transpose=False):
+        """lp_spmv_noalloc on device buffers (torch float64 tensors or raw
+        device addresses); enqueues only, the caller synchronises the stream."""
+        pin = d_in if isinstance(d_in, int) else d_in.data_ptr()
+        pout = d_out if isinstance(d_out, int) else d_out.data_ptr()
+        self._check(library().lp_spmv_noalloc(self.h, int(bool(transpose)), C.c_void_p(pin), C.c_void_p(pout)))
 
     def kernel_time(self, which):
         cnt = C.c_int64(); ms = C.c_double()

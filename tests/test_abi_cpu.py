@@ -106,6 +106,7 @@ def test_null_arguments():
     assert L.lp_load(C.byref(h), None, None, None, None, None, 0, None) == -1
     assert L.lp_solve(None, 1e-4, 10, 0.0) == -1
     assert L.lp_result(None, None, None, None, None) == -1
+    assert L.lp_spmv_noalloc(None, 0, None, None) == -1
     L.lp_free(None)
 
 
