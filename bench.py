@@ -176,7 +176,6 @@ def compare_with_fp64(lp, data, prob, ttt, stream, args):
     evaluated in FP64 on the GPU (an FP64 handle started at the mixed point,
     zero iterations), and the objective against an FP64 solve to the same
     tolerance."""
-    import numpy as np
     import torch
     x, y, _, _ = prob.result()
     p64 = lp.Problem(data, precision="fp64", stream=stream)
@@ -194,15 +193,8 @@ def compare_with_fp64(lp, data, prob, ttt, stream, args):
            "fp64_solve": {"status": ref["status"], "iterations": ref["iterations"], "seconds": t64,
                           "pobj": ref["pobj"], "rel_kkt": ref["rel_kkt"]},
            "objective_rel_diff": abs(ttt["pobj"] - ref["pobj"]) / max(1.0, abs(ref["pobj"]))}
-    # how far apart the objectives of two points meeting the criteria at eps
-    # can be, to first order (value-function sensitivity to the residuals)
-    band = 2.0 * (eps * (1 + abs(ev["pobj"]) + abs(ev["dobj"]))
-                  + np.linalg.norm(y) * eps * (1 + np.linalg.norm(data.q))
-                  + np.linalg.norm(x) * eps * (1 + np.linalg.norm(data.c)))
-    out["objective_band_rel"] = band / max(1.0, abs(ref["pobj"]))
     print(f"[bench] mixed point in FP64: rel KKT {ev['rel_kkt']:.3e}; objective vs FP64 solve "
-          f"{out['objective_rel_diff']:.2e}, first-order band {out['objective_band_rel']:.2e} "
-          f"(FP64 solve {t64:.2f}s, {ref['iterations']} it)",
+          f"{out['objective_rel_diff']:.2e} (FP64 solve {t64:.2f}s, {ref['iterations']} it)",
           file=sys.stderr, flush=True)
     return out
 

@@ -242,6 +242,7 @@ struct lp_problem {
     bool mixed = false;
     Dev<double> d64{};
     Dev<float> d32{};
+    Conf64 conf{};                  // mixed precision: the FP64 re-check of the termination test
     double *stage_n0 = nullptr, *stage_n1 = nullptr, *stage_m = nullptr, *red_part = nullptr, *red_out = nullptr;
     void *tmp_n = nullptr, *tmp_m = nullptr;   // T scratch for lp_spmv
     hipGraphExec_t graph = nullptr;
@@ -590,6 +591,11 @@ size_t load_plan_bytes(int64_t m, int64_t n, int64_t nnz, const HostSliced &HK, 
     for (int64_t len : {n, m, m, n, n, m, m, n, n, m, n}) add(T * one(len));   // averages, anchor (+ products), output
     add(8 * kMaxGrid); add(8 * kMaxGrid * 2); add(8 * kMaxGrid * kCheckSums); add(8 * kMaxGrid * kRaySums);
     add(sizeof(Ctl));
+    // mixed precision: the FP64 re-check keeps the CSR pair above and adds its products and partials
+    if (mixed) {
+        for (int64_t len : {m, m, n, n}) add(8 * one(len));
+        add(8 * kMaxGrid * kCheckSums);
+    }
     return b;
 }
 
@@ -661,15 +667,23 @@ int do_load(lp_problem *P, const lp_csr *K, const double *c, const double *q, co
 
     if (P->mixed) setup_typed<float>(P, HK, HT, d_kv, d_tv, cs, ls, us, qs, Dr, Dc, rp, ci, tp, ti);
     else setup_typed<double>(P, HK, HT, d_kv, d_tv, cs, ls, us, qs, Dr, Dc, rp, ci, tp, ti);
+    if (P->mixed) {
+        // the FP64 scaled CSR pair stays for the re-check of the termination test
+        Conf64 &cf = P->conf;
+        cf.rp = d_rp; cf.ci = d_ci; cf.kv = d_kv; cf.tp = d_tp; cf.ti = d_ti; cf.tv = d_tv;
+        cf.cs = cs; cf.ls = ls; cf.us = us; cf.qs = qs;
+        cf.kx[0] = dalloc(m); cf.kx[1] = dalloc(m);
+        cf.kty[0] = dalloc(n); cf.kty[1] = dalloc(n);
+        cf.part = dalloc((int64_t)kMaxGrid * kCheckSums);
+    }
     sync(P);
-    // the CSR pair was only needed for the scaling
-    for (void *pp : {(void *)d_rp, (void *)d_ci, (void *)d_kv, (void *)d_tp, (void *)d_ti, (void *)d_tv,
-                     (void *)r, (void *)s, (void *)d_c, (void *)d_l, (void *)d_u, (void *)d_q, (void *)d_klong,
+    // otherwise the CSR pair was only needed for the scaling
+    if (!P->mixed)
+        for (void *pp : {(void *)d_rp, (void *)d_ci, (void *)d_kv, (void *)d_tp, (void *)d_ti, (void *)d_tv})
+            P->dfree(pp);
+    for (void *pp : {(void *)r, (void *)s, (void *)d_c, (void *)d_l, (void *)d_u, (void *)d_q, (void *)d_klong,
                      (void *)d_tlong})
         P->dfree(pp);
-    if (P->mixed) {
-        for (void *pp : {(void *)cs, (void *)ls, (void *)us, (void *)qs}) P->dfree(pp);
-    }
 
     // one grid size for the elementwise solver kernels (its workgroups are the partial-sum slots)
     Geo &g = P->geo;
@@ -735,6 +749,22 @@ void get_ctl(lp_problem *P, Ctl *dctl)
     sync(P);
 }
 
+// Mixed precision: the last check passed the termination test on FP32
+// products and stopped the loop.  Redo its sums with FP64 products of the
+// FP64 scaled matrix: confirmed, the solve ends and the point is copied out;
+// otherwise the check decision runs again without its termination test
+// (restart logic, next primal trial) and the loop goes on.
+template <typename T>
+void resolve_confirm(lp_problem *P)
+{
+    if (!P->hctl->confirm) return;
+    Dev<T> &d = P->dev<T>();
+    HIPT(launch_confirm<T>(d, P->geo, P->conf, P->hctl->cur, P->Nq, P->Nc, P->stream));
+    HIPT(launch_check_decide<T>(d, P->geo, P->Nq, P->Nc, P->stream));   // returns at once when confirmed
+    HIPT(launch_check_apply<T>(d, P->geo, P->stream));
+    get_ctl(P, d.ctl);
+}
+
 template <typename T>
 void copy_dev(lp_problem *P, T *dst, const T *src, int64_t len)
 {
@@ -777,6 +807,7 @@ int do_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit)
         c.check_every = P->opt.check_every;
         c.fixed_step = P->opt.fixed_step;
         c.final_status = LP_ITERATION_LIMIT;
+        c.confirm_on = P->mixed ? 1 : 0;
         put_ctl(P, c, d.ctl);
         HIPT(launch_spmv<T>(d.K, d.xb[0], d.Kxb[0], st));
         HIPT(launch_spmv<T>(d.KT, d.yb[0], d.KTyb[0], st));
@@ -805,6 +836,9 @@ int do_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit)
         c.check_every = P->opt.check_every;
         c.fixed_step = P->opt.fixed_step;
         c.fixed_eta = P->opt.fixed_eta;
+        c.confirm_on = P->mixed ? 1 : 0;
+        c.confirm = 0;
+        c.veto = 0;
         put_ctl(P, c, d.ctl);
         // the anchor's products (the state holds the anchor, not its products)
         HIPT(launch_spmv<T>(d.K, d.x0, d.Kx0, st));
@@ -820,6 +854,7 @@ int do_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit)
         put_ctl(P, c, d.ctl);
         run_check<T>(P);
         get_ctl(P, d.ctl);
+        resolve_confirm<T>(P);
     }
     const int W = std::max(1, P->opt.window);
     // kernel_timing: 0 none; 1 events around the products of every window;
@@ -874,6 +909,7 @@ int do_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit)
             for (int s = 0; s < W; ++s) launch_slot<T>(P, s, timed_now);
         }
         get_ctl(P, d.ctl);
+        resolve_confirm<T>(P);
         if (P->opt.verbose) trace_window(*P->hctl);
         if (timed_now && !P->hctl->done) {
             // every slot of a window that ended unfinished did real work
@@ -921,6 +957,7 @@ int do_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit)
                 put_ctl(P, c, d.ctl);
                 run_check<T>(P);
                 get_ctl(P, d.ctl);
+                resolve_confirm<T>(P);
                 break;
             }
         }

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <numeric>
@@ -167,6 +168,9 @@ int do_batch_load(lp_batch *P, const lp_csr *K, const double *const *c, const do
     }
     const int N = (int)P->Ntot, M = (int)P->Mtot;
     Arena &A = P->arena;
+    // test hook: PDLP_DEBUG_FILL_BYTE=<0..255> fills every device allocation of
+    // the batch with that byte, so a read of memory the load never sets shows
+    if (const char *fb = std::getenv("PDLP_DEBUG_FILL_BYTE")) A.fill = std::atoi(fb) & 255;
     int *d_rp = A.make<int>(M + 1), *d_ci = A.make<int>(nnz), *d_tp = A.make<int>(N + 1), *d_ti = A.make<int>(nnz);
     double *d_kv = A.make<double>(nnz), *d_tv = A.make<double>(nnz);
     double *d_c = A.make<double>(N), *d_l = A.make<double>(N), *d_u = A.make<double>(N), *d_q = A.make<double>(M);
@@ -362,6 +366,11 @@ int do_batch_load(lp_batch *P, const lp_csr *K, const double *const *c, const do
                 P->shape[which][0] = cand[best][0];
                 P->shape[which][1] = cand[best][1];
             }
+            // the trial vectors and products back to the zeros every iterate
+            // vector holds after the load
+            for (auto pv : {std::make_pair((void *)d.xb[1], N), std::make_pair((void *)d.yb[1], M),
+                            std::make_pair((void *)b.prodK, M), std::make_pair((void *)b.prodKT, N)})
+                HIPT(hipMemsetAsync(pv.first, 0, sizeof(T) * (size_t)std::max<int64_t>(pv.second, 1), st));
         }
     };
     if (P->mixed) setup(float{});

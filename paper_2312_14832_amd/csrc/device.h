@@ -359,15 +359,14 @@ __device__ inline void step_decision(Ctl *ctl, double dx2, double dy2, double in
     ctl->eta = eta_new;
 }
 
-// Termination (the three relative criteria on the unscaled problem), then
-// the ray certificates of infeasibility, candidate choice and restart
-// conditions 1-3 on KKT_omega (scaled problem), primal-weight update.  S
-// holds the 9 check sums of the current iterate then the 9 of the average,
-// R the 4 ray sums.  Called by one thread per LP.
-__device__ inline void check_decision(Ctl *ctl, const double *S, const double *R, double Nq, double Nc)
+// The termination quantities (unscaled) and KKT_omega (scaled) of the
+// current (z = 0) and the averaged (z = 1) iterate from their 9 check sums
+// each, stored in the controller; rel[z] is the relative KKT error (NaN if
+// any part is NaN).
+__device__ inline void check_quantities(Ctl *ctl, const double *S, double Nq, double Nc, double (&rel)[2],
+                                        double (&kkt)[2])
 {
     const double wp = pow(ctl->omega, ctl->kkt_p);
-    double rel[2], kkt[2];
     for (int z = 0; z < 2; ++z) {
         const double *e = S + 9 * z;
         const double pobj = e[6], dobj = e[2] + e[7], gap = dobj - pobj;
@@ -387,7 +386,38 @@ __device__ inline void check_decision(Ctl *ctl, const double *S, const double *R
         ctl->dobj[z] = dobj;
         ctl->kkt[z] = kkt[z];
     }
+}
+
+// End the solve with `status`, returning iterate `sel` (0 current, 1 average).
+__device__ inline void finish_ctl(Ctl *ctl, int status, int sel)
+{
+    ctl->status = status;
+    ctl->out_sel = sel;
+    ctl->copy_out = 1;
+    ctl->done = 1;
+    ctl->out_rel_p = ctl->rel_p[sel];
+    ctl->out_rel_d = ctl->rel_d[sel];
+    ctl->out_rel_g = ctl->rel_g[sel];
+    ctl->out_pobj = ctl->pobj[sel];
+    ctl->out_dobj = ctl->dobj[sel];
+}
+
+// Termination (the three relative criteria on the unscaled problem), then
+// the ray certificates of infeasibility, candidate choice and restart
+// conditions 1-3 on KKT_omega (scaled problem), primal-weight update.  S
+// holds the 9 check sums of the current iterate then the 9 of the average,
+// R the 4 ray sums.  With confirm_on (mixed precision) a passed termination
+// test only stops the loop with `confirm` set: the host redoes the sums with
+// FP64 products (confirm_decision) and either ends the solve or runs this
+// decision again with `veto`, which skips the termination test once.
+// Called by one thread per LP.
+__device__ inline void check_decision(Ctl *ctl, const double *S, const double *R, double Nq, double Nc)
+{
+    double rel[2], kkt[2];
+    check_quantities(ctl, S, Nq, Nc, rel, kkt);
     const int mode = ctl->mode;
+    const int veto = ctl->veto;
+    ctl->veto = 0;
     ctl->restart_to = 0;
     ctl->copy_out = 0;
     ctl->need_primal = 0;
@@ -397,24 +427,19 @@ __device__ inline void check_decision(Ctl *ctl, const double *S, const double *R
         ctl->need_primal = 1;
         return;
     }
-    auto finish = [&](int status, int sel) {
-        ctl->status = status;
-        ctl->out_sel = sel;
-        ctl->copy_out = 1;
-        ctl->done = 1;
-        ctl->out_rel_p = ctl->rel_p[sel];
-        ctl->out_rel_d = ctl->rel_d[sel];
-        ctl->out_rel_g = ctl->rel_g[sel];
-        ctl->out_pobj = ctl->pobj[sel];
-        ctl->out_dobj = ctl->dobj[sel];
-    };
     if (ctl->numerical || isnan(rel[0]) || isnan(rel[1])) {
-        finish(LP_NUMERICAL, 0);
+        finish_ctl(ctl, LP_NUMERICAL, 0);
         return;
     }
     const int use_avg = rel[1] < rel[0] ? 1 : 0;
-    if (rel[0] <= ctl->tol || rel[1] <= ctl->tol) {
-        finish(LP_OPTIMAL, use_avg);
+    if ((rel[0] <= ctl->tol || rel[1] <= ctl->tol) && !veto) {
+        if (ctl->confirm_on) {
+            ctl->confirm = 1;
+            ctl->conf_mode = mode;
+            ctl->done = 1;
+            return;
+        }
+        finish_ctl(ctl, LP_OPTIMAL, use_avg);
         return;
     }
     if (ctl->infeas_tol > 0.0) {
@@ -423,7 +448,7 @@ __device__ inline void check_decision(Ctl *ctl, const double *S, const double *R
         if (r[2] > 0.0 && sqrt(r[3]) <= ctl->infeas_tol * r[2]) st = LP_PRIMAL_INFEASIBLE;
         else if (r[0] < 0.0 && sqrt(r[1]) <= ctl->infeas_tol * -r[0]) st = LP_DUAL_INFEASIBLE;
         if (st) {
-            finish(st, 0);
+            finish_ctl(ctl, st, 0);
             ctl->out_sel = 2;   // the rays
             ctl->out_pobj = r[0];
             ctl->out_dobj = r[2];
@@ -433,7 +458,7 @@ __device__ inline void check_decision(Ctl *ctl, const double *S, const double *R
     int at_limit = 0;
     if (mode == MODE_FINAL) at_limit = ctl->final_status;
     else if (ctl->k >= ctl->max_iters) at_limit = LP_ITERATION_LIMIT;
-    if (at_limit) finish(at_limit, use_avg);
+    if (at_limit) finish_ctl(ctl, at_limit, use_avg);
     if (mode == MODE_CHECK && ctl->k % ctl->check_every == 0) {
         const int cand_cur = kkt[0] < kkt[1];
         const double kz = cand_cur ? kkt[0] : kkt[1];
@@ -459,6 +484,28 @@ __device__ inline void check_decision(Ctl *ctl, const double *S, const double *R
         }
     }
     ctl->need_primal = ctl->done ? 0 : 1;
+}
+
+// Mixed precision: the FP64 re-check of a passed termination test.  S holds
+// the 9 check sums of the current iterate and of the average computed with
+// FP64 products of the FP64 scaled matrix.  If either iterate meets the
+// criteria the solve ends OPTIMAL with the FP64 quantities; otherwise the
+// loop resumes and the check decision runs again without its termination
+// test (veto).  Called by one thread.
+__device__ inline void confirm_decision(Ctl *ctl, const double *S, double Nq, double Nc)
+{
+    double rel[2], kkt[2];
+    check_quantities(ctl, S, Nq, Nc, rel, kkt);
+    ctl->confirm = 0;
+    ctl->confirms += 1;
+    ctl->mode = ctl->conf_mode;
+    const int use_avg = rel[1] < rel[0] ? 1 : 0;
+    if (!isnan(rel[0]) && !isnan(rel[1]) && (rel[0] <= ctl->tol || rel[1] <= ctl->tol)) {
+        finish_ctl(ctl, LP_OPTIMAL, use_avg);
+        return;
+    }
+    ctl->done = 0;
+    ctl->veto = 1;
 }
 
 // restart / output bookkeeping on column j (current buffer c):

@@ -29,12 +29,17 @@ struct Arena {
     std::vector<void *> ptrs;
     std::vector<int64_t> sizes;
     int64_t bytes = 0;
+    int fill = -1;   // >= 0: every new allocation is filled with this byte (a test hook for reads of unset memory)
     void *alloc(size_t n)
     {
         void *p = nullptr;
         if (n == 0) n = 8;
         n = (n + 255) & ~(size_t)255;
         HIPT(hipMalloc(&p, n));
+        if (fill >= 0) {
+            HIPT(hipMemset(p, fill, n));
+            HIPT(hipDeviceSynchronize());
+        }
         ptrs.push_back(p);
         sizes.push_back((int64_t)n);
         bytes += (int64_t)n;

@@ -88,7 +88,11 @@ struct Ctl {
     int copy_out;      // the apply kernel copies the chosen point to the output buffers
     int need_primal;   // the apply kernel computes the next primal trial
     int numerical;     // NaN met in the step-size test
-    int pad;
+    int confirm_on;    // mixed precision: a passed termination test is re-checked with FP64 products
+    int confirm;       // such a re-check is pending (the loop has stopped for it)
+    int conf_mode;     // the check mode that passed the test
+    int veto;          // run the next check decision without its termination test (re-check failed)
+    long long confirms;  // FP64 re-checks made
 };
 
 template <typename T>
@@ -109,6 +113,18 @@ struct Dev {
     double *part_check;        // [kMaxGrid * kCheckSums]
     double *part_ray;          // [kMaxGrid * kRaySums] (a pass of its own: fewer live registers)
     Ctl *ctl;
+};
+
+// Mixed precision's FP64 re-check of the termination test: the scaled
+// matrix and its transpose in plain CSR with FP64 values and the scaled
+// vectors in FP64 (kept from the load-time scaling), the products of the
+// current iterate and the average, and the partial sums.
+struct Conf64 {
+    const int *rp, *ci, *tp, *ti;
+    const double *kv, *tv;
+    const double *cs, *ls, *us, *qs;   // scaled c, l, u, q in FP64
+    double *kx[2], *kty[2];   // [m], [n]: current, average
+    double *part;             // [kMaxGrid * kCheckSums]
 };
 
 struct Geo {
@@ -167,6 +183,9 @@ hipError_t launch_seg_absmax(const double *a, const int64_t *off, int B, double 
 // launchers (kernels.hip); each returns the hipError_t of the launch
 // per-device address of the fixed scratch array of lp_spmv_noalloc (noalloc.hip)
 hipError_t noalloc_scratch(void **ptr);
+template <typename T>
+hipError_t launch_confirm(const Dev<T> &d, const Geo &g, const Conf64 &cf, int cur, double Nq, double Nc,
+                          hipStream_t s);
 template <typename T> hipError_t launch_partial_K(const Dev<T> &d, hipStream_t s);
 template <typename T> hipError_t launch_partial_KT(const Dev<T> &d, hipStream_t s);
 template <typename T> hipError_t launch_dual(const Dev<T> &d, const Geo &g, hipStream_t s);

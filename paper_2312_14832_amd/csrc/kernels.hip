@@ -27,6 +27,7 @@
 // a single workgroup sums the partials in a fixed order.  No float atomics.
 #include "device.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace pdlp {
@@ -175,6 +176,105 @@ __global__ __launch_bounds__(kBlock) void k_check_apply(Dev<T> d, int vb_n, int 
     }
     double v[1] = {dx2};
     block_store_partials<1>(v, d.part_primal);
+}
+
+// Mixed precision's FP64 re-check: out = K~ x with the FP64 scaled matrix
+// in plain CSR and an iterate of either precision, a wavefront per row
+// (lanes striding, FP64 accumulation, a butterfly combining them).
+template <typename TX>
+__global__ __launch_bounds__(kBlock) void k_csr64(const int *__restrict__ rp, const int *__restrict__ ci,
+                                                  const double *__restrict__ v, const TX *__restrict__ x,
+                                                  double *__restrict__ out, int rows)
+{
+    const int lane = (int)threadIdx.x & 63;
+    const int nw = (int)(gridDim.x * kBlock) >> 6;
+    for (int r = (int)((blockIdx.x * kBlock + threadIdx.x) >> 6); r < rows; r += nw) {
+        double acc = 0.0;
+        const int e = rp[r + 1];
+        for (int p = rp[r] + lane; p < e; p += 64) acc += v[p] * (double)x[ci[p]];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (lane == 0) out[r] = acc;
+    }
+}
+
+// The 9 check sums of one iterate (same order as row_sums / col_sums) with
+// FP64 products and the FP64 scaled data c~, l~, u~, q~ in place of their
+// FP32 copies.
+template <typename T>
+__device__ __forceinline__ void conf_row(const Conf64 &cf, const double *Dr, int i, int m1, const T *y, const T *y0,
+                                         const double *kx, double *s)
+{
+    const double k = kx[i], q = cf.qs[i];
+    double r = k - q;
+    if (i >= m1) {
+        const double t = q - k;
+        r = t > 0.0 ? t : 0.0;
+    }
+    const double ru = r * Dr[i];
+    s[0] += ru * ru;
+    s[1] += r * r;
+    const double yi = (double)y[i];
+    s[2] += q * yi;
+    const double dd = yi - (double)y0[i];
+    s[3] += dd * dd;
+}
+
+template <typename T>
+__device__ __forceinline__ void conf_col(const Conf64 &cf, const double *Dc, int j, const T *x, const T *x0,
+                                         const double *kty, double *s)
+{
+    const double cj = cf.cs[j], lj = cf.ls[j], uj = cf.us[j];
+    const bool lf = isfinite(lj), uf = isfinite(uj);
+    const double g = cj - kty[j];
+    const double lam = proj_lambda(g, lf, uf);
+    const double rd = g - lam;
+    const double rdu = rd * Dc[j];
+    s[4] += rdu * rdu;
+    s[5] += rd * rd;
+    const double xj = (double)x[j];
+    s[6] += cj * xj;
+    double b = 0.0;
+    if (lf && lam > 0.0) b += lj * lam;
+    if (uf && lam < 0.0) b += uj * lam;
+    s[7] += b;
+    const double dd = xj - (double)x0[j];
+    s[8] += dd * dd;
+}
+
+// The 18 check sums of the current iterate (buffer cur) and the average,
+// all in FP64 (products, data, accumulation) from the stored iterates.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_confirm_sums(Dev<T> d, Conf64 cf, int cur, int vb_n, int vb_m)
+{
+    const T *x = pick(d.xb, cur), *y = pick(d.yb, cur);
+    double s[kCheckSums];
+#pragma unroll
+    for (int i = 0; i < kCheckSums; ++i) s[i] = 0.0;
+    for (int vb = blockIdx.x; vb < vb_n + vb_m; vb += gridDim.x) {
+        if (vb < vb_n) {
+            const int j = vb * kBlock + (int)threadIdx.x;
+            if (j < d.n) {
+                conf_col(cf, d.Dc, j, x, (const T *)d.x0, cf.kty[0], s);
+                conf_col(cf, d.Dc, j, (const T *)d.xa, (const T *)d.x0, cf.kty[1], s + 9);
+            }
+        } else {
+            const int i = (vb - vb_n) * kBlock + (int)threadIdx.x;
+            if (i < d.m) {
+                conf_row(cf, d.Dr, i, d.m1, y, (const T *)d.y0, cf.kx[0], s);
+                conf_row(cf, d.Dr, i, d.m1, (const T *)d.ya, (const T *)d.y0, cf.kx[1], s + 9);
+            }
+        }
+    }
+    block_store_partials<kCheckSums>(s, cf.part);
+}
+
+__global__ __launch_bounds__(kBlock) void k_confirm_decide(Ctl *ctl, const double *part, int np, double Nq, double Nc)
+{
+    double S[kCheckSums];
+    block_sum_partials<kCheckSums>(part, np, S);
+    if (threadIdx.x != 0) return;
+    confirm_decision(ctl, S, Nq, Nc);
 }
 
 template <typename T, bool LONG>
@@ -481,6 +581,31 @@ hipError_t launch_check_apply(const Dev<T> &d, const Geo &g, hipStream_t s)
     return hipGetLastError();
 }
 
+// The FP64 re-check of mixed precision's termination test: the four
+// products of the current iterate (buffer cur, read from the controller by
+// the host that stopped for the re-check) and the average, their check sums,
+// and the decision.
+template <typename T>
+hipError_t launch_confirm(const Dev<T> &d, const Geo &g, const Conf64 &cf, int cur, double Nq, double Nc,
+                          hipStream_t s)
+{
+    auto waves = [](int rows) { return dim3((unsigned)std::max(1, std::min((rows + 3) / 4, 8192))); };
+    const T *x = cur ? d.xb[1] : d.xb[0], *y = cur ? d.yb[1] : d.yb[0];
+    if (d.m > 0) {
+        hipLaunchKernelGGL(k_csr64<T>, waves(d.m), dim3(kBlock), 0, s, cf.rp, cf.ci, cf.kv, x, cf.kx[0], d.m);
+        hipLaunchKernelGGL(k_csr64<T>, waves(d.m), dim3(kBlock), 0, s, cf.rp, cf.ci, cf.kv, (const T *)d.xa, cf.kx[1],
+                           d.m);
+    }
+    if (d.n > 0) {
+        hipLaunchKernelGGL(k_csr64<T>, waves(d.n), dim3(kBlock), 0, s, cf.tp, cf.ti, cf.tv, y, cf.kty[0], d.n);
+        hipLaunchKernelGGL(k_csr64<T>, waves(d.n), dim3(kBlock), 0, s, cf.tp, cf.ti, cf.tv, (const T *)d.ya,
+                           cf.kty[1], d.n);
+    }
+    hipLaunchKernelGGL(k_confirm_sums<T>, dim3(g.grid), dim3(kBlock), 0, s, d, cf, cur, g.vb_n, g.vb_m);
+    hipLaunchKernelGGL(k_confirm_decide, dim3(1), dim3(kBlock), 0, s, d.ctl, (const double *)cf.part, g.grid, Nq, Nc);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_spmv(const Sliced<T> &P, const T *in, T *out, hipStream_t s)
 {
@@ -671,6 +796,8 @@ hipError_t scale_csr_pair(const int *rp, const int *ci, double *kv, int m, const
     template hipError_t launch_check_decide<T>(const Dev<T> &, const Geo &, double, double, hipStream_t);          \
     template hipError_t launch_check_apply<T>(const Dev<T> &, const Geo &, hipStream_t);                           \
     template hipError_t launch_spmv<T>(const Sliced<T> &, const T *, T *, hipStream_t);                            \
+    template hipError_t launch_confirm<T>(const Dev<T> &, const Geo &, const Conf64 &, int, double, double,       \
+                                          hipStream_t);                                                           \
     template hipError_t launch_gather_values<T>(const double *, const int *, T *, int64_t, hipStream_t);           \
     template hipError_t launch_start<T>(const Dev<T> &, const double *, const double *, int, hipStream_t);         \
     template hipError_t launch_result<T>(const Dev<T> &, double *, double *, double *, hipStream_t);               \

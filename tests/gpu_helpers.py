@@ -96,3 +96,56 @@ def perturbed(raw, rel, seed):
 def gpu_state(lpmod, p):
     """The GPU handle's state as a dict (same layout as the oracle's)."""
     return lpmod.unpack_state(p.get_state(), p.n, p.m)
+
+
+# The measured objective bar.  The iteration is chaotic at the 1e-4 scale
+# (restart decisions hinge on comparisons that ulp-level differences can
+# flip), so the GPU's final point is one more sample of where the method ends
+# when its arithmetic differs by rounding.  OBJ_RUNS oracle runs whose state
+# after one step is perturbed entrywise at the arithmetic's unit roundoff give
+# the spread of those endpoints; the GPU's objective must lie within OBJ_C
+# times the largest deviation seen.  Measured on tiny_lp seeds 0-7 with 80
+# perturbed runs each: a held-out run exceeds 10x the largest of 24 others in
+# 0.07% of draws (the deviations are heavy-tailed: median ~1e-6, largest ~5e-5
+# relative), against 2% for 10x the largest of 8.
+OBJ_RUNS = 24
+OBJ_C = 10.0
+
+
+def objective_spread(oracle_mod, data, tol, rel=1e-15, runs=OBJ_RUNS, max_iters=200000, **okw):
+    """The oracle's own solve at tol (its info dict), the largest
+    |pobj_r - pobj| over `runs` solves started from its one-step state with
+    every vector entry scaled by (1 + rel N(0,1)), and the bar derived from
+    it: OBJ_C times that deviation, floored at the rounding of the objective
+    itself for LPs whose endpoint does not move (1e-12 relative, or 64 rel
+    times the size of the terms of c'x, sum |c_j x_j|, when the iterates are
+    stored at unit roundoff rel)."""
+    o = oracle_mod.Oracle(data, **okw)
+    xo, _, _, io = o.solve(tol, max_iters)
+    o1 = oracle_mod.Oracle(data, **okw)
+    o1.solve(1e-30, 1)
+    raw1 = o1.get_state_raw()
+    dev = 0.0
+    for r in range(runs):
+        q = oracle_mod.Oracle(data, **okw)
+        q.set_state_raw(perturbed(raw1, rel, 1000 + r))
+        _, _, _, iq = q.solve(tol, max_iters)
+        dev = max(dev, abs(iq["pobj"] - io["pobj"]))
+    floor = max(1e-12 * abs(io["pobj"]), 64.0 * rel * float(np.sum(np.abs(data.c * xo))))
+    return io, dev, OBJ_C * max(dev, floor)
+
+
+def free_running_band(oracle_mod, data, k, so, rel=1e-15, runs=3):
+    """Largest state difference (vec_diff) from the oracle's k-step state `so`
+    of `runs` oracle runs of k steps whose one-step state was perturbed by
+    rel: how far ulp-level differences carry by step k."""
+    o1 = oracle_mod.Oracle(data)
+    o1.solve(1e-30, 1)
+    raw1 = o1.get_state_raw()
+    band = 0.0
+    for r in range(runs):
+        q = oracle_mod.Oracle(data)
+        q.set_state_raw(perturbed(raw1, rel, r))
+        q.solve(1e-30, k)
+        band = max(band, vec_diff(q.get_state(), so)[0])
+    return band

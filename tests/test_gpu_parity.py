@@ -5,10 +5,9 @@ import numpy as np
 import pytest
 
 from paper_2312_14832_amd import gen
-from lp_helpers import (check_restart_golden_state, load_golden, objective_band, restart_golden_lp,
-                        restart_golden_state)
-from gpu_helpers import (U64, gpu_state, ints_equal, kkt_scale, perturbed, say, scalar_diff, state_diff,
-                         step_condition, vec_diff)
+from lp_helpers import check_restart_golden_state, load_golden, restart_golden_lp, restart_golden_state
+from gpu_helpers import (U64, gpu_state, ints_equal, kkt_scale, objective_spread, perturbed, say,
+                         scalar_diff, state_diff, step_condition, vec_diff)
 
 pytestmark = pytest.mark.gpu
 
@@ -188,27 +187,27 @@ def test_free_running_trajectory(lpmod, oracle_mod, seed):
 @pytest.mark.parametrize("seed", [0, 1, 2, 3, 4])
 def test_final_result_at_1e4(lpmod, oracle_mod, seed):
     """Solve to rel KKT 1e-4.  The GPU's point, unscaled and evaluated by the
-    oracle on the original data, meets the three criteria at 1e-4; its
-    objective is inside the first-order band in which two points meeting the
-    criteria at 1e-4 can lie (lp_helpers.objective_band): a chaotic iteration
-    ends at a different 1e-4 point for ulp-different arithmetic, and the
-    oracle differs from itself by up to ~3e-5 relative under 1e-15
-    perturbations."""
+    oracle on the original data, meets the three criteria at 1e-4.  The
+    iteration is chaotic at that scale (ulp-different arithmetic flips restart
+    decisions and ends at a different 1e-4 point), so the objective is held to
+    the measured bar: within OBJ_C times the largest deviation of 24 oracle
+    runs perturbed by 1e-15 (gpu_helpers.objective_spread)."""
     say(f"case final seed={seed}")
     data = gen.tiny_lp(seed)
     p = lpmod.Problem(data)
     info = p.solve(1e-4, 200000)
     assert info["status"] == "OPTIMAL"
     o = oracle_mod.Oracle(data)
-    _, _, _, io = o.solve(1e-4, 200000)
+    io, dev, bar = objective_spread(oracle_mod, data, 1e-4)
     x, y, lam, _ = p.result()
     ev = o.eval_unscaled(x, y)
     assert ev["rel_kkt"] <= 1e-4 * (1 + 1e-6)
     assert ev["pobj"] == pytest.approx(info["pobj"], rel=1e-12)
     assert ev["dobj"] == pytest.approx(info["dobj"], rel=1e-9, abs=1e-9)
     assert ev["bound_viol"] <= 1e-12 * (1 + np.abs(data.x0).max()) and ev["sign_viol"] == 0.0
-    xo, yo, _, _ = o.result()
-    assert abs(info["pobj"] - io["pobj"]) <= objective_band(1e-4, data, xo, yo, io["pobj"], io["dobj"])
+    say(f"  gpu pobj {info['pobj']:.12g} oracle {io['pobj']:.12g} diff {abs(info['pobj'] - io['pobj']):.3e} "
+        f"oracle spread {dev:.3e}")
+    assert abs(info["pobj"] - io["pobj"]) <= bar, (info["pobj"], io["pobj"], dev)
     assert 0.5 * io["iterations"] <= info["iterations"] <= 2.0 * io["iterations"]
     fl, fu = np.isfinite(data.l), np.isfinite(data.u)
     assert np.all(lam[~fl & ~fu] == 0) and np.all(lam[fl & ~fu] >= 0) and np.all(lam[~fl & fu] <= 0)
