@@ -297,6 +297,48 @@ const char *lp_strerror(int code);
 const char *lp_last_error(const lp_problem *P);
 
 /* ------------------------------------------------------------------------
+ * Batched solves of one family: count <= 256 LPs that share the matrix K
+ * (pattern and values) and the number of equality rows m1, each with its own
+ * c, q, l, u (a parametric family, e.g. the training set of the warm-start
+ * network).  The method per instance is exactly the one lp_solve runs; the
+ * scaling depends on K alone, so every instance gets the same factors.  The
+ * iterates of all instances are interleaved on the device, so each sparse
+ * product of an iteration (K x and K'y, Sec. 2 "Restarted PDHG") reads K
+ * once for all instances (an SpMM) instead of once per instance.  Host
+ * pointers only; the handle allocates its own device memory (ptr_kind =
+ * LP_DEVICE, a workspace or presolve is LP_ERR_ARG).
+ * ------------------------------------------------------------------------ */
+typedef struct lp_shared lp_shared;   /* opaque; owned by the library */
+
+/* K as in lp_load (validated once); c[i], q[i], l[i], u[i] of instance i,
+ * validated as in lp_load (l[i] or u[i] may point to the same array for every
+ * instance).  Errors: LP_ERR_ARG (count outside 1..256, NULL, unsupported
+ * options), the lp_load codes of K and of the first failing instance,
+ * LP_ERR_TOO_LARGE when (n + 1) or (m + 1) times count rounded up to a power
+ * of two reaches 2^30. */
+int lp_shared_load(lp_shared **S, int32_t count, const lp_csr *K, const double *const *c, const double *const *q,
+                   const double *const *l, const double *const *u, int64_t m1, const lp_options *opt);
+/* Start of instance i for the next lp_shared_solve, as lp_set_start (x0[n],
+ * y0[m] unscaled, either NULL = projected 0), with primal weight omega
+ * (<= 0: |c~|/|q~|), as lp_set_start_weight.  Cancels states set by
+ * lp_shared_set_state.  Errors: LP_ERR_ARG for a bad i or a NaN/inf omega. */
+int lp_shared_set_start(lp_shared *S, int32_t i, const double *x0, const double *y0, double omega);
+/* Solve every instance from its start (or resume, when lp_shared_set_state
+ * was called for every instance since the last solve) until each is optimal
+ * at tol, reaches max_iters accepted steps, or the time limit ends the call. */
+int lp_shared_solve(lp_shared *S, double tol, int64_t max_iters, double time_limit_s);
+/* Result of instance i as lp_result; info->seconds is the time into the last
+ * lp_shared_solve at which the host saw instance i finish.  LP_ERR_STATE
+ * before the first solve. */
+int lp_shared_result(const lp_shared *S, int32_t i, double *x, double *y, double *lambda, lp_info *info);
+/* State of instance i in the layout of lp_get_state; set_state restores it. */
+int lp_shared_get_state(const lp_shared *S, int32_t i, double *buf, int64_t *len);
+int lp_shared_set_state(lp_shared *S, int32_t i, const double *buf, int64_t len);
+int lp_shared_device_bytes(const lp_shared *S, int64_t *bytes);
+void lp_shared_free(lp_shared *S);
+const char *lp_shared_last_error(const lp_shared *S);
+
+/* ------------------------------------------------------------------------
  * Learned warm start for a parametric LP family (fixed K; b, h, c vary).
  * A network maps a standardized sketch of an instance's perturbation to a
  * primal-dual start point for lp_set_start: `layers` ReLU layers of width

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdlp_amd.so")
-SOURCES = ["kernels.hip", "batch.hip", "mlp.hip", "noalloc.hip", "host_util.cpp", "presolve.cpp", "api.cpp", "batch_api.cpp"]
+SOURCES = ["kernels.hip", "batch.hip", "mlp.hip", "noalloc.hip", "shared.hip", "host_util.cpp", "presolve.cpp", "api.cpp", "batch_api.cpp", "shared_api.cpp"]
 ARCH = os.environ.get("PDLP_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -63,9 +63,10 @@ __device__ __forceinline__ void block_store_partials(double (&v)[NV], double *ou
 }
 
 // Sum np partials of NV values each inside one workgroup; every thread gets
-// the same (deterministic) totals.
+// the same (deterministic) totals.  Partial idx starts at part[idx * stride * NV]
+// (stride > 1: the partials of one instance among interleaved ones).
 template <int NV>
-__device__ __forceinline__ void block_sum_partials(const double *part, int np, double (&out)[NV])
+__device__ __forceinline__ void block_sum_partials(const double *part, int np, double (&out)[NV], int stride = 1)
 {
     __shared__ double sh[kBlock / 64][NV];
     double acc[NV];
@@ -80,7 +81,7 @@ __device__ __forceinline__ void block_sum_partials(const double *part, int np, d
         for (int u = 0; u < U; ++u) {
             const int idx = b + u * kBlock;
 #pragma unroll
-            for (int i = 0; i < NV; ++i) t[u][i] = idx < np ? part[(size_t)idx * NV + i] : 0.0;
+            for (int i = 0; i < NV; ++i) t[u][i] = idx < np ? part[(size_t)idx * stride * NV + i] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -102,6 +103,46 @@ __device__ __forceinline__ void block_sum_partials(const double *part, int np, d
 #pragma unroll
     for (int i = 0; i < NV; ++i) out[i] = ((sh[0][i] + sh[1][i]) + sh[2][i]) + sh[3][i];
     __syncthreads();
+}
+
+// Per-instance partials of a workgroup whose thread t always works for
+// instance t % Bp (Bp a power of two <= kBlock; interleaved vectors of a
+// shared-matrix batch): the values of the threads of one instance are added
+// in a fixed order (a butterfly over the lanes of a wavefront, then the
+// wavefronts in order) and stored at out[(blockIdx.x * Bp + b) * NV + k].
+// With only_checking set, instance b's slot is written only while
+// only_checking[b].mode != MODE_NONE.  Every thread must call it.
+template <int NV>
+__device__ __forceinline__ void store_inst_partials(const double (&v)[NV], int Bp, double *out,
+                                                    const Ctl *only_checking = nullptr)
+{
+    __shared__ double sh[kBlock / 64][64];
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+    const int b = (int)threadIdx.x;
+    const bool writer = b < Bp && (!only_checking || only_checking[b].mode != MODE_NONE);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double a = v[k];
+        for (int off = 32; off >= Bp; off >>= 1) a += __shfl_xor(a, off);
+        sh[wave][lane] = a;
+        __syncthreads();
+        if (writer) {
+            double t = 0.0;
+            if (Bp <= 64) {
+                // every wavefront holds instance b's sum in lane b
+                t = ((sh[0][b] + sh[1][b]) + sh[2][b]) + sh[3][b];
+            } else {
+                // wavefront w serves instances (64 w .. 64 w + 63) mod Bp
+#pragma unroll
+                for (int w = 0; w < kBlock / 64; ++w) {
+                    const int base = (w * 64) & (Bp - 1);
+                    if (b >= base && b < base + 64) t += sh[w][b - base];
+                }
+            }
+            out[((size_t)blockIdx.x * Bp + b) * NV + k] = t;
+        }
+        __syncthreads();
+    }
 }
 
 // ----------------------------------------------------------------------------

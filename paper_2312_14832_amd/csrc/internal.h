@@ -165,6 +165,45 @@ struct BDev {
     int *gate;                // 1 while some instance is in a check this slot
 };
 
+// Batched solves of one family: every instance shares the matrix K (pattern
+// and values) and has its own c, q, l, u.  Vectors are interleaved, [row][Bp]
+// with the instance fastest (Bp = the instance count rounded up to a power
+// of two, at most kBlock; padded instances are inert and finished from the
+// start), so a product reads K once for every instance and each gather of
+// x[j][0..Bp) is a contiguous run.  d holds the interleaved vectors with
+// d.n = n Bp, d.m = m Bp, d.m1 = m1 Bp and the scaling factors replicated per
+// instance, so the element functions of the single-LP path apply unchanged
+// with element e = row * Bp + instance.
+template <typename T>
+struct SDev {
+    Dev<T> d;
+    int B, Bp, lgB;           // instances, padded count, log2(Bp)
+    int n, m;                 // columns and rows of K (per instance)
+    const int *krp, *kci;     // K~  (m x n) CSR, shared
+    const T *kv;
+    const int *trp, *tci;     // K~' (n x m) CSR, shared
+    const T *tv;
+    int grid;                 // workgroups of the update / check / apply walks (the same walk in each)
+    int grid_m;               // workgroups of the dual kernel
+    const double *Nq, *Nc;    // [Bp] |q|, |c| of each instance's unscaled data
+    Ctl *ctl;                 // [Bp]
+    int *gate;                // 1 while some instance is in a check this slot
+};
+
+template <typename T> hipError_t launch_shared_slot(const SDev<T> &S, hipStream_t s);
+// the check kernels alone (ungated: start, resume and final checks)
+template <typename T> hipError_t launch_shared_check(const SDev<T> &S, int gated, hipStream_t s);
+template <typename T> hipError_t launch_shared_apply(const SDev<T> &S, hipStream_t s);
+// out = K~ in (which = 0) or K~' in (which = 1) for every instance, interleaved
+template <typename T> hipError_t launch_shared_product(const SDev<T> &S, int which, const T *in, T *out,
+                                                       hipStream_t s);
+// instance b of an interleaved vector of `rows` rows to / from a plain FP64 vector
+template <typename T> hipError_t launch_shared_extract(const T *src, int lgB, int b, double *dst, int rows,
+                                                       hipStream_t s);
+template <typename T> hipError_t launch_shared_insert(const double *src, int lgB, int b, T *dst, int rows,
+                                                      hipStream_t s);
+hipError_t launch_shared_set_final(Ctl *ctl, int Bp, int status, hipStream_t s);
+
 template <typename T> hipError_t launch_batch_product(const BDev<T> &b, int which, hipStream_t s);
 template <typename T> hipError_t launch_batch_product_plain(const BDev<T> &b, int which, const T *in, T *out,
                                                             hipStream_t s);

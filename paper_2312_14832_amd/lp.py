@@ -29,7 +29,9 @@ EXPORTS = ["lp_default_options", "lp_workspace_size", "lp_load", "lp_set_start",
            "lp_strerror", "lp_last_error", "lp_batch_load", "lp_batch_solve", "lp_batch_result",
            "lp_batch_get_state", "lp_batch_set_state", "lp_batch_device_bytes", "lp_batch_layout_blocks",
            "lp_batch_free",
-           "lp_batch_last_error"]
+           "lp_batch_last_error", "lp_shared_load", "lp_shared_set_start", "lp_shared_solve", "lp_shared_result",
+           "lp_shared_get_state", "lp_shared_set_state", "lp_shared_device_bytes", "lp_shared_free",
+           "lp_shared_last_error"]
 
 
 class LPCsr(C.Structure):
@@ -105,6 +107,18 @@ def library():
         L.lp_batch_free.restype = None
         L.lp_batch_last_error.argtypes = [C.c_void_p]
         L.lp_batch_last_error.restype = C.c_char_p
+        L.lp_shared_load.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(LPCsr), PP, PP, PP, PP, C.c_int64,
+                                     C.POINTER(LPOptions)]
+        L.lp_shared_set_start.argtypes = [C.c_void_p, C.c_int32, dp, dp, C.c_double]
+        L.lp_shared_solve.argtypes = [C.c_void_p, C.c_double, C.c_int64, C.c_double]
+        L.lp_shared_result.argtypes = [C.c_void_p, C.c_int32, dp, dp, dp, C.POINTER(LPInfo)]
+        L.lp_shared_get_state.argtypes = [C.c_void_p, C.c_int32, dp, C.POINTER(C.c_int64)]
+        L.lp_shared_set_state.argtypes = [C.c_void_p, C.c_int32, dp, C.c_int64]
+        L.lp_shared_device_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
+        L.lp_shared_free.argtypes = [C.c_void_p]
+        L.lp_shared_free.restype = None
+        L.lp_shared_last_error.argtypes = [C.c_void_p]
+        L.lp_shared_last_error.restype = C.c_char_p
         _lib = L
     return _lib
 
@@ -409,4 +423,84 @@ class Batch:
     def device_bytes(self):
         b = C.c_int64()
         self._check(library().lp_batch_device_bytes(self.h, C.byref(b)))
+        return b.value
+
+
+class Shared:
+    """A batch of one family: instances that share K (lp_shared_*).  `lps`
+    are LPData with the same row_ptr / col / val and m1; their c, q, l, u
+    are each instance's own."""
+
+    def __init__(self, lps, **options):
+        L = library()
+        self.h = None
+        self.count = len(lps)
+        p0 = lps[0]
+        self.n, self.m = int(p0.n), int(p0.m)
+        self.opt = default_options(**options)
+        rp = np.ascontiguousarray(p0.row_ptr, np.int32)
+        ci = np.ascontiguousarray(p0.col, np.int32)
+        v = _f64(p0.val)
+        self._keep = [rp, ci, v]
+        K = LPCsr(self.m, self.n, int(rp[-1]), rp.ctypes.data_as(C.POINTER(C.c_int32)),
+                  ci.ctypes.data_as(C.POINTER(C.c_int32)), _dp(v))
+        arr = {k: (C.POINTER(C.c_double) * self.count)() for k in "cqlu"}
+        for i, p in enumerate(lps):
+            for k in "cqlu":
+                a = _f64(getattr(p, k))
+                self._keep.append(a)
+                arr[k][i] = _dp(a)
+        h = C.c_void_p()
+        rc = L.lp_shared_load(C.byref(h), self.count, C.byref(K), arr["c"], arr["q"], arr["l"], arr["u"],
+                              int(p0.m1), C.byref(self.opt))
+        self._keep = None
+        if rc != 0:
+            raise LPError(rc, L.lp_strerror(rc).decode())
+        self.h = h
+
+    def _check(self, rc):
+        if rc != 0:
+            raise LPError(rc, library().lp_shared_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.lp_shared_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def set_start(self, i, x=None, y=None, omega=0.0):
+        xs = None if x is None else _f64(x)
+        ys = None if y is None else _f64(y)
+        self._check(library().lp_shared_set_start(self.h, int(i), _dp(xs), _dp(ys), float(omega)))
+
+    def solve(self, tol=1e-4, max_iters=10**7, time_limit=0.0):
+        self._check(library().lp_shared_solve(self.h, float(tol), int(max_iters), float(time_limit)))
+
+    def info(self, i):
+        inf = LPInfo()
+        self._check(library().lp_shared_result(self.h, int(i), None, None, None, C.byref(inf)))
+        return _info_dict(inf)
+
+    def result(self, i):
+        x = np.empty(self.n); y = np.empty(self.m); lam = np.empty(self.n)
+        inf = LPInfo()
+        self._check(library().lp_shared_result(self.h, int(i), _dp(x), _dp(y), _dp(lam), C.byref(inf)))
+        return x, y, lam, _info_dict(inf)
+
+    def get_state(self, i):
+        ln = C.c_int64()
+        self._check(library().lp_shared_get_state(self.h, int(i), None, C.byref(ln)))
+        buf = np.empty(ln.value)
+        self._check(library().lp_shared_get_state(self.h, int(i), _dp(buf), C.byref(ln)))
+        return buf
+
+    def set_state(self, i, buf):
+        buf = _f64(buf)
+        self._check(library().lp_shared_set_state(self.h, int(i), _dp(buf), buf.size))
+
+    def device_bytes(self):
+        b = C.c_int64()
+        self._check(library().lp_shared_device_bytes(self.h, C.byref(b)))
         return b.value
