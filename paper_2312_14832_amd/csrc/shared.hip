@@ -14,8 +14,39 @@
 
 namespace pdlp {
 
+// One row of the SpMM for instance b: sum over the row's entries [rs, re)
+// of v[p] x[ci[p]][b], in entry order.  Eight entries at a time in three
+// straight-line phases (indices and values, then the eight gathers, then the
+// products), so eight gathers of the row are in flight at once; slots past
+// the row's end re-read its last entry and are masked out of the sum.
+template <typename T>
+__device__ __forceinline__ T spmm_row(const int *__restrict__ ci, const T *__restrict__ v, const T *__restrict__ x,
+                                      int rs, int re, int lgB, int b)
+{
+    constexpr int U = 8;
+    T acc = T(0);
+    for (int p = rs; p < re; p += U) {
+        int c[U];
+        T a[U], g[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = min(p + u, re - 1);
+            c[u] = ci[t];
+            a[u] = v[t];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) g[u] = x[((size_t)c[u] << lgB) + b];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (p + u < re) acc += a[u] * g[u];
+    }
+    return acc;
+}
+
 // K~ x' for every instance fused with the dual step: element e = i * Bp + b.
-// Workgroup 0 lowers the check gate (this slot's step decisions raise it).
+// The step's own operands are loaded before the row's product so their
+// latency overlaps the gathers.  Workgroup 0 lowers the check gate (this
+// slot's step decisions raise it).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void sk_dual(SDev<T> S)
 {
@@ -27,18 +58,23 @@ __global__ __launch_bounds__(kBlock) void sk_dual(SDev<T> S)
     if (!ctl->done) {
         const int c = ctl->cur;
         const T *x = pick(d.xb, c ^ 1);
-        DualEpi<T> epi{pick(d.yb, c), pick(d.Kxb, c), d.qs, pick(d.yb, c ^ 1), pick(d.Kxb, c ^ 1), d.m1,
-                       (T)(ctl->eta * ctl->omega), 0.0, 0.0};
+        const T *y = pick(d.yb, c), *kx = pick(d.Kxb, c);
+        T *yn = pick(d.yb, c ^ 1), *kxn = pick(d.Kxb, c ^ 1);
+        const T sigma = (T)(ctl->eta * ctl->omega);
         const int total = S.m << S.lgB;
         for (int e = (int)(blockIdx.x * kBlock + threadIdx.x); e < total; e += (int)(gridDim.x * kBlock)) {
             const int i = e >> S.lgB;
-            const int p1 = S.krp[i + 1];
-            T acc = T(0);
-            for (int p = S.krp[i]; p < p1; ++p) acc += S.kv[p] * x[((size_t)S.kci[p] << S.lgB) + b];
-            epi(e, acc);
+            const T yo = y[e], ko = kx[e], qi = d.qs[e];
+            const T s = spmm_row(S.kci, S.kv, x, S.krp[i], S.krp[i + 1], S.lgB, b);
+            // the dual step of DualEpi
+            T val = yo + sigma * (qi - T(2) * s + ko);
+            if (e >= d.m1 && val < T(0)) val = T(0);
+            yn[e] = val;
+            kxn[e] = s;
+            const double dd = (double)val - (double)yo;
+            v[0] += dd * dd;
+            v[1] += dd * ((double)s - (double)ko);
         }
-        v[0] = epi.dy2;
-        v[1] = epi.inter;
     }
     store_inst_partials<2>(v, S.Bp, d.part_dual);
 }
@@ -80,18 +116,27 @@ __global__ __launch_bounds__(kBlock) void sk_update(SDev<T> S)
         if (!ctl->accepted) {
             for (int e = e0; e < nt; e += stride) primal_elem(d, c, tau, e, v[0]);
         } else {
-            UpdateEpi<T> epi{pick(d.xb, c), d.cs, d.ls, d.us, pick(d.KTyb, c), d.xa, d.KTya, pick(d.xb, c ^ 1),
-                             (T)ctl->avg_w, tau, ctl->mode == MODE_NONE, 0.0};
-            const T *y = pick(d.yb, c);
+            const T *x = pick(d.xb, c), *y = pick(d.yb, c);
+            T *kty = pick(d.KTyb, c), *xn = pick(d.xb, c ^ 1);
+            const T w = (T)ctl->avg_w;
+            const bool primal = ctl->mode == MODE_NONE;
             for (int e = e0; e < nt; e += stride) {
                 const int j = e >> S.lgB;
-                const int p1 = S.trp[j + 1];
-                T acc = T(0);
-                for (int p = S.trp[j]; p < p1; ++p) acc += S.tv[p] * y[((size_t)S.tci[p] << S.lgB) + b];
-                epi(e, acc);
+                const T xj = x[e], a = d.xa[e], bb = d.KTya[e];
+                const T cj = d.cs[e], lj = d.ls[e], uj = d.us[e];
+                const T s = spmm_row(S.tci, S.tv, y, S.trp[j], S.trp[j + 1], S.lgB, b);
+                // the averages and next primal trial of UpdateEpi
+                kty[e] = s;
+                d.xa[e] = a + w * (xj - a);
+                d.KTya[e] = bb + w * (s - bb);
+                if (primal) {
+                    const T nv = clampv(xj - tau * (cj - s), lj, uj);
+                    xn[e] = nv;
+                    const double dd = (double)nv - (double)xj;
+                    v[0] += dd * dd;
+                }
             }
-            for (int e = e0; e < mt; e += stride) average_row(d, e, c, epi.w);
-            v[0] = epi.dx2;
+            for (int e = e0; e < mt; e += stride) average_row(d, e, c, w);
         }
     }
     store_inst_partials<1>(v, S.Bp, d.part_primal);
@@ -175,13 +220,8 @@ __global__ __launch_bounds__(kBlock) void sk_product(SDev<T> S, const T *__restr
     const T *v = WHICH ? S.tv : S.kv;
     const int total = (WHICH ? S.n : S.m) << S.lgB;
     const int b = (int)threadIdx.x & (S.Bp - 1);
-    for (int e = (int)(blockIdx.x * kBlock + threadIdx.x); e < total; e += (int)(gridDim.x * kBlock)) {
-        const int i = e >> S.lgB;
-        const int p1 = rp[i + 1];
-        T acc = T(0);
-        for (int p = rp[i]; p < p1; ++p) acc += v[p] * in[((size_t)ci[p] << S.lgB) + b];
-        out[e] = acc;
-    }
+    for (int e = (int)(blockIdx.x * kBlock + threadIdx.x); e < total; e += (int)(gridDim.x * kBlock))
+        out[e] = spmm_row(ci, v, in, rp[e >> S.lgB], rp[(e >> S.lgB) + 1], S.lgB, b);
 }
 
 template <typename T>

@@ -152,10 +152,11 @@ void setup(lp_shared *P, const std::vector<int> &rp, const std::vector<int> &ci,
         HIPT(hipMemsetAsync(p, 0, sizeof(T) * (size_t)std::max<int64_t>(N, 1), st));
     for (T *p : {d.yb[0], d.yb[1], d.Kxb[0], d.Kxb[1], d.ya, d.Kxa, d.y0, d.Kx0, d.yo})
         HIPT(hipMemsetAsync(p, 0, sizeof(T) * (size_t)std::max<int64_t>(M, 1), st));
-    // the element walks: enough workgroups to cover the longer side, at most 1024
+    // the element walks: enough workgroups to cover the longer side, at most
+    // 2048 (eight 256-thread workgroups per CU)
     const int64_t wn = (std::max(N, M) + kBlock - 1) / kBlock;
-    S.grid = (int)std::max<int64_t>(1, std::min<int64_t>(wn, 1024));
-    S.grid_m = (int)std::max<int64_t>(1, std::min<int64_t>((M + kBlock - 1) / kBlock, 1024));
+    S.grid = (int)std::max<int64_t>(1, std::min<int64_t>(wn, 2048));
+    S.grid_m = (int)std::max<int64_t>(1, std::min<int64_t>((M + kBlock - 1) / kBlock, 2048));
     d.part_primal = A.make<double>((int64_t)S.grid * S.Bp);
     d.part_dual = A.make<double>((int64_t)S.grid_m * S.Bp * 2);
     d.part_check = A.make<double>((int64_t)S.grid * S.Bp * kCheckSums);

@@ -211,14 +211,17 @@ class Family:
         return out
 
 
-def solve_labels(lps, tol=1e-5, group=64, precision="fp64", max_iters=200000, log=None):
-    """Solve the instances with the batched solver; returns (Z [N x (n+m)]
-    float32 numpy of the unscaled (x*, y*), list of infos)."""
+def solve_labels(lps, tol=1e-5, group=64, precision="fp64", max_iters=200000, log=None, shared=True):
+    """Solve the instances (members of one family: the same K) in groups with
+    the shared-matrix batch (one SpMM pass over K per product for the whole
+    group; shared=False: the general batch, which reads K once per
+    instance); returns (Z [N x (n+m)] float32 numpy of the unscaled
+    (x*, y*), list of infos)."""
     Zs, infos = [], []
     for g0 in range(0, len(lps), group):
         part = lps[g0:g0 + group]
         t0 = time.perf_counter()
-        bt = lpmod.Batch(part, precision=precision)
+        bt = lpmod.Shared(part, precision=precision) if shared else lpmod.Batch(part, precision=precision)
         bt.solve(tol, max_iters)
         if log:
             log(f"labels {g0 + len(part)}/{len(lps)} ({time.perf_counter() - t0:.1f}s for this group)")
