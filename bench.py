@@ -252,9 +252,11 @@ def main():
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance solve")
     ap.add_argument("--ttt-tol", type=float, default=1e-4, help="relative KKT tolerance of that solve")
     ap.add_argument("--ttt-limit", type=float, default=90.0)
-    ap.add_argument("--ws-train", type=int, default=512, help="warmstart: training instances")
-    ap.add_argument("--ws-eval", type=int, default=128, help="warmstart: held-out instances")
+    ap.add_argument("--ws-train", type=int, default=2048, help="warmstart: training instances")
+    ap.add_argument("--ws-eval", type=int, default=1000, help="warmstart: held-out instances")
     ap.add_argument("--ws-epochs", type=int, default=120)
+    ap.add_argument("--ws-time-sample", type=int, default=64,
+                    help="warmstart: held-out members also timed one by one on single handles")
     ap.add_argument("--workload", choices=["large", "pagerank", "tiny", "batch", "warmstart", "gemm"],
                     default="large",
                     help="large: one 2e6x1e6 LP (default); pagerank: the LP of a random graph's PageRank "
@@ -611,11 +613,16 @@ def bench_batch(args):
 def bench_warmstart(args):
     """Learned warm start on the parametric family (fixed K: n=2e5,
     m1=m2=5e4, 10 nonzeros per column; b, h, c from the base certificate
-    perturbed by 10% relative noise).  Training labels: this solver (batched,
-    FP64) to rel KKT 1e-5; network 256 -> 3x1024 ReLU -> 64 -> n+m in BF16 on
-    the GPU.  Held-out instances are solved cold, from the base solution
-    alone (ablation), and from the network's prediction (sketch + inference
-    time included; a failed warm solve falls back to cold).
+    perturbed by 10% relative noise).  Training labels: this solver (the
+    shared-matrix batch, FP64) to rel KKT 1e-5; targets are the scaled
+    solution and the log primal weight of each label solve; network 256 ->
+    3x1024 ReLU -> 64 -> n+m+1 in BF16 on the GPU.  Held-out members are
+    solved (shared batch, iterations) from: cold; the base solution (mean
+    label) with the default primal weight, i.e. the method without the
+    network; the base solution with the family's primal weight; the
+    network's point with the default weight; the network's point and
+    weight.  Single-handle wall times (sketch + inference included) are
+    taken on a sample of the held-out members.
     """
     import numpy as np
     import torch
@@ -627,75 +634,101 @@ def bench_warmstart(args):
     fam = ws.Family(base)
     train_lps = [gen.parametric_instance(base, 10_000 + i) for i in range(args.ws_train)]
     eval_lps = [gen.parametric_instance(base, 30_000 + i) for i in range(args.ws_eval)]
-    log("instances generated")
     log(f"generated family n={base.n} m={base.m} nnz={base.nnz}: {len(train_lps)} train, {len(eval_lps)} held out "
         f"in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
-    Z, infos = ws.solve_labels(train_lps, tol=1e-5, group=64, max_iters=20000, log=log)
+    Z, infos = ws.solve_labels(train_lps, tol=1e-5, group=128, max_iters=20000, log=log)
     label_s = time.perf_counter() - t0
     ok = sum(1 for i in infos if i["status"] == "OPTIMAL")
-    log(f"labels: {ok}/{len(infos)} optimal at 1e-5 in {label_s:.1f}s")
+    log(f"labels: {ok}/{len(infos)} optimal at 1e-5 in {label_s:.1f}s ({len(infos) / label_s:.2f} per second)")
     keep = np.array([i["status"] == "OPTIMAL" for i in infos])
-    X = fam.sketch(train_lps)
-    sel = torch.from_numpy(np.nonzero(keep)[0]).cuda()
-    X = X.index_select(0, sel).contiguous()
-    Zd = torch.from_numpy(Z[keep]).cuda()
+    T = fam.encode(Z[keep], [i["omega"] for i, k in zip(infos, keep) if k])
+    X = fam.sketch([p for p, k in zip(train_lps, keep) if k])
+    Td = torch.from_numpy(T).cuda()
     mu = X.mean(0).cpu().numpy()
     sig = X.std(0).cpu().numpy() + 1e-6
-    zbase = Z[keep].mean(0)
-    omega_fam = float(np.median([i["omega"] for i in infos if i["status"] == "OPTIMAL"]))
-    net = ws.Net(base.n + base.m, max_batch=256)
-    net.init_params(0, out_bias=zbase)
-    net.set_norm(mu, sig)
-    t0 = time.perf_counter()
-    losses = ws.train(net, X, Zd, epochs=args.ws_epochs, batch=256, lr=1e-3, log=log)
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t0
+    tbase = T.mean(0)
+    xb, yb, om_fam = fam.decode(tbase)
+    Xe = fam.sketch(eval_lps)
+
+    def trained(count):
+        net = ws.Net(fam.out_dim, max_batch=256)
+        net.init_params(0, out_bias=T[:count].mean(0))
+        net.set_norm(mu, sig)
+        t1 = time.perf_counter()
+        losses = ws.train(net, X[:count].contiguous(), Td[:count].contiguous(), epochs=args.ws_epochs, batch=256,
+                          lr=1e-3)
+        torch.cuda.synchronize()
+        pred = np.concatenate([net.forward(Xe[b0:b0 + 256].contiguous()).cpu().numpy()
+                               for b0 in range(0, len(eval_lps), 256)])
+        return net, losses, time.perf_counter() - t1, pred
+
+    def mean_iters(starts, label):
+        t1 = time.perf_counter()
+        r = ws.solve_starts(eval_lps, starts, tol=1e-4, group=128)
+        it = np.array([t["iterations"] for t in r], np.float64)
+        out = {"iters_mean": float(it.mean()), "iters_median": float(np.median(it)),
+               "optimal": sum(1 for t in r if t["status"] == "OPTIMAL"), "fallbacks": sum(t["fallback"] for t in r),
+               "batch_seconds": time.perf_counter() - t1}
+        log(f"{label}: mean {out['iters_mean']:.0f} it, median {out['iters_median']:.0f}, "
+            f"{out['optimal']}/{len(r)} optimal, {out['fallbacks']} fallbacks ({out['batch_seconds']:.1f}s)")
+        return out
+
+    used = int(keep.sum())
+    net, losses, train_s, pred = trained(used)
+    starts_net = [fam.decode(r) for r in pred]
+    summ = {
+        "cold": mean_iters([None] * len(eval_lps), "cold"),
+        "base_start": mean_iters([(xb, yb, 0.0)] * len(eval_lps), "base solution, default weight"),
+        "base_start_family_omega": mean_iters([(xb, yb, om_fam)] * len(eval_lps),
+                                              "base solution, family weight"),
+        "net_point_default_omega": mean_iters([(x, y, 0.0) for x, y, _ in starts_net],
+                                              "network point, default weight"),
+        "net_start": mean_iters(starts_net, "network point and weight"),
+    }
+    summ["base_start_family_omega"]["omega"] = om_fam
+    # learning curve: the network trained on the first `count` labels
+    curve = []
+    for count in sorted({c for c in (used // 8, used // 4, used // 2) if c >= 64}):
+        _, lc, _, pc = trained(count)
+        r = mean_iters([fam.decode(v) for v in pc], f"network trained on {count}")
+        curve.append({"train": count, "loss_last": lc[-1], "iters_mean": r["iters_mean"]})
+    curve.append({"train": used, "loss_last": losses[-1], "iters_mean": summ["net_start"]["iters_mean"]})
+    # single-handle wall time on a sample (sketch and inference in the warm time)
     rows = []
-    for i, p in enumerate(eval_lps):
+    for i, p in enumerate(eval_lps[:args.ws_time_sample]):
         ic, tc, _ = ws.solve_with_start(p, None)
-        ib, tb, fbb = ws.solve_with_start(p, zbase.astype(np.float64))
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        pred = net.forward(fam.sketch([p]))[0].cpu().numpy().astype(np.float64)
+        out = net.forward(fam.sketch([p]))[0].cpu().numpy()
+        x0, y0, om = fam.decode(out)
         inf_s = time.perf_counter() - t1
-        iw, tw, fbw = ws.solve_with_start(p, pred)
-        io, to, fbo = ws.solve_with_start(p, pred, omega=omega_fam)
-        rows.append((ic["iterations"], tc, ib["iterations"], tb, fbb, iw["iterations"], tw + inf_s, fbw, inf_s,
-                     io["iterations"], to + inf_s, fbo))
-        if i % 16 == 0:
-            log(f"eval {i}: cold {ic['iterations']} it {tc:.3f}s | base {ib['iterations']} | "
-                f"net {iw['iterations']} it {tw + inf_s:.3f}s | net+omega {io['iterations']} it")
+        iw, tw, fbw = ws.solve_with_start(p, np.concatenate([x0, y0]), omega=om)
+        rows.append((ic["iterations"], tc, iw["iterations"], tw + inf_s, fbw, inf_s))
     r = np.array(rows, dtype=np.float64)
     gm = lambda v: float(np.exp(np.mean(np.log(np.maximum(v, 1e-12)))))
-    summ = {
-        "cold": {"iters_mean": r[:, 0].mean(), "iters_median": float(np.median(r[:, 0])), "time_mean_s": r[:, 1].mean(),
-                 "time_geomean_s": gm(r[:, 1])},
-        "base_start": {"iters_mean": r[:, 2].mean(), "iters_median": float(np.median(r[:, 2])),
-                       "time_mean_s": r[:, 3].mean(), "fallbacks": int(r[:, 4].sum())},
-        "net_start": {"iters_mean": r[:, 5].mean(), "iters_median": float(np.median(r[:, 5])),
-                      "time_mean_s": r[:, 6].mean(), "time_geomean_s": gm(r[:, 6]), "fallbacks": int(r[:, 7].sum()),
-                      "inference_mean_s": r[:, 8].mean()},
-        "net_start_with_family_omega": {"omega": omega_fam, "iters_mean": r[:, 9].mean(),
-                                        "iters_median": float(np.median(r[:, 9])), "time_mean_s": r[:, 10].mean(),
-                                        "time_geomean_s": gm(r[:, 10]), "fallbacks": int(r[:, 11].sum())},
-    }
-    log(f"cold {summ['cold']['iters_mean']:.0f} it {summ['cold']['time_mean_s']:.3f}s | base "
-        f"{summ['base_start']['iters_mean']:.0f} it | net {summ['net_start']['iters_mean']:.0f} it "
-        f"{summ['net_start']['time_mean_s']:.3f}s | net+omega {summ['net_start_with_family_omega']['iters_mean']:.0f} it")
+    timing = {"sample": len(rows), "cold_time_mean_s": r[:, 1].mean(), "cold_time_geomean_s": gm(r[:, 1]),
+              "net_time_mean_s": r[:, 3].mean(), "net_time_geomean_s": gm(r[:, 3]),
+              "inference_mean_s": r[:, 5].mean(), "fallbacks": int(r[:, 4].sum()),
+              "cold_iters_mean": r[:, 0].mean(), "net_iters_mean": r[:, 2].mean()}
+    log(f"single-handle sample of {len(rows)}: cold {timing['cold_time_mean_s']:.3f}s, "
+        f"network {timing['net_time_mean_s']:.3f}s (inference {timing['inference_mean_s'] * 1e3:.1f} ms)")
     out = {
         "metric": "time-to-1e-4 KKT, warm-start vs plain",
-        "value": summ["cold"]["time_mean_s"] / summ["net_start_with_family_omega"]["time_mean_s"],
-        "unit": "x speedup (mean cold time / mean warm time)",
+        "value": timing["cold_time_mean_s"] / timing["net_time_mean_s"],
+        "unit": "x speedup (mean cold time / mean warm time, single-handle solves)",
         "n_gpus": 1, "steps": len(eval_lps), "warmup": 0,
-        "ms_per_step": 1e3 * summ["net_start"]["time_mean_s"],
+        "ms_per_step": 1e3 * timing["net_time_mean_s"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64 solve, bf16 network",
         "data": "synthetic",
         "config": {"workload": "parametric_family_n200000", "n": base.n, "m1": base.m1, "m2": base.m - base.m1,
-                   "nnz": base.nnz, "train": len(train_lps), "train_used": int(keep.sum()), "held_out": len(eval_lps),
+                   "nnz": base.nnz, "train": len(train_lps), "train_used": used, "held_out": len(eval_lps),
                    "label_tol": 1e-5, "tol": 1e-4, "epochs": args.ws_epochs, "perturbation": 0.1},
         "summary": summ,
-        "training": {"loss_first": losses[0], "loss_last": losses[-1], "seconds": train_s, "label_seconds": label_s},
+        "learning_curve": curve,
+        "timing": timing,
+        "training": {"loss_first": losses[0], "loss_last": losses[-1], "seconds": train_s, "label_seconds": label_s,
+                     "labels_per_second": len(infos) / label_s},
     }
     print(json.dumps(out))
 

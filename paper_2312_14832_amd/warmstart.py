@@ -178,20 +178,50 @@ def gemm(A, B, trans_a=False, trans_b=False, precision="bf16"):
 
 
 class Family:
-    """A parametric family: base LP, sketch of the perturbation vectors, and
-    the base solution that the network's output bias starts from."""
+    """A parametric family: base LP, sketch of the perturbation vectors, the
+    scaling of its shared matrix, and the coding of a member's solution as
+    the network's output.
+
+    The network's targets are a member's solution in the scaled space the
+    method iterates in (x~ = x Dc, y~ = y Dr; the scaling depends on K alone,
+    so it is the same for every member) followed by one more coordinate, the
+    log of the primal weight the member's solve converged to, times
+    sqrt(n + m) so that its squared error weighs about as much as the whole
+    solution's in the mean squared error."""
 
     def __init__(self, base, sketch_rows=256, sketch_seed=4242):
         import torch
         from . import gen
         self.base = base
+        self.n, self.m = base.n, base.m
         self.dim = base.m + base.n
+        self.out_dim = self.dim + 1
+        self.omega_scale = float(np.sqrt(self.dim))
         rp, ci, v = gen.sketch_matrix(self.dim, rows=sketch_rows, seed=sketch_seed)
         self.S = (torch.from_numpy(rp.astype(np.int32)).cuda(), torch.from_numpy(ci.astype(np.int32)).cuda(),
                   torch.from_numpy(v).cuda())
         self.rows = sketch_rows
         self.q0 = base.q.copy()
         self.c0 = base.c.copy()
+        p = lpmod.Problem(base)
+        self.Dr, self.Dc = p.scaling()
+        p.close()
+
+    def encode(self, Z, omegas):
+        """[N x (n+m+1)] float32 targets from unscaled solutions Z [N x (n+m)]
+        and the primal weights their solves converged to."""
+        n = self.n
+        T = np.empty((Z.shape[0], self.out_dim), np.float32)
+        T[:, :n] = Z[:, :n] * self.Dc
+        T[:, n:self.dim] = Z[:, n:] * self.Dr
+        T[:, self.dim] = self.omega_scale * np.log(np.asarray(omegas, np.float64))
+        return T
+
+    def decode(self, out):
+        """(x0, y0, omega) of one output row, unscaled, for lp_set_start."""
+        out = np.asarray(out, np.float64)
+        n = self.n
+        return out[:n] / self.Dc, out[n:self.dim] / self.Dr, float(np.exp(out[self.dim] / self.omega_scale))
 
     def deltas(self, lps):
         """[B x (m+n)] float32 on the GPU: (q - q_base, c - c_base) per instance."""
@@ -252,6 +282,39 @@ def train(net, X, Z, epochs=50, batch=256, lr=1e-3, seed=0, log=None):
         if log and (ep % max(1, epochs // 10) == 0 or ep == epochs - 1):
             log(f"epoch {ep}: loss {losses[-1]:.6g}")
     return losses
+
+
+def solve_starts(lps, starts, tol=1e-4, group=128, precision="fp64", max_iters=200000):
+    """Solve members of one family with the shared batch, member i from
+    starts[i] = None (cold) or (x0, y0, omega) (omega <= 0: the default
+    weight); a member whose warm solve does not end OPTIMAL is redone cold
+    (the fallback, counted in its iterations).  Returns a list of dicts with
+    iterations, status and fallback per member."""
+    out = [None] * len(lps)
+    for g0 in range(0, len(lps), group):
+        idx = list(range(g0, min(g0 + group, len(lps))))
+        sh = lpmod.Shared([lps[i] for i in idx], precision=precision)
+        for k, i in enumerate(idx):
+            if starts[i] is not None:
+                x0, y0, om = starts[i]
+                sh.set_start(k, x0, y0, om)
+        sh.solve(tol, max_iters)
+        redo = []
+        for k, i in enumerate(idx):
+            info = sh.info(k)
+            out[i] = {"iterations": info["iterations"], "status": info["status"], "fallback": False}
+            if starts[i] is not None and info["status"] != "OPTIMAL":
+                redo.append((k, i))
+        if redo:
+            for k, _ in redo:
+                sh.set_start(k, None, None, 0.0)
+            sh.solve(tol, max_iters)
+            for k, i in redo:
+                info = sh.info(k)
+                out[i] = {"iterations": out[i]["iterations"] + info["iterations"], "status": info["status"],
+                          "fallback": True}
+        sh.close()
+    return out
 
 
 def solve_with_start(p, start=None, tol=1e-4, max_iters=200000, precision="fp64", omega=0.0):

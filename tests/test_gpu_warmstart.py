@@ -163,39 +163,52 @@ def test_sketch_matches_numpy(ws):
 
 
 def test_trained_network_beats_cold_start(ws):
-    """Train on 384 solved members of a small family, then on 24 held-out
-    members: warm starts take fewer iterations to rel KKT 1e-4 than cold
-    starts, every solve ends OPTIMAL, and a hopeless start falls back to cold."""
+    """Train on 384 solved members of a small family (targets: the scaled
+    solution and the log primal weight of each member's solve), then solve 48
+    held-out members to rel KKT 1e-4 from four starts: cold; the base
+    solution (the mean training solution) with the default primal weight,
+    which is the method without the network; the base solution with the
+    family's primal weight (their geometric mean); and the network's
+    prediction (point and primal weight).  Every solve ends OPTIMAL, the
+    network start takes fewer iterations than the cold and the base-solution
+    starts, and a hopeless start falls back to cold."""
     import torch
     base = gen.parametric_base(6, n=2000, m1=500, m2=500, per_col=8)
     fam = ws.Family(base)
     train_lps = [gen.parametric_instance(base, 10_000 + i) for i in range(384)]
-    test_lps = [gen.parametric_instance(base, 30_000 + i) for i in range(24)]
+    test_lps = [gen.parametric_instance(base, 30_000 + i) for i in range(48)]
     say("case warm start: labels")
     Z, infos = ws.solve_labels(train_lps, tol=1e-5, group=128)
     assert all(i["status"] == "OPTIMAL" for i in infos)
+    T = fam.encode(Z, [i["omega"] for i in infos])
     X = fam.sketch(train_lps)
     mu = X.mean(0).cpu().numpy(); sig = X.std(0).cpu().numpy() + 1e-6
-    zbase = Z.mean(0)
-    net = ws.Net(base.n + base.m, hidden=256, layers=3, rank=32, max_batch=128)
-    net.init_params(0, out_bias=zbase)
+    tbase = T.mean(0)
+    net = ws.Net(fam.out_dim, hidden=256, layers=3, rank=32, max_batch=128)
+    net.init_params(0, out_bias=tbase)
     net.set_norm(mu, sig)
-    Zd = torch.from_numpy(Z).cuda()
+    Td = torch.from_numpy(T).cuda()
     say("case warm start: train")
-    losses = ws.train(net, X, Zd, epochs=80, batch=128, lr=1e-3)
+    losses = ws.train(net, X, Td, epochs=80, batch=128, lr=1e-3)
     say(f"  training loss {losses[0]:.4g} -> {losses[-1]:.4g}")
     assert losses[-1] < 0.8 * losses[0], (losses[0], losses[-1])
     say("case warm start: evaluate")
-    Xt = fam.sketch(test_lps)
-    pred = net.forward(Xt).cpu().numpy().astype(np.float64)
-    cold, warm = [], []
-    for i, p in enumerate(test_lps):
-        ic, _, _ = ws.solve_with_start(p, None)
-        iw, _, fb = ws.solve_with_start(p, pred[i])
-        assert ic["status"] == "OPTIMAL" and iw["status"] == "OPTIMAL"
-        cold.append(ic["iterations"]); warm.append(iw["iterations"] + (ic["iterations"] if fb else 0))
-    say(f"  cold mean {np.mean(cold):.0f}  warm mean {np.mean(warm):.0f}")
-    assert np.mean(warm) < np.mean(cold)
+    pred = net.forward(fam.sketch(test_lps)).cpu().numpy()
+    xb, yb, om_fam = fam.decode(tbase)
+    zb = Z.mean(0).astype(np.float64)
+    assert np.allclose(xb, zb[:base.n], rtol=1e-5, atol=1e-5)
+    starts = {"cold": [None] * len(test_lps),
+              "base": [(xb, yb, 0.0)] * len(test_lps),
+              "base+family omega": [(xb, yb, om_fam)] * len(test_lps),
+              "network": [fam.decode(r) for r in pred]}
+    res = {k: ws.solve_starts(test_lps, v, tol=1e-4) for k, v in starts.items()}
+    mean = {}
+    for k, r in res.items():
+        assert all(t["status"] == "OPTIMAL" for t in r), k
+        mean[k] = float(np.mean([t["iterations"] for t in r]))
+    say("  mean iterations: " + ", ".join(f"{k} {v:.0f}" for k, v in mean.items()))
+    assert mean["network"] < mean["cold"]
+    assert mean["network"] < mean["base"]
     bad = np.full(base.n + base.m, 1e30)
     info, _, fb = ws.solve_with_start(test_lps[0], bad, max_iters=4000)
     assert fb and info["status"] == "OPTIMAL"
