@@ -257,10 +257,12 @@ def main():
     ap.add_argument("--ws-epochs", type=int, default=120)
     ap.add_argument("--ws-time-sample", type=int, default=64,
                     help="warmstart: held-out members also timed one by one on single handles")
-    ap.add_argument("--workload", choices=["large", "pagerank", "tiny", "batch", "warmstart", "gemm"],
+    ap.add_argument("--workload", choices=["large", "pagerank", "tiny", "batch", "warmstart", "gemm", "shared"],
                     default="large",
                     help="large: one 2e6x1e6 LP (default); pagerank: the LP of a random graph's PageRank "
-                         "vector; batch: 512 uneven LPs solved together")
+                         "vector; batch: 512 uneven LPs solved together; shared: members of the warm-start "
+                         "family solved over one shared matrix")
+    ap.add_argument("--shared-count", type=int, default=64, help="shared: instances per handle")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--seq-sample", type=int, default=32,
                     help="batch workload: instances solved one by one for the sequential comparison")
@@ -308,6 +310,8 @@ def main():
         return bench_gemm(args)
     if args.workload == "warmstart":
         return bench_warmstart(args)
+    if args.workload == "shared":
+        return bench_shared(args)
     n = args.n
     t0 = time.perf_counter()
     if args.workload == "pagerank":
@@ -730,6 +734,53 @@ def bench_warmstart(args):
         "training": {"loss_first": losses[0], "loss_last": losses[-1], "seconds": train_s, "label_seconds": label_s,
                      "labels_per_second": len(infos) / label_s},
     }
+    print(json.dumps(out))
+
+
+def shared_bytes(which, n, m, nnz, B, s=8):
+    """Algorithmic bytes of one launch of the shared batch's two product
+    kernels for B instances: the matrix once (values, int32 columns, row
+    pointers), the gathered vector once per instance, and the vectors the
+    fused step reads and writes per instance (the single-LP counts times B)."""
+    if which == 0:   # sk_dual: K x' + dual step (y, Kx, q read; y', Kx' written)
+        return nnz * (s + 4) + 4 * (m + 1) + B * s * n + 5 * B * s * m
+    # sk_update: K'y' + averages + next primal (x, c, l, u, xbar, K'ybar read; K'y, xbar, K'ybar, x'' written;
+    # y, Kx read and ybar, Kxbar read and written)
+    return nnz * (s + 4) + 4 * (n + 1) + B * s * m + 10 * B * s * n + 6 * B * s * m
+
+
+def bench_shared(args):
+    """The shared-matrix batch on `--shared-count` members of the warm-start
+    family (n=2e5, m1=m2=5e4, 2e6 nonzeros): a warm-up solve, then a fresh
+    solve of `steps` windows of 64 attempt slots timed end to end (start
+    products included; instance-iterations per second), and the two product
+    kernels' algorithmic bytes per launch."""
+    import numpy as np
+    import torch
+    from paper_2312_14832_amd import gen, lp
+
+    base = gen.parametric_base(4)
+    B = args.shared_count
+    lps = [gen.parametric_instance(base, 10_000 + i) for i in range(B)]
+    sh = lp.Shared(lps, precision=args.precision)
+    sh.solve(1e-30, ITERS_PER_STEP * max(args.warmup, 1))   # warm-up (every solve starts afresh)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sh.solve(1e-30, ITERS_PER_STEP * args.steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    its = sum(sh.info(i)["iterations"] for i in range(B))
+    s = 8 if args.precision == "fp64" else 4
+    out = {"metric": "shared-matrix batch instance-iterations/sec", "value": its / dt, "unit": "instance-it/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if args.precision == "fp64" else "f32+f64acc", "data": "synthetic",
+           "config": {"workload": f"parametric_family_n200000_shared{B}", "n": base.n, "m": base.m,
+                      "nnz": base.nnz, "instances": B, "precision": args.precision},
+           "alg_bytes_per_launch": {"sk_dual": shared_bytes(0, base.n, base.m, base.nnz, B, s),
+                                    "sk_update": shared_bytes(1, base.n, base.m, base.nnz, B, s)}}
+    print(f"[bench] {B} instances: {its / dt:.0f} instance-it/s, {1e3 * dt / (args.steps * ITERS_PER_STEP):.3f} "
+          f"ms per slot", file=sys.stderr, flush=True)
     print(json.dumps(out))
 
 
