@@ -257,7 +257,7 @@ def main():
     ap.add_argument("--ws-epochs", type=int, default=120)
     ap.add_argument("--ws-time-sample", type=int, default=64,
                     help="warmstart: held-out members also timed one by one on single handles")
-    ap.add_argument("--workload", choices=["large", "pagerank", "tiny", "batch", "warmstart", "gemm", "shared"],
+    ap.add_argument("--workload", choices=["large", "pagerank", "tiny", "batch", "warmstart", "gemm", "shared", "gather"],
                     default="large",
                     help="large: one 2e6x1e6 LP (default); pagerank: the LP of a random graph's PageRank "
                          "vector; batch: 512 uneven LPs solved together; shared: members of the warm-start "
@@ -312,6 +312,8 @@ def main():
         return bench_warmstart(args)
     if args.workload == "shared":
         return bench_shared(args)
+    if args.workload == "gather":
+        return bench_gather(args)
     n = args.n
     t0 = time.perf_counter()
     if args.workload == "pagerank":
@@ -367,6 +369,28 @@ def main():
                 "traffic": counter_traffic(dom, workload, {"K": list(lk), "KT": list(lt)}),
                 "alg_bytes_per_launch": d["alg_bytes"],
                 "timed_launches": d["launches"]}
+    # the gather ceiling at the dominant product's layout (lp_gather_probe: i.i.d.
+    # columns over the same slices, dealt to the XCDs the same way)
+    gather_roofline = None
+    try:
+        import numpy as np
+        wdom = list(spmv).index(dom)
+        S_dom = prob.layout()[wdom]
+        vec_len = n if wdom == 0 else m1 + m2
+        slice_len = (vec_len + S_dom - 1) // S_dom
+        per = data.nnz // S_dom
+        grng = np.random.Generator(np.random.PCG64(11))
+        gidx = torch.from_numpy(grng.integers(0, slice_len, size=per * S_dom).astype(np.int32)).cuda()
+        gx = torch.ones(S_dom * slice_len, dtype=torch.float64 if s == 8 else torch.float32, device="cuda")
+        gms = lp.gather_probe(gidx, gx, S_dom, slice_len, reps=20)
+        ceiling = per * S_dom / (gms * 1e-3) / 1e9
+        gather_roofline = {"kernel": dom, "bound": "gathers", "achieved": d["G_gathers_s"], "peak": ceiling,
+                           "unit": "G gathers/s", "frac": d["G_gathers_s"] / ceiling,
+                           "peak_source": f"lp_gather_probe: {per * S_dom} i.i.d. gathers over {S_dom} slices of "
+                                          f"{slice_len} entries, measured in this run"}
+        del gidx, gx
+    except Exception as exc:   # the probe is context; the bench line stands without it
+        print(f"[bench] gather probe skipped: {exc}", file=sys.stderr, flush=True)
     print(f"[bench] {K} windows in {dt:.3f}s -> {iters / dt:.0f} it/s; "
           + "; ".join(f"{k} {v['avg_us']:.1f}us {v['GB_s'] or 0:.0f}GB/s" for k, v in spmv.items()),
           file=sys.stderr, flush=True)
@@ -415,6 +439,7 @@ def main():
                    "column_slices": list(prob_layout), "row_blocks": blocks,
                    "generator": recipe},
         "roofline": roofline,
+        "gather_roofline": gather_roofline,
         "spmv": spmv,
         "time_to_tol": ttt,
         "mixed_vs_fp64": mixed_vs_fp64,
@@ -781,6 +806,56 @@ def bench_shared(args):
                                     "sk_update": shared_bytes(1, base.n, base.m, base.nnz, B, s)}}
     print(f"[bench] {B} instances: {its / dt:.0f} instance-it/s, {1e3 * dt / (args.steps * ITERS_PER_STEP):.3f} "
           f"ms per slot", file=sys.stderr, flush=True)
+    print(json.dumps(out))
+
+
+def bench_gather(args):
+    """The gather ceiling of the sparse products (lp_gather_probe): 2e7
+    gathers, as in one product of the 2e6-column LP, from 8 column slices
+    dealt to the XCDs as the products deal them (and from one slice, the
+    unsliced case), for slices of 256 KiB to 64 MiB of the gathered vector.
+    Patterns: i.i.d. uniform indices (a random sparse matrix), the same
+    sorted inside each 2048-index chunk (a row block whose entries were
+    ordered by column), and consecutive indices (the coalesced bound)."""
+    import numpy as np
+    import torch
+    from paper_2312_14832_amd import lp
+
+    rng = np.random.Generator(np.random.PCG64(7))
+    s = 8 if args.precision == "fp64" else 4
+    dt = torch.float64 if args.precision == "fp64" else torch.float32
+    count = 20_000_000
+    rows = []
+    for S, kib in [(8, 256), (8, 1024), (8, 2048), (8, 4096), (8, 8192), (1, 16384), (1, 65536)]:
+        slice_len = kib * 1024 // s
+        per = count // S
+        x = torch.ones(S * slice_len, dtype=dt, device="cuda")
+        for pattern in ("random", "sorted2048", "consecutive"):
+            if pattern == "consecutive":
+                h = np.tile(np.arange(per, dtype=np.int64) % slice_len, S)
+            else:
+                h = rng.integers(0, slice_len, size=S * per)
+                if pattern == "sorted2048":
+                    h = h.reshape(S, -1)
+                    full = (per // 2048) * 2048
+                    h[:, :full] = np.sort(h[:, :full].reshape(S, -1, 2048), axis=2).reshape(S, full)
+                    h = h.ravel()
+            idx = torch.from_numpy(h.astype(np.int32)).cuda()
+            ms = lp.gather_probe(idx, x, S, slice_len, reps=20)
+            rate = S * per / (ms * 1e-3) / 1e9
+            rows.append({"slices": S, "slice_kib": kib, "pattern": pattern, "ms": ms, "G_gathers_s": rate,
+                         "useful_GB_s": rate * s})
+            print(f"[bench] S={S} slice {kib} KiB {pattern:12s}: {ms:.3f} ms, {rate:.1f} G gathers/s",
+                  file=sys.stderr, flush=True)
+            del idx
+        del x
+    head = next(r for r in rows if r["slices"] == 8 and r["slice_kib"] == 2048 and r["pattern"] == "random")
+    out = {"metric": "random gathers per second", "value": head["G_gathers_s"], "unit": "G gathers/s",
+           "n_gpus": 1, "steps": 20, "warmup": 1, "ms_per_step": head["ms"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64" if s == 8 else "f32", "data": "synthetic",
+           "config": {"workload": "gather_probe_2e7", "gathers": count,
+                      "headline": "8 slices of 2 MiB, i.i.d. indices (the 2e6-column LP's K product)"},
+           "table": rows}
     print(json.dumps(out))
 
 

@@ -243,6 +243,20 @@ int lp_spmv_noalloc(lp_problem *P, int transpose, const double *in, double *out)
  * with kernel_timing = 2).  Zeros when timing was off. */
 int lp_kernel_time(const lp_problem *P, int which, int64_t *count, double *total_ms);
 
+/* Measurement helper (not a step of the method): the rate of the random
+ * gathers that bound the sparse products, without their matrix.  idx
+ * (device, int32, count entries, slice-major: count / slices per slice, each
+ * in [0, slice_len)) indexes x (device; double for LP_FP64, float for
+ * LP_MIXED; slices * slice_len entries, slice s at s * slice_len).
+ * Workgroups are dealt to slices as in the products (slice s on the XCDs
+ * congruent to s); each thread makes eight gathers per 2048-index chunk.
+ * out (device, same type as x) receives 4096 * 256 sums at most.  Runs one
+ * untimed pass, then reps passes on stream, and stores the mean pass time.
+ * Errors: LP_ERR_ARG (NULL, non-positive sizes, count not divisible by
+ * slices, more than 4096 slices), LP_ERR_HIP. */
+int lp_gather_probe(const int32_t *idx, const void *x, int precision, int64_t count, int slices, int64_t slice_len,
+                    void *out, int reps, void *stream, double *ms_per_pass);
+
 /* Device bytes held by the handle. */
 int lp_device_bytes(const lp_problem *P, int64_t *bytes);
 

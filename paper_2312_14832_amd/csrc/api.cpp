@@ -1464,6 +1464,37 @@ int lp_spmv_noalloc(lp_problem *P, int transpose, const double *in, double *out)
     }
 }
 
+int lp_gather_probe(const int32_t *idx, const void *x, int precision, int64_t count, int slices, int64_t slice_len,
+                    void *out, int reps, void *stream, double *ms_per_pass)
+{
+    if (!idx || !x || !out || !ms_per_pass || count <= 0 || slices <= 0 || slice_len <= 0 || reps <= 0 ||
+        count % slices != 0 || slices > 4096 || (precision != LP_FP64 && precision != LP_MIXED))
+        return LP_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t per = count / slices;
+    const int unit = std::max(slices, kXcds);
+    const int grid = std::max(4096 / unit, 1) * unit;
+    try {
+        EventPair ev;
+        auto pass = [&] {
+            if (precision == LP_FP64)
+                HIPT(launch_gather_probe<double>(idx, (const double *)x, per, slices, slice_len, (double *)out, grid,
+                                                 st));
+            else
+                HIPT(launch_gather_probe<float>(idx, (const float *)x, per, slices, slice_len, (float *)out, grid, st));
+        };
+        pass();
+        HIPT(hipEventRecord(ev.a, st));
+        for (int r = 0; r < reps; ++r) pass();
+        HIPT(hipEventRecord(ev.b, st));
+        HIPT(hipEventSynchronize(ev.b));
+        *ms_per_pass = (double)ev.ms() / reps;
+    } catch (const HipError &) {
+        return LP_ERR_HIP;
+    }
+    return LP_OK;
+}
+
 int lp_kernel_time(const lp_problem *P, int which, int64_t *count, double *total_ms)
 {
     if (!P || !count || !total_ms || which < 0 || which > 1) return LP_ERR_ARG;

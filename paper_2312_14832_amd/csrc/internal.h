@@ -225,6 +225,9 @@ hipError_t noalloc_scratch(void **ptr);
 template <typename T>
 hipError_t launch_confirm(const Dev<T> &d, const Geo &g, const Conf64 &cf, int cur, double Nq, double Nc,
                           hipStream_t s);
+template <typename T>
+hipError_t launch_gather_probe(const int *idx, const T *x, int64_t per_slice, int S, int64_t slice_len, T *out,
+                               int grid, hipStream_t s);
 template <typename T> hipError_t launch_partial_K(const Dev<T> &d, hipStream_t s);
 template <typename T> hipError_t launch_partial_KT(const Dev<T> &d, hipStream_t s);
 template <typename T> hipError_t launch_dual(const Dev<T> &d, const Geo &g, hipStream_t s);

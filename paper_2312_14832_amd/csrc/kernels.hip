@@ -277,6 +277,40 @@ __global__ __launch_bounds__(kBlock) void k_confirm_decide(Ctl *ctl, const doubl
     confirm_decision(ctl, S, Nq, Nc);
 }
 
+// Gather-rate probe (a measurement helper, not a step of the method): the
+// access pattern of a sliced product's gathers without its matrix.  Indices
+// are slice-major, count / S per slice, local to the slice; workgroup b
+// works on slice b % S (so a slice stays on the XCDs congruent to it, as in
+// the products) and walks that slice's chunks of 2048 indices; each thread
+// loads 8 indices, then makes their 8 gathers, then adds them, the same
+// three phases as a row block.  One sum per thread is stored.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gather_probe(const int *__restrict__ idx, const T *__restrict__ x,
+                                                         int64_t per_slice, int S, int64_t slice_len,
+                                                         T *__restrict__ out)
+{
+    constexpr int U = kStreamNB / kBlock;
+    const int s = (int)blockIdx.x % S;
+    const int64_t chunks = (per_slice + kStreamNB - 1) / kStreamNB;
+    const int *ix = idx + (size_t)s * per_slice;
+    const T *xs = x + (size_t)s * slice_len;
+    T acc = T(0);
+    for (int64_t k = (int64_t)blockIdx.x / S; k < chunks; k += (int64_t)gridDim.x / S) {
+        const int64_t b0 = k * kStreamNB;
+        const int cnt = (int)(per_slice - b0 < kStreamNB ? per_slice - b0 : kStreamNB);
+        int c[U];
+        T g[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) c[u] = __builtin_nontemporal_load(ix + b0 + min((int)threadIdx.x + u * kBlock, cnt - 1));
+#pragma unroll
+        for (int u = 0; u < U; ++u) g[u] = xs[c[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if ((int)threadIdx.x + u * kBlock < cnt) acc += g[u];
+    }
+    out[(size_t)blockIdx.x * kBlock + threadIdx.x] = acc;
+}
+
 template <typename T, bool LONG>
 __global__ __launch_bounds__(kBlock) void k_partial_plain(Sliced<T> P, const T *__restrict__ x)
 {
@@ -607,6 +641,14 @@ hipError_t launch_confirm(const Dev<T> &d, const Geo &g, const Conf64 &cf, int c
 }
 
 template <typename T>
+hipError_t launch_gather_probe(const int *idx, const T *x, int64_t per_slice, int S, int64_t slice_len, T *out,
+                               int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gather_probe<T>, dim3(grid), dim3(kBlock), 0, s, idx, x, per_slice, S, slice_len, out);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_spmv(const Sliced<T> &P, const T *in, T *out, hipStream_t s)
 {
     if (P.rows <= 0) return hipSuccess;
@@ -796,6 +838,7 @@ hipError_t scale_csr_pair(const int *rp, const int *ci, double *kv, int m, const
     template hipError_t launch_check_decide<T>(const Dev<T> &, const Geo &, double, double, hipStream_t);          \
     template hipError_t launch_check_apply<T>(const Dev<T> &, const Geo &, hipStream_t);                           \
     template hipError_t launch_spmv<T>(const Sliced<T> &, const T *, T *, hipStream_t);                            \
+    template hipError_t launch_gather_probe<T>(const int *, const T *, int64_t, int, int64_t, T *, int, hipStream_t); \
     template hipError_t launch_confirm<T>(const Dev<T> &, const Geo &, const Conf64 &, int, double, double,       \
                                           hipStream_t);                                                           \
     template hipError_t launch_gather_values<T>(const double *, const int *, T *, int64_t, hipStream_t);           \

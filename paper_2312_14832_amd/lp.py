@@ -24,7 +24,7 @@ NSCALARS = 16
 
 # every symbol include/lp.h declares
 EXPORTS = ["lp_default_options", "lp_workspace_size", "lp_load", "lp_set_start", "lp_set_start_weight", "lp_solve", "lp_result", "lp_get_state",
-           "lp_set_state", "lp_get_scaling", "lp_spmv", "lp_spmv_noalloc", "lp_kernel_time", "lp_device_bytes", "lp_layout",
+           "lp_set_state", "lp_get_scaling", "lp_spmv", "lp_spmv_noalloc", "lp_gather_probe", "lp_kernel_time", "lp_device_bytes", "lp_layout",
            "lp_layout_blocks", "lp_presolved_size", "lp_free",
            "lp_strerror", "lp_last_error", "lp_batch_load", "lp_batch_solve", "lp_batch_result",
            "lp_batch_get_state", "lp_batch_set_state", "lp_batch_device_bytes", "lp_batch_layout_blocks",
@@ -82,6 +82,8 @@ def library():
         L.lp_get_scaling.argtypes = [C.c_void_p, dp, dp]
         L.lp_spmv.argtypes = [C.c_void_p, C.c_int, dp, dp]
         L.lp_spmv_noalloc.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+        L.lp_gather_probe.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int64, C.c_int, C.c_int64, C.c_void_p,
+                                      C.c_int, C.c_void_p, C.POINTER(C.c_double)]
         L.lp_kernel_time.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
         L.lp_device_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
         L.lp_layout.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]
@@ -504,3 +506,19 @@ class Shared:
         b = C.c_int64()
         self._check(library().lp_shared_device_bytes(self.h, C.byref(b)))
         return b.value
+
+
+def gather_probe(idx, x, slices, slice_len, reps=20, stream=None):
+    """lp_gather_probe on torch device tensors (idx int32, x float64 or
+    float32); returns milliseconds per pass."""
+    import torch
+    out = torch.empty(4096 * 256, dtype=x.dtype, device=x.device)
+    prec = LP_FP64 if x.dtype == torch.float64 else LP_MIXED
+    st = stream if stream is not None else torch.cuda.current_stream()
+    ms = C.c_double()
+    rc = library().lp_gather_probe(C.c_void_p(idx.data_ptr()), C.c_void_p(x.data_ptr()), prec, idx.numel(),
+                                   int(slices), int(slice_len), C.c_void_p(out.data_ptr()), int(reps),
+                                   C.c_void_p(st.cuda_stream), C.byref(ms))
+    if rc != 0:
+        raise LPError(rc, "lp_gather_probe")
+    return ms.value

@@ -98,3 +98,32 @@ def test_device_pointers_match_host_pointers(lpmod, precision):
     assert np.array_equal(xd.cpu().numpy(), xh)
     assert np.array_equal(yd.cpu().numpy(), yh)
     assert np.array_equal(ld.cpu().numpy(), lh)
+
+
+@pytest.mark.parametrize("slices", [1, 8, 16])
+def test_gather_probe_gathers_what_it_is_given(lpmod, slices):
+    """lp_gather_probe (the measurement helper behind bench.py --workload
+    gather) reads exactly the indexed entries: with x = 0, 1, 2, ... the sum
+    of its per-thread sums equals the sum of the indexed values."""
+    import torch
+    say(f"case gather probe slices={slices}")
+    rng = np.random.default_rng(slices)
+    slice_len, per = 5000, 7001
+    h = rng.integers(0, slice_len, size=slices * per)
+    x = torch.arange(slices * slice_len, dtype=torch.float64, device="cuda")
+    idx = torch.from_numpy(h.astype(np.int32)).cuda()
+    out = torch.empty(4096 * 256, dtype=torch.float64, device="cuda")
+    import ctypes as C
+    ms = C.c_double()
+    L = lpmod.library()
+    rc = L.lp_gather_probe(C.c_void_p(idx.data_ptr()), C.c_void_p(x.data_ptr()), 0, idx.numel(), slices, slice_len,
+                           C.c_void_p(out.data_ptr()), 1, C.c_void_p(torch.cuda.current_stream().cuda_stream),
+                           C.byref(ms))
+    torch.cuda.synchronize()
+    assert rc == 0 and ms.value > 0
+    unit = max(slices, 8)
+    grid = max(4096 // unit, 1) * unit
+    got = out[:grid * 256].sum().item()
+    want = float(sum(np.sum(s * slice_len + h[s * per:(s + 1) * per]) for s in range(slices)))
+    assert got == want
+    assert L.lp_gather_probe(None, None, 0, 0, 1, 1, None, 1, None, C.byref(ms)) == -1
