@@ -452,53 +452,65 @@ def main():
 
 def bench_tiny(args):
     """The tiny LP (n=1000, m1=200, m2=300, 5 nonzeros per column; seeds
-    0..9).  Its data (about 0.2 MB) sits in L2, so the rate is set by kernel
-    launch and synchronisation latency, not by memory: the iteration rate of
-    captured graph windows, the time to rel KKT 1e-6 per instance (fresh
-    handle, load excluded), and the oracle's time to 1e-6 on one host core."""
+    0..9).  Its data (about 0.2 MB) sits in L2, so the rate is set by launch
+    and synchronisation latency, not by memory.  Both loop forms are timed:
+    the one-workgroup loop (the default for LPs this small: one launch per
+    window, workgroup barriers between the steps) and the seven launches per
+    slot of captured graph windows.  Reported: the iteration rate, the time
+    to rel KKT 1e-6 per instance (fresh handle, load excluded), and the
+    oracle's time to 1e-6 on one host core."""
     import numpy as np
     import torch
     from paper_2312_14832_amd import gen, lp
 
     lps = [gen.tiny_lp(s) for s in range(10)]
     st = torch.cuda.current_stream()
-    p = lp.Problem(lps[0], stream=st)
-    p.solve(1e-30, ITERS_PER_STEP * max(args.warmup, 1))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    info = p.solve(1e-30, ITERS_PER_STEP * args.steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    iters = info["iterations"]
-    p.close()
-    print(f"[bench] tiny: {iters / dt:.0f} it/s", file=sys.stderr, flush=True)
-    ttt, ora = [], []
-    for s, data in enumerate(lps):
-        q = lp.Problem(data, stream=st)
-        t0 = time.perf_counter()
-        inf = q.solve(1e-6, 10**6)
+    forms = {}
+    for name, pers in (("one_workgroup", 1), ("launches", 0)):
+        p = lp.Problem(lps[0], stream=st, persistent=pers)
+        p.solve(1e-30, ITERS_PER_STEP * max(args.warmup, 1))
         torch.cuda.synchronize()
-        ttt.append({"seed": s, "seconds": time.perf_counter() - t0, "iterations": inf["iterations"],
-                    "status": inf["status"]})
-        q.close()
-        if not args.no_cpu:
-            from oracle.oracle import Oracle
+        t0 = time.perf_counter()
+        info = p.solve(1e-30, ITERS_PER_STEP * args.steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        p.close()
+        ttt = []
+        for s, data in enumerate(lps):
+            q = lp.Problem(data, stream=st, persistent=pers)
+            t0 = time.perf_counter()
+            inf = q.solve(1e-6, 10**6)
+            torch.cuda.synchronize()
+            ttt.append({"seed": s, "seconds": time.perf_counter() - t0, "iterations": inf["iterations"],
+                        "status": inf["status"]})
+            q.close()
+        med = float(np.median([t["seconds"] for t in ttt]))
+        forms[name] = {"iters_per_s": info["iterations"] / dt, "ms_per_step": 1e3 * dt / args.steps,
+                       "time_to_1e6_median_s": med, "runs": ttt}
+        print(f"[bench] tiny, {name}: {info['iterations'] / dt:.0f} it/s, median time to 1e-6 {med * 1e3:.1f} ms",
+              file=sys.stderr, flush=True)
+    ora = []
+    if not args.no_cpu:
+        from oracle.oracle import Oracle
+        for s, data in enumerate(lps):
             o = Oracle(data)
             t0 = time.perf_counter()
             _, _, _, oi = o.solve(1e-6, 10**6)
             ora.append({"seed": s, "seconds": time.perf_counter() - t0, "iterations": oi["iterations"]})
-    med = float(np.median([t["seconds"] for t in ttt]))
-    print(f"[bench] tiny: median time to 1e-6 {med * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        print(f"[bench] tiny, CPU oracle: median time to 1e-6 "
+              f"{1e3 * float(np.median([o['seconds'] for o in ora])):.1f} ms", file=sys.stderr, flush=True)
+    head = forms["one_workgroup"]
     out = {
-        "metric": "PDHG iters/sec", "value": iters / dt, "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * dt / args.steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "metric": "PDHG iters/sec", "value": head["iters_per_s"], "unit": "iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "tiny_lp_n1000", "n": 1000, "m1": 200, "m2": 300, "nnz": lps[0].nnz,
-                   "seeds": list(range(10)), "iters_per_step": ITERS_PER_STEP},
+                   "seeds": list(range(10)), "iters_per_step": ITERS_PER_STEP, "loop": "one workgroup"},
         "roofline": {"bound": "latency", "achieved": None, "peak": None, "unit": None, "frac": None,
                      "traffic": None,
-                     "note": "0.2 MB of data per iteration, resident in L2: launch and sync latency bound"},
-        "time_to_tol": {"tol": 1e-6, "median_s": med, "runs": ttt},
+                     "note": "0.2 MB of data per iteration, resident in L2: launch and barrier latency bound"},
+        "time_to_tol": {"tol": 1e-6, "median_s": head["time_to_1e6_median_s"], "runs": head["runs"]},
+        "forms": {k: {kk: vv for kk, vv in v.items() if kk != "runs"} for k, v in forms.items()},
         "cpu_baseline": ({"kind": "oracle", "cores": 1, "unit": "s to 1e-6",
                           "median_s": float(np.median([o["seconds"] for o in ora])), "runs": ora}
                          if ora else None),

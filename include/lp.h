@@ -131,6 +131,14 @@ typedef struct {
                                reduced problem (lp_presolved_size).  A stand-in for the presolvers the
                                paper's experiments run first (Table 1).  Not with LP_DEVICE or a workspace
                                (LP_ERR_ARG). */
+    int persistent;         /* small LPs: run the whole iteration loop in one workgroup (one kernel launch per
+                               64 x window attempt slots, barriers in place of kernel boundaries) instead of
+                               seven launches per slot.  Eligible: both products one column slice and no row
+                               longer than 8192 entries.  -1 (default): when eligible and K, K' and the two
+                               vectors the products gather fit in 150 KiB of LDS (about 5,600 nonzeros with
+                               1,500 rows and columns in FP64), where it is faster than the launches; 1:
+                               whenever eligible; 0: never.  Same method, same results up to the summation
+                               order of the reductions.  lp_kernel_time reports zeros for such solves. */
 } lp_options;
 
 typedef struct {

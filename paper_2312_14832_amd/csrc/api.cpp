@@ -538,7 +538,8 @@ int check_options(const lp_options &o)
         (o.ptr_kind != LP_HOST && o.ptr_kind != LP_DEVICE) || !(o.infeas_tol >= 0.0) || std::isinf(o.infeas_tol) ||
         o.kernel_timing < 0 || o.kernel_timing > 2 ||
         (o.workspace && (reinterpret_cast<uintptr_t>(o.workspace) % 256 != 0)) ||
-        (o.presolve != 0 && o.presolve != 1) || (o.presolve && (o.ptr_kind == LP_DEVICE || o.workspace)))
+        (o.presolve != 0 && o.presolve != 1) || (o.presolve && (o.ptr_kind == LP_DEVICE || o.workspace)) ||
+        o.persistent < -1 || o.persistent > 1)
         return LP_ERR_ARG;
     return LP_OK;
 }
@@ -760,7 +761,11 @@ void resolve_confirm(lp_problem *P)
     if (!P->hctl->confirm) return;
     Dev<T> &d = P->dev<T>();
     HIPT(launch_confirm<T>(d, P->geo, P->conf, P->hctl->cur, P->Nq, P->Nc, P->stream));
-    HIPT(launch_check_decide<T>(d, P->geo, P->Nq, P->Nc, P->stream));   // returns at once when confirmed
+    // not confirmed: the check sums again (the one-workgroup loop keeps its own
+    // in registers), then the decision without its termination test; both
+    // return at once when confirmed
+    HIPT(launch_check_reduce<T>(d, P->geo, P->stream));
+    HIPT(launch_check_decide<T>(d, P->geo, P->Nq, P->Nc, P->stream));
     HIPT(launch_check_apply<T>(d, P->geo, P->stream));
     get_ctl(P, d.ctl);
 }
@@ -769,6 +774,22 @@ template <typename T>
 void copy_dev(lp_problem *P, T *dst, const T *src, int64_t len)
 {
     if (len > 0) HIPT(hipMemcpyAsync(dst, src, sizeof(T) * (size_t)len, hipMemcpyDeviceToDevice, P->stream));
+}
+
+// The one-workgroup loop applies when both products are a single column
+// slice without long rows (their slice is then a plain CSR) and the option
+// asks for it: persistent = 1 always then; the default (-1) only when K, K'
+// and the gathered vectors fit in LDS, the case where it beats the
+// launches (without the LDS copies each thread walks its elements with a
+// round trip to L2 apiece, slower than the launches from a few thousand
+// columns on).
+template <typename T>
+bool small_loop_eligible(lp_problem *P)
+{
+    const Dev<T> &d = P->dev<T>();
+    if (P->opt.persistent == 0 || d.K.S != 1 || d.KT.S != 1 || d.K.nlong != 0 || d.KT.nlong != 0) return false;
+    return P->opt.persistent == 1 ||
+           small_stage_bytes<T>((int)P->m, (int)P->n, (int)P->nnz, (int)P->nnz) <= kSmallStageMax;
 }
 
 template <typename T>
@@ -857,6 +878,36 @@ int do_solve(lp_problem *P, double tol, int64_t max_iters, double time_limit)
         resolve_confirm<T>(P);
     }
     const int W = std::max(1, P->opt.window);
+    if (small_loop_eligible<T>(P)) {
+        // the whole loop in one workgroup: 64 W attempt slots per launch
+        for (; !P->hctl->done;) {
+            const long long k_before = P->hctl->k, a_before = P->hctl->attempts;
+            HIPT(launch_small_loop<T>(d, (int)P->nnz, (int)P->nnz, 64 * W, P->Nq, P->Nc, st));
+            get_ctl(P, d.ctl);
+            resolve_confirm<T>(P);
+            if (P->opt.verbose) trace_window(*P->hctl);
+            if (P->hctl->done) break;
+            if (P->hctl->k == k_before && P->hctl->attempts == a_before) {
+                P->err = "no step decision in a whole window (controller stalled)";
+                return LP_ERR_HIP;
+            }
+            if (time_limit > 0.0 &&
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count() > time_limit) {
+                Ctl c = *P->hctl;
+                c.mode = MODE_FINAL;
+                c.final_status = LP_TIME_LIMIT;
+                put_ctl(P, c, d.ctl);
+                run_check<T>(P);
+                get_ctl(P, d.ctl);
+                resolve_confirm<T>(P);
+                break;
+            }
+        }
+        sync(P);
+        P->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        P->has_result = true;
+        return LP_OK;
+    }
     // kernel_timing: 0 none; 1 events around the products of every window;
     // 2 only in the first window (plain launches), the rest replaying the
     // untimed graph
@@ -1179,6 +1230,7 @@ void lp_default_options(lp_options *o)
     o->autotune = 0;
     o->verbose = 0;
     o->infeas_tol = 1e-8;
+    o->persistent = -1;
 }
 
 int lp_workspace_size(const lp_csr *K, const lp_options *opt, size_t *bytes)

@@ -17,6 +17,8 @@ constexpr int kStreamNB = 2048;  // nonzeros staged in LDS per row block
 constexpr int kStreamRB = 1024;  // most rows per row block (each thread sums every 256th row)
 constexpr int kWaveRow = 64;     // rows longer than this are summed by a whole wavefront
 constexpr int kLongRow = 4 * kStreamNB;  // rows longer than this are cut into chunks
+constexpr int kSmall = 1024;     // threads of the one workgroup that runs a small LP's whole loop
+constexpr size_t kSmallStageMax = 150 * 1024;   // dynamic LDS of the staged loop (of 160 KiB per CU)
 constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;  // device scratch of lp_spmv_noalloc (64 MiB per GPU)
 // A row block is either a run of rows of at most kWaveRow entries (thread per
 // row) or up to kBlock/64 longer rows (wavefront per row); a wavefront block's
@@ -225,6 +227,20 @@ hipError_t noalloc_scratch(void **ptr);
 template <typename T>
 hipError_t launch_confirm(const Dev<T> &d, const Geo &g, const Conf64 &cf, int cur, double Nq, double Nc,
                           hipStream_t s);
+// Bytes of LDS the staged one-workgroup loop needs: K and K' (values,
+// columns, row pointers) and the two gathered vectors (the primal trial and
+// the dual trial), values first so they stay 8-byte aligned.
+template <typename T>
+__host__ __device__ inline size_t small_stage_bytes(int m, int n, int nnz_k, int nnz_t)
+{
+    return sizeof(T) * ((size_t)nnz_k + nnz_t + n + m) + sizeof(int) * ((size_t)m + 1 + nnz_k + n + 1 + nnz_t);
+}
+
+// attempt slots of a small LP in one workgroup (one column slice per product,
+// no long rows); K and K' (nnz_k, nnz_t entries) and the gathered vectors are
+// staged in LDS when they fit in kSmallStageMax bytes
+template <typename T> hipError_t launch_small_loop(const Dev<T> &d, int nnz_k, int nnz_t, int max_slots, double Nq,
+                                                   double Nc, hipStream_t s);
 template <typename T>
 hipError_t launch_gather_probe(const int *idx, const T *x, int64_t per_slice, int S, int64_t slice_len, T *out,
                                int grid, hipStream_t s);

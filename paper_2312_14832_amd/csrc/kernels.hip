@@ -277,6 +277,238 @@ __global__ __launch_bounds__(kBlock) void k_confirm_decide(Ctl *ctl, const doubl
     confirm_decision(ctl, S, Nq, Nc);
 }
 
+// ----------------------------------------------------------------------------
+// the whole loop of a small LP in one workgroup
+// ----------------------------------------------------------------------------
+
+// Sum NV values over the kSmall threads of the workgroup in a fixed order
+// (wavefront butterflies, then the wavefronts in index order); every thread
+// gets the totals.  Every thread must call it.
+template <int NV>
+__device__ __forceinline__ void small_sum(double (&v)[NV], double (*sh)[kCheckSums])
+{
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double a = v[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+        v[i] = a;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) sh[wave][i] = v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double t = sh[0][i];
+        for (int w = 1; w < kSmall / 64; ++w) t += sh[w][i];
+        v[i] = t;
+    }
+    __syncthreads();
+}
+
+// The decisions outside the loop body's register allocation: inlined, their
+// math calls would make the whole kernel spill.  Only thread 0 calls them.
+__device__ __noinline__ void small_step_decision(Ctl *c, double dx2, double dy2, double inter)
+{
+    step_decision(c, dx2, dy2, inter);
+}
+
+__device__ __noinline__ void small_check_decision(Ctl *c, const double *S, const double *R, double Nq, double Nc)
+{
+    check_decision(c, S, R, Nq, Nc);
+}
+
+// row r of a plain CSR (rp, ci, v) against x, entries in order; eight at a
+// time in straight-line phases so their loads overlap (slots past the row's
+// end re-read its last entry and are masked out of the sum)
+template <typename T>
+__device__ __forceinline__ T small_row(const int *__restrict__ rp, const int *__restrict__ ci,
+                                       const T *__restrict__ v, const T *__restrict__ x, int r)
+{
+    constexpr int U = 8;
+    const int e = rp[r + 1];
+    T acc = T(0);
+    for (int p = rp[r]; p < e; p += U) {
+        int c[U];
+        T a[U], g[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = min(p + u, e - 1);
+            c[u] = ci[t];
+            a[u] = v[t];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) g[u] = x[c[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (p + u < e) acc += a[u] * g[u];
+    }
+    return acc;
+}
+
+// Attempt slots of a small LP (both products one column slice, no long rows)
+// run by one workgroup until the LP is done or max_slots slots have passed.
+// Each slot is the multi-kernel slot's steps in order (K x' and the dual
+// step, the step decision, K'y' with the averages and next primal trial or
+// the new trial after a rejection, and at a check its sums, decision and
+// restart / output bookkeeping), with workgroup barriers in place of kernel
+// boundaries and the controller in LDS.  STAGE: K, K' and the vectors the
+// products gather (the primal trial x', the dual trial y') are kept in LDS,
+// so the products never leave the CU; every value written to a trial vector
+// goes to its LDS copy too.  |x' - x|^2 of the pending trial is recomputed
+// from the stored buffers at entry.
+template <typename T, bool STAGE>
+__global__ __launch_bounds__(kSmall) void k_small_loop(Dev<T> d, int max_slots, double Nq, double Nc)
+{
+    extern __shared__ double dyn[];
+    __shared__ Ctl sc;
+    __shared__ double sh[kSmall / 64][kCheckSums];
+    const int tid = (int)threadIdx.x;
+    const int nk = d.K.rp[d.m], nt = d.KT.rp[d.n];
+    const int *krp = d.K.rp, *kci = d.K.ci, *trp = d.KT.rp, *tci = d.KT.ci;
+    const T *kv = d.K.v, *tv = d.KT.v;
+    T *sx = nullptr, *sy = nullptr;
+    if constexpr (STAGE) {
+        T *tb = reinterpret_cast<T *>(dyn);
+        T *skv = tb, *stv = skv + nk;
+        sx = stv + nt;
+        sy = sx + d.n;
+        int *ib = reinterpret_cast<int *>(sy + d.m);
+        int *skrp = ib, *skci = skrp + d.m + 1, *strp = skci + nk, *stci = strp + d.n + 1;
+        for (int t = tid; t < nk; t += kSmall) {
+            skv[t] = kv[t];
+            skci[t] = kci[t];
+        }
+        for (int t = tid; t < nt; t += kSmall) {
+            stv[t] = tv[t];
+            stci[t] = tci[t];
+        }
+        for (int t = tid; t <= d.m; t += kSmall) skrp[t] = krp[t];
+        for (int t = tid; t <= d.n; t += kSmall) strp[t] = trp[t];
+        krp = skrp; kci = skci; kv = skv;
+        trp = strp; tci = stci; tv = stv;
+    }
+    if (tid == 0) sc = *d.ctl;
+    __syncthreads();
+    double dx2 = 0.0;
+    {
+        const T *x = pick(d.xb, sc.cur), *xt = pick(d.xb, sc.cur ^ 1);
+        for (int j = tid; j < d.n; j += kSmall) {
+            const T v = xt[j];
+            if constexpr (STAGE) sx[j] = v;
+            const double dd = (double)v - (double)x[j];
+            dx2 += dd * dd;
+        }
+    }
+    __syncthreads();
+    for (int slot = 0; slot < max_slots; ++slot) {
+        if (sc.done) break;   // the same LDS value for every thread
+        {
+            // K x' and the dual step (the arithmetic of DualEpi)
+            const int c = sc.cur;
+            const T *xg = STAGE ? (const T *)sx : (const T *)pick(d.xb, c ^ 1);
+            const T *y = pick(d.yb, c), *kx = pick(d.Kxb, c);
+            T *yn = pick(d.yb, c ^ 1), *kxn = pick(d.Kxb, c ^ 1);
+            const T sigma = (T)(sc.eta * sc.omega);
+            double v[3] = {dx2, 0.0, 0.0};
+            for (int i = tid; i < d.m; i += kSmall) {
+                const T yo = y[i], ko = kx[i], qi = d.qs[i];
+                const T s = small_row(krp, kci, kv, xg, i);
+                T val = yo + sigma * (qi - T(2) * s + ko);
+                if (i >= d.m1 && val < T(0)) val = T(0);
+                yn[i] = val;
+                kxn[i] = s;
+                if constexpr (STAGE) sy[i] = val;
+                const double dd = (double)val - (double)yo;
+                v[1] += dd * dd;
+                v[2] += dd * ((double)s - (double)ko);
+            }
+            small_sum<3>(v, sh);
+            if (tid == 0) small_step_decision(&sc, v[0], v[1], v[2]);
+            __syncthreads();
+        }
+        {
+            const int c = sc.cur;
+            const T tau = (T)(sc.eta / sc.omega);
+            T *xn = pick(d.xb, c ^ 1);
+            const T *x = pick(d.xb, c);
+            dx2 = 0.0;
+            if (!sc.accepted) {
+                // a new primal trial from the same point with the smaller step
+                for (int j = tid; j < d.n; j += kSmall) {
+                    const T xj = x[j];
+                    const T nv = clampv(xj - tau * (d.cs[j] - pick(d.KTyb, c)[j]), d.ls[j], d.us[j]);
+                    xn[j] = nv;
+                    if constexpr (STAGE) sx[j] = nv;
+                    const double dd = (double)nv - (double)xj;
+                    dx2 += dd * dd;
+                }
+            } else {
+                // K'y', the averages and the next primal trial (the arithmetic of UpdateEpi)
+                const T *yg = STAGE ? (const T *)sy : (const T *)pick(d.yb, c);
+                T *kty = pick(d.KTyb, c);
+                const T w = (T)sc.avg_w;
+                const bool primal = sc.mode == MODE_NONE;
+                for (int j = tid; j < d.n; j += kSmall) {
+                    const T xj = x[j], a = d.xa[j], b = d.KTya[j];
+                    const T s = small_row(trp, tci, tv, yg, j);
+                    kty[j] = s;
+                    d.xa[j] = a + w * (xj - a);
+                    d.KTya[j] = b + w * (s - b);
+                    if (primal) {
+                        const T nv = clampv(xj - tau * (d.cs[j] - s), d.ls[j], d.us[j]);
+                        xn[j] = nv;
+                        if constexpr (STAGE) sx[j] = nv;
+                        const double dd = (double)nv - (double)xj;
+                        dx2 += dd * dd;
+                    }
+                }
+                for (int i = tid; i < d.m; i += kSmall) average_row(d, i, c, w);
+            }
+            __syncthreads();
+        }
+        if (sc.mode != MODE_NONE) {
+            const int c = sc.cur;
+            double cs[kCheckSums], rs[kRaySums];
+            const T *x = pick(d.xb, c), *kty = pick(d.KTyb, c), *y = pick(d.yb, c), *kx = pick(d.Kxb, c);
+#pragma unroll
+            for (int k = 0; k < kCheckSums; ++k) cs[k] = 0.0;
+#pragma unroll
+            for (int k = 0; k < kRaySums; ++k) rs[k] = 0.0;
+            for (int j = tid; j < d.n; j += kSmall) {
+                col_sums(d, j, x, kty, cs);
+                col_sums(d, j, (const T *)d.xa, (const T *)d.KTya, cs + 9);
+                ray_col_sums(d, j, x, kty, rs);
+            }
+            for (int i = tid; i < d.m; i += kSmall) {
+                row_sums(d, i, d.m1, y, kx, cs);
+                row_sums(d, i, d.m1, (const T *)d.ya, (const T *)d.Kxa, cs + 9);
+                ray_row_sums(d, i, d.m1, y, kx, rs);
+            }
+            small_sum<kCheckSums>(cs, sh);
+            small_sum<kRaySums>(rs, sh);
+            if (tid == 0) small_check_decision(&sc, cs, rs, Nq, Nc);
+            __syncthreads();
+            const int rt = sc.restart_to, co = sc.copy_out, sel = sc.out_sel, np = sc.need_primal;
+            const T tau = (T)(sc.eta / sc.omega);
+            dx2 = 0.0;
+            for (int j = tid; j < d.n; j += kSmall) {
+                apply_col(d, j, c, rt, co, sel, np, tau, dx2);
+                // each thread re-reads only the trial entries it wrote itself
+                if constexpr (STAGE) {
+                    if (np) sx[j] = pick(d.xb, c ^ 1)[j];
+                }
+            }
+            for (int i = tid; i < d.m; i += kSmall) apply_row(d, i, c, rt, co, sel);
+            __syncthreads();
+        }
+    }
+    if (tid == 0) *d.ctl = sc;
+}
+
 // Gather-rate probe (a measurement helper, not a step of the method): the
 // access pattern of a sliced product's gathers without its matrix.  Indices
 // are slice-major, count / S per slice, local to the slice; workgroup b
@@ -641,6 +873,26 @@ hipError_t launch_confirm(const Dev<T> &d, const Geo &g, const Conf64 &cf, int c
 }
 
 template <typename T>
+hipError_t launch_small_loop(const Dev<T> &d, int nnz_k, int nnz_t, int max_slots, double Nq, double Nc,
+                             hipStream_t s)
+{
+    const size_t lds = small_stage_bytes<T>(d.m, d.n, nnz_k, nnz_t);
+    if (lds <= kSmallStageMax) {
+        static bool attr_set = false;   // the kernel's LDS limit raised once per process
+        if (!attr_set) {
+            const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_small_loop<T, true>),
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallStageMax);
+            if (e != hipSuccess) return e;
+            attr_set = true;
+        }
+        hipLaunchKernelGGL((k_small_loop<T, true>), dim3(1), dim3(kSmall), lds, s, d, max_slots, Nq, Nc);
+    } else {
+        hipLaunchKernelGGL((k_small_loop<T, false>), dim3(1), dim3(kSmall), 0, s, d, max_slots, Nq, Nc);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_gather_probe(const int *idx, const T *x, int64_t per_slice, int S, int64_t slice_len, T *out,
                                int grid, hipStream_t s)
 {
@@ -839,6 +1091,7 @@ hipError_t scale_csr_pair(const int *rp, const int *ci, double *kv, int m, const
     template hipError_t launch_check_apply<T>(const Dev<T> &, const Geo &, hipStream_t);                           \
     template hipError_t launch_spmv<T>(const Sliced<T> &, const T *, T *, hipStream_t);                            \
     template hipError_t launch_gather_probe<T>(const int *, const T *, int64_t, int, int64_t, T *, int, hipStream_t); \
+    template hipError_t launch_small_loop<T>(const Dev<T> &, int, int, int, double, double, hipStream_t);        \
     template hipError_t launch_confirm<T>(const Dev<T> &, const Geo &, const Conf64 &, int, double, double,       \
                                           hipStream_t);                                                           \
     template hipError_t launch_gather_values<T>(const double *, const int *, T *, int64_t, hipStream_t);           \

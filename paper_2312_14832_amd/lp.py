@@ -47,7 +47,7 @@ class LPOptions(C.Structure):
                 ("window", C.c_int), ("kernel_timing", C.c_int), ("slice_kib", C.c_int),
                 ("autotune", C.c_int), ("verbose", C.c_int), ("ptr_kind", C.c_int),
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t), ("infeas_tol", C.c_double),
-                ("presolve", C.c_int)]
+                ("presolve", C.c_int), ("persistent", C.c_int)]
 
 
 class LPInfo(C.Structure):

@@ -87,15 +87,18 @@ def long_rows_lp(seed):
 LOCKSTEP_POINTS = [0, 1, 2, 7, 62, 63, 64, 65, 100, 126, 127, 128, 191, 255, 300, 383, 511, 640, 767, 900, 1023]
 
 
-@pytest.mark.parametrize("seed,slice_kib,n", [(0, 2048, 0), (1, 2048, 0), (2, 1, 0), (4, 1, 2000), (5, 1, 20000)])
-def test_lockstep_one_step_fp64(lpmod, oracle_mod, seed, slice_kib, n):
+@pytest.mark.parametrize("seed,slice_kib,n,persistent", [(0, 2048, 0, 1), (0, 2048, 0, 0), (1, 2048, 0, 1),
+                                                         (1, 2048, 0, 0), (2, 1, 0, -1), (4, 1, 2000, -1),
+                                                         (5, 1, 20000, -1)])
+def test_lockstep_one_step_fp64(lpmod, oracle_mod, seed, slice_kib, n, persistent):
     """Per-iteration parity: from the oracle's state after k accepted steps,
     one more accepted step on the GPU (including the check and restart that
     fall on k+1) equals the oracle's next state.  n > 0 takes a power-law LP
     of that size: with 1 KiB slices, 16 and 32 column slices (the epilogue's
-    compile-time and run-time slice-count paths)."""
+    compile-time and run-time slice-count paths).  persistent = 1 runs the
+    tiny LP's slots in the one-workgroup loop, 0 as seven launches each."""
     data = gen.tiny_lp(seed) if n == 0 else gen.large_lp(seed=seed, n=n, m1=n // 4, m2=n // 4)
-    p = lpmod.Problem(data, slice_kib=slice_kib)
+    p = lpmod.Problem(data, slice_kib=slice_kib, persistent=persistent)
     if n == 2000:
         assert p.layout()[0] == 16
     if n == 20000:
@@ -126,11 +129,11 @@ def test_lockstep_one_step_fp64(lpmod, oracle_mod, seed, slice_kib, n):
         say("k=%5d kappa=%9.3g  vec %9.2e (%s)  scalar %9.2e (%s)" % r)
 
 
-@pytest.mark.parametrize("seed", [0, 3])
-def test_lockstep_windows_fp64(lpmod, oracle_mod, seed):
+@pytest.mark.parametrize("seed,persistent", [(0, 1), (0, 0), (3, 1), (3, 0)])
+def test_lockstep_windows_fp64(lpmod, oracle_mod, seed, persistent):
     """Short windows of 8 accepted steps that straddle checks and restarts."""
     data = gen.tiny_lp(seed)
-    p = lpmod.Problem(data)
+    p = lpmod.Problem(data, persistent=persistent)
     o = oracle_mod.Oracle(data)
     Dr, Dc, _ = o.scaling()
     for k in [60, 124, 188, 252, 316, 508, 764]:
@@ -148,8 +151,8 @@ def test_lockstep_windows_fp64(lpmod, oracle_mod, seed):
         assert_states_close(sg, so, step_condition(prev, so), f"window k={k}", kkt_scale(so, Dr, Dc, data))
 
 
-@pytest.mark.parametrize("seed", [0, 2])
-def test_free_running_trajectory(lpmod, oracle_mod, seed):
+@pytest.mark.parametrize("seed,persistent", [(0, 1), (0, 0), (2, 1)])
+def test_free_running_trajectory(lpmod, oracle_mod, seed, persistent):
     """Fresh GPU runs of k steps against the oracle.  Up to k=120 the two agree
     to 1e-10.  Later the method itself amplifies rounding (the adaptive step
     divides by norms of iterate differences): there the GPU must stay inside
@@ -157,7 +160,7 @@ def test_free_running_trajectory(lpmod, oracle_mod, seed):
     perturbed by 1e-15 (x100 margin), i.e. it behaves as an ulp perturbation.
     Within the first check window the 1e-10 bar holds outright."""
     data = gen.tiny_lp(seed)
-    p = lpmod.Problem(data)
+    p = lpmod.Problem(data, persistent=persistent)
     o = oracle_mod.Oracle(data)
     o.solve(1e-30, 1)
     raw1 = o.get_state_raw()
@@ -247,8 +250,8 @@ def test_resume_is_bitwise(lpmod):
 def test_deterministic_and_graph_equals_stream(lpmod):
     say("case determinism")
     data = gen.tiny_lp(6)
-    a = lpmod.Problem(data, use_graph=1)
-    b = lpmod.Problem(data, use_graph=0)
+    a = lpmod.Problem(data, use_graph=1, persistent=0)
+    b = lpmod.Problem(data, use_graph=0, persistent=0)
     a.solve(1e-30, 500)
     s1 = a.get_state()
     a.solve(1e-30, 500)
@@ -259,6 +262,29 @@ def test_deterministic_and_graph_equals_stream(lpmod):
     assert np.array_equal(s1, s3)
 
 
+def test_one_workgroup_loop_is_deterministic_and_matches_launches(lpmod):
+    """The one-workgroup loop repeats itself bit for bit, resumes bit for bit
+    across its own window boundaries (window = 1: 64 slots per launch), and
+    agrees with the seven-launch slots to 1e-10 over the first 64 steps (only
+    the summation order of the reductions differs)."""
+    say("case one-workgroup loop")
+    data = gen.tiny_lp(7)
+    a = lpmod.Problem(data, persistent=1)
+    b = lpmod.Problem(data, persistent=1, window=1)
+    c = lpmod.Problem(data, persistent=0)
+    a.solve(1e-30, 500)
+    s1 = a.get_state()
+    a.solve(1e-30, 500)
+    assert np.array_equal(s1, a.get_state())
+    b.solve(1e-30, 500)
+    assert np.array_equal(s1, b.get_state())
+    a.solve(1e-30, 64)
+    c.solve(1e-30, 64)
+    sa, sc = gpu_state(lpmod, a), gpu_state(lpmod, c)
+    assert ints_equal(sa, sc)
+    assert vec_diff(sa, sc)[0] < PER_STEP_TOL
+
+
 def test_kernel_timing_modes_agree(lpmod):
     """Event timing changes nothing computed: modes 0 (graph), 1 (events in
     every window) and 2 (events in the first window, then the graph) give
@@ -267,7 +293,7 @@ def test_kernel_timing_modes_agree(lpmod):
     data = gen.tiny_lp(6)
     states, counts = [], []
     for mode in (0, 1, 2):
-        p = lpmod.Problem(data, kernel_timing=mode)
+        p = lpmod.Problem(data, kernel_timing=mode, persistent=0)
         p.solve(1e-30, 640)
         states.append(p.get_state())
         counts.append([p.kernel_time(w) for w in (0, 1)])
