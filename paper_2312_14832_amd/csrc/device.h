@@ -281,44 +281,55 @@ __device__ __forceinline__ void primal_elem(const Dev<T> &d, int c, T tau, int j
 
 // the 9 check sums of one iterate; s[0..3] rows, s[4..8] columns:
 // |r_p|^2 unscaled, |r_p|^2 scaled, q'y, |y-y0|^2,
-// |r_d|^2 unscaled, |r_d|^2 scaled, c'x, l'lam+ - u'lam-, |x-x0|^2
-template <typename T>
-__device__ __forceinline__ void row_sums(const Dev<T> &d, int i, int m1, const T *y, const T *kx, double *s)
+// |r_d|^2 unscaled, |r_d|^2 scaled, c'x, l'lam+ - u'lam-, |x-x0|^2.
+// The *_v forms take the element's values (k = (K x)_i, g_kty = (K'y)_j);
+// the array forms read them.
+__device__ __forceinline__ void row_sums_v(double k, double q, double Dr, double yi, double y0i, bool ineq,
+                                           double *s)
 {
-    const double k = (double)kx[i], q = (double)d.qs[i];
     double r = k - q;
-    if (i >= m1) {
+    if (ineq) {
         const double t = q - k;
         r = t > 0.0 ? t : 0.0;
     }
-    const double ru = r * d.Dr[i];
+    const double ru = r * Dr;
     s[0] += ru * ru;
     s[1] += r * r;
-    const double yi = (double)y[i];
     s[2] += q * yi;
-    const double dd = yi - (double)d.y0[i];
+    const double dd = yi - y0i;
     s[3] += dd * dd;
 }
 
-template <typename T>
-__device__ __forceinline__ void col_sums(const Dev<T> &d, int j, const T *x, const T *kty, double *s)
+__device__ __forceinline__ void col_sums_v(double cj, double lj, double uj, double Dc, double kty, double xj,
+                                           double x0j, double *s)
 {
-    const double cj = (double)d.cs[j], lj = (double)d.ls[j], uj = (double)d.us[j];
     const bool lf = isfinite(lj), uf = isfinite(uj);
-    const double g = cj - (double)kty[j];
+    const double g = cj - kty;
     const double lam = proj_lambda(g, lf, uf);
     const double rd = g - lam;
-    const double rdu = rd * d.Dc[j];
+    const double rdu = rd * Dc;
     s[4] += rdu * rdu;
     s[5] += rd * rd;
-    const double xj = (double)x[j];
     s[6] += cj * xj;
     double b = 0.0;
     if (lf && lam > 0.0) b += lj * lam;
     if (uf && lam < 0.0) b += uj * lam;
     s[7] += b;
-    const double dd = xj - (double)d.x0[j];
+    const double dd = xj - x0j;
     s[8] += dd * dd;
+}
+
+template <typename T>
+__device__ __forceinline__ void row_sums(const Dev<T> &d, int i, int m1, const T *y, const T *kx, double *s)
+{
+    row_sums_v((double)kx[i], (double)d.qs[i], d.Dr[i], (double)y[i], (double)d.y0[i], i >= m1, s);
+}
+
+template <typename T>
+__device__ __forceinline__ void col_sums(const Dev<T> &d, int j, const T *x, const T *kty, double *s)
+{
+    col_sums_v((double)d.cs[j], (double)d.ls[j], (double)d.us[j], d.Dc[j], (double)kty[j], (double)x[j],
+               (double)d.x0[j], s);
 }
 
 // The 4 ray sums of the current iterate (difference from the anchor, taken
@@ -326,43 +337,67 @@ __device__ __forceinline__ void col_sums(const Dev<T> &d, int j, const T *x, con
 // objectives): s[0] c'd, s[1] |(A d, max(-G d, 0), bound-cone violation)|^2,
 // s[2] q'w + l'lam+ - u'lam- with lam = proj_Lambda(-K'w),
 // s[3] |(-K'w - lam, min(w_G, 0))|^2; d = (x - x0)/Dc, w = (y - y0)/Dr.
+__device__ __forceinline__ void ray_row_sums_v(double kx, double kx0, double Dr, double yi, double y0i, double q,
+                                               bool ineq, double *s)
+{
+    const double kd = (kx - kx0) * Dr;
+    double r = kd;
+    if (ineq) r = -kd > 0.0 ? -kd : 0.0;
+    s[1] += r * r;
+    const double dy = yi - y0i;
+    s[2] += q * dy;
+    if (ineq) {
+        const double w = dy / Dr;
+        if (w < 0.0) s[3] += w * w;
+    }
+}
+
+__device__ __forceinline__ void ray_col_sums_v(double cj, double lj, double uj, double Dc, double xj, double x0j,
+                                               double kty, double kty0, double *s)
+{
+    const bool lf = isfinite(lj), uf = isfinite(uj);
+    const double dx = xj - x0j;
+    s[0] += cj * dx;
+    const double dj = dx / Dc;
+    if ((lf && dj < 0.0) || (uf && dj > 0.0)) s[1] += dj * dj;
+    const double g = kty0 - kty;
+    const double lam = proj_lambda(g, lf, uf);
+    const double r = (g - lam) * Dc;
+    s[3] += r * r;
+    if (lf && lam > 0.0) s[2] += lj * lam;
+    if (uf && lam < 0.0) s[2] += uj * lam;
+}
+
 template <typename T>
 __device__ __forceinline__ void ray_row_sums(const Dev<T> &d, int i, int m1, const T *y, const T *kx, double *s)
 {
-    const double kd = ((double)kx[i] - (double)d.Kx0[i]) * d.Dr[i];
-    double r = kd;
-    if (i >= m1) r = -kd > 0.0 ? -kd : 0.0;
-    s[1] += r * r;
-    const double dy = (double)y[i] - (double)d.y0[i];
-    s[2] += (double)d.qs[i] * dy;
-    if (i >= m1) {
-        const double w = dy / d.Dr[i];
-        if (w < 0.0) s[3] += w * w;
-    }
+    ray_row_sums_v((double)kx[i], (double)d.Kx0[i], d.Dr[i], (double)y[i], (double)d.y0[i], (double)d.qs[i],
+                   i >= m1, s);
 }
 
 template <typename T>
 __device__ __forceinline__ void ray_col_sums(const Dev<T> &d, int j, const T *x, const T *kty, double *s)
 {
-    const double lj = (double)d.ls[j], uj = (double)d.us[j];
-    const bool lf = isfinite(lj), uf = isfinite(uj);
-    const double dx = (double)x[j] - (double)d.x0[j];
-    s[0] += (double)d.cs[j] * dx;
-    const double dj = dx / d.Dc[j];
-    if ((lf && dj < 0.0) || (uf && dj > 0.0)) s[1] += dj * dj;
-    const double g = (double)d.KTy0[j] - (double)kty[j];
-    const double lam = proj_lambda(g, lf, uf);
-    const double r = (g - lam) * d.Dc[j];
-    s[3] += r * r;
-    if (lf && lam > 0.0) s[2] += lj * lam;
-    if (uf && lam < 0.0) s[2] += uj * lam;
+    ray_col_sums_v((double)d.cs[j], (double)d.ls[j], (double)d.us[j], d.Dc[j], (double)x[j], (double)d.x0[j],
+                   (double)kty[j], (double)d.KTy0[j], s);
 }
 
 // Adaptive step-size test (PDLP's rule; the paper uses eta without stating
 // the rule): eta_bar = (omega|dx|^2 + |dy|^2/omega) / (2|dy.K dx|),
 // eta' = min((1-kk^-0.3) eta_bar, (1+kk^-0.6) eta) with kk counting from 2;
 // accept iff eta <= eta_bar.  Called by one thread per LP.
-__device__ inline void step_decision(Ctl *ctl, double dx2, double dy2, double inter)
+// The two factors of the step rule at accepted count k: 1 - kk^-0.3 and
+// 1 + kk^-0.6 with kk = k + 2.
+__device__ inline void step_factors(long long k, double &f_lo, double &f_hi)
+{
+    const double kk = (double)(k + 1) + 1.0;
+    f_lo = 1.0 - pow(kk, -0.3);
+    f_hi = 1.0 + pow(kk, -0.6);
+}
+
+// The step decision with the factors of the current accepted count given
+// (step_factors), for callers that tabulate them ahead.
+__device__ inline void step_decision_f(Ctl *ctl, double dx2, double dy2, double inter, double f_lo, double f_hi)
 {
     const double eta = ctl->eta, omega = ctl->omega;
     double eta_new = eta;
@@ -378,9 +413,8 @@ __device__ inline void step_decision(Ctl *ctl, double dx2, double dy2, double in
             return;
         }
         const double eta_bar = D > 0.0 ? N / D : INFINITY;
-        const double kk = (double)(ctl->k + 1) + 1.0;
-        const double lo = (1.0 - pow(kk, -0.3)) * eta_bar;
-        const double hi = (1.0 + pow(kk, -0.6)) * eta;
+        const double lo = f_lo * eta_bar;
+        const double hi = f_hi * eta;
         eta_new = lo < hi ? lo : hi;
         accept = eta <= eta_bar;
     }
@@ -398,6 +432,13 @@ __device__ inline void step_decision(Ctl *ctl, double dx2, double dy2, double in
         ctl->mode = MODE_NONE;
     }
     ctl->eta = eta_new;
+}
+
+__device__ inline void step_decision(Ctl *ctl, double dx2, double dy2, double inter)
+{
+    double f_lo = 0.0, f_hi = 0.0;
+    if (!ctl->fixed_step) step_factors(ctl->k, f_lo, f_hi);
+    step_decision_f(ctl, dx2, dy2, inter, f_lo, f_hi);
 }
 
 // The termination quantities (unscaled) and KKT_omega (scaled) of the

@@ -18,7 +18,9 @@ constexpr int kStreamRB = 1024;  // most rows per row block (each thread sums ev
 constexpr int kWaveRow = 64;     // rows longer than this are summed by a whole wavefront
 constexpr int kLongRow = 4 * kStreamNB;  // rows longer than this are cut into chunks
 constexpr int kSmall = 1024;     // threads of the one workgroup that runs a small LP's whole loop
+constexpr int kSmallReg = 512;   // threads of its registers-per-thread form (two columns and rows each at most)
 constexpr size_t kSmallStageMax = 150 * 1024;   // dynamic LDS of the staged loop (of 160 KiB per CU)
+constexpr size_t kSmallRegLds = 156 * 1024;     // dynamic LDS of the registers-per-thread loop (stage + table)
 constexpr size_t kNoallocScratchBytes = (size_t)64 << 20;  // device scratch of lp_spmv_noalloc (64 MiB per GPU)
 // A row block is either a run of rows of at most kWaveRow entries (thread per
 // row) or up to kBlock/64 longer rows (wavefront per row); a wavefront block's

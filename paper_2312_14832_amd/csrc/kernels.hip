@@ -284,7 +284,7 @@ __global__ __launch_bounds__(kBlock) void k_confirm_decide(Ctl *ctl, const doubl
 // Sum NV values over the kSmall threads of the workgroup in a fixed order
 // (wavefront butterflies, then the wavefronts in index order); every thread
 // gets the totals.  Every thread must call it.
-template <int NV>
+template <int NV, int NT = kSmall>
 __device__ __forceinline__ void small_sum(double (&v)[NV], double (*sh)[kCheckSums])
 {
     const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
@@ -303,7 +303,7 @@ __device__ __forceinline__ void small_sum(double (&v)[NV], double (*sh)[kCheckSu
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
         double t = sh[0][i];
-        for (int w = 1; w < kSmall / 64; ++w) t += sh[w][i];
+        for (int w = 1; w < NT / 64; ++w) t += sh[w][i];
         v[i] = t;
     }
     __syncthreads();
@@ -324,11 +324,10 @@ __device__ __noinline__ void small_check_decision(Ctl *c, const double *S, const
 // row r of a plain CSR (rp, ci, v) against x, entries in order; eight at a
 // time in straight-line phases so their loads overlap (slots past the row's
 // end re-read its last entry and are masked out of the sum)
-template <typename T>
+template <typename T, int U = 8>
 __device__ __forceinline__ T small_row(const int *__restrict__ rp, const int *__restrict__ ci,
                                        const T *__restrict__ v, const T *__restrict__ x, int r)
 {
-    constexpr int U = 8;
     const int e = rp[r + 1];
     T acc = T(0);
     for (int p = rp[r]; p < e; p += U) {
@@ -504,6 +503,258 @@ __global__ __launch_bounds__(kSmall) void k_small_loop(Dev<T> d, int max_slots, 
             }
             for (int i = tid; i < d.m; i += kSmall) apply_row(d, i, c, rt, co, sel);
             __syncthreads();
+        }
+    }
+    if (tid == 0) *d.ctl = sc;
+}
+
+// The one-workgroup loop for LPs with at most R * kSmallReg rows and
+// columns, K and K' staged in LDS as above: thread t owns columns and rows
+// t + r kSmallReg (r < R), and every vector entry of them (current point,
+// primal trial, K'y and K x, the averages, the data) stays in its registers
+// for the whole launch; they are loaded at entry and stored back at exit in
+// the layout of the multi-kernel path (the current buffer and the pending
+// primal trial).  The anchor and the scaling factors, read only at checks,
+// stay in memory.  Only the two trial vectors the products gather go
+// through LDS.  The arithmetic is that of the element functions: the dual
+// step of DualEpi, the averages and trial of UpdateEpi and primal_elem, the
+// sums of row_sums_v / col_sums_v / ray_*_v, the bookkeeping of apply_col /
+// apply_row.  The step rule's two factors for the accepted counts this
+// launch can reach (at most max_slots of them) are tabulated in LDS at
+// entry, so the per-slot decision is plain arithmetic in thread 0, inline.
+// kSmallReg threads (fewer than the other forms) leave each thread enough
+// registers to hold its R columns and rows without spilling.
+template <typename T, int R>
+__global__ __launch_bounds__(kSmallReg) void k_small_reg(Dev<T> d, int max_slots, double Nq, double Nc)
+{
+    constexpr int NT = kSmallReg;
+    extern __shared__ double dyn[];
+    __shared__ Ctl sc;
+    __shared__ double sh[NT / 64][kCheckSums];
+    const int tid = (int)threadIdx.x;
+    const int nk = d.K.rp[d.m], nt = d.KT.rp[d.n];
+    T *skv = reinterpret_cast<T *>(dyn), *stv = skv + nk;
+    T *sx = stv + nt, *sy = sx + d.n;
+    int *skrp = reinterpret_cast<int *>(sy + d.m), *skci = skrp + d.m + 1, *strp = skci + nk, *stci = strp + d.n + 1;
+    double *tab = dyn + (small_stage_bytes<T>(d.m, d.n, nk, nt) + 7) / 8;   // [max_slots][2]
+    for (int t = tid; t < nk; t += NT) {
+        skv[t] = d.K.v[t];
+        skci[t] = d.K.ci[t];
+    }
+    for (int t = tid; t < nt; t += NT) {
+        stv[t] = d.KT.v[t];
+        stci[t] = d.KT.ci[t];
+    }
+    for (int t = tid; t <= d.m; t += NT) skrp[t] = d.K.rp[t];
+    for (int t = tid; t <= d.n; t += NT) strp[t] = d.KT.rp[t];
+    if (tid == 0) sc = *d.ctl;
+    __syncthreads();
+    const long long k0 = sc.k;
+    for (int t = tid; t < max_slots; t += NT) step_factors(k0 + t, tab[2 * t], tab[2 * t + 1]);
+    // columns j = tid + r NT, rows i = tid + r NT
+    T xc[R], xt[R], ktc[R], xa[R], kta[R], cj[R], lj[R], uj[R];
+    T yc[R], kxc[R], ya[R], kxa[R], qi[R], yt[R], kxt[R];
+    double dx2 = 0.0;
+    {
+        const int c = sc.cur;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int j = tid + r * NT, i = j;
+            xc[r] = xt[r] = ktc[r] = xa[r] = kta[r] = cj[r] = lj[r] = uj[r] = T(0);
+            yc[r] = kxc[r] = ya[r] = kxa[r] = qi[r] = yt[r] = kxt[r] = T(0);
+            if (j < d.n) {
+                xc[r] = pick(d.xb, c)[j];
+                xt[r] = pick(d.xb, c ^ 1)[j];
+                ktc[r] = pick(d.KTyb, c)[j];
+                xa[r] = d.xa[j]; kta[r] = d.KTya[j];
+                cj[r] = d.cs[j]; lj[r] = d.ls[j]; uj[r] = d.us[j];
+                sx[j] = xt[r];
+                const double dd = (double)xt[r] - (double)xc[r];
+                dx2 += dd * dd;
+            }
+            if (i < d.m) {
+                yc[r] = pick(d.yb, c)[i];
+                kxc[r] = pick(d.Kxb, c)[i];
+                ya[r] = d.ya[i]; kxa[r] = d.Kxa[i];
+                qi[r] = d.qs[i];
+            }
+        }
+    }
+    __syncthreads();
+    for (int slot = 0; slot < max_slots; ++slot) {
+        if (sc.done) break;   // the same LDS value for every thread
+        {
+            // K x' and the dual step
+            const T sigma = (T)(sc.eta * sc.omega);
+            double v[3] = {dx2, 0.0, 0.0};
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int i = tid + r * NT;
+                if (i < d.m) {
+                    const T s = small_row<T, 4>(skrp, skci, skv, (const T *)sx, i);
+                    T val = yc[r] + sigma * (qi[r] - T(2) * s + kxc[r]);
+                    if (i >= d.m1 && val < T(0)) val = T(0);
+                    yt[r] = val;
+                    kxt[r] = s;
+                    sy[i] = val;
+                    const double dd = (double)val - (double)yc[r];
+                    v[1] += dd * dd;
+                    v[2] += dd * ((double)s - (double)kxc[r]);
+                }
+            }
+            small_sum<3, NT>(v, sh);
+            if (tid == 0) {
+                const int at = (int)(sc.k - k0);   // < max_slots: one accepted step per slot at most
+                step_decision_f(&sc, v[0], v[1], v[2], tab[2 * at], tab[2 * at + 1]);
+            }
+            __syncthreads();
+        }
+        {
+            const T tau = (T)(sc.eta / sc.omega);
+            dx2 = 0.0;
+            if (!sc.accepted) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int j = tid + r * NT;
+                    if (j < d.n) {
+                        const T nv = clampv(xc[r] - tau * (cj[r] - ktc[r]), lj[r], uj[r]);
+                        xt[r] = nv;
+                        sx[j] = nv;
+                        const double dd = (double)nv - (double)xc[r];
+                        dx2 += dd * dd;
+                    }
+                }
+            } else {
+                // the trials become the current point; K'y', averages, next trial
+                const T w = (T)sc.avg_w;
+                const bool primal = sc.mode == MODE_NONE;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int i = tid + r * NT, j = i;
+                    if (i < d.m) {
+                        yc[r] = yt[r];
+                        kxc[r] = kxt[r];
+                        ya[r] = ya[r] + w * (yc[r] - ya[r]);
+                        kxa[r] = kxa[r] + w * (kxc[r] - kxa[r]);
+                    }
+                    if (j < d.n) {
+                        xc[r] = xt[r];
+                        const T s = small_row<T, 4>(strp, stci, stv, (const T *)sy, j);
+                        ktc[r] = s;
+                        xa[r] = xa[r] + w * (xc[r] - xa[r]);
+                        kta[r] = kta[r] + w * (s - kta[r]);
+                        if (primal) {
+                            const T nv = clampv(xc[r] - tau * (cj[r] - s), lj[r], uj[r]);
+                            xt[r] = nv;
+                            sx[j] = nv;
+                            const double dd = (double)nv - (double)xc[r];
+                            dx2 += dd * dd;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (sc.mode != MODE_NONE) {
+            double cs[kCheckSums], rs[kRaySums];
+#pragma unroll
+            for (int k = 0; k < kCheckSums; ++k) cs[k] = 0.0;
+#pragma unroll
+            for (int k = 0; k < kRaySums; ++k) rs[k] = 0.0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int i = tid + r * NT, j = i;
+                if (j < d.n) {
+                    const double x0 = (double)d.x0[j], kt0 = (double)d.KTy0[j], Dcj = d.Dc[j];
+                    col_sums_v((double)cj[r], (double)lj[r], (double)uj[r], Dcj, (double)ktc[r], (double)xc[r], x0,
+                               cs);
+                    col_sums_v((double)cj[r], (double)lj[r], (double)uj[r], Dcj, (double)kta[r], (double)xa[r], x0,
+                               cs + 9);
+                    ray_col_sums_v((double)cj[r], (double)lj[r], (double)uj[r], Dcj, (double)xc[r], x0,
+                                   (double)ktc[r], kt0, rs);
+                }
+                if (i < d.m) {
+                    const double y0 = (double)d.y0[i], kx0 = (double)d.Kx0[i], Dri = d.Dr[i];
+                    const bool ineq = i >= d.m1;
+                    row_sums_v((double)kxc[r], (double)qi[r], Dri, (double)yc[r], y0, ineq, cs);
+                    row_sums_v((double)kxa[r], (double)qi[r], Dri, (double)ya[r], y0, ineq, cs + 9);
+                    ray_row_sums_v((double)kxc[r], kx0, Dri, (double)yc[r], y0, (double)qi[r], ineq, rs);
+                }
+            }
+            small_sum<kCheckSums, NT>(cs, sh);
+            small_sum<kRaySums, NT>(rs, sh);
+            if (tid == 0) small_check_decision(&sc, cs, rs, Nq, Nc);
+            __syncthreads();
+            const int rt = sc.restart_to, co = sc.copy_out, sel = sc.out_sel, np = sc.need_primal;
+            const T tau = (T)(sc.eta / sc.omega);
+            dx2 = 0.0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int i = tid + r * NT, j = i;
+                if (j < d.n) {
+                    if (co) {
+                        if (sel == 2) {
+                            d.xo[j] = xc[r] - d.x0[j];
+                            d.KTyo[j] = cj[r] + (ktc[r] - d.KTy0[j]);
+                        } else {
+                            d.xo[j] = sel ? xa[r] : xc[r];
+                            d.KTyo[j] = sel ? kta[r] : ktc[r];
+                        }
+                    }
+                    if (rt == 2) {
+                        xc[r] = xa[r];
+                        ktc[r] = kta[r];
+                        d.x0[j] = xa[r];
+                        d.KTy0[j] = kta[r];
+                    } else if (rt == 1) {
+                        xa[r] = xc[r];
+                        kta[r] = ktc[r];
+                        d.x0[j] = xc[r];
+                        d.KTy0[j] = ktc[r];
+                    }
+                    if (np) {
+                        const T nv = clampv(xc[r] - tau * (cj[r] - ktc[r]), lj[r], uj[r]);
+                        xt[r] = nv;
+                        sx[j] = nv;
+                        const double dd = (double)nv - (double)xc[r];
+                        dx2 += dd * dd;
+                    }
+                }
+                if (i < d.m) {
+                    if (co) d.yo[i] = sel == 2 ? yc[r] - d.y0[i] : (sel ? ya[r] : yc[r]);
+                    if (rt == 2) {
+                        yc[r] = ya[r];
+                        kxc[r] = kxa[r];
+                        d.y0[i] = ya[r];
+                        d.Kx0[i] = kxa[r];
+                    } else if (rt == 1) {
+                        ya[r] = yc[r];
+                        kxa[r] = kxc[r];
+                        d.y0[i] = yc[r];
+                        d.Kx0[i] = kxc[r];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // back to the buffers of the multi-kernel path
+    const int c = sc.cur;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = tid + r * NT, j = i;
+        if (j < d.n) {
+            pick(d.xb, c)[j] = xc[r];
+            pick(d.xb, c ^ 1)[j] = xt[r];
+            pick(d.KTyb, c)[j] = ktc[r];
+            d.xa[j] = xa[r];
+            d.KTya[j] = kta[r];
+        }
+        if (i < d.m) {
+            pick(d.yb, c)[i] = yc[r];
+            pick(d.Kxb, c)[i] = kxc[r];
+            d.ya[i] = ya[r];
+            d.Kxa[i] = kxa[r];
         }
     }
     if (tid == 0) *d.ctl = sc;
@@ -878,14 +1129,29 @@ hipError_t launch_small_loop(const Dev<T> &d, int nnz_k, int nnz_t, int max_slot
 {
     const size_t lds = small_stage_bytes<T>(d.m, d.n, nnz_k, nnz_t);
     if (lds <= kSmallStageMax) {
-        static bool attr_set = false;   // the kernel's LDS limit raised once per process
+        static bool attr_set = false;   // the kernels' LDS limit raised once per process
         if (!attr_set) {
-            const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_small_loop<T, true>),
-                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallStageMax);
+            hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_small_loop<T, true>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallStageMax);
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_small_reg<T, 1>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallRegLds);
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_small_reg<T, 2>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallRegLds);
             if (e != hipSuccess) return e;
             attr_set = true;
         }
-        hipLaunchKernelGGL((k_small_loop<T, true>), dim3(1), dim3(kSmall), lds, s, d, max_slots, Nq, Nc);
+        if (d.n <= 2 * kSmallReg && d.m <= 2 * kSmallReg && lds + 16 * 64 <= kSmallRegLds) {
+            // as many slots as the factor table in the rest of the LDS holds
+            const int tab = (int)std::min<size_t>((kSmallRegLds - ((lds + 7) / 8) * 8) / 16, (size_t)max_slots);
+            const size_t bytes = ((lds + 7) / 8) * 8 + 16 * (size_t)tab;
+            if (d.n <= kSmallReg && d.m <= kSmallReg)
+                hipLaunchKernelGGL((k_small_reg<T, 1>), dim3(1), dim3(kSmallReg), bytes, s, d, tab, Nq, Nc);
+            else
+                hipLaunchKernelGGL((k_small_reg<T, 2>), dim3(1), dim3(kSmallReg), bytes, s, d, tab, Nq, Nc);
+        } else
+            hipLaunchKernelGGL((k_small_loop<T, true>), dim3(1), dim3(kSmall), lds, s, d, max_slots, Nq, Nc);
     } else {
         hipLaunchKernelGGL((k_small_loop<T, false>), dim3(1), dim3(kSmall), 0, s, d, max_slots, Nq, Nc);
     }

@@ -89,15 +89,24 @@ LOCKSTEP_POINTS = [0, 1, 2, 7, 62, 63, 64, 65, 100, 126, 127, 128, 191, 255, 300
 
 @pytest.mark.parametrize("seed,slice_kib,n,persistent", [(0, 2048, 0, 1), (0, 2048, 0, 0), (1, 2048, 0, 1),
                                                          (1, 2048, 0, 0), (2, 1, 0, -1), (4, 1, 2000, -1),
-                                                         (5, 1, 20000, -1)])
+                                                         (5, 1, 20000, -1), (6, 2048, -1500, 1),
+                                                         (7, 2048, -4000, 1)])
 def test_lockstep_one_step_fp64(lpmod, oracle_mod, seed, slice_kib, n, persistent):
     """Per-iteration parity: from the oracle's state after k accepted steps,
     one more accepted step on the GPU (including the check and restart that
     fall on k+1) equals the oracle's next state.  n > 0 takes a power-law LP
     of that size: with 1 KiB slices, 16 and 32 column slices (the epilogue's
     compile-time and run-time slice-count paths).  persistent = 1 runs the
-    tiny LP's slots in the one-workgroup loop, 0 as seven launches each."""
-    data = gen.tiny_lp(seed) if n == 0 else gen.large_lp(seed=seed, n=n, m1=n // 4, m2=n // 4)
+    tiny LP's slots in the one-workgroup loop (its registers-per-thread form,
+    n and m <= 1024), 0 as seven launches each.  n < 0 takes a tiny-LP
+    generator instance with -n columns in that loop: 1500 (more columns than
+    threads: the LDS-staged form) and 4000 (too large to stage: the form that
+    reads K from L2)."""
+    if n < 0:
+        nn = -n
+        data = gen.tiny_lp(seed, n=nn, m1=nn // 15, m2=nn // 15, per_col=2 if nn < 2000 else 5)
+    else:
+        data = gen.tiny_lp(seed) if n == 0 else gen.large_lp(seed=seed, n=n, m1=n // 4, m2=n // 4)
     p = lpmod.Problem(data, slice_kib=slice_kib, persistent=persistent)
     if n == 2000:
         assert p.layout()[0] == 16
@@ -105,7 +114,7 @@ def test_lockstep_one_step_fp64(lpmod, oracle_mod, seed, slice_kib, n, persisten
         assert p.layout() == (32, 32)
     o = oracle_mod.Oracle(data)
     Dr, Dc, _ = o.scaling()
-    points = LOCKSTEP_POINTS if n == 0 else [0, 1, 63, 64, 65, 127, 128]
+    points = LOCKSTEP_POINTS if n <= 0 else [0, 1, 63, 64, 65, 127, 128]
     o.solve(1e-30, max(points) + 1)
     total = o.get_state()
     rows = []
