@@ -264,7 +264,9 @@ def main():
                          "family solved over one shared matrix")
     ap.add_argument("--shared-count", type=int, default=64, help="shared: instances per handle")
     ap.add_argument("--batch-count", type=int, default=512)
-    ap.add_argument("--seq-sample", type=int, default=32,
+    ap.add_argument("--batch-fixed-iters", type=int, default=0,
+                    help="batch: only a fixed number of iterations with every instance active (profiling)")
+    ap.add_argument("--seq-sample", type=int, default=128,
                     help="batch workload: instances solved one by one for the sequential comparison")
     ap.add_argument("--kernel-timing", type=int, default=2, choices=[0, 1, 2],
                     help="2: HIP events around the two fused products in the first window of the timed "
@@ -593,9 +595,34 @@ def bench_batch(args):
     shapes = {"K": bt.layout_blocks(0), "KT": bt.layout_blocks(1)}
     print(f"[bench] batch loaded in {load_s:.1f}s ({bt.device_bytes() / 2**30:.2f} GiB), row blocks "
           f"(nonzeros, rows) {shapes}", file=sys.stderr, flush=True)
+    # algorithmic bytes per launch with every instance active (padded sizes:
+    # each instance's vectors are padded to whole 256-element chunks)
+    sv = 8 if args.precision == "fp64" else 4
+    Np = sum((p.n + 255) // 256 * 256 for p in lps)
+    Mp = sum((p.m + 255) // 256 * 256 for p in lps)
+    alg = {"bk_product<0> (K x')": nnz * (sv + 4) + 4 * (Mp + 1) + sv * Np + sv * Mp,
+           "bk_dual (y, K x, q, K x' read; y', K x' written)": 6 * sv * Mp,
+           "bk_product<1> (K'y')": nnz * (sv + 4) + 4 * (Np + 1) + sv * Mp + sv * Np,
+           "bk_update (averages and next primal)": 11 * sv * Np + 6 * sv * Mp}
     # warm-up: a short solve (graph capture, caches)
     bt.solve(1e-30, 64 * max(args.warmup, 1))
     torch.cuda.synchronize()
+    if args.batch_fixed_iters > 0:
+        # every instance active for the whole run: the profiling workload
+        t0 = time.perf_counter()
+        bt.solve(1e-30, args.batch_fixed_iters)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(json.dumps({"metric": "batch attempt slots per second (all instances active)",
+                          "value": args.batch_fixed_iters / dt, "unit": "slots/s", "n_gpus": 1,
+                          "steps": args.batch_fixed_iters, "warmup": args.warmup,
+                          "ms_per_step": 1e3 * dt / args.batch_fixed_iters, "higher_is_better": True,
+                          "scaling": "weak", "vs_baseline": None,
+                          "dtype": "f64" if args.precision == "fp64" else "f32+f64acc", "data": "synthetic",
+                          "config": {"workload": f"batch_{len(lps)}_uneven_lps", "count": len(lps), "sum_nnz": nnz,
+                                     "padded_n": Np, "padded_m": Mp, "precision": args.precision},
+                          "alg_bytes_per_launch": alg}))
+        return
     t0 = time.perf_counter()
     bt.solve(1e-4, 10**6, args.ttt_limit)
     torch.cuda.synchronize()
@@ -609,17 +636,22 @@ def bench_batch(args):
     stride = max(1, len(lps) // max(args.seq_sample, 1))
     sample = list(range(0, len(lps), stride))
     seq_s = 0.0
-    seq_iters = []
+    seq_iters, seq_times = [], []
     for i in sample:
         p = lp.Problem(lps[i], precision=args.precision, stream=torch.cuda.current_stream())
         p.solve(1e-30, 64)   # same warm-up as the batch
         t1 = time.perf_counter()
         d = p.solve(1e-4, 10**6, args.ttt_limit)
         torch.cuda.synchronize()
-        seq_s += time.perf_counter() - t1
+        seq_times.append(time.perf_counter() - t1)
+        seq_s += seq_times[-1]
         seq_iters.append(d["iterations"])
         p.close()
     seq_est = seq_s * len(lps) / len(sample)
+    # the extrapolation's standard error: the sample is every stride-th
+    # instance, so its per-instance times are treated as a random sample
+    seq_times = np.array(seq_times)
+    seq_err = len(lps) * float(np.std(seq_times, ddof=1)) / np.sqrt(len(sample)) if len(sample) > 1 else None
     print(f"[bench] sequential: {len(sample)} instances in {seq_s:.2f}s -> {seq_est:.1f}s for all "
           f"(speedup {seq_est / batch_s:.1f}x)", file=sys.stderr, flush=True)
     out = {
@@ -643,8 +675,9 @@ def bench_batch(args):
         "iterations_median": float(np.median(iters)),
         "iterations_max": int(iters.max()),
         "sequential": {"sample": len(sample), "stride": stride, "seconds_sample": seq_s,
-                       "seconds_extrapolated": seq_est, "speedup": seq_est / batch_s,
-                       "iterations_median": float(np.median(seq_iters))},
+                       "seconds_extrapolated": seq_est, "seconds_extrapolated_stderr": seq_err,
+                       "speedup": seq_est / batch_s, "iterations_median": float(np.median(seq_iters))},
+        "alg_bytes_per_launch": alg,
         "load_s": load_s,
         "gen_s": gen_s,
     }
