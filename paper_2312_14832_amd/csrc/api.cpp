@@ -44,6 +44,7 @@ int slices_for(int64_t bytes, int64_t slice_bytes)
 struct HostSliced {
     int S = 1, rows = 0, cols = 0, nb = kStreamNB, rb = kStreamRB;
     std::vector<int> rp, ci, src, brow, boff;
+    std::vector<unsigned short> ro;   // per slice and row: start relative to its row block's first entry
     std::vector<int4> blk;   // per row block: first row, end row, first entry, end entry
     std::vector<int> lrow, loff{0};   // long rows and their slot offsets
     int max_blocks = 0;
@@ -185,6 +186,20 @@ void build_sliced(HostSliced &H, int rows, int cols, const std::vector<int> &rp,
                 start = lr + 1;
             }
             plain(start, rows);
+        }
+    });
+    // row starts relative to their block (a block holds at most kStreamNB
+    // entries unless it is a single row, so the offsets fit 16 bits)
+    H.ro.assign((size_t)S * (size_t)rows, 0);
+    run_threads(T2, [&](int t) {
+        for (int sl = t; sl < S; sl += T2) {
+            const int *r = &H.rp[(size_t)sl * (rows + 1)];
+            unsigned short *o = &H.ro[(size_t)sl * (size_t)rows];
+            for (const int4 &q : bs[(size_t)sl]) {
+                if (q.x < 0) continue;   // a chunk of a long row
+                const int r1 = q.y < 0 ? ~q.y : q.y;
+                for (int i = q.x; i < r1; ++i) o[i] = (unsigned short)(r[i] - q.z);
+            }
         }
     });
     H.max_blocks = 0;
@@ -341,6 +356,7 @@ Sliced<T> upload_sliced(lp_problem *P, const HostSliced &H, const double *scaled
     q.rows = H.rows;
     q.grid = partial_grid(H.S, H.max_blocks);
     int *rp = (int *)P->dalloc(sizeof(int) * H.rp.size());
+    unsigned short *ro = (unsigned short *)P->dalloc(sizeof(unsigned short) * std::max<size_t>(H.ro.size(), 1));
     int *ci = (int *)P->dalloc(sizeof(int) * (size_t)std::max<int64_t>(nnz, 1));
     int4 *blk = (int4 *)P->dalloc(sizeof(int4) * std::max<size_t>(H.blk.size(), 1));
     int *boff = (int *)P->dalloc(sizeof(int) * H.boff.size());
@@ -354,6 +370,7 @@ Sliced<T> upload_sliced(lp_problem *P, const HostSliced &H, const double *scaled
     upload(P, lrow, H.lrow.data(), nlong);
     upload(P, loff, H.loff.data(), (int64_t)H.loff.size());
     upload(P, rp, H.rp.data(), (int64_t)H.rp.size());
+    upload(P, ro, H.ro.data(), (int64_t)H.ro.size());
     upload(P, ci, H.ci.data(), nnz);
     upload(P, blk, H.blk.data(), (int64_t)H.blk.size());
     upload(P, boff, H.boff.data(), (int64_t)H.boff.size());
@@ -361,7 +378,7 @@ Sliced<T> upload_sliced(lp_problem *P, const HostSliced &H, const double *scaled
     HIPT(launch_gather_values<T>(scaled_csr_vals, src, v, nnz, P->stream));
     sync(P);
     P->dfree(src);
-    q.rp = rp; q.ci = ci; q.blk = blk; q.boff = boff; q.v = v; q.part = part;
+    q.rp = rp; q.ro = ro; q.ci = ci; q.blk = blk; q.boff = boff; q.v = v; q.part = part;
     q.nlong = nlong; q.lrow = lrow; q.loff = loff; q.lpart = lpart;
     q.nlpart = H.loff.back();
     return q;
@@ -370,7 +387,7 @@ Sliced<T> upload_sliced(lp_problem *P, const HostSliced &H, const double *scaled
 template <typename T>
 void free_sliced(lp_problem *P, Sliced<T> &q)
 {
-    for (const void *p : {(const void *)q.rp, (const void *)q.ci, (const void *)q.blk, (const void *)q.boff,
+    for (const void *p : {(const void *)q.rp, (const void *)q.ro, (const void *)q.ci, (const void *)q.blk, (const void *)q.boff,
                           (const void *)q.v, (const void *)q.part, (const void *)q.lrow, (const void *)q.loff,
                           (const void *)q.lpart})
         P->dfree(const_cast<void *>(p));
@@ -579,6 +596,7 @@ size_t load_plan_bytes(int64_t m, int64_t n, int64_t nnz, const HostSliced &HK, 
     add(T * one(n)); add(T * one(m));
     for (const HostSliced *H : {&HK, &HT}) {
         add(sizeof(int) * H->rp.size());
+        add(sizeof(unsigned short) * std::max<size_t>(H->ro.size(), 1));
         add(4 * one(nnz));
         add(sizeof(int4) * std::max<size_t>(H->blk.size(), 1));
         add(sizeof(int) * H->boff.size());

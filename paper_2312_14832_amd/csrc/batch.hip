@@ -18,7 +18,7 @@ __device__ __forceinline__ void batch_block(const int *rp, const int *ci, const 
     const int r0 = L.r0[blk], r1e = L.r1[blk];
     const bool wave = r1e < 0;
     const int r1 = wave ? ~r1e : r1e;
-    stream_block(rp, ci, v, x, r0, r1, wave, rp[r0], rp[r1], out, prod, red);
+    stream_block(RowsPlain{rp}, ci, v, x, r0, r1, wave, rp[r0], rp[r1], out, prod, red);
 }
 
 template <typename T, int WHICH>

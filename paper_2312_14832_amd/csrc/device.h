@@ -657,15 +657,34 @@ __device__ __forceinline__ void average_row(const Dev<T> &d, int i, int c, T w)
     d.Kxa[i] = b + w * (kx[i] - b);
 }
 
-// CSR-Stream sums of one row block: rows [r0, r1) whose entries are [b, e)
-// of a CSR with global row pointers rp.  Products are staged in LDS; in a
+// Row extents for stream_block, of row r of a block holding rows [r0, r1)
+// and entries [b, e).  RowsPlain: a CSR's own row pointers.  RowsRel: each
+// row's start relative to its block's first entry in 16 bits (the end of the
+// block's last row is e); every load stays inside rows [r0, r1).
+struct RowsPlain {
+    const int *__restrict__ rp;
+    __device__ __forceinline__ int start(int r, int) const { return rp[r]; }
+    __device__ __forceinline__ int end(int r, int, int, int) const { return rp[r + 1]; }
+};
+struct RowsRel {
+    const unsigned short *__restrict__ ro;
+    __device__ __forceinline__ int start(int r, int b) const { return b + (int)ro[r]; }
+    __device__ __forceinline__ int end(int r, int r1, int b, int e) const
+    {
+        const int nx = b + (int)ro[min(r + 1, r1 - 1)];
+        return r + 1 < r1 ? nx : e;
+    }
+};
+
+// CSR-Stream sums of one row block: rows [r0, r1) whose entries are [b, e),
+// row extents from rows (RowsPlain or RowsRel).  Products are staged in LDS; in a
 // block of short rows (at most kStreamRB) each thread sums every kBlock-th
 // row in index order, in a block of long rows (wave set, at most kBlock/64)
 // each wavefront sums one row, lanes striding and a butterfly combining them.
 // A block of one row longer than kStreamNB is summed by the whole workgroup.
 // Every thread of the workgroup must call it.
-template <typename T>
-__device__ __forceinline__ void stream_block(const int *__restrict__ rp, const int *__restrict__ ci,
+template <typename T, typename ROWS>
+__device__ __forceinline__ void stream_block(const ROWS &rows, const int *__restrict__ ci,
                                              const T *__restrict__ v, const T *__restrict__ x, int r0, int r1,
                                              bool wave, int b, int e, T *__restrict__ out, T *prod, double *red)
 {
@@ -690,8 +709,8 @@ __device__ __forceinline__ void stream_block(const int *__restrict__ rp, const i
 #pragma unroll
         for (int j = 0; j < RU; ++j) {
             const int r = min(r0 + (int)threadIdx.x + j * kBlock, r1 - 1);
-            rs[j] = rp[r];
-            re[j] = rp[r + 1];
+            rs[j] = rows.start(r, b);
+            re[j] = rows.end(r, r1, b, e);
         }
         if (cnt > 0) {
 #pragma unroll
@@ -716,9 +735,9 @@ __device__ __forceinline__ void stream_block(const int *__restrict__ rp, const i
         } else {
             const int r = r0 + ((int)threadIdx.x >> 6), lane = (int)threadIdx.x & 63;
             if (r < r1) {   // uniform over the wavefront
-                const int p1 = rp[r + 1] - b;
+                const int p1 = rows.end(r, r1, b, e) - b;
                 T acc = T(0);
-                for (int p = rp[r] - b + lane; p < p1; p += 64) acc += prod[p];
+                for (int p = rows.start(r, b) - b + lane; p < p1; p += 64) acc += prod[p];
 #pragma unroll
                 for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
                 if (lane == 0) out[r] = acc;
@@ -826,7 +845,7 @@ __device__ __forceinline__ void sliced_partial(const Sliced<T> &P, const T *__re
     const int S = P.S;
     const int s = (int)blockIdx.x % S;
     const int chunk0 = (int)blockIdx.x / S, stride = (int)gridDim.x / S;
-    const int *rp = P.rp + (size_t)s * (P.rows + 1);
+    const RowsRel rows{P.ro + (size_t)s * P.rows};
     T *out = P.part + (size_t)s * P.rows;
     const int nblk = P.boff[s + 1] - P.boff[s];
     const int4 *bd = P.blk + P.boff[s];
@@ -840,7 +859,7 @@ __device__ __forceinline__ void sliced_partial(const Sliced<T> &P, const T *__re
             }
         }
         const bool wave = q.y < 0;
-        stream_block(rp, P.ci, P.v, x, q.x, wave ? ~q.y : q.y, wave, q.z, q.w, out, prod, red);
+        stream_block(rows, P.ci, P.v, x, q.x, wave ? ~q.y : q.y, wave, q.z, q.w, out, prod, red);
     }
 }
 

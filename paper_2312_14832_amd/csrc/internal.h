@@ -44,7 +44,9 @@ struct Sliced {
     int S;            // column slices (a power of two)
     int rows;         // rows of the product
     int grid;         // workgroups of the partial pass (a multiple of 8 and of S)
-    const int *rp;    // [S*(rows+1)] per-slice row pointers into ci / v
+    const int *rp;    // [S*(rows+1)] per-slice row pointers into ci / v (the one-workgroup loop's CSR)
+    const unsigned short *ro;   // [S*rows] start of each row relative to its row block's first entry:
+                                // what the partial passes read (2 bytes per row and slice, not 4)
     const int *ci;    // column indices, slice-major
     const T *v;       // values, same layout
     const int4 *blk;  // row blocks {first row, end row (~end: wavefront rows), first entry, end entry};
