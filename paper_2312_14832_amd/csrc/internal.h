@@ -9,7 +9,9 @@
 namespace pdlp {
 
 constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
-constexpr int kMaxGrid = 2048;   // workgroups of an elementwise solver kernel = partial-sum slots
+constexpr int kMaxGrid = 1024;   // workgroups of an elementwise solver kernel = partial-sum slots
+                                 // (1024: 1.8% more iterations/s than 2048 on a 2e6-column LP, fewer
+                                 // partials for the one-workgroup decisions and a lighter idle launch)
 constexpr int kCheckSums = 18;   // 9 sums for the current and 9 for the averaged iterate
 constexpr int kRaySums = 4;      // the current iterate's rays (difference from the anchor)
 constexpr int kXcds = 8;         // MI355X: 8 XCDs, workgroups dealt to them round-robin

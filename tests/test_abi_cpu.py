@@ -115,7 +115,7 @@ def test_workspace_size_is_host_only_and_sane():
     matrix twice (solver layout and the scaling's CSR pair, values and int32
     columns) and ten vectors per row and column; FP32 mode needs less apart
     from what its FP64 re-check of the termination test adds (two products
-    of each length in FP64 and 2048 x 18 partial sums); a larger LP more."""
+    of each length in FP64 and 1024 x 18 partial sums); a larger LP more."""
     lp = _lib()
     small, big = gen.tiny_lp(0), gen.large_lp(seed=2, n=20000, m1=5000, m2=5000)
     for data in (small, big):
@@ -124,7 +124,7 @@ def test_workspace_size_is_host_only_and_sane():
         b32 = lp.workspace_size(data, precision="mixed")
         assert b64 >= 2 * nnz * (8 + 4) * 2 + 8 * 10 * (n + m)
         assert b64 <= 4 * (2 * nnz * (8 + 4) * 2 + 8 * 40 * (n + m)) + (4 << 20)
-        recheck = 8 * 2 * (n + m) + 8 * 2048 * 18 + 5 * 256
+        recheck = 8 * 2 * (n + m) + 8 * 1024 * 18 + 5 * 256
         assert b32 < b64 + recheck
         if data is big:
             assert b32 < b64
