@@ -250,6 +250,9 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-tolerance solve")
+    ap.add_argument("--no-other-configs", action="store_true",
+                    help="default workload: skip the short runs of the tiny, mixed-precision and batched "
+                         "configurations that the line carries under other_configs")
     ap.add_argument("--ttt-tol", type=float, default=1e-4, help="relative KKT tolerance of that solve")
     ap.add_argument("--ttt-limit", type=float, default=90.0)
     ap.add_argument("--ws-train", type=int, default=2048, help="warmstart: training instances")
@@ -449,7 +452,83 @@ def main():
         "load_s": load_s,
         "gen_s": gen_s,
     }
+    if (args.workload == "large" and args.n == 2_000_000 and args.precision == "fp64" and not args.no_ttt
+            and not args.no_other_configs):
+        out["other_configs"] = other_configs(args)
     print(json.dumps(out))
+
+
+def other_configs(args):
+    """Short runs of the other configurations, so that one default bench run
+    measures them all: the tiny LPs (one-workgroup loop and launches, time to
+    1e-6, the oracle's time beside them), the 4e6-column LP in mixed precision
+    (iteration rate, time to 1e-4, the returned point evaluated in FP64), and
+    the batch of 512 uneven LPs (time to 1e-4, against a sample of them solved
+    one by one).  Each result is in the unit of its own configuration."""
+    import torch
+    res = {}
+    print("[bench] other configurations: tiny", file=sys.stderr, flush=True)
+    t = run_tiny(args, steps=20, warmup=2, with_cpu=True)
+    res[t["config"]["workload"]] = {k: t[k] for k in ("metric", "value", "unit", "dtype", "config", "time_to_tol",
+                                                      "forms", "cpu_baseline")}
+    torch.cuda.empty_cache()
+    print("[bench] other configurations: mixed precision, n = 4e6", file=sys.stderr, flush=True)
+    res["large_powerlaw_lp_n4000000_mixed"] = run_mixed_short(args)
+    torch.cuda.empty_cache()
+    print("[bench] other configurations: batch of 512", file=sys.stderr, flush=True)
+    b = run_batch(args, precision="mixed", seq_sample=32)
+    res[b["config"]["workload"] + "_mixed"] = {k: b[k] for k in ("metric", "value", "unit", "dtype", "config",
+                                                                 "batch_seconds", "solved", "iterations_median",
+                                                                 "iterations_max", "sequential")}
+    torch.cuda.empty_cache()
+    return res
+
+
+def run_mixed_short(args):
+    """The 4e6 x 2e6 power-law LP (seed 2) in mixed precision: 10 timed
+    windows (after one warm-up), a cold solve to rel KKT 1e-4, and the
+    returned point's criteria evaluated in FP64 (an FP64 handle started at it,
+    zero iterations)."""
+    import torch
+    from paper_2312_14832_amd import gen, lp
+    n = 4_000_000
+    data = gen.large_lp(seed=2, n=n, m1=n // 4, m2=n // 4)
+    st = torch.cuda.current_stream()
+    prob = lp.Problem(data, precision="mixed", stream=st, kernel_timing=2)
+    prob.solve(1e-30, ITERS_PER_STEP)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = prob.solve(1e-30, ITERS_PER_STEP * 10)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pairs = {}
+    for w in (0, 1):
+        cnt, ms = prob.kernel_time(w)
+        avg_us = 1e3 * ms / max(cnt, 1)
+        b = kernel_bytes(w, n, data.m, data.nnz, 4)
+        pairs[kernel_names("mixed")[w]] = {"avg_us": avg_us, "alg_bytes": b,
+                                           "hbm_frac": b / (avg_us * 1e-6) / 1e9 / HBM_PEAK_GBS}
+    t0 = time.perf_counter()
+    tinfo = prob.solve(1e-4, 10**7, args.ttt_limit)
+    torch.cuda.synchronize()
+    tt = time.perf_counter() - t0
+    x, y, _, _ = prob.result()
+    prob.close()
+    p64 = lp.Problem(data, precision="fp64", stream=st)
+    p64.set_start(x, y)
+    ev = p64.solve(1e-4, 0)
+    p64.close()
+    print(f"[bench] mixed 4e6: {info['iterations'] / dt:.0f} it/s; time to 1e-4 {tt:.2f}s {tinfo['status']} "
+          f"({tinfo['iterations']} it); FP64 rel KKT of the point {ev['rel_kkt']:.3e}", file=sys.stderr, flush=True)
+    return {"metric": "PDHG iters/sec", "value": info["iterations"] / dt, "unit": "iters/s",
+            "dtype": "f32+f64acc",
+            "config": {"workload": "large_powerlaw_lp_n4000000_mixed", "n": n, "m1": data.m1,
+                       "m2": data.m - data.m1, "nnz": data.nnz, "seed": 2, "timed_windows": 10},
+            "spmv": pairs,
+            "time_to_tol": {"tol": 1e-4, "seconds": tt, "status": tinfo["status"],
+                            "iterations": tinfo["iterations"]},
+            "fp64_eval_of_point": {"rel_primal": ev["rel_primal"], "rel_dual": ev["rel_dual"],
+                                   "rel_gap": ev["rel_gap"], "rel_kkt": ev["rel_kkt"]}}
 
 
 def bench_tiny(args):
@@ -461,6 +540,11 @@ def bench_tiny(args):
     slot of captured graph windows.  Reported: the iteration rate, the time
     to rel KKT 1e-6 per instance (fresh handle, load excluded), and the
     oracle's time to 1e-6 on one host core."""
+    print(json.dumps(run_tiny(args, args.steps, args.warmup, not args.no_cpu)))
+
+
+def run_tiny(args, steps, warmup, with_cpu):
+    """The tiny-LP measurements of bench_tiny, as a dict."""
     import numpy as np
     import torch
     from paper_2312_14832_amd import gen, lp
@@ -470,10 +554,10 @@ def bench_tiny(args):
     forms = {}
     for name, pers in (("one_workgroup", 1), ("launches", 0)):
         p = lp.Problem(lps[0], stream=st, persistent=pers)
-        p.solve(1e-30, ITERS_PER_STEP * max(args.warmup, 1))
+        p.solve(1e-30, ITERS_PER_STEP * max(warmup, 1))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        info = p.solve(1e-30, ITERS_PER_STEP * args.steps)
+        info = p.solve(1e-30, ITERS_PER_STEP * steps)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         p.close()
@@ -487,12 +571,12 @@ def bench_tiny(args):
                         "status": inf["status"]})
             q.close()
         med = float(np.median([t["seconds"] for t in ttt]))
-        forms[name] = {"iters_per_s": info["iterations"] / dt, "ms_per_step": 1e3 * dt / args.steps,
+        forms[name] = {"iters_per_s": info["iterations"] / dt, "ms_per_step": 1e3 * dt / steps,
                        "time_to_1e6_median_s": med, "runs": ttt}
         print(f"[bench] tiny, {name}: {info['iterations'] / dt:.0f} it/s, median time to 1e-6 {med * 1e3:.1f} ms",
               file=sys.stderr, flush=True)
     ora = []
-    if not args.no_cpu:
+    if with_cpu:
         from oracle.oracle import Oracle
         for s, data in enumerate(lps):
             o = Oracle(data)
@@ -504,7 +588,7 @@ def bench_tiny(args):
     head = forms["one_workgroup"]
     out = {
         "metric": "PDHG iters/sec", "value": head["iters_per_s"], "unit": "iters/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
+        "steps": steps, "warmup": warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "tiny_lp_n1000", "n": 1000, "m1": 200, "m2": 300, "nnz": lps[0].nnz,
                    "seeds": list(range(10)), "iters_per_step": ITERS_PER_STEP, "loop": "one workgroup"},
@@ -517,7 +601,7 @@ def bench_tiny(args):
                           "median_s": float(np.median([o["seconds"] for o in ora])), "runs": ora}
                          if ora else None),
     }
-    print(json.dumps(out))
+    return out
 
 
 def bench_gemm(args):
@@ -579,7 +663,33 @@ def bench_batch(args):
     fp64).  The sequential leg solves every (count/seq_sample)-th instance
     with the single-LP path (load excluded) and scales the sum up.
     """
-    import numpy as np
+    if args.batch_fixed_iters <= 0:
+        print(json.dumps(run_batch(args, args.precision, args.seq_sample)))
+        return
+    import torch
+    lps, bt, shapes, alg, nnz, gen_s, load_s = _batch_setup(args, args.precision)
+    # every instance active for the whole run: the profiling workload
+    t0 = time.perf_counter()
+    bt.solve(1e-30, args.batch_fixed_iters)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({"metric": "batch attempt slots per second (all instances active)",
+                      "value": args.batch_fixed_iters / dt, "unit": "slots/s", "n_gpus": 1,
+                      "steps": args.batch_fixed_iters, "warmup": args.warmup,
+                      "ms_per_step": 1e3 * dt / args.batch_fixed_iters, "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None,
+                      "dtype": "f64" if args.precision == "fp64" else "f32+f64acc", "data": "synthetic",
+                      "config": {"workload": f"batch_{len(lps)}_uneven_lps", "count": len(lps), "sum_nnz": nnz,
+                                 "padded_n": sum((p.n + 255) // 256 * 256 for p in lps),
+                                 "padded_m": sum((p.m + 255) // 256 * 256 for p in lps),
+                                 "precision": args.precision},
+                      "alg_bytes_per_launch": alg}))
+
+
+def _batch_setup(args, precision):
+    """Generate and load the batch, time nothing: (lps, handle, row-block
+    shapes, algorithmic bytes per launch, sum nnz, generation and load
+    seconds).  One warm-up solve of the handle is included."""
     import torch
     from paper_2312_14832_amd import gen, lp
 
@@ -590,14 +700,14 @@ def bench_batch(args):
     print(f"[bench] generated {len(lps)} LPs, sum n={sum(p.n for p in lps)}, sum nnz={nnz} in {gen_s:.1f}s",
           file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    bt = lp.Batch(lps, precision=args.precision, stream=torch.cuda.current_stream(), autotune=args.autotune)
+    bt = lp.Batch(lps, precision=precision, stream=torch.cuda.current_stream(), autotune=args.autotune)
     load_s = time.perf_counter() - t0
     shapes = {"K": bt.layout_blocks(0), "KT": bt.layout_blocks(1)}
     print(f"[bench] batch loaded in {load_s:.1f}s ({bt.device_bytes() / 2**30:.2f} GiB), row blocks "
           f"(nonzeros, rows) {shapes}", file=sys.stderr, flush=True)
     # algorithmic bytes per launch with every instance active (padded sizes:
     # each instance's vectors are padded to whole 256-element chunks)
-    sv = 8 if args.precision == "fp64" else 4
+    sv = 8 if precision == "fp64" else 4
     Np = sum((p.n + 255) // 256 * 256 for p in lps)
     Mp = sum((p.m + 255) // 256 * 256 for p in lps)
     alg = {"bk_product<0> (K x')": nnz * (sv + 4) + 4 * (Mp + 1) + sv * Np + sv * Mp,
@@ -607,22 +717,17 @@ def bench_batch(args):
     # warm-up: a short solve (graph capture, caches)
     bt.solve(1e-30, 64 * max(args.warmup, 1))
     torch.cuda.synchronize()
-    if args.batch_fixed_iters > 0:
-        # every instance active for the whole run: the profiling workload
-        t0 = time.perf_counter()
-        bt.solve(1e-30, args.batch_fixed_iters)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        print(json.dumps({"metric": "batch attempt slots per second (all instances active)",
-                          "value": args.batch_fixed_iters / dt, "unit": "slots/s", "n_gpus": 1,
-                          "steps": args.batch_fixed_iters, "warmup": args.warmup,
-                          "ms_per_step": 1e3 * dt / args.batch_fixed_iters, "higher_is_better": True,
-                          "scaling": "weak", "vs_baseline": None,
-                          "dtype": "f64" if args.precision == "fp64" else "f32+f64acc", "data": "synthetic",
-                          "config": {"workload": f"batch_{len(lps)}_uneven_lps", "count": len(lps), "sum_nnz": nnz,
-                                     "padded_n": Np, "padded_m": Mp, "precision": args.precision},
-                          "alg_bytes_per_launch": alg}))
-        return
+    return lps, bt, shapes, alg, nnz, gen_s, load_s
+
+
+def run_batch(args, precision, seq_sample):
+    """The batch's time to rel KKT 1e-4 and the sequential comparison on
+    every (count/seq_sample)-th instance, as a dict."""
+    import numpy as np
+    import torch
+    from paper_2312_14832_amd import lp
+
+    lps, bt, shapes, alg, nnz, gen_s, load_s = _batch_setup(args, precision)
     t0 = time.perf_counter()
     bt.solve(1e-4, 10**6, args.ttt_limit)
     torch.cuda.synchronize()
@@ -633,12 +738,12 @@ def bench_batch(args):
     print(f"[bench] batch: {solved}/{len(lps)} optimal in {batch_s:.2f}s; iterations median {np.median(iters):.0f} "
           f"max {iters.max()}", file=sys.stderr, flush=True)
     bt.close()
-    stride = max(1, len(lps) // max(args.seq_sample, 1))
+    stride = max(1, len(lps) // max(seq_sample, 1))
     sample = list(range(0, len(lps), stride))
     seq_s = 0.0
     seq_iters, seq_times = [], []
     for i in sample:
-        p = lp.Problem(lps[i], precision=args.precision, stream=torch.cuda.current_stream())
+        p = lp.Problem(lps[i], precision=precision, stream=torch.cuda.current_stream())
         p.solve(1e-30, 64)   # same warm-up as the batch
         t1 = time.perf_counter()
         d = p.solve(1e-4, 10**6, args.ttt_limit)
@@ -665,11 +770,11 @@ def bench_batch(args):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64acc",
+        "dtype": "f64" if precision == "fp64" else "f32+f64acc",
         "data": "synthetic",
         "config": {"workload": f"batch_{len(lps)}_uneven_lps", "count": len(lps), "sum_nnz": nnz,
                    "row_blocks": {k: {"nnz_per_block": v[0], "rows_per_block": v[1]} for k, v in shapes.items()},
-                   "seeds": [1000, 1000 + len(lps) - 1], "precision": args.precision, "tol": 1e-4},
+                   "seeds": [1000, 1000 + len(lps) - 1], "precision": precision, "tol": 1e-4},
         "batch_seconds": batch_s,
         "solved": solved,
         "iterations_median": float(np.median(iters)),
@@ -681,7 +786,7 @@ def bench_batch(args):
         "load_s": load_s,
         "gen_s": gen_s,
     }
-    print(json.dumps(out))
+    return out
 
 
 def bench_warmstart(args):
