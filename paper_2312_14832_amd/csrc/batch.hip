@@ -61,32 +61,35 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void bk_dual(BDev<T> b)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) *b.gate = 0;
-    if ((int)blockIdx.x >= b.ncm) return;
-    const int inst = b.cinst_m[blockIdx.x];
+    if ((int)blockIdx.x >= b.acm) return;
+    const int chunk = b.act_cm ? b.act_cm[blockIdx.x] : (int)blockIdx.x;
+    const int inst = b.cinst_m[chunk];
     const Ctl *ctl = b.ctl + inst;
     if (ctl->done) return;
     const Dev<T> &d = b.d;
     const int c = ctl->cur;
     DualEpi<T> epi{pick(d.yb, c), pick(d.Kxb, c), d.qs, pick(d.yb, c ^ 1), pick(d.Kxb, c ^ 1), b.m1g[inst],
                    (T)(ctl->eta * ctl->omega), 0.0, 0.0};
-    const int i = blockIdx.x * kBlock + (int)threadIdx.x;
+    const int i = chunk * kBlock + (int)threadIdx.x;
     epi(i, b.prodK[i]);
     double v[2] = {epi.dy2, epi.inter};
-    block_store_partials<2>(v, d.part_dual);
+    block_store_partials<2>(v, d.part_dual, chunk);
 }
 
 // one workgroup per instance
 template <typename T>
 __global__ __launch_bounds__(kBlock) void bk_step_decide(BDev<T> b)
 {
-    Ctl *ctl = b.ctl + blockIdx.x;
+    if ((int)blockIdx.x >= b.aci) return;
+    const int inst = b.act_i ? b.act_i[blockIdx.x] : (int)blockIdx.x;
+    Ctl *ctl = b.ctl + inst;
     if (ctl->done) {
         if (threadIdx.x == 0) ctl->mode = MODE_NONE;
         return;
     }
     double a[1], c2[2];
-    block_sum_partials<1>(b.d.part_primal + b.nc0[blockIdx.x], b.ncc[blockIdx.x], a);
-    block_sum_partials<2>(b.d.part_dual + 2 * (size_t)b.mc0[blockIdx.x], b.mcc[blockIdx.x], c2);
+    block_sum_partials<1>(b.d.part_primal + b.nc0[inst], b.ncc[inst], a);
+    block_sum_partials<2>(b.d.part_dual + 2 * (size_t)b.mc0[inst], b.mcc[inst], c2);
     if (threadIdx.x == 0) {
         step_decision(ctl, a[0], c2[0], c2[1]);
         if (ctl->mode != MODE_NONE) atomicExch(b.gate, 1);
@@ -97,8 +100,9 @@ __global__ __launch_bounds__(kBlock) void bk_step_decide(BDev<T> b)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void bk_update(BDev<T> b)
 {
-    const bool nside = (int)blockIdx.x < b.ncn;
-    const int chunk = nside ? (int)blockIdx.x : (int)blockIdx.x - b.ncn;
+    const bool nside = (int)blockIdx.x < b.acn;
+    const int at = nside ? (int)blockIdx.x : (int)blockIdx.x - b.acn;
+    const int chunk = nside ? (b.act_cn ? b.act_cn[at] : at) : (b.act_cm ? b.act_cm[at] : at);
     const int inst = nside ? b.cinst_n[chunk] : b.cinst_m[chunk];
     const Ctl *ctl = b.ctl + inst;
     if (ctl->done) return;
@@ -119,7 +123,7 @@ __global__ __launch_bounds__(kBlock) void bk_update(BDev<T> b)
     }
     if (nside) {
         double v[1] = {dx2};
-        block_store_partials<1>(v, d.part_primal);
+        block_store_partials<1>(v, d.part_primal, chunk);
     }
 }
 
@@ -132,9 +136,11 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void bk_check_reduce(BDev<T> b, int gated)
 {
     if (gated && *b.gate == 0) return;
-    for (int ch = blockIdx.x; ch < b.ncn + b.ncm; ch += gridDim.x) {
-        const bool nside = ch < b.ncn;
-        const int chunk = nside ? ch : ch - b.ncn;
+    for (int t = blockIdx.x; t < b.acn + b.acm; t += gridDim.x) {
+        const bool nside = t < b.acn;
+        const int at = nside ? t : t - b.acn;
+        const int chunk = nside ? (b.act_cn ? b.act_cn[at] : at) : (b.act_cm ? b.act_cm[at] : at);
+        const int ch = nside ? chunk : b.ncn + chunk;   // the chunk's partial slot
         const int inst = nside ? b.cinst_n[chunk] : b.cinst_m[chunk];
         const Ctl *ctl = b.ctl + inst;
         if (ctl->mode == MODE_NONE || ctl->done) continue;
@@ -163,29 +169,30 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void bk_check_decide(BDev<T> b, int gated)
 {
     if (gated && *b.gate == 0) return;
-    Ctl *ctl = b.ctl + blockIdx.x;
+    if ((int)blockIdx.x >= b.aci) return;
+    const int inst = b.act_i ? b.act_i[blockIdx.x] : (int)blockIdx.x;
+    Ctl *ctl = b.ctl + inst;
     if (ctl->mode == MODE_NONE || ctl->done) return;
     double Sn[kCheckSums], Sm[kCheckSums], Rn[kRaySums], Rm[kRaySums];
-    block_sum_partials<kCheckSums>(b.d.part_check + (size_t)kCheckSums * b.nc0[blockIdx.x], b.ncc[blockIdx.x], Sn);
-    block_sum_partials<kCheckSums>(b.d.part_check + (size_t)kCheckSums * (b.ncn + b.mc0[blockIdx.x]),
-                                   b.mcc[blockIdx.x], Sm);
-    block_sum_partials<kRaySums>(b.d.part_ray + (size_t)kRaySums * b.nc0[blockIdx.x], b.ncc[blockIdx.x], Rn);
-    block_sum_partials<kRaySums>(b.d.part_ray + (size_t)kRaySums * (b.ncn + b.mc0[blockIdx.x]), b.mcc[blockIdx.x],
-                                 Rm);
+    block_sum_partials<kCheckSums>(b.d.part_check + (size_t)kCheckSums * b.nc0[inst], b.ncc[inst], Sn);
+    block_sum_partials<kCheckSums>(b.d.part_check + (size_t)kCheckSums * (b.ncn + b.mc0[inst]), b.mcc[inst], Sm);
+    block_sum_partials<kRaySums>(b.d.part_ray + (size_t)kRaySums * b.nc0[inst], b.ncc[inst], Rn);
+    block_sum_partials<kRaySums>(b.d.part_ray + (size_t)kRaySums * (b.ncn + b.mc0[inst]), b.mcc[inst], Rm);
     if (threadIdx.x != 0) return;
     double S[kCheckSums], R[kRaySums];
     for (int i = 0; i < kCheckSums; ++i) S[i] = Sn[i] + Sm[i];
     for (int i = 0; i < kRaySums; ++i) R[i] = Rn[i] + Rm[i];
-    check_decision(ctl, S, R, b.Nq[blockIdx.x], b.Nc[blockIdx.x]);
+    check_decision(ctl, S, R, b.Nq[inst], b.Nc[inst]);
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void bk_check_apply(BDev<T> b, int gated)
 {
     if (gated && *b.gate == 0) return;
-    for (int ch = blockIdx.x; ch < b.ncn + b.ncm; ch += gridDim.x) {
-        const bool nside = ch < b.ncn;
-        const int chunk = nside ? ch : ch - b.ncn;
+    for (int t = blockIdx.x; t < b.acn + b.acm; t += gridDim.x) {
+        const bool nside = t < b.acn;
+        const int at = nside ? t : t - b.acn;
+        const int chunk = nside ? (b.act_cn ? b.act_cn[at] : at) : (b.act_cm ? b.act_cm[at] : at);
         const int inst = nside ? b.cinst_n[chunk] : b.cinst_m[chunk];
         const Ctl *ctl = b.ctl + inst;
         if (ctl->mode == MODE_NONE) continue;
@@ -272,30 +279,30 @@ hipError_t launch_batch_product_plain(const BDev<T> &b, int which, const T *in, 
 template <typename T>
 hipError_t launch_batch_dual(const BDev<T> &b, hipStream_t s)
 {
-    hipLaunchKernelGGL(bk_dual<T>, dim3(b.ncm > 0 ? b.ncm : 1), dim3(kBlock), 0, s, b);
+    hipLaunchKernelGGL(bk_dual<T>, dim3(b.acm > 0 ? b.acm : 1), dim3(kBlock), 0, s, b);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_batch_step_decide(const BDev<T> &b, hipStream_t s)
 {
-    hipLaunchKernelGGL(bk_step_decide<T>, dim3(b.B), dim3(kBlock), 0, s, b);
+    hipLaunchKernelGGL(bk_step_decide<T>, dim3(b.aci > 0 ? b.aci : 1), dim3(kBlock), 0, s, b);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_batch_update(const BDev<T> &b, hipStream_t s)
 {
-    hipLaunchKernelGGL(bk_update<T>, dim3(b.ncn + b.ncm), dim3(kBlock), 0, s, b);
+    hipLaunchKernelGGL(bk_update<T>, dim3(b.acn + b.acm > 0 ? b.acn + b.acm : 1), dim3(kBlock), 0, s, b);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_batch_check(const BDev<T> &b, int gated, hipStream_t s)
 {
-    hipLaunchKernelGGL(bk_check_reduce<T>, dim3(chunk_grid(b.ncn + b.ncm)), dim3(kBlock), 0, s, b, gated);
-    hipLaunchKernelGGL(bk_check_decide<T>, dim3(b.B), dim3(kBlock), 0, s, b, gated);
-    hipLaunchKernelGGL(bk_check_apply<T>, dim3(chunk_grid(b.ncn + b.ncm)), dim3(kBlock), 0, s, b, gated);
+    hipLaunchKernelGGL(bk_check_reduce<T>, dim3(chunk_grid(b.acn + b.acm)), dim3(kBlock), 0, s, b, gated);
+    hipLaunchKernelGGL(bk_check_decide<T>, dim3(b.aci > 0 ? b.aci : 1), dim3(kBlock), 0, s, b, gated);
+    hipLaunchKernelGGL(bk_check_apply<T>, dim3(chunk_grid(b.acn + b.acm)), dim3(kBlock), 0, s, b, gated);
     return hipGetLastError();
 }
 

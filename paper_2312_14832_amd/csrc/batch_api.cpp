@@ -50,6 +50,14 @@ struct lp_batch {
     bool has_result = false;
     std::vector<char> state_set;
     std::vector<double> finish_s;   // per instance: seconds into the last solve when it finished
+    // Narrowed launches once most instances have finished (see compact_active):
+    // the owners of every chunk, host copies of the full block lists, and
+    // device room for the narrowed chunk and block lists
+    std::vector<int> cin, cim;
+    std::vector<int> lorder[2], linst[2];
+    BlockList full[2]{};
+    int *act_cn = nullptr, *act_cm = nullptr, *act_i = nullptr, *act_order[2] = {nullptr, nullptr};
+    int active = -1;   // unfinished instances the lists were narrowed to (-1: full lists)
     int shape[2][2] = {{kStreamNB, kStreamRB}, {kStreamNB, kStreamRB}};   // K, K': most nonzeros, rows per block
     double seconds = 0;
     std::string err;
@@ -257,6 +265,10 @@ int do_batch_load(lp_batch *P, const lp_csr *K, const double *const *c, const do
         b.B = B;
         b.ncn = N / kBlock;
         b.ncm = M / kBlock;
+        b.act_cn = b.act_cm = b.act_i = nullptr;
+        b.acn = b.ncn;
+        b.acm = b.ncm;
+        b.aci = B;
         b.krp = d_rp; b.kci = d_ci; b.trp = d_tp; b.tci = d_ti;
         if (std::is_same<T, double>::value) {
             b.kv = (const T *)d_kv; b.tv = (const T *)d_tv;
@@ -375,6 +387,8 @@ int do_batch_load(lp_batch *P, const lp_csr *K, const double *const *c, const do
     };
     if (P->mixed) setup(float{});
     else setup(double{});
+    P->cin = std::move(cin);
+    P->cim = std::move(cim);
     // controller blocks start zeroed (buffer 0 current)
     HIPT(hipMemcpyAsync(P->mixed ? P->b32.ctl : P->b64.ctl, P->hctl, sizeof(Ctl) * (size_t)B, hipMemcpyHostToDevice,
                         st));
@@ -383,6 +397,89 @@ int do_batch_load(lp_batch *P, const lp_csr *K, const double *const *c, const do
     if (P->mixed)
         for (void *pp : {(void *)d_kv, (void *)d_tv, (void *)cs, (void *)ls, (void *)us, (void *)qs}) A.release(pp);
     return LP_OK;
+}
+
+// Launch only for unfinished instances: the elementwise and check kernels
+// get the chunks of the instances with live[i] set, the decision kernels
+// those instances, the products their row blocks (each XCD's list keeps its
+// order).  Finished instances would otherwise still cost a workgroup per
+// chunk in every launch (the kernels skip them, but they are dispatched).
+// Each chunk's partial keeps its slot, so the sums are those of the full
+// launches.  live = nullptr restores the full lists.  The caller captures
+// the window again afterwards.
+template <typename T>
+void compact_active(lp_batch *P, const std::vector<char> *live)
+{
+    BDev<T> &b = P->dev<T>();
+    hipStream_t st = P->stream;
+    if (P->active < 0) {   // the full lists are current: keep them, with host copies
+        for (int w = 0; w < 2; ++w) {
+            const BlockList &L = w ? b.LT : b.LK;
+            P->full[w] = L;
+            P->lorder[w].resize((size_t)std::max(L.nblk, 1));
+            P->linst[w].resize((size_t)std::max(L.nblk, 1));
+            if (L.nblk > 0) {
+                HIPT(hipMemcpyAsync(P->lorder[w].data(), L.order, sizeof(int) * (size_t)L.nblk,
+                                    hipMemcpyDeviceToHost, st));
+                HIPT(hipMemcpyAsync(P->linst[w].data(), L.inst, sizeof(int) * (size_t)L.nblk,
+                                    hipMemcpyDeviceToHost, st));
+            }
+            if (!P->act_order[w]) P->act_order[w] = P->arena.make<int>(L.nblk);
+        }
+        if (!P->act_cn) P->act_cn = P->arena.make<int>(b.ncn);
+        if (!P->act_cm) P->act_cm = P->arena.make<int>(b.ncm);
+        if (!P->act_i) P->act_i = P->arena.make<int>(b.B);
+        bsync(P);
+    }
+    if (!live) {
+        b.LK = P->full[0];
+        b.LT = P->full[1];
+        b.act_cn = b.act_cm = b.act_i = nullptr;
+        b.acn = b.ncn;
+        b.acm = b.ncm;
+        b.aci = b.B;
+        P->active = -1;
+        return;
+    }
+    const std::vector<char> &on = *live;
+    for (int w = 0; w < 2; ++w) {
+        const BlockList &F = P->full[w];
+        BlockList L = F;
+        std::vector<int> ord;
+        int maxper = 1;
+        for (int x = 0; x < kXcds; ++x) {
+            L.xoff[x] = (int)ord.size();
+            for (int k = F.xoff[x]; k < F.xoff[x + 1]; ++k) {
+                const int blk = P->lorder[w][(size_t)k];
+                if (on[(size_t)P->linst[w][(size_t)blk]]) ord.push_back(blk);
+            }
+            maxper = std::max(maxper, (int)ord.size() - L.xoff[x]);
+        }
+        L.xoff[kXcds] = (int)ord.size();
+        L.grid = kXcds * std::min(maxper, 512);
+        L.order = P->act_order[w];
+        h2d(st, P->act_order[w], ord.data(), (int64_t)ord.size());
+        bsync(P);   // ord is a local
+        (w ? b.LT : b.LK) = L;
+    }
+    std::vector<int> cn, cm, ins;
+    for (int c = 0; c < b.ncn; ++c)
+        if (on[(size_t)P->cin[(size_t)c]]) cn.push_back(c);
+    for (int c = 0; c < b.ncm; ++c)
+        if (on[(size_t)P->cim[(size_t)c]]) cm.push_back(c);
+    for (int i = 0; i < b.B; ++i)
+        if (on[(size_t)i]) ins.push_back(i);
+    h2d(st, P->act_cn, cn.data(), (int64_t)cn.size());
+    h2d(st, P->act_cm, cm.data(), (int64_t)cm.size());
+    h2d(st, P->act_i, ins.data(), (int64_t)ins.size());
+    bsync(P);
+    b.act_cn = P->act_cn;
+    b.act_cm = P->act_cm;
+    b.act_i = P->act_i;
+    b.acn = (int)cn.size();
+    b.acm = (int)cm.size();
+    b.aci = (int)ins.size();
+    P->active = b.aci;
 }
 
 template <typename T>
@@ -437,6 +534,10 @@ int do_batch_solve(lp_batch *P, double tol, int64_t max_iters, double time_limit
     const int64_t N = P->Ntot, M = P->Mtot;
     auto t0 = std::chrono::steady_clock::now();
     auto elapsed = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
+    // a solve starts with every instance's chunks and blocks in the lists
+    // (the start products below need all of them)
+    const bool narrowed = P->active >= 0;
+    if (narrowed) compact_active<T>(P, nullptr);
     const bool resume = std::all_of(P->state_set.begin(), P->state_set.end(), [](char v) { return v != 0; }) && B > 0;
     if (!resume) {
         HIPT(launch_batch_start<T>(b, st));
@@ -493,7 +594,7 @@ int do_batch_solve(lp_batch *P, double tol, int64_t max_iters, double time_limit
     }
     P->finish_s.assign(B, -1.0);
     const int W = std::max(1, P->opt.window);
-    if (P->opt.use_graph && (!P->graph || P->graph_window != W)) {
+    auto capture = [&] {
         if (P->graph) {
             (void)hipGraphExecDestroy(P->graph);
             P->graph = nullptr;
@@ -505,7 +606,8 @@ int do_batch_solve(lp_batch *P, double tol, int64_t max_iters, double time_limit
         HIPT(hipGraphInstantiate(&P->graph, g, nullptr, nullptr, 0));
         (void)hipGraphDestroy(g);
         P->graph_window = W;
-    }
+    };
+    if (P->opt.use_graph && (!P->graph || P->graph_window != W || narrowed)) capture();
     auto note_finished = [&] {
         int left = 0;
         const double now = elapsed();
@@ -522,6 +624,14 @@ int do_batch_solve(lp_batch *P, double tol, int64_t max_iters, double time_limit
             for (int s = 0; s < W; ++s) batch_slot<T>(P);
         get_ctls(P, b.ctl);
         left = note_finished();
+        // narrow the launches to the unfinished instances each time their
+        // count has halved
+        if (left > 0 && 2 * left <= (P->active < 0 ? B : P->active)) {
+            std::vector<char> live((size_t)B);
+            for (int i = 0; i < B; ++i) live[(size_t)i] = P->hctl[i].done ? 0 : 1;
+            compact_active<T>(P, &live);
+            if (P->opt.use_graph) capture();
+        }
         if (left > 0 && time_limit > 0.0 && elapsed() > time_limit) {
             HIPT(launch_batch_set_final(b.ctl, B, LP_TIME_LIMIT, st));
             HIPT(launch_batch_check<T>(b, 0, st));

@@ -171,6 +171,13 @@ struct BDev {
     const double *Nq, *Nc;    // per instance: |q|, |c| of the unscaled data
     Ctl *ctl;                 // [B]
     int *gate;                // 1 while some instance is in a check this slot
+    // The chunks the solver kernels visit: act_cn[0 .. acn) and
+    // act_cm[0 .. acm), or every chunk in order when null; the instances the
+    // decision kernels visit: act_i[0 .. aci), or all.  Once most instances
+    // have finished, the host narrows these (and LK, LT) to the unfinished
+    // ones between windows.
+    const int *act_cn, *act_cm, *act_i;
+    int acn, acm, aci;
 };
 
 // Batched solves of one family: every instance shares the matrix K (pattern
