@@ -237,3 +237,28 @@ def test_batch_resume_on_dirty_memory(lpmod, oracle_mod, monkeypatch, autotune):
         assert ints_equal(sg, so), i
         for name in ("eta_hat", "omega", "W", "eta_last"):
             assert abs(sg[name] - so[name]) <= 1e-9 * abs(so[name]) + 1e-300, (i, name, sg[name], so[name])
+
+
+def test_batch_narrowed_launches_change_nothing(lpmod):
+    """Once half of the instances have finished, the batch launches only the
+    chunks and row blocks of the others.  An instance's arithmetic does not
+    depend on its neighbours, so the instances that finish last end bit for
+    bit where they end when solved alone (a batch of one, never narrowed)."""
+    say("case batch narrowing")
+    lps = small_batch(10, seed0=4000)
+    bt = lpmod.Batch(lps, autotune=0)
+    bt.solve(1e-6, 200_000, 120.0)
+    infos = [bt.info(i) for i in range(len(lps))]
+    order = sorted(range(len(lps)), key=lambda i: infos[i]["iterations"])
+    last = order[-1]
+    # more than half finished at least a window (64 slots) before the last one
+    early = sum(1 for d in infos if d["iterations"] + 64 <= infos[last]["iterations"])
+    say(f"  iterations {[d['iterations'] for d in infos]}; {early} finished a window or more before the last")
+    assert 2 * early > len(lps)
+    for i in order[-2:]:
+        alone = lpmod.Batch([lps[i]], autotune=0)
+        alone.solve(1e-6, 200_000, 120.0)
+        a = alone.info(0)
+        assert a["status"] == infos[i]["status"] == "OPTIMAL", (i, a, infos[i])
+        assert a["iterations"] == infos[i]["iterations"], (i, a["iterations"], infos[i]["iterations"])
+        assert np.array_equal(alone.get_state(0), bt.get_state(i)), i
