@@ -9,6 +9,7 @@ import sys
 import pytest
 
 from oracle import build as obuild
+import test_oracle_highprec as highprec
 import test_oracle_pins as pins
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -28,6 +29,23 @@ def check_infeasibility_bounded(om, libpath=None):
     except subprocess.TimeoutExpired:
         raise AssertionError("infeasibility pins did not finish in 20 s")
     assert r.returncode == 0, r.stderr.decode()[-400:]
+
+def check_highprec_bounded(om, libpath=None):
+    """The 50-digit replay (both cases); on a planted-mistake build in a child
+    process under a 60 s limit (it needs about 2 s)."""
+    if libpath is None:
+        for case in highprec.CASES:
+            highprec.check_highprec_replay(om, case)
+        return
+    code = ("import sys; sys.path[:0] = [%r, %r]\n"
+            "from oracle import oracle as O\nimport test_oracle_highprec as h\n"
+            "[h.check_highprec_replay(O, c, libpath=%r) for c in h.CASES]\n") % (HERE, os.path.dirname(HERE), libpath)
+    try:
+        r = subprocess.run([sys.executable, "-c", code], timeout=60, capture_output=True)
+    except subprocess.TimeoutExpired:
+        raise AssertionError("50-digit replay did not finish in 60 s")
+    assert r.returncode == 0, r.stderr.decode()[-400:]
+
 
 MUTATIONS = {
     1: "primal step uses c + K'y",
@@ -56,6 +74,7 @@ CHECKS = [
     ("vertex enumeration", lambda om, libpath=None: pins.check_vertex_objective(om, 11, 3, 1, 2, libpath,
                                                                                   max_iters=200_000)),
     ("infeasibility certificates", check_infeasibility_bounded),
+    ("50-digit replay", check_highprec_bounded),
 ]
 
 
