@@ -138,7 +138,11 @@ typedef struct {
                                vectors the products gather fit in 150 KiB of LDS (about 5,600 nonzeros with
                                1,500 rows and columns in FP64), where it is faster than the launches; 1:
                                whenever eligible; 0: never.  Same method, same results up to the summation
-                               order of the reductions.  lp_kernel_time reports zeros for such solves. */
+                               order of the reductions.  lp_kernel_time reports zeros for such solves.
+                               lp_batch_load: -1 or 1 run a batch as one workgroup per instance, each on its
+                               own loop (one launch per 64 x window slots for the whole batch), when every
+                               instance has 1 to 1024 rows and columns and its K, K' and vectors fit the
+                               LDS (lp_batch_loop_form); 0: the batched kernel launches. */
 } lp_options;
 
 typedef struct {
@@ -281,9 +285,12 @@ void lp_free(lp_problem *P);
 
 /* ------------------------------------------------------------------------
  * Batched solves: many independent LPs of the form above advanced together
- * by one set of kernels per iteration (one captured hipGraph window), each
- * with its own step size, primal weight, restarts and termination.  The
- * method per instance is exactly the one lp_solve runs.
+ * by one set of kernels per iteration (one captured hipGraph window), or,
+ * when every instance is small, by one workgroup per instance running that
+ * instance's whole loop (lp_options.persistent, lp_batch_loop_form); each
+ * instance has its own step size, primal weight, restarts and termination.
+ * The method per instance is exactly the one lp_solve runs, including mixed
+ * precision's FP64 re-check of a termination test passed on FP32 products.
  * ------------------------------------------------------------------------ */
 typedef struct lp_batch lp_batch;   /* opaque; owned by the library */
 
@@ -312,6 +319,11 @@ int lp_batch_device_bytes(const lp_batch *B, int64_t *bytes);
  * the block-diagonal matrix and keeps the fastest; otherwise 2048 and 1024.
  * Errors: LP_ERR_ARG for a bad `which`. */
 int lp_batch_layout_blocks(const lp_batch *B, int which, int *nnz_per_block, int *rows_per_block);
+/* How the batch iterates: *form = 0 for the batched kernel launches (one set
+ * per attempt slot, captured as a hipGraph window), 1 for one workgroup per
+ * instance running that instance's whole loop (lp_options.persistent, small
+ * instances only). */
+int lp_batch_loop_form(const lp_batch *B, int *form);
 void lp_batch_free(lp_batch *B);
 const char *lp_batch_last_error(const lp_batch *B);
 const char *lp_strerror(int code);

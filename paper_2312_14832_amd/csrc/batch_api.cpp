@@ -58,6 +58,21 @@ struct lp_batch {
     BlockList full[2]{};
     int *act_cn = nullptr, *act_cm = nullptr, *act_i = nullptr, *act_order[2] = {nullptr, nullptr};
     int active = -1;   // unfinished instances the lists were narrowed to (-1: full lists)
+    // The one-workgroup loop per instance (set up at load when every instance
+    // fits its register form): per-instance views (Dev<T>, device array), the
+    // instances' norms, the form (1 or 2 columns and rows per thread, 0: not
+    // set up), the largest LDS stage and the slots per launch
+    // Mixed precision's FP64 re-check of a passed termination test (as
+    // lp_solve's): the FP64 scaled matrices and vectors kept from the load,
+    // the batch's CSR pair, and scratch for one instance at a time
+    const double *kv64 = nullptr, *tv64 = nullptr, *cs64 = nullptr, *ls64 = nullptr, *us64 = nullptr,
+                 *qs64 = nullptr;
+    const int *g_rp = nullptr, *g_ci = nullptr, *g_tp = nullptr, *g_ti = nullptr;
+    double *ckx[2] = {nullptr, nullptr}, *ckty[2] = {nullptr, nullptr}, *cpart = nullptr;
+    void *small_devs = nullptr;
+    double *small_nq = nullptr, *small_nc = nullptr;
+    int small_R = 0, small_slots = 0;
+    size_t small_stage = 0;
     int shape[2][2] = {{kStreamNB, kStreamRB}, {kStreamNB, kStreamRB}};   // K, K': most nonzeros, rows per block
     double seconds = 0;
     std::string err;
@@ -90,6 +105,102 @@ int fail(lp_batch *P, const HipError &h)
     snprintf(buf, sizeof(buf), "%s failed: %s", h.what, hipGetErrorString(h.e));
     if (P) P->err = buf;
     return h.e == hipErrorOutOfMemory ? LP_ERR_NOMEM : LP_ERR_HIP;
+}
+
+// Instance i's view of the batch's vectors and controller (its own indices
+// 0 .. n_i, 0 .. m_i); the products are left unset.
+template <typename T>
+Dev<T> view_of(lp_batch *P, int i)
+{
+    const BDev<T> &b = P->dev<T>();
+    const Dev<T> &d = b.d;
+    const int64_t mo = P->moff[i], no = P->noff[i];
+    Dev<T> v{};
+    v.m = (int)P->m[i];
+    v.n = (int)P->n[i];
+    v.m1 = (int)P->m1[i];
+    v.cs = d.cs + no; v.ls = d.ls + no; v.us = d.us + no; v.qs = d.qs + mo;
+    v.Dr = d.Dr + mo; v.Dc = d.Dc + no;
+    for (int k = 0; k < 2; ++k) {
+        v.xb[k] = d.xb[k] + no; v.yb[k] = d.yb[k] + mo; v.Kxb[k] = d.Kxb[k] + mo; v.KTyb[k] = d.KTyb[k] + no;
+    }
+    v.xa = d.xa + no; v.ya = d.ya + mo; v.Kxa = d.Kxa + mo; v.KTya = d.KTya + no;
+    v.x0 = d.x0 + no; v.y0 = d.y0 + mo; v.Kx0 = d.Kx0 + mo; v.KTy0 = d.KTy0 + no;
+    v.xo = d.xo + no; v.yo = d.yo + mo; v.KTyo = d.KTyo + no;
+    v.ctl = b.ctl + i;
+    return v;
+}
+
+// The one-workgroup loop for a batch of small LPs: when every instance has
+// rows and columns for the register form (at most 2 kSmallReg each, at least
+// one) and its stage fits the LDS, each gets a view of the batch (its
+// vectors, its controller, and a plain CSR of its own K and K' with row
+// pointers from 0 and indices inside the instance, sharing the batch's
+// scaled values), and the solve runs one workgroup per instance.
+template <typename T>
+void setup_small(lp_batch *P, const std::vector<int> &rp, const std::vector<int> &ci, const std::vector<int> &tp,
+                 const std::vector<int> &ti)
+{
+    const int B = P->B;
+    BDev<T> &b = P->dev<T>();
+    size_t stage = 0;
+    int R = 1;
+    for (int i = 0; i < B; ++i) {
+        const int64_t m = P->m[i], n = P->n[i];
+        if (m < 1 || n < 1 || m > 2 * kSmallReg || n > 2 * kSmallReg) return;
+        if (m > kSmallReg || n > kSmallReg) R = 2;
+        const int64_t nk = rp[P->moff[i] + m] - rp[P->moff[i]], nt = tp[P->noff[i] + n] - tp[P->noff[i]];
+        stage = std::max(stage, small_stage_bytes<T>((int)m, (int)n, (int)nk, (int)nt));
+    }
+    const size_t lds = (stage + 7) / 8 * 8;
+    if (B < 1 || lds + 16 * 64 > kSmallRegLds) return;
+    std::vector<int> lrp, ltp, lci(ci.size()), lti(ti.size());
+    std::vector<int64_t> krow(B), trow(B);
+    for (int i = 0; i < B; ++i) {
+        const int64_t mo = P->moff[i], no = P->noff[i], m = P->m[i], n = P->n[i];
+        const int e0 = rp[mo], t0 = tp[no];
+        krow[i] = (int64_t)lrp.size();
+        for (int64_t r = 0; r <= m; ++r) lrp.push_back(rp[mo + r] - e0);
+        for (int p = e0; p < rp[mo + m]; ++p) lci[p] = ci[p] - (int)no;
+        trow[i] = (int64_t)ltp.size();
+        for (int64_t r = 0; r <= n; ++r) ltp.push_back(tp[no + r] - t0);
+        for (int p = t0; p < tp[no + n]; ++p) lti[p] = ti[p] - (int)mo;
+    }
+    Arena &A = P->arena;
+    hipStream_t st = P->stream;
+    int *d_lrp = A.make<int>((int64_t)lrp.size()), *d_ltp = A.make<int>((int64_t)ltp.size());
+    int *d_lci = A.make<int>((int64_t)lci.size()), *d_lti = A.make<int>((int64_t)lti.size());
+    h2d(st, d_lrp, lrp.data(), (int64_t)lrp.size());
+    h2d(st, d_ltp, ltp.data(), (int64_t)ltp.size());
+    h2d(st, d_lci, lci.data(), (int64_t)lci.size());
+    h2d(st, d_lti, lti.data(), (int64_t)lti.size());
+    std::vector<Dev<T>> views((size_t)B);
+    for (int i = 0; i < B; ++i) {
+        const int64_t mo = P->moff[i], no = P->noff[i];
+        Dev<T> v = view_of<T>(P, i);
+        v.K.S = 1;
+        v.K.rows = v.m;
+        v.K.rp = d_lrp + krow[i];
+        v.K.ci = d_lci + rp[mo];
+        v.K.v = b.kv + rp[mo];
+        v.KT.S = 1;
+        v.KT.rows = v.n;
+        v.KT.rp = d_ltp + trow[i];
+        v.KT.ci = d_lti + tp[no];
+        v.KT.v = b.tv + tp[no];
+        views[(size_t)i] = v;
+    }
+    Dev<T> *d_views = (Dev<T> *)A.alloc(sizeof(Dev<T>) * (size_t)B);
+    h2d(st, d_views, views.data(), B);
+    P->small_nq = A.make<double>(B);
+    P->small_nc = A.make<double>(B);
+    h2d(st, P->small_nq, P->Nq.data(), B);
+    h2d(st, P->small_nc, P->Nc.data(), B);
+    bsync(P);
+    P->small_devs = d_views;
+    P->small_R = R;
+    P->small_stage = stage;
+    P->small_slots = (int)std::min<size_t>((kSmallRegLds - lds) / 16, (size_t)64 * std::max(1, P->opt.window));
 }
 
 // row blocks (at most nb nonzeros and rb rows) of every instance's padded
@@ -387,6 +498,10 @@ int do_batch_load(lp_batch *P, const lp_csr *K, const double *const *c, const do
     };
     if (P->mixed) setup(float{});
     else setup(double{});
+    if (P->opt.persistent != 0) {
+        if (P->mixed) setup_small<float>(P, rp, ci, tp, ti);
+        else setup_small<double>(P, rp, ci, tp, ti);
+    }
     P->cin = std::move(cin);
     P->cim = std::move(cim);
     // controller blocks start zeroed (buffer 0 current)
@@ -394,8 +509,21 @@ int do_batch_load(lp_batch *P, const lp_csr *K, const double *const *c, const do
                         st));
     bsync(P);
     for (void *pp : {(void *)r, (void *)s, (void *)d_c, (void *)d_l, (void *)d_u, (void *)d_q}) A.release(pp);
-    if (P->mixed)
-        for (void *pp : {(void *)d_kv, (void *)d_tv, (void *)cs, (void *)ls, (void *)us, (void *)qs}) A.release(pp);
+    if (P->mixed) {
+        // kept for the FP64 re-check of termination tests passed on FP32 products
+        P->kv64 = d_kv; P->tv64 = d_tv; P->cs64 = cs; P->ls64 = ls; P->us64 = us; P->qs64 = qs;
+        P->g_rp = d_rp; P->g_ci = d_ci; P->g_tp = d_tp; P->g_ti = d_ti;
+        int64_t mmax = 1, nmax = 1;
+        for (int i = 0; i < B; ++i) {
+            mmax = std::max(mmax, P->m[i]);
+            nmax = std::max(nmax, P->n[i]);
+        }
+        for (int k = 0; k < 2; ++k) {
+            P->ckx[k] = A.make<double>(mmax);
+            P->ckty[k] = A.make<double>(nmax);
+        }
+        P->cpart = A.make<double>((int64_t)kMaxGrid * kCheckSums);
+    }
     return LP_OK;
 }
 
@@ -521,7 +649,63 @@ Ctl fresh_ctl(const lp_batch *P, int i, double tol, int64_t max_iters)
     c.check_every = P->opt.check_every;
     c.fixed_step = P->opt.fixed_step;
     c.final_status = LP_ITERATION_LIMIT;
+    c.confirm_on = P->mixed ? 1 : 0;
     return c;
+}
+
+// Mixed precision: instances whose termination test passed on FP32 products
+// stopped with `confirm` set.  Each is re-checked with FP64 products of the
+// FP64 scaled matrix (its rows of the batch's CSR pair, gathering from the
+// batch's vectors): confirmed, it ends OPTIMAL with the FP64 quantities;
+// otherwise its check decision runs again without the termination test
+// (restart logic, next primal trial) and it resumes in the next window.
+// Returns whether any instance was re-checked (the host controllers are then
+// current again).
+template <typename T>
+bool resolve_batch_confirms(lp_batch *P)
+{
+    if (!P->mixed) return false;
+    BDev<T> &b = P->dev<T>();
+    const Dev<T> &d = b.d;
+    hipStream_t st = P->stream;
+    bool any = false;
+    for (int i = 0; i < P->B; ++i) {
+        const Ctl &c = P->hctl[i];
+        if (!c.confirm) continue;
+        any = true;
+        const int64_t mo = P->moff[i], no = P->noff[i];
+        const Dev<T> v = view_of<T>(P, i);
+        Conf64 cf{};
+        cf.rp = P->g_rp + mo; cf.ci = P->g_ci; cf.kv = P->kv64;
+        cf.tp = P->g_tp + no; cf.ti = P->g_ti; cf.tv = P->tv64;
+        cf.cs = P->cs64 + no; cf.ls = P->ls64 + no; cf.us = P->us64 + no; cf.qs = P->qs64 + mo;
+        for (int k = 0; k < 2; ++k) {
+            cf.kx[k] = P->ckx[k];
+            cf.kty[k] = P->ckty[k];
+        }
+        cf.part = P->cpart;
+        Geo g{};
+        g.vb_n = (int)((v.n + kBlock - 1) / kBlock);
+        g.vb_m = (int)((v.m + kBlock - 1) / kBlock);
+        g.grid = std::max(1, std::min(kMaxGrid, g.vb_n + g.vb_m));
+        const int cur = c.cur;
+        HIPT(launch_confirm_gather<T>(v, g, cf, cur, (const T *)d.xb[cur], (const T *)d.xa, (const T *)d.yb[cur],
+                                      (const T *)d.ya, P->Nq[i], P->Nc[i], st));
+    }
+    if (!any) return false;
+    // the vetoed instances' check decisions (the confirmed ones only copy
+    // out); every other instance is kept out of these check kernels (an
+    // instance whose last slot was a check still has that check's mode; its
+    // next step decision sets the mode afresh)
+    std::vector<char> conf((size_t)P->B);
+    for (int i = 0; i < P->B; ++i) conf[(size_t)i] = P->hctl[i].confirm ? 1 : 0;
+    get_ctls(P, b.ctl);
+    for (int i = 0; i < P->B; ++i)
+        if (!conf[(size_t)i]) P->hctl[i].mode = MODE_NONE;
+    put_ctls(P, b.ctl);
+    HIPT(launch_batch_check<T>(b, 0, st));
+    get_ctls(P, b.ctl);
+    return true;
 }
 
 template <typename T>
@@ -574,6 +758,9 @@ int do_batch_solve(lp_batch *P, double tol, int64_t max_iters, double time_limit
             c.check_every = P->opt.check_every;
             c.fixed_step = P->opt.fixed_step;
             c.fixed_eta = P->opt.fixed_eta;
+            c.confirm_on = P->mixed ? 1 : 0;
+            c.confirm = 0;
+            c.veto = 0;
         }
         put_ctls(P, b.ctl);
         // the anchor's products (the state holds the anchor, not its products)
@@ -591,9 +778,53 @@ int do_batch_solve(lp_batch *P, double tol, int64_t max_iters, double time_limit
         HIPT(launch_batch_set_final(b.ctl, B, LP_ITERATION_LIMIT, st));
         HIPT(launch_batch_check<T>(b, 0, st));
         get_ctls(P, b.ctl);
+        resolve_batch_confirms<T>(P);
     }
     P->finish_s.assign(B, -1.0);
     const int W = std::max(1, P->opt.window);
+    if (P->small_R > 0) {
+        // a workgroup per instance runs its whole loop (up to small_slots
+        // attempt slots per launch); the host polls between launches
+        auto progress = [&] {
+            long long s = 0;
+            for (int i = 0; i < B; ++i) s += P->hctl[i].k + P->hctl[i].attempts;
+            return s;
+        };
+        int left = 0;
+        const double now0 = elapsed();
+        for (int i = 0; i < B; ++i) {
+            if (P->hctl[i].done && P->finish_s[i] < 0) P->finish_s[i] = now0;
+            if (!P->hctl[i].done) ++left;
+        }
+        while (left > 0) {
+            const long long before = progress();
+            HIPT(launch_small_loop_batch<T>((const Dev<T> *)P->small_devs, P->small_nq, P->small_nc, B, P->small_R,
+                                            P->small_stage, P->small_slots, st));
+            get_ctls(P, b.ctl);
+            resolve_batch_confirms<T>(P);
+            left = 0;
+            const double now = elapsed();
+            for (int i = 0; i < B; ++i) {
+                if (P->hctl[i].done && P->finish_s[i] < 0) P->finish_s[i] = now;
+                if (!P->hctl[i].done) ++left;
+            }
+            if (left > 0 && progress() == before) {
+                P->err = "no step decision in a whole launch (controller stalled)";
+                return LP_ERR_HIP;
+            }
+            if (left > 0 && time_limit > 0.0 && now > time_limit) {
+                HIPT(launch_batch_set_final(b.ctl, B, LP_TIME_LIMIT, st));
+                HIPT(launch_batch_check<T>(b, 0, st));
+                get_ctls(P, b.ctl);
+                resolve_batch_confirms<T>(P);
+                break;
+            }
+        }
+        bsync(P);
+        P->seconds = elapsed();
+        P->has_result = true;
+        return LP_OK;
+    }
     auto capture = [&] {
         if (P->graph) {
             (void)hipGraphExecDestroy(P->graph);
@@ -623,6 +854,7 @@ int do_batch_solve(lp_batch *P, double tol, int64_t max_iters, double time_limit
         else
             for (int s = 0; s < W; ++s) batch_slot<T>(P);
         get_ctls(P, b.ctl);
+        resolve_batch_confirms<T>(P);
         left = note_finished();
         // narrow the launches to the unfinished instances each time their
         // count has halved
@@ -636,6 +868,7 @@ int do_batch_solve(lp_batch *P, double tol, int64_t max_iters, double time_limit
             HIPT(launch_batch_set_final(b.ctl, B, LP_TIME_LIMIT, st));
             HIPT(launch_batch_check<T>(b, 0, st));
             get_ctls(P, b.ctl);
+            resolve_batch_confirms<T>(P);
             left = note_finished();
             break;
         }
@@ -854,6 +1087,13 @@ int lp_batch_layout_blocks(const lp_batch *P, int which, int *nnz_per_block, int
     if (!P || (which != 0 && which != 1)) return LP_ERR_ARG;
     if (nnz_per_block) *nnz_per_block = P->shape[which][0];
     if (rows_per_block) *rows_per_block = P->shape[which][1];
+    return LP_OK;
+}
+
+int lp_batch_loop_form(const lp_batch *P, int *form)
+{
+    if (!P || !form) return LP_ERR_ARG;
+    *form = P->small_R > 0 ? 1 : 0;
     return LP_OK;
 }
 

@@ -240,6 +240,13 @@ hipError_t noalloc_scratch(void **ptr);
 template <typename T>
 hipError_t launch_confirm(const Dev<T> &d, const Geo &g, const Conf64 &cf, int cur, double Nq, double Nc,
                           hipStream_t s);
+// the same re-check with the FP64 products gathering from gx, gxa (current
+// and averaged x) and gy, gya, which cf's column indices address: an LP's own
+// vectors, or a whole batch's when cf holds one instance's rows of the
+// batch's matrices (the products are written to cf's buffers by local row)
+template <typename T>
+hipError_t launch_confirm_gather(const Dev<T> &d, const Geo &g, const Conf64 &cf, int cur, const T *gx,
+                                 const T *gxa, const T *gy, const T *gya, double Nq, double Nc, hipStream_t s);
 // Bytes of LDS the staged one-workgroup loop needs: K and K' (values,
 // columns, row pointers) and the two gathered vectors (the primal trial and
 // the dual trial), values first so they stay 8-byte aligned.
@@ -254,6 +261,14 @@ __host__ __device__ inline size_t small_stage_bytes(int m, int n, int nnz_k, int
 // staged in LDS when they fit in kSmallStageMax bytes
 template <typename T> hipError_t launch_small_loop(const Dev<T> &d, int nnz_k, int nnz_t, int max_slots, double Nq,
                                                    double Nc, hipStream_t s);
+// the register form of that loop for count LPs at once, workgroup b on LP b
+// (devs[b]: its view; nq, nc: its norms): R = 1 when every LP has at most
+// kSmallReg rows and columns, 2 for at most twice that; stage_bytes the
+// largest small_stage_bytes of them; max_slots the slots per launch (its
+// step factors are tabulated in the LDS after the stage)
+template <typename T>
+hipError_t launch_small_loop_batch(const Dev<T> *devs, const double *nq, const double *nc, int count, int R,
+                                   size_t stage_bytes, int max_slots, hipStream_t s);
 template <typename T>
 hipError_t launch_gather_probe(const int *idx, const T *x, int64_t per_slice, int S, int64_t slice_len, T *out,
                                int grid, hipStream_t s);

@@ -523,9 +523,10 @@ __global__ __launch_bounds__(kSmall) void k_small_loop(Dev<T> d, int max_slots, 
 // launch can reach (at most max_slots of them) are tabulated in LDS at
 // entry, so the per-slot decision is plain arithmetic in thread 0, inline.
 // kSmallReg threads (fewer than the other forms) leave each thread enough
-// registers to hold its R columns and rows without spilling.
+// registers to hold its R columns and rows without spilling.  The body is
+// shared by the single-LP kernel and the batched one (a workgroup per LP).
 template <typename T, int R>
-__global__ __launch_bounds__(kSmallReg) void k_small_reg(Dev<T> d, int max_slots, double Nq, double Nc)
+__device__ __forceinline__ void small_reg_body(const Dev<T> &d, int max_slots, double Nq, double Nc)
 {
     constexpr int NT = kSmallReg;
     extern __shared__ double dyn[];
@@ -758,6 +759,23 @@ __global__ __launch_bounds__(kSmallReg) void k_small_reg(Dev<T> d, int max_slots
         }
     }
     if (tid == 0) *d.ctl = sc;
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(kSmallReg) void k_small_reg(Dev<T> d, int max_slots, double Nq, double Nc)
+{
+    small_reg_body<T, R>(d, max_slots, Nq, Nc);
+}
+
+// Many small LPs, workgroup b on LP b: devs[b] is LP b's view of a batch
+// (its vectors, its own plain CSR of K and K', its controller), nq / nc its
+// norms; every LP runs until it is done or max_slots slots have passed.
+template <typename T, int R>
+__global__ __launch_bounds__(kSmallReg) void k_small_reg_batch(const Dev<T> *__restrict__ devs,
+                                                               const double *__restrict__ nq,
+                                                               const double *__restrict__ nc, int max_slots)
+{
+    small_reg_body<T, R>(devs[blockIdx.x], max_slots, nq[blockIdx.x], nc[blockIdx.x]);
 }
 
 // Gather-rate probe (a measurement helper, not a step of the method): the
@@ -1106,20 +1124,48 @@ template <typename T>
 hipError_t launch_confirm(const Dev<T> &d, const Geo &g, const Conf64 &cf, int cur, double Nq, double Nc,
                           hipStream_t s)
 {
+    return launch_confirm_gather<T>(d, g, cf, cur, cur ? d.xb[1] : d.xb[0], d.xa, cur ? d.yb[1] : d.yb[0], d.ya, Nq,
+                                    Nc, s);
+}
+
+template <typename T>
+hipError_t launch_confirm_gather(const Dev<T> &d, const Geo &g, const Conf64 &cf, int cur, const T *gx,
+                                 const T *gxa, const T *gy, const T *gya, double Nq, double Nc, hipStream_t s)
+{
     auto waves = [](int rows) { return dim3((unsigned)std::max(1, std::min((rows + 3) / 4, 8192))); };
-    const T *x = cur ? d.xb[1] : d.xb[0], *y = cur ? d.yb[1] : d.yb[0];
     if (d.m > 0) {
-        hipLaunchKernelGGL(k_csr64<T>, waves(d.m), dim3(kBlock), 0, s, cf.rp, cf.ci, cf.kv, x, cf.kx[0], d.m);
-        hipLaunchKernelGGL(k_csr64<T>, waves(d.m), dim3(kBlock), 0, s, cf.rp, cf.ci, cf.kv, (const T *)d.xa, cf.kx[1],
-                           d.m);
+        hipLaunchKernelGGL(k_csr64<T>, waves(d.m), dim3(kBlock), 0, s, cf.rp, cf.ci, cf.kv, gx, cf.kx[0], d.m);
+        hipLaunchKernelGGL(k_csr64<T>, waves(d.m), dim3(kBlock), 0, s, cf.rp, cf.ci, cf.kv, gxa, cf.kx[1], d.m);
     }
     if (d.n > 0) {
-        hipLaunchKernelGGL(k_csr64<T>, waves(d.n), dim3(kBlock), 0, s, cf.tp, cf.ti, cf.tv, y, cf.kty[0], d.n);
-        hipLaunchKernelGGL(k_csr64<T>, waves(d.n), dim3(kBlock), 0, s, cf.tp, cf.ti, cf.tv, (const T *)d.ya,
-                           cf.kty[1], d.n);
+        hipLaunchKernelGGL(k_csr64<T>, waves(d.n), dim3(kBlock), 0, s, cf.tp, cf.ti, cf.tv, gy, cf.kty[0], d.n);
+        hipLaunchKernelGGL(k_csr64<T>, waves(d.n), dim3(kBlock), 0, s, cf.tp, cf.ti, cf.tv, gya, cf.kty[1], d.n);
     }
     hipLaunchKernelGGL(k_confirm_sums<T>, dim3(g.grid), dim3(kBlock), 0, s, d, cf, cur, g.vb_n, g.vb_m);
     hipLaunchKernelGGL(k_confirm_decide, dim3(1), dim3(kBlock), 0, s, d.ctl, (const double *)cf.part, g.grid, Nq, Nc);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_small_loop_batch(const Dev<T> *devs, const double *nq, const double *nc, int count, int R,
+                                   size_t stage_bytes, int max_slots, hipStream_t s)
+{
+    static bool attr_set = false;   // the kernels' LDS limit raised once per process
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_small_reg_batch<T, 1>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallRegLds);
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_small_reg_batch<T, 2>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallRegLds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const size_t bytes = ((stage_bytes + 7) / 8) * 8 + 16 * (size_t)max_slots;
+    if (count <= 0 || max_slots <= 0 || bytes > kSmallRegLds || (R != 1 && R != 2)) return hipErrorInvalidValue;
+    if (R == 1)
+        hipLaunchKernelGGL((k_small_reg_batch<T, 1>), dim3(count), dim3(kSmallReg), bytes, s, devs, nq, nc, max_slots);
+    else
+        hipLaunchKernelGGL((k_small_reg_batch<T, 2>), dim3(count), dim3(kSmallReg), bytes, s, devs, nq, nc, max_slots);
     return hipGetLastError();
 }
 
@@ -1358,8 +1404,12 @@ hipError_t scale_csr_pair(const int *rp, const int *ci, double *kv, int m, const
     template hipError_t launch_spmv<T>(const Sliced<T> &, const T *, T *, hipStream_t);                            \
     template hipError_t launch_gather_probe<T>(const int *, const T *, int64_t, int, int64_t, T *, int, hipStream_t); \
     template hipError_t launch_small_loop<T>(const Dev<T> &, int, int, int, double, double, hipStream_t);        \
+    template hipError_t launch_small_loop_batch<T>(const Dev<T> *, const double *, const double *, int, int,      \
+                                                   size_t, int, hipStream_t);                                     \
     template hipError_t launch_confirm<T>(const Dev<T> &, const Geo &, const Conf64 &, int, double, double,       \
                                           hipStream_t);                                                           \
+    template hipError_t launch_confirm_gather<T>(const Dev<T> &, const Geo &, const Conf64 &, int, const T *,     \
+                                                 const T *, const T *, const T *, double, double, hipStream_t);   \
     template hipError_t launch_gather_values<T>(const double *, const int *, T *, int64_t, hipStream_t);           \
     template hipError_t launch_start<T>(const Dev<T> &, const double *, const double *, int, hipStream_t);         \
     template hipError_t launch_result<T>(const Dev<T> &, double *, double *, double *, hipStream_t);               \

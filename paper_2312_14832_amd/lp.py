@@ -27,7 +27,7 @@ EXPORTS = ["lp_default_options", "lp_workspace_size", "lp_load", "lp_set_start",
            "lp_set_state", "lp_get_scaling", "lp_spmv", "lp_spmv_noalloc", "lp_gather_probe", "lp_kernel_time", "lp_device_bytes", "lp_layout",
            "lp_layout_blocks", "lp_presolved_size", "lp_free",
            "lp_strerror", "lp_last_error", "lp_batch_load", "lp_batch_solve", "lp_batch_result",
-           "lp_batch_get_state", "lp_batch_set_state", "lp_batch_device_bytes", "lp_batch_layout_blocks",
+           "lp_batch_get_state", "lp_batch_set_state", "lp_batch_device_bytes", "lp_batch_layout_blocks", "lp_batch_loop_form",
            "lp_batch_free",
            "lp_batch_last_error", "lp_shared_load", "lp_shared_set_start", "lp_shared_solve", "lp_shared_result",
            "lp_shared_get_state", "lp_shared_set_state", "lp_shared_device_bytes", "lp_shared_free",
@@ -105,6 +105,7 @@ def library():
         L.lp_batch_set_state.argtypes = [C.c_void_p, C.c_int32, dp, C.c_int64]
         L.lp_batch_device_bytes.argtypes = [C.c_void_p, C.POINTER(C.c_int64)]
         L.lp_batch_layout_blocks.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.lp_batch_loop_form.argtypes = [C.c_void_p, C.POINTER(C.c_int)]
         L.lp_batch_free.argtypes = [C.c_void_p]
         L.lp_batch_free.restype = None
         L.lp_batch_last_error.argtypes = [C.c_void_p]
@@ -426,6 +427,12 @@ class Batch:
         b = C.c_int64()
         self._check(library().lp_batch_device_bytes(self.h, C.byref(b)))
         return b.value
+
+    def loop_form(self):
+        """0: batched kernel launches; 1: one workgroup per instance."""
+        f = C.c_int()
+        self._check(library().lp_batch_loop_form(self.h, C.byref(f)))
+        return f.value
 
 
 class Shared:

