@@ -267,6 +267,8 @@ def main():
                          "family solved over one shared matrix")
     ap.add_argument("--shared-count", type=int, default=64, help="shared: instances per handle")
     ap.add_argument("--batch-count", type=int, default=512)
+    ap.add_argument("--batch-kind", choices=["uneven", "tiny"], default="uneven",
+                    help="batch: 512 uneven LPs (n 2e3..2e5, to 1e-4) or 512 tiny LPs (n=1000, to 1e-6)")
     ap.add_argument("--batch-fixed-iters", type=int, default=0,
                     help="batch: only a fixed number of iterations with every instance active (profiling)")
     ap.add_argument("--seq-sample", type=int, default=128,
@@ -663,6 +665,9 @@ def bench_batch(args):
     fp64).  The sequential leg solves every (count/seq_sample)-th instance
     with the single-LP path (load excluded) and scales the sum up.
     """
+    if args.batch_kind == "tiny":
+        print(json.dumps(run_batch_tiny(args)))
+        return
     if args.batch_fixed_iters <= 0:
         print(json.dumps(run_batch(args, args.precision, args.seq_sample)))
         return
@@ -684,6 +689,65 @@ def bench_batch(args):
                                  "padded_m": sum((p.m + 255) // 256 * 256 for p in lps),
                                  "precision": args.precision},
                       "alg_bytes_per_launch": alg}))
+
+
+def run_batch_tiny(args):
+    """A batch of tiny LPs (the tiny generator, n=1000, m1=200, m2=300, 5
+    nonzeros per column; seeds 2000..) solved to rel KKT 1e-6: one workgroup
+    per instance (the default for such a batch), the batched launches
+    (persistent = 0), and a sample solved one by one on single-LP handles
+    (each on its own one-workgroup loop)."""
+    import numpy as np
+    import torch
+    from paper_2312_14832_amd import gen, lp
+
+    tol = 1e-6
+    lps = [gen.tiny_lp(2000 + i) for i in range(args.batch_count)]
+    st = torch.cuda.current_stream()
+    forms = {}
+    for name, pers in (("one_workgroup_per_lp", -1), ("launches", 0)):
+        bt = lp.Batch(lps, precision=args.precision, stream=st, persistent=pers)
+        bt.solve(1e-30, 64)   # warm-up (graph capture, caches)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bt.solve(tol, 10**6, args.ttt_limit)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        infos = [bt.info(i) for i in range(len(lps))]
+        its = np.array([d["iterations"] for d in infos])
+        forms[name] = {"loop_form": bt.loop_form(), "seconds": dt,
+                       "solved": sum(1 for d in infos if d["status"] == "OPTIMAL"),
+                       "iterations_median": float(np.median(its)), "iterations_max": int(its.max())}
+        print(f"[bench] tiny batch, {name}: {forms[name]['solved']}/{len(lps)} optimal in {dt:.3f}s "
+              f"(iterations median {np.median(its):.0f}, max {its.max()})", file=sys.stderr, flush=True)
+        bt.close()
+    stride = max(1, len(lps) // max(args.seq_sample, 1))
+    times = []
+    for i in range(0, len(lps), stride):
+        p = lp.Problem(lps[i], precision=args.precision, stream=st)
+        p.solve(1e-30, 64)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        p.solve(tol, 10**6, args.ttt_limit)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t1)
+        p.close()
+    times = np.array(times)
+    seq_est = float(times.sum()) * len(lps) / len(times)
+    seq_err = len(lps) * float(np.std(times, ddof=1)) / np.sqrt(len(times)) if len(times) > 1 else None
+    head = forms["one_workgroup_per_lp"]
+    print(f"[bench] tiny batch, one by one: {len(times)} in {times.sum():.2f}s -> {seq_est:.1f}s for all "
+          f"(speedup {seq_est / head['seconds']:.0f}x)", file=sys.stderr, flush=True)
+    return {"metric": "batch time-to-1e-6 KKT", "value": len(lps) / head["seconds"], "unit": "LPs/s", "n_gpus": 1,
+            "steps": 1, "warmup": 1, "ms_per_step": 1e3 * head["seconds"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None,
+            "dtype": "f64" if args.precision == "fp64" else "f32+f64acc", "data": "synthetic",
+            "config": {"workload": f"batch_{len(lps)}_tiny_lps", "count": len(lps), "n": 1000, "m1": 200, "m2": 300,
+                       "seeds": [2000, 2000 + len(lps) - 1], "precision": args.precision, "tol": tol},
+            "forms": forms,
+            "sequential": {"sample": len(times), "stride": stride, "seconds_sample": float(times.sum()),
+                           "seconds_extrapolated": seq_est, "seconds_extrapolated_stderr": seq_err,
+                           "speedup": seq_est / head["seconds"]}}
 
 
 def _batch_setup(args, precision):
