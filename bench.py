@@ -464,9 +464,11 @@ def other_configs(args):
     """Short runs of the other configurations, so that one default bench run
     measures them all: the tiny LPs (one-workgroup loop and launches, time to
     1e-6, the oracle's time beside them), the 4e6-column LP in mixed precision
-    (iteration rate, time to 1e-4, the returned point evaluated in FP64), and
-    the batch of 512 uneven LPs (time to 1e-4, against a sample of them solved
-    one by one).  Each result is in the unit of its own configuration."""
+    (iteration rate, time to 1e-4, the returned point evaluated in FP64), the
+    batch of 512 uneven LPs (time to 1e-4, against a sample of them solved one
+    by one), and a batch of 512 tiny LPs (one workgroup per LP, the batched
+    launches, 32 of them one by one).  Each result is in the unit of its own
+    configuration."""
     import torch
     res = {}
     print("[bench] other configurations: tiny", file=sys.stderr, flush=True)
@@ -482,6 +484,14 @@ def other_configs(args):
     res[b["config"]["workload"] + "_mixed"] = {k: b[k] for k in ("metric", "value", "unit", "dtype", "config",
                                                                  "batch_seconds", "solved", "iterations_median",
                                                                  "iterations_max", "sequential")}
+    torch.cuda.empty_cache()
+    print("[bench] other configurations: batch of 512 tiny LPs", file=sys.stderr, flush=True)
+    saved = (args.seq_sample, args.precision)
+    args.seq_sample, args.precision = 32, "fp64"
+    t = run_batch_tiny(args)
+    args.seq_sample, args.precision = saved
+    res[t["config"]["workload"]] = {k: t[k] for k in ("metric", "value", "unit", "dtype", "config", "forms",
+                                                      "sequential")}
     torch.cuda.empty_cache()
     return res
 
