@@ -359,7 +359,9 @@ int lp_shared_load(lp_shared **S, int32_t count, const lp_csr *K, const double *
 int lp_shared_set_start(lp_shared *S, int32_t i, const double *x0, const double *y0, double omega);
 /* Solve every instance from its start (or resume, when lp_shared_set_state
  * was called for every instance since the last solve) until each is optimal
- * at tol, reaches max_iters accepted steps, or the time limit ends the call. */
+ * at tol, reaches max_iters accepted steps, or the time limit ends the call.
+ * In LP_MIXED an instance whose termination test passes on FP32 products is
+ * confirmed with FP64 products before it ends OPTIMAL, as in lp_solve. */
 int lp_shared_solve(lp_shared *S, double tol, int64_t max_iters, double time_limit_s);
 /* Result of instance i as lp_result; info->seconds is the time into the last
  * lp_shared_solve at which the host saw instance i finish.  LP_ERR_STATE

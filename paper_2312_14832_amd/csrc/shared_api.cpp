@@ -45,6 +45,12 @@ struct lp_shared {
     double *start_x = nullptr, *start_y = nullptr;                         // interleaved start (unscaled)
     std::vector<char> has_start;
     std::vector<double> omega_start;
+    // Mixed precision's FP64 re-check of a passed termination test (as
+    // lp_solve's): the FP64 scaled matrices and interleaved vectors kept from
+    // the load, the scaling as plain vectors, and one instance's FP64 copies
+    const double *kv64 = nullptr, *tv64 = nullptr, *cs64 = nullptr, *ls64 = nullptr, *us64 = nullptr,
+                 *qs64 = nullptr;
+    double *cDr = nullptr, *cDc = nullptr, *cvec[10] = {}, *ckx[2] = {}, *ckty[2] = {}, *cpart = nullptr;
     hipGraphExec_t graph = nullptr;
     int graph_window = 0;
     bool has_result = false, result_ready = false;
@@ -276,12 +282,27 @@ int do_load(lp_shared *P, const lp_csr *K, const double *const *c, const double 
     P->start_y = A.make<double>(M);
     if (P->mixed) setup<float>(P, rp, ci, tp, ti, d_kv, d_tv, cs, ls, us, qs, Drr, Dcr);
     else setup<double>(P, rp, ci, tp, ti, d_kv, d_tv, cs, ls, us, qs, Drr, Dcr);
-    for (void *pp : {(void *)d_rp, (void *)d_ci, (void *)d_tp, (void *)d_ti, (void *)d_kv, (void *)d_tv, (void *)r,
-                     (void *)s, (void *)Dr, (void *)Dc, (void *)d_kl, (void *)d_tl, (void *)d_c, (void *)d_l,
-                     (void *)d_u, (void *)d_q, (void *)red_part, (void *)red_out})
+    for (void *pp : {(void *)d_rp, (void *)d_ci, (void *)d_tp, (void *)d_ti, (void *)r, (void *)s, (void *)Dr,
+                     (void *)Dc, (void *)d_kl, (void *)d_tl, (void *)d_c, (void *)d_l, (void *)d_u, (void *)d_q,
+                     (void *)red_part, (void *)red_out})
         A.release(pp);
-    if (P->mixed)
-        for (void *pp : {(void *)cs, (void *)ls, (void *)us, (void *)qs}) A.release(pp);
+    if (P->mixed) {
+        // kept for the FP64 re-check of termination tests passed on FP32 products
+        P->kv64 = d_kv; P->tv64 = d_tv; P->cs64 = cs; P->ls64 = ls; P->us64 = us; P->qs64 = qs;
+        P->cDr = A.make<double>(m);
+        P->cDc = A.make<double>(n);
+        h2d(st, P->cDr, P->Dr.data(), m);
+        h2d(st, P->cDc, P->Dc.data(), n);
+        for (int k = 0; k < 10; ++k) P->cvec[k] = A.make<double>(k < 6 ? n : m);
+        for (int k = 0; k < 2; ++k) {
+            P->ckx[k] = A.make<double>(m);
+            P->ckty[k] = A.make<double>(n);
+        }
+        P->cpart = A.make<double>((int64_t)kMaxGrid * kCheckSums);
+    } else {
+        A.release(d_kv);
+        A.release(d_tv);
+    }
     // the controllers: padded instances are finished from the start
     std::memset(P->hctl, 0, sizeof(Ctl) * (size_t)Bp);
     for (int b = B; b < Bp; ++b) P->hctl[b].done = 1;
@@ -313,6 +334,81 @@ void apply_options(const lp_shared *P, Ctl &c, double tol, int64_t max_iters)
     c.check_every = P->opt.check_every;
     c.fixed_step = P->opt.fixed_step;
     c.final_status = LP_ITERATION_LIMIT;
+    c.confirm_on = P->mixed ? 1 : 0;
+    c.confirm = 0;
+    c.veto = 0;
+}
+
+// Mixed precision: members whose termination test passed on FP32 products
+// stopped with `confirm` set.  Each is re-checked with FP64 products of the
+// FP64 scaled matrix on FP64 copies of its vectors: confirmed, it ends
+// OPTIMAL with the FP64 quantities; otherwise its check decision runs again
+// without the termination test and it resumes in the next window.
+template <typename T>
+void resolve_shared_confirms(lp_shared *P)
+{
+    if (!P->mixed) return;
+    SDev<T> &S = P->dev<T>();
+    const Dev<T> &d = S.d;
+    hipStream_t st = P->stream;
+    const int n = (int)P->n, m = (int)P->m;
+    double *const *v = P->cvec;   // n-vectors x, x avg, x0, c~, l~, u~; m-vectors y, y avg, y0, q~
+    std::vector<char> conf((size_t)P->Bp, 0);
+    bool any = false;
+    for (int b = 0; b < P->B; ++b) {
+        const Ctl &c = P->hctl[b];
+        if (!c.confirm) continue;
+        any = true;
+        conf[(size_t)b] = 1;
+        const int cur = c.cur;
+        HIPT(launch_shared_extract<T>(d.xb[cur], S.lgB, b, v[0], n, st));
+        HIPT(launch_shared_extract<T>(d.xa, S.lgB, b, v[1], n, st));
+        HIPT(launch_shared_extract<T>(d.x0, S.lgB, b, v[2], n, st));
+        HIPT(launch_shared_extract<double>(P->cs64, S.lgB, b, v[3], n, st));
+        HIPT(launch_shared_extract<double>(P->ls64, S.lgB, b, v[4], n, st));
+        HIPT(launch_shared_extract<double>(P->us64, S.lgB, b, v[5], n, st));
+        HIPT(launch_shared_extract<T>(d.yb[cur], S.lgB, b, v[6], m, st));
+        HIPT(launch_shared_extract<T>(d.ya, S.lgB, b, v[7], m, st));
+        HIPT(launch_shared_extract<T>(d.y0, S.lgB, b, v[8], m, st));
+        HIPT(launch_shared_extract<double>(P->qs64, S.lgB, b, v[9], m, st));
+        Dev<double> w{};   // member b as a plain FP64 LP (only what the re-check reads)
+        w.m = m;
+        w.n = n;
+        w.m1 = (int)P->m1;
+        w.Dr = P->cDr;
+        w.Dc = P->cDc;
+        w.xb[0] = w.xb[1] = v[0];
+        w.xa = v[1];
+        w.x0 = v[2];
+        w.yb[0] = w.yb[1] = v[6];
+        w.ya = v[7];
+        w.y0 = v[8];
+        w.ctl = S.ctl + b;
+        Conf64 cf{};
+        cf.rp = S.krp; cf.ci = S.kci; cf.kv = P->kv64;
+        cf.tp = S.trp; cf.ti = S.tci; cf.tv = P->tv64;
+        cf.cs = v[3]; cf.ls = v[4]; cf.us = v[5]; cf.qs = v[9];
+        for (int k = 0; k < 2; ++k) {
+            cf.kx[k] = P->ckx[k];
+            cf.kty[k] = P->ckty[k];
+        }
+        cf.part = P->cpart;
+        Geo g{};
+        g.vb_n = (n + kBlock - 1) / kBlock;
+        g.vb_m = (m + kBlock - 1) / kBlock;
+        g.grid = std::max(1, std::min(kMaxGrid, g.vb_n + g.vb_m));
+        HIPT(launch_confirm<double>(w, g, cf, 0, P->Nq[b], P->Nc[b], st));
+    }
+    if (!any) return;
+    // the vetoed members' check decisions (the confirmed ones only copy out);
+    // every other member is kept out of these check kernels (its next step
+    // decision sets its mode afresh)
+    get_ctls(P, S.ctl);
+    for (int b = 0; b < P->Bp; ++b)
+        if (!conf[(size_t)b]) P->hctl[b].mode = MODE_NONE;
+    put_ctls(P, S.ctl);
+    HIPT(launch_shared_check<T>(S, 0, st));
+    get_ctls(P, S.ctl);
 }
 
 template <typename T>
@@ -385,6 +481,7 @@ int do_solve(lp_shared *P, double tol, int64_t max_iters, double time_limit)
         HIPT(launch_shared_set_final(S.ctl, Bp, LP_ITERATION_LIMIT, st));
         HIPT(launch_shared_check<T>(S, 0, st));
         get_ctls(P, S.ctl);
+        resolve_shared_confirms<T>(P);
     }
     P->finish_s.assign(B, -1.0);
     const int W = std::max(1, P->opt.window);
@@ -419,6 +516,7 @@ int do_solve(lp_shared *P, double tol, int64_t max_iters, double time_limit)
             for (int s = 0; s < W; ++s) HIPT(launch_shared_slot<T>(S, st));
         get_ctls(P, S.ctl);
         for (int b = 0; b < B; ++b) moved += P->hctl[b].attempts;
+        resolve_shared_confirms<T>(P);
         left = note_finished();
         if (left > 0 && moved == 0) {
             // every slot takes a step decision for every unfinished instance
@@ -429,6 +527,7 @@ int do_solve(lp_shared *P, double tol, int64_t max_iters, double time_limit)
             HIPT(launch_shared_set_final(S.ctl, Bp, LP_TIME_LIMIT, st));
             HIPT(launch_shared_check<T>(S, 0, st));
             get_ctls(P, S.ctl);
+            resolve_shared_confirms<T>(P);
             left = note_finished();
             break;
         }

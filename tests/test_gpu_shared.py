@@ -149,6 +149,10 @@ def test_shared_solves_to_1e4(lpmod, oracle_mod, precision):
         assert info["status"] == "OPTIMAL", (i, info)
         ev = oracle_mod.Oracle(p).eval_unscaled(x, y)
         assert ev["rel_kkt"] <= 1e-4 * (1 + 1e-6), (i, ev)
+        if precision == "mixed":
+            # the reported criteria are the FP64 re-check's, i.e. the oracle's evaluation
+            for k, kk in (("rel_primal", "rel_p"), ("rel_dual", "rel_d"), ("rel_gap", "rel_g")):
+                assert info[k] == pytest.approx(ev[kk], rel=1e-8, abs=1e-14), (i, k, info[k], ev[kk])
         io, dev, bar = objective_spread(oracle_mod, p, 1e-4, rel=rel)
         assert abs(info["pobj"] - io["pobj"]) <= bar, (i, info["pobj"], io["pobj"], dev)
         fl, fu = np.isfinite(p.l), np.isfinite(p.u)
