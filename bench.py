@@ -86,6 +86,11 @@ def profiled_layout(dirpath):
     default 2048 nonzeros and 1024 rows unless the line names them)."""
     import re
     text = open(os.path.join(dirpath, "stats.log")).read()
+    m = re.search(r"layout K \(S, nnz/block, rows/block, split sums\) = \((\d+), (\d+), (\d+), (\d+)\), "
+                  r"K' = \((\d+), (\d+), (\d+), (\d+)\)", text)
+    if m:
+        v = [int(g) for g in m.groups()]
+        return {"K": v[:4], "KT": v[4:]}
     m = re.search(r"layout K \(S, nnz/block, rows/block\) = \((\d+), (\d+), (\d+)\), "
                   r"K' = \((\d+), (\d+), (\d+)\)", text)
     if m:
@@ -279,6 +284,9 @@ def main():
                          "1: events in every window (plain launches); 0: no events")
     ap.add_argument("--autotune", type=int, default=1, choices=[0, 1],
                     help="1: time neighbouring layouts at load and keep the fastest; 0: the default layout")
+    ap.add_argument("--split-sums", type=int, default=-1, choices=[-1, 0, 1],
+                    help="row sums of short-row blocks: 1 split by entries, 0 one row per thread, -1 the "
+                         "library's default (split; with --autotune 1 the other form is timed per product)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run 5 plain device-to-device copies of this many MiB (counter calibration)")
     ap.add_argument("--traffic-from", default=None,
@@ -339,13 +347,13 @@ def main():
     stream = torch.cuda.current_stream()
     t0 = time.perf_counter()
     prob = lp.Problem(data, precision=args.precision, stream=stream, kernel_timing=args.kernel_timing,
-                      autotune=args.autotune)
+                      autotune=args.autotune, split_sums=args.split_sums)
     torch.cuda.synchronize()
     load_s = time.perf_counter() - t0
-    lk, lt = prob.layout_blocks(0), prob.layout_blocks(1)
+    lk, lt = (prob.layout_blocks(w) + (prob.layout_split(w),) for w in (0, 1))
     print(f"[bench] loaded in {load_s:.1f}s ({prob.device_bytes() / 2**30:.2f} GiB on device), "
-          f"column slices (K, K') = {prob.layout()}; layout K (S, nnz/block, rows/block) = {lk}, K' = {lt}",
-          file=sys.stderr, flush=True)
+          f"column slices (K, K') = {prob.layout()}; layout K (S, nnz/block, rows/block, split sums) = {lk}, "
+          f"K' = {lt}", file=sys.stderr, flush=True)
 
     # warm-up windows (also compiles nothing: kernels are prebuilt)
     prob.solve(1e-30, ITERS_PER_STEP * max(args.warmup, 0))
@@ -403,7 +411,8 @@ def main():
           file=sys.stderr, flush=True)
 
     prob_layout = prob.layout()
-    blocks = {name: dict(zip(("slices", "nnz_per_block", "rows_per_block"), prob.layout_blocks(w)))
+    blocks = {name: dict(zip(("slices", "nnz_per_block", "rows_per_block", "split_sums"),
+                             prob.layout_blocks(w) + (prob.layout_split(w),)))
               for w, name in ((0, "K"), (1, "KT"))}
     ttt = None
     if not args.no_ttt:
@@ -774,7 +783,8 @@ def _batch_setup(args, precision):
     print(f"[bench] generated {len(lps)} LPs, sum n={sum(p.n for p in lps)}, sum nnz={nnz} in {gen_s:.1f}s",
           file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    bt = lp.Batch(lps, precision=precision, stream=torch.cuda.current_stream(), autotune=args.autotune)
+    bt = lp.Batch(lps, precision=precision, stream=torch.cuda.current_stream(), autotune=args.autotune,
+                  split_sums=args.split_sums)
     load_s = time.perf_counter() - t0
     shapes = {"K": bt.layout_blocks(0), "KT": bt.layout_blocks(1)}
     print(f"[bench] batch loaded in {load_s:.1f}s ({bt.device_bytes() / 2**30:.2f} GiB), row blocks "

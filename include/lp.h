@@ -143,6 +143,19 @@ typedef struct {
                                own loop (one launch per 64 x window slots for the whole batch), when every
                                instance has 1 to 1024 rows and columns and its K, K' and vectors fit the
                                LDS (lp_batch_loop_form); 0: the batched kernel launches. */
+    int split_sums;         /* how the products' partial passes add up blocks of short rows (at most 64
+                               entries per row and column slice).  0: one row per thread, in index order;
+                               1: split by entries, each thread adding the products of 8 consecutive
+                               entries row by row and a row that crosses those chunks finished from the
+                               chunks' open parts in a fixed order (a few long rows among short ones then
+                               no longer hold up their wavefront); -1 (default): split in a product of at
+                               least 1024 row blocks (about 2 million nonzeros; in smaller ones the
+                               split's extra barriers cost more than they save), and with autotune the
+                               other form is timed on each product's chosen layout and kept when at
+                               least 3% faster (lp_layout_split).  Both forms are deterministic;
+                               they differ only in the rounding order of the row sums.  lp_batch_load:
+                               1 split, -1 or 0 by rows (the batched workloads' rows are short and even,
+                               and splitting them measured no faster); shared-matrix batches: ignored. */
 } lp_options;
 
 typedef struct {
@@ -280,6 +293,10 @@ int lp_layout(const lp_problem *P, int *slices_K, int *slices_KT);
  * forms a block of its own).  Any output may be NULL; LP_ERR_ARG for a bad
  * `which`. */
 int lp_layout_blocks(const lp_problem *P, int which, int *slices, int *nnz_per_block, int *rows_per_block);
+/* How the partial passes of K (which = 0) or K' (which = 1) add up their
+ * blocks of short rows: *split = 1 split by entries, 0 one row per thread
+ * (lp_options.split_sums).  LP_ERR_ARG on a NULL pointer or another which. */
+int lp_layout_split(const lp_problem *P, int which, int *split);
 
 void lp_free(lp_problem *P);
 

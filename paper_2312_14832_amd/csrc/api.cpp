@@ -268,6 +268,7 @@ struct lp_problem {
     int device = -1;                // device current at lp_load (the handle's GPU)
     void *nscratch = nullptr;       // that device's fixed scratch array (lp_spmv_noalloc); null if unavailable
     int shape_K[3] = {1, kStreamNB, kStreamRB}, shape_KT[3] = {1, kStreamNB, kStreamRB};  // S, nnz, rows per block
+    int split_K = 0, split_KT = 0;   // Sliced::split of the two products
     std::vector<TuneTrial> tune_log_K, tune_log_KT;   // layouts tried by the autotuner
     std::vector<hipEvent_t> ev;
     int64_t t_count[2] = {0, 0};
@@ -348,11 +349,12 @@ void sync(lp_problem *P) { HIPT(hipStreamSynchronize(P->stream)); }
 // Device side of a sliced product: structure uploaded from H, values gathered
 // from the scaled FP64 CSR values by the recorded source positions.
 template <typename T>
-Sliced<T> upload_sliced(lp_problem *P, const HostSliced &H, const double *scaled_csr_vals)
+Sliced<T> upload_sliced(lp_problem *P, const HostSliced &H, const double *scaled_csr_vals, int split)
 {
     const int64_t nnz = H.rp[(size_t)H.S * (H.rows + 1) - 1];
     Sliced<T> q{};
     q.S = H.S;
+    q.split = split;
     q.rows = H.rows;
     q.grid = partial_grid(H.S, H.max_blocks);
     int *rp = (int *)P->dalloc(sizeof(int) * H.rp.size());
@@ -410,6 +412,14 @@ float time_product(lp_problem *P, const Sliced<T> &q, T *in, T *out, int64_t in_
     return ev.ms() / reps;
 }
 
+// Row blocks from which a product's short-row sums are split by entries by
+// default: below that the partial pass is a few workgroups whose time is
+// latency, which the split's two extra barriers lengthen (the 5,000-entry LP:
+// 51k against 44k iterations per second in launched slots), while above it
+// the split evens out the threads' work (the 2e7-entry power-law LP: K' pass
+// 128 against 124 us).
+constexpr size_t kSplitMinBlocks = 1024;
+
 // A trial layout replaces the incumbent only when it is this much faster, so
 // that near-ties (timing noise) keep the earlier, default-side layout and
 // two processes rarely pick different layouts.
@@ -421,11 +431,14 @@ constexpr float kTuneMargin = 0.97f;
 // the best slice count, on the actual matrix, and keeps the fastest.  The walk
 // matters on very sparse matrices with many rows: each slice adds a row
 // pointer and a partial per row, which can outweigh the L2 locality it buys.
+// Last, when split_sums is -1, it times the other form of the row sums on the
+// chosen layout (same device arrays) and keeps the faster.
 template <typename T>
 Sliced<T> tuned_sliced(lp_problem *P, const HostSliced &H0, const std::vector<int> &rp, const std::vector<int> &ci,
-                       const double *vals, T *in, T *out, int64_t in_len, std::vector<TuneTrial> &log, int *shape)
+                       const double *vals, T *in, T *out, int64_t in_len, std::vector<TuneTrial> &log, int *shape,
+                       int split)
 {
-    Sliced<T> best = upload_sliced<T>(P, H0, vals);
+    Sliced<T> best = upload_sliced<T>(P, H0, vals, split);
     float best_ms = time_product<T>(P, best, in, out, in_len);
     log.push_back({H0.S, H0.nb, H0.rb, best_ms});
     shape[0] = H0.S; shape[1] = H0.nb; shape[2] = H0.rb;
@@ -433,7 +446,7 @@ Sliced<T> tuned_sliced(lp_problem *P, const HostSliced &H0, const std::vector<in
     auto trial = [&](int S, int nb, int rb) {
         HostSliced H;
         build_sliced(H, H0.rows, H0.cols, rp, ci, S, nb, rb);
-        Sliced<T> q = upload_sliced<T>(P, H, vals);
+        Sliced<T> q = upload_sliced<T>(P, H, vals, split);
         const float ms = time_product<T>(P, q, in, out, in_len);
         log.push_back({S, nb, rb, ms});
         if (ms < kTuneMargin * best_ms) {
@@ -453,6 +466,18 @@ Sliced<T> tuned_sliced(lp_problem *P, const HostSliced &H0, const std::vector<in
     const int S = shape[0];
     if (H0.nb / 2 >= 1) trial(S, H0.nb / 2, H0.rb);
     if (H0.rb != 256) trial(S, shape[1], 256);
+    if (P->opt.split_sums == -1) {
+        Sliced<T> q = best;
+        q.split = !best.split;
+        const float ms = time_product<T>(P, q, in, out, in_len);
+        if (P->opt.verbose)
+            std::fprintf(stderr, "[lp] layout %s row sums %s: %.3f ms against %.3f\n", &log == &P->tune_log_K ? "K" : "K'",
+                         q.split ? "split by entries" : "by rows", ms, best_ms);
+        if (ms < kTuneMargin * best_ms) {
+            best.split = q.split;
+            best_ms = ms;
+        }
+    }
     if (P->opt.verbose)
         for (const auto &t : log)
             std::fprintf(stderr, "[lp] layout %s S=%d nnz/block=%d rows/block=%d: %.3f ms\n",
@@ -475,17 +500,26 @@ void setup_typed(lp_problem *P, const HostSliced &HK, const HostSliced &HT, cons
     auto tvec = [&](int64_t len) { return (T *)P->dalloc(sizeof(T) * (size_t)std::max<int64_t>(len, 1)); };
     P->tmp_n = tvec(n);
     P->tmp_m = tvec(m);
+    // row sums split by entries where a product has enough row blocks to
+    // fill the GPU (split_sums -1), or as asked (0 or 1)
+    auto split_of = [&](const HostSliced &H) {
+        return P->opt.split_sums == -1 ? (int)(H.blk.size() >= (size_t)kSplitMinBlocks) : P->opt.split_sums;
+    };
+    const int split_K = split_of(HK), split_KT = split_of(HT);
     if (P->opt.autotune && !P->ws) {
-        d.K = tuned_sliced<T>(P, HK, rp, ci, kv64, (T *)P->tmp_n, (T *)P->tmp_m, n, P->tune_log_K, P->shape_K);
-        d.KT = tuned_sliced<T>(P, HT, tp, ti, tv64, (T *)P->tmp_m, (T *)P->tmp_n, m, P->tune_log_KT, P->shape_KT);
+        d.K = tuned_sliced<T>(P, HK, rp, ci, kv64, (T *)P->tmp_n, (T *)P->tmp_m, n, P->tune_log_K, P->shape_K, split_K);
+        d.KT = tuned_sliced<T>(P, HT, tp, ti, tv64, (T *)P->tmp_m, (T *)P->tmp_n, m, P->tune_log_KT, P->shape_KT,
+                               split_KT);
     } else {
-        d.K = upload_sliced<T>(P, HK, kv64);
-        d.KT = upload_sliced<T>(P, HT, tv64);
+        d.K = upload_sliced<T>(P, HK, kv64, split_K);
+        d.KT = upload_sliced<T>(P, HT, tv64, split_KT);
         P->shape_K[0] = HK.S; P->shape_K[1] = HK.nb; P->shape_K[2] = HK.rb;
         P->shape_KT[0] = HT.S; P->shape_KT[1] = HT.nb; P->shape_KT[2] = HT.rb;
     }
     P->slices_K = d.K.S;
     P->slices_KT = d.KT.S;
+    P->split_K = d.K.split;
+    P->split_KT = d.KT.split;
     if (std::is_same<T, double>::value) {
         d.cs = (const T *)cs64; d.ls = (const T *)ls64; d.us = (const T *)us64; d.qs = (const T *)qs64;
     } else {
@@ -556,7 +590,7 @@ int check_options(const lp_options &o)
         o.kernel_timing < 0 || o.kernel_timing > 2 ||
         (o.workspace && (reinterpret_cast<uintptr_t>(o.workspace) % 256 != 0)) ||
         (o.presolve != 0 && o.presolve != 1) || (o.presolve && (o.ptr_kind == LP_DEVICE || o.workspace)) ||
-        o.persistent < -1 || o.persistent > 1)
+        o.persistent < -1 || o.persistent > 1 || o.split_sums < -1 || o.split_sums > 1)
         return LP_ERR_ARG;
     return LP_OK;
 }
@@ -1249,6 +1283,7 @@ void lp_default_options(lp_options *o)
     o->verbose = 0;
     o->infeas_tol = 1e-8;
     o->persistent = -1;
+    o->split_sums = -1;
 }
 
 int lp_workspace_size(const lp_csr *K, const lp_options *opt, size_t *bytes)
@@ -1595,6 +1630,13 @@ int lp_layout_blocks(const lp_problem *P, int which, int *slices, int *nnz_per_b
     if (slices) *slices = s[0];
     if (nnz_per_block) *nnz_per_block = s[1];
     if (rows_per_block) *rows_per_block = s[2];
+    return LP_OK;
+}
+
+int lp_layout_split(const lp_problem *P, int which, int *split)
+{
+    if (!P || (which != 0 && which != 1) || !split) return LP_ERR_ARG;
+    *split = which ? P->split_KT : P->split_K;
     return LP_OK;
 }
 

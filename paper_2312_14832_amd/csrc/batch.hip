@@ -11,21 +11,27 @@
 namespace pdlp {
 
 // row block blk of a batch product (end row complemented for long rows)
-template <typename T>
+template <bool SPLIT, typename T>
 __device__ __forceinline__ void batch_block(const int *rp, const int *ci, const T *v, const T *x, const BlockList &L,
-                                            int blk, T *out, T *prod, double *red)
+                                            int blk, T *out, T *prod, double *red, SplitLds<T> *sl)
 {
     const int r0 = L.r0[blk], r1e = L.r1[blk];
     const bool wave = r1e < 0;
     const int r1 = wave ? ~r1e : r1e;
-    stream_block(RowsPlain{rp}, ci, v, x, r0, r1, wave, rp[r0], rp[r1], out, prod, red);
+    stream_block<SPLIT>(RowsPlain{rp}, ci, v, x, r0, r1, wave, rp[r0], rp[r1], out, prod, red, sl);
 }
 
-template <typename T, int WHICH>
+// SPLIT (here and below): short-row blocks summed split by entries (BlockList::split)
+template <typename T, int WHICH, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void bk_product(BDev<T> b)
 {
     __shared__ T prod[kStreamNB];
     __shared__ double red[kBlock / 64];
+    SplitLds<T> *sl = nullptr;
+    if constexpr (SPLIT) {
+        __shared__ SplitLds<T> split_lds;
+        sl = &split_lds;
+    }
     const BlockList &L = WHICH ? b.LT : b.LK;
     const int xcd = (int)blockIdx.x % kXcds;
     const int per = (int)gridDim.x / kXcds;
@@ -34,24 +40,30 @@ __global__ __launch_bounds__(kBlock) void bk_product(BDev<T> b)
         const Ctl *c = b.ctl + L.inst[blk];
         if (c->done || (WHICH == 1 && !c->accepted)) continue;
         if (WHICH == 0)
-            batch_block(b.krp, b.kci, b.kv, (const T *)pick(b.d.xb, c->cur ^ 1), L, blk, b.prodK, prod, red);
+            batch_block<SPLIT>(b.krp, b.kci, b.kv, (const T *)pick(b.d.xb, c->cur ^ 1), L, blk, b.prodK, prod, red,
+                               sl);
         else
-            batch_block(b.trp, b.tci, b.tv, (const T *)pick(b.d.yb, c->cur), L, blk, b.prodKT, prod, red);
+            batch_block<SPLIT>(b.trp, b.tci, b.tv, (const T *)pick(b.d.yb, c->cur), L, blk, b.prodKT, prod, red, sl);
     }
 }
 
-template <typename T, int WHICH>
+template <typename T, int WHICH, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void bk_product_plain(BDev<T> b, const T *__restrict__ in, T *__restrict__ out)
 {
     __shared__ T prod[kStreamNB];
     __shared__ double red[kBlock / 64];
+    SplitLds<T> *sl = nullptr;
+    if constexpr (SPLIT) {
+        __shared__ SplitLds<T> split_lds;
+        sl = &split_lds;
+    }
     const BlockList &L = WHICH ? b.LT : b.LK;
     const int xcd = (int)blockIdx.x % kXcds;
     const int per = (int)gridDim.x / kXcds;
     for (int k = L.xoff[xcd] + (int)blockIdx.x / kXcds; k < L.xoff[xcd + 1]; k += per) {
         const int blk = L.order[k];
-        if (WHICH == 0) batch_block(b.krp, b.kci, b.kv, in, L, blk, out, prod, red);
-        else batch_block(b.trp, b.tci, b.tv, in, L, blk, out, prod, red);
+        if (WHICH == 0) batch_block<SPLIT>(b.krp, b.kci, b.kv, in, L, blk, out, prod, red, sl);
+        else batch_block<SPLIT>(b.trp, b.tci, b.tv, in, L, blk, out, prod, red, sl);
     }
 }
 
@@ -263,16 +275,30 @@ inline int chunk_grid(int chunks) { return chunks < 1 ? 1 : (chunks < 4096 ? chu
 template <typename T>
 hipError_t launch_batch_product(const BDev<T> &b, int which, hipStream_t s)
 {
-    if (which == 0) hipLaunchKernelGGL((bk_product<T, 0>), dim3(b.LK.grid), dim3(kBlock), 0, s, b);
-    else hipLaunchKernelGGL((bk_product<T, 1>), dim3(b.LT.grid), dim3(kBlock), 0, s, b);
+    const BlockList &L = which ? b.LT : b.LK;
+    const dim3 g(L.grid), t(kBlock);
+    if (which == 0) {
+        if (L.split) hipLaunchKernelGGL((bk_product<T, 0, true>), g, t, 0, s, b);
+        else hipLaunchKernelGGL((bk_product<T, 0, false>), g, t, 0, s, b);
+    } else {
+        if (L.split) hipLaunchKernelGGL((bk_product<T, 1, true>), g, t, 0, s, b);
+        else hipLaunchKernelGGL((bk_product<T, 1, false>), g, t, 0, s, b);
+    }
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_batch_product_plain(const BDev<T> &b, int which, const T *in, T *out, hipStream_t s)
 {
-    if (which == 0) hipLaunchKernelGGL((bk_product_plain<T, 0>), dim3(b.LK.grid), dim3(kBlock), 0, s, b, in, out);
-    else hipLaunchKernelGGL((bk_product_plain<T, 1>), dim3(b.LT.grid), dim3(kBlock), 0, s, b, in, out);
+    const BlockList &L = which ? b.LT : b.LK;
+    const dim3 g(L.grid), t(kBlock);
+    if (which == 0) {
+        if (L.split) hipLaunchKernelGGL((bk_product_plain<T, 0, true>), g, t, 0, s, b, in, out);
+        else hipLaunchKernelGGL((bk_product_plain<T, 0, false>), g, t, 0, s, b, in, out);
+    } else {
+        if (L.split) hipLaunchKernelGGL((bk_product_plain<T, 1, true>), g, t, 0, s, b, in, out);
+        else hipLaunchKernelGGL((bk_product_plain<T, 1, false>), g, t, 0, s, b, in, out);
+    }
     return hipGetLastError();
 }
 

@@ -235,6 +235,7 @@ BlockList make_blocks(lp_batch *P, const std::vector<int> &rp, const std::vector
     }
     L.xoff[kXcds] = (int)order.size();
     L.grid = kXcds * std::min(maxper, 512);
+    L.split = P->opt.split_sums == 1;   // by rows unless asked: no faster on the batched workloads
     int *d_r0 = P->arena.make<int>(L.nblk), *d_r1 = P->arena.make<int>(L.nblk);
     int *d_inst = P->arena.make<int>(L.nblk), *d_order = P->arena.make<int>(L.nblk);
     h2d(P->stream, d_r0, r0.data(), L.nblk);
@@ -1002,7 +1003,7 @@ int lp_batch_load(lp_batch **out, int32_t count, const lp_csr *K, const double *
     else lp_default_options(&o);
     if ((o.precision != LP_FP64 && o.precision != LP_MIXED) || o.check_every <= 0 || o.ruiz_iters < 0 ||
         (o.fixed_step && !(o.fixed_eta > 0.0)) || o.window <= 0 || !(o.infeas_tol >= 0.0) ||
-        std::isinf(o.infeas_tol))
+        std::isinf(o.infeas_tol) || o.split_sums < -1 || o.split_sums > 1)
         return LP_ERR_ARG;
     std::unique_ptr<lp_batch> P(new lp_batch());
     P->B = count;

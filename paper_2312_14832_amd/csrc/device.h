@@ -676,17 +676,103 @@ struct RowsRel {
     }
 };
 
+// LDS of the split row sums of a block of short rows (stream_block, SPLIT).
+// Thread t walks the products of chunk t, entries [8t, 8t + 8) of the block.
+template <typename T>
+struct SplitLds {
+    unsigned short rend[kStreamRB];   // each row's end, relative to the block's first entry
+    unsigned short head[kBlock];      // the row holding each chunk's first entry
+    unsigned short crow[kBlock];      // the row a chunk's walk leaves open (kNoRow: none)
+    T cval[kBlock];                   // that row's sum over the chunk
+};
+constexpr unsigned short kNoRow = 0xFFFF;
+
+// The split sums of stream_block (SPLIT, a block of short rows, rows
+// [r0, r1) with entries [b, b + cnt)), after the products, row ends and chunk
+// heads are in LDS and a barrier; rs, re hold the extents of the thread's
+// rows r0 + t + kBlock j, which it stores to out at the end.  See
+// stream_block.
+template <int U, int RU, typename T>
+__device__ __forceinline__ void split_row_sums(const int (&rs)[RU], const int (&re)[RU], int r0, int r1, int b,
+                                               int cnt, T *__restrict__ out, T *prod, SplitLds<T> *L)
+{
+    const int t = (int)threadIdx.x, c0 = t * U, c1 = min(c0 + U, cnt);
+    int prow = -1;   // the crossing row this thread finishes, if any
+    T pval = T(0);
+    if (c0 < cnt) {
+        int i = L->head[t];
+        int is = i ? (int)L->rend[i - 1] : 0, ie = L->rend[i];
+        const bool crossing = is < c0;
+        bool first = true;
+        T acc = T(0);
+        for (int p = c0; p < c1; ++p) {
+            if (p >= ie) {   // row i ended before entry p
+                if (first && crossing) {
+                    prow = i;
+                    pval = acc;
+                } else {
+                    prod[is] = acc;
+                }
+                first = false;
+                acc = T(0);
+                do {   // on to the row holding p (past empty rows)
+                    ++i;
+                    is = ie;
+                    ie = L->rend[i];
+                } while (ie <= p);
+            }
+            acc += prod[p];
+        }
+        if (ie == c1) {   // the last row ends with the chunk
+            if (first && crossing) {
+                prow = i;
+                pval = acc;
+            } else {
+                prod[is] = acc;
+            }
+            L->crow[t] = kNoRow;
+        } else {
+            L->crow[t] = (unsigned short)i;
+            L->cval[t] = acc;
+        }
+    } else {
+        L->crow[t] = kNoRow;
+    }
+    __syncthreads();
+    if (prow >= 0) {   // the open parts of the chunks before this one, nearest first
+        T tot = pval;
+        for (int u = t - 1; u >= 0 && (int)L->crow[u] == prow; --u) tot = L->cval[u] + tot;
+        prod[prow ? (int)L->rend[prow - 1] : 0] = tot;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < RU; ++j) {
+        const int r = r0 + t + j * kBlock;
+        if (r < r1) out[r] = rs[j] == re[j] ? T(0) : prod[rs[j] - b];
+    }
+}
+
 // CSR-Stream sums of one row block: rows [r0, r1) whose entries are [b, e),
-// row extents from rows (RowsPlain or RowsRel).  Products are staged in LDS; in a
-// block of short rows (at most kStreamRB) each thread sums every kBlock-th
-// row in index order, in a block of long rows (wave set, at most kBlock/64)
-// each wavefront sums one row, lanes striding and a butterfly combining them.
-// A block of one row longer than kStreamNB is summed by the whole workgroup.
-// Every thread of the workgroup must call it.
-template <typename T, typename ROWS>
+// row extents from rows (RowsPlain or RowsRel).  Products are staged in LDS.
+// In a block of short rows (at most kStreamRB) each thread sums every
+// kBlock-th row in index order; with SPLIT the sums are split by entries
+// instead, so that a few long rows among short ones do not hold up their
+// wavefront: thread t adds up the products of chunk t (8 entries) row by
+// row, a row that lies wholly in the chunk is finished there, and a row that
+// crosses chunks is finished by the thread holding its last entry, which adds
+// the open parts of the chunks before its own in a fixed order.  Every
+// finished sum is parked in the LDS slot of its row's first product (a slot
+// the chunk's own walk has already read, or, for a crossing row, after a
+// barrier), then every thread stores its rows as before.  In a block of long
+// rows (wave set, at most kBlock/64) each wavefront sums one row, lanes
+// striding and a butterfly combining them.  A block of one row longer than
+// kStreamNB is summed by the whole workgroup.  Every thread of the workgroup
+// must call it.
+template <bool SPLIT = false, typename T, typename ROWS>
 __device__ __forceinline__ void stream_block(const ROWS &rows, const int *__restrict__ ci,
                                              const T *__restrict__ v, const T *__restrict__ x, int r0, int r1,
-                                             bool wave, int b, int e, T *__restrict__ out, T *prod, double *red)
+                                             bool wave, int b, int e, T *__restrict__ out, T *prod, double *red,
+                                             SplitLds<T> *L = nullptr)
 {
     const int cnt = e - b;
     // a multi-row block never exceeds kStreamNB nonzeros, only a single row can
@@ -721,8 +807,23 @@ __device__ __forceinline__ void stream_block(const ROWS &rows, const int *__rest
                 if (t < cnt) prod[t] = a[u] * g[u];
             }
         }
+        if constexpr (SPLIT) {
+            if (!wave) {   // row ends, and the row of each chunk's first entry
+#pragma unroll
+                for (int j = 0; j < RU; ++j) {
+                    const int r = (int)threadIdx.x + j * kBlock;
+                    if (r0 + r < r1) {
+                        const int s = rs[j] - b, f = re[j] - b;
+                        L->rend[r] = (unsigned short)f;
+                        for (int k = (s + U - 1) / U; k * U < f; ++k) L->head[k] = (unsigned short)r;
+                    }
+                }
+            }
+        }
         __syncthreads();
-        if (!wave) {
+        if (SPLIT && !wave) {
+            split_row_sums<U>(rs, re, r0, r1, b, cnt, out, prod, L);
+        } else if (!wave) {
 #pragma unroll
             for (int j = 0; j < RU; ++j) {
                 const int r = r0 + (int)threadIdx.x + j * kBlock;
@@ -837,11 +938,16 @@ __device__ __forceinline__ void ray_sums_pass(const Dev<T> &d, int c, int vb_n, 
 // One column slice's partial products (see Sliced): workgroup b takes slice
 // b % S and walks that slice's row blocks with stride gridDim / S.  LONG:
 // the product has long rows, so some blocks are chunks of one.
-template <bool LONG, typename T>
+template <bool LONG, bool SPLIT = false, typename T>
 __device__ __forceinline__ void sliced_partial(const Sliced<T> &P, const T *__restrict__ x)
 {
     __shared__ T prod[kStreamNB];
     __shared__ double red[kBlock / 64];
+    SplitLds<T> *split = nullptr;
+    if constexpr (SPLIT) {
+        __shared__ SplitLds<T> split_lds;
+        split = &split_lds;
+    }
     const int S = P.S;
     const int s = (int)blockIdx.x % S;
     const int chunk0 = (int)blockIdx.x / S, stride = (int)gridDim.x / S;
@@ -859,7 +965,7 @@ __device__ __forceinline__ void sliced_partial(const Sliced<T> &P, const T *__re
             }
         }
         const bool wave = q.y < 0;
-        stream_block(rows, P.ci, P.v, x, q.x, wave ? ~q.y : q.y, wave, q.z, q.w, out, prod, red);
+        stream_block<SPLIT>(rows, P.ci, P.v, x, q.x, wave ? ~q.y : q.y, wave, q.z, q.w, out, prod, red, split);
     }
 }
 

@@ -60,6 +60,7 @@ struct Sliced {
     const int *loff;  // [nlong+1] long row k owns lpart[loff[k] .. loff[k+1]), slice-major
     T *lpart;         // chunk dot products of the long rows
     int nlpart;       // entries of lpart (loff[nlong])
+    int split;        // 1: blocks of short rows summed split by entries, not one row per thread
 };
 
 // check modes
@@ -148,6 +149,7 @@ struct BlockList {
     const int *r0, *r1, *inst, *order;   // r1 complemented for wavefront-row blocks
     int xoff[kXcds + 1];
     int grid;                 // workgroups of the product kernel (a multiple of 8)
+    int split;                // 1: short-row blocks summed split by entries (stream_block SPLIT)
 };
 
 // A batch of LPs concatenated block-diagonally.  Every instance's n- and

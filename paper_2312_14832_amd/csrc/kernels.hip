@@ -37,22 +37,23 @@ namespace pdlp {
 // ----------------------------------------------------------------------------
 
 // K x' partial products (x' = the primal trial).  LONG (here and below): the
-// product has rows cut into chunks.
-template <typename T, bool LONG>
+// product has rows cut into chunks; SPLIT: its short-row blocks are summed
+// split by entries (Sliced::split).
+template <typename T, bool LONG, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_partial_K(Dev<T> d)
 {
     const Ctl *ctl = d.ctl;
     if (ctl->done) return;
-    sliced_partial<LONG>(d.K, (const T *)pick(d.xb, ctl->cur ^ 1));
+    sliced_partial<LONG, SPLIT>(d.K, (const T *)pick(d.xb, ctl->cur ^ 1));
 }
 
 // K' y' partial products, only after an accepted step
-template <typename T, bool LONG>
+template <typename T, bool LONG, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_partial_KT(Dev<T> d)
 {
     const Ctl *ctl = d.ctl;
     if (ctl->done || !ctl->accepted) return;
-    sliced_partial<LONG>(d.KT, (const T *)pick(d.yb, ctl->cur));
+    sliced_partial<LONG, SPLIT>(d.KT, (const T *)pick(d.yb, ctl->cur));
 }
 
 template <typename T, int NS, bool LONG>
@@ -812,10 +813,10 @@ __global__ __launch_bounds__(kBlock) void k_gather_probe(const int *__restrict__
     out[(size_t)blockIdx.x * kBlock + threadIdx.x] = acc;
 }
 
-template <typename T, bool LONG>
+template <typename T, bool LONG, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_partial_plain(Sliced<T> P, const T *__restrict__ x)
 {
-    sliced_partial<LONG>(P, x);
+    sliced_partial<LONG, SPLIT>(P, x);
 }
 
 template <typename T, bool LONG>
@@ -1030,16 +1031,28 @@ static inline int blocks_for(int64_t len) { return (int)((len + kBlock - 1) / kB
 template <typename T>
 hipError_t launch_partial_K(const Dev<T> &d, hipStream_t s)
 {
-    if (d.K.nlong) hipLaunchKernelGGL((k_partial_K<T, true>), dim3(d.K.grid), dim3(kBlock), 0, s, d);
-    else hipLaunchKernelGGL((k_partial_K<T, false>), dim3(d.K.grid), dim3(kBlock), 0, s, d);
+    const dim3 g(d.K.grid), t(kBlock);
+    if (d.K.nlong) {
+        if (d.K.split) hipLaunchKernelGGL((k_partial_K<T, true, true>), g, t, 0, s, d);
+        else hipLaunchKernelGGL((k_partial_K<T, true, false>), g, t, 0, s, d);
+    } else {
+        if (d.K.split) hipLaunchKernelGGL((k_partial_K<T, false, true>), g, t, 0, s, d);
+        else hipLaunchKernelGGL((k_partial_K<T, false, false>), g, t, 0, s, d);
+    }
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_partial_KT(const Dev<T> &d, hipStream_t s)
 {
-    if (d.KT.nlong) hipLaunchKernelGGL((k_partial_KT<T, true>), dim3(d.KT.grid), dim3(kBlock), 0, s, d);
-    else hipLaunchKernelGGL((k_partial_KT<T, false>), dim3(d.KT.grid), dim3(kBlock), 0, s, d);
+    const dim3 g(d.KT.grid), t(kBlock);
+    if (d.KT.nlong) {
+        if (d.KT.split) hipLaunchKernelGGL((k_partial_KT<T, true, true>), g, t, 0, s, d);
+        else hipLaunchKernelGGL((k_partial_KT<T, true, false>), g, t, 0, s, d);
+    } else {
+        if (d.KT.split) hipLaunchKernelGGL((k_partial_KT<T, false, true>), g, t, 0, s, d);
+        else hipLaunchKernelGGL((k_partial_KT<T, false, false>), g, t, 0, s, d);
+    }
     return hipGetLastError();
 }
 
@@ -1217,10 +1230,12 @@ hipError_t launch_spmv(const Sliced<T> &P, const T *in, T *out, hipStream_t s)
 {
     if (P.rows <= 0) return hipSuccess;
     if (P.nlong) {
-        hipLaunchKernelGGL((k_partial_plain<T, true>), dim3(P.grid), dim3(kBlock), 0, s, P, in);
+        if (P.split) hipLaunchKernelGGL((k_partial_plain<T, true, true>), dim3(P.grid), dim3(kBlock), 0, s, P, in);
+        else hipLaunchKernelGGL((k_partial_plain<T, true, false>), dim3(P.grid), dim3(kBlock), 0, s, P, in);
         hipLaunchKernelGGL((k_sum_slices<T, true>), dim3(blocks_for(P.rows)), dim3(kBlock), 0, s, P, out);
     } else {
-        hipLaunchKernelGGL((k_partial_plain<T, false>), dim3(P.grid), dim3(kBlock), 0, s, P, in);
+        if (P.split) hipLaunchKernelGGL((k_partial_plain<T, false, true>), dim3(P.grid), dim3(kBlock), 0, s, P, in);
+        else hipLaunchKernelGGL((k_partial_plain<T, false, false>), dim3(P.grid), dim3(kBlock), 0, s, P, in);
         hipLaunchKernelGGL((k_sum_slices<T, false>), dim3(blocks_for(P.rows)), dim3(kBlock), 0, s, P, out);
     }
     return hipGetLastError();

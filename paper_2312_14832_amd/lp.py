@@ -25,7 +25,7 @@ NSCALARS = 16
 # every symbol include/lp.h declares
 EXPORTS = ["lp_default_options", "lp_workspace_size", "lp_load", "lp_set_start", "lp_set_start_weight", "lp_solve", "lp_result", "lp_get_state",
            "lp_set_state", "lp_get_scaling", "lp_spmv", "lp_spmv_noalloc", "lp_gather_probe", "lp_kernel_time", "lp_device_bytes", "lp_layout",
-           "lp_layout_blocks", "lp_presolved_size", "lp_free",
+           "lp_layout_blocks", "lp_layout_split", "lp_presolved_size", "lp_free",
            "lp_strerror", "lp_last_error", "lp_batch_load", "lp_batch_solve", "lp_batch_result",
            "lp_batch_get_state", "lp_batch_set_state", "lp_batch_device_bytes", "lp_batch_layout_blocks", "lp_batch_loop_form",
            "lp_batch_free",
@@ -47,7 +47,7 @@ class LPOptions(C.Structure):
                 ("window", C.c_int), ("kernel_timing", C.c_int), ("slice_kib", C.c_int),
                 ("autotune", C.c_int), ("verbose", C.c_int), ("ptr_kind", C.c_int),
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t), ("infeas_tol", C.c_double),
-                ("presolve", C.c_int), ("persistent", C.c_int)]
+                ("presolve", C.c_int), ("persistent", C.c_int), ("split_sums", C.c_int)]
 
 
 class LPInfo(C.Structure):
@@ -89,6 +89,7 @@ def library():
         L.lp_layout.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.lp_layout_blocks.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                        C.POINTER(C.c_int)]
+        L.lp_layout_split.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_int)]
         L.lp_presolved_size.argtypes = [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.lp_free.argtypes = [C.c_void_p]
         L.lp_free.restype = None
@@ -318,6 +319,12 @@ class Problem:
         s, nb, rb = C.c_int(), C.c_int(), C.c_int()
         self._check(library().lp_layout_blocks(self.h, which, C.byref(s), C.byref(nb), C.byref(rb)))
         return s.value, nb.value, rb.value
+
+    def layout_split(self, which):
+        """1 if the partial passes of K (0) or K' (1) sum short rows split by entries, else 0."""
+        v = C.c_int()
+        self._check(library().lp_layout_split(self.h, which, C.byref(v)))
+        return v.value
 
     def device_bytes(self):
         b = C.c_int64()

@@ -40,9 +40,12 @@ def tiny_batch(count=8, seed0=5000):
     return lps
 
 
-def test_batch_lockstep_fp64(lpmod, oracle_mod):
+@pytest.mark.parametrize("split", [-1, 1])
+def test_batch_lockstep_fp64(lpmod, oracle_mod, split):
+    """split: the products' short-row blocks summed one row per thread (the
+    default) or split by entries."""
     lps = small_batch()
-    bt = lpmod.Batch(lps)
+    bt = lpmod.Batch(lps, split_sums=split)
     assert bt.loop_form() == 0
     batch_lockstep(lpmod, oracle_mod, lps, bt, [0, 1, 63, 64, 200, 511])
 

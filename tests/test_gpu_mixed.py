@@ -108,6 +108,7 @@ def test_mixed_full_size(lpmod, oracle_mod):
     say("case mixed full size: load")
     p = lpmod.Problem(data, precision="mixed")
     assert p.layout() == (8, 4)
+    assert (p.layout_split(0), p.layout_split(1)) == (1, 1)
     o = oracle_mod.Oracle(data)
     Dr, Dc = p.scaling()
     Dr_o, Dc_o, _ = o.scaling()

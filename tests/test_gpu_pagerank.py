@@ -126,6 +126,7 @@ def test_pagerank_full_size(lpmod, oracle_mod):
     data = gen.pagerank_lp(1, 1_000_000)
     say("case pagerank full size: load")
     p = lpmod.Problem(data)
+    assert (p.layout_split(0), p.layout_split(1)) == (1, 1)
     o = oracle_mod.Oracle(data)
     Dr, Dc = p.scaling()
     Dr_o, Dc_o, _ = o.scaling()

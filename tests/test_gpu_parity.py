@@ -45,19 +45,27 @@ def test_scaling_matches_oracle(lpmod, oracle_mod, seed):
     assert np.max(np.abs(Dc - Dc_o) / Dc_o) < 1e-13
 
 
+@pytest.mark.parametrize("split", [-1, 0, 1])
 @pytest.mark.parametrize("slice_kib", [2048, 1])
-@pytest.mark.parametrize("maker", ["tiny", "powerlaw", "long_rows"])
-def test_spmv_matches_oracle(lpmod, oracle_mod, maker, slice_kib):
+@pytest.mark.parametrize("maker", ["tiny", "powerlaw", "long_rows", "mixed_rows"])
+def test_spmv_matches_oracle(lpmod, oracle_mod, maker, slice_kib, split):
     """Both sliced products against the oracle's plain CSR loops; slice_kib=1
-    forces many column slices (and row blocks) even on small inputs."""
-    say(f"case spmv {maker} slice_kib={slice_kib}")
+    forces many column slices (and row blocks) even on small inputs.  split:
+    the row sums of short-row blocks one row per thread (0), split by entries
+    (1), or the default (split in a product of at least 1024 row blocks; no
+    autotuning here)."""
+    say(f"case spmv {maker} slice_kib={slice_kib} split={split}")
     if maker == "tiny":
         data = gen.tiny_lp(3)
     elif maker == "powerlaw":
         data = gen.large_lp(seed=5, n=20000, m1=5000, m2=5000)
+    elif maker == "mixed_rows":
+        data = mixed_rows_lp(8)
     else:
         data = long_rows_lp(7)
-    p = lpmod.Problem(data, slice_kib=slice_kib)
+    p = lpmod.Problem(data, slice_kib=slice_kib, split_sums=split)
+    if split >= 0:
+        assert (p.layout_split(0), p.layout_split(1)) == (split, split)
     if slice_kib == 1:
         assert p.layout()[0] > 1
     o = oracle_mod.Oracle(data)
@@ -84,6 +92,18 @@ def long_rows_lp(seed):
     return lpd
 
 
+def mixed_rows_lp(seed):
+    """Columns of 0 to 200 nonzeros, most of them short: rows of K' of every
+    length a short-row block holds (0 to 64 entries, so rows that cross the
+    8-entry chunks of the split row sums, runs of empty rows, rows ending on
+    a chunk boundary) next to rows long enough for the wavefront blocks."""
+    rng = np.random.default_rng(seed)
+    n, m1, m2 = 3000, 1000, 1500
+    counts = rng.choice([0, 1, 1, 2, 3, 7, 8, 9, 15, 16, 17, 33, 63, 64, 65, 120, 200], size=n)
+    from paper_2312_14832_amd.gen import certificate_lp
+    return certificate_lp(np.random.Generator(np.random.PCG64(seed)), m1, m2, counts.astype(np.int64))
+
+
 LOCKSTEP_POINTS = [0, 1, 2, 7, 62, 63, 64, 65, 100, 126, 127, 128, 191, 255, 300, 383, 511, 640, 767, 900, 1023]
 
 
@@ -92,6 +112,18 @@ LOCKSTEP_POINTS = [0, 1, 2, 7, 62, 63, 64, 65, 100, 126, 127, 128, 191, 255, 300
                                                          (5, 1, 20000, -1), (6, 2048, -1500, 1),
                                                          (7, 2048, -4000, 1)])
 def test_lockstep_one_step_fp64(lpmod, oracle_mod, seed, slice_kib, n, persistent):
+    run_lockstep_one_step(lpmod, oracle_mod, seed, slice_kib, n, persistent)
+
+
+@pytest.mark.parametrize("seed,slice_kib,n,split", [(5, 1, 20000, 1), (5, 1, 20000, 0), (2, 2048, 20000, 1),
+                                                    (0, 2048, 0, 1)])
+def test_lockstep_split_sums(lpmod, oracle_mod, seed, slice_kib, n, split):
+    """The same per-step parity with the row sums of both products split by
+    entries (split = 1) or one row per thread in both (split = 0)."""
+    run_lockstep_one_step(lpmod, oracle_mod, seed, slice_kib, n, 0, split_sums=split)
+
+
+def run_lockstep_one_step(lpmod, oracle_mod, seed, slice_kib, n, persistent, **opts):
     """Per-iteration parity: from the oracle's state after k accepted steps,
     one more accepted step on the GPU (including the check and restart that
     fall on k+1) equals the oracle's next state.  n > 0 takes a power-law LP
@@ -107,10 +139,10 @@ def test_lockstep_one_step_fp64(lpmod, oracle_mod, seed, slice_kib, n, persisten
         data = gen.tiny_lp(seed, n=nn, m1=nn // 15, m2=nn // 15, per_col=2 if nn < 2000 else 5)
     else:
         data = gen.tiny_lp(seed) if n == 0 else gen.large_lp(seed=seed, n=n, m1=n // 4, m2=n // 4)
-    p = lpmod.Problem(data, slice_kib=slice_kib, persistent=persistent)
-    if n == 2000:
+    p = lpmod.Problem(data, slice_kib=slice_kib, persistent=persistent, **opts)
+    if n == 2000 and slice_kib == 1:
         assert p.layout()[0] == 16
-    if n == 20000:
+    if n == 20000 and slice_kib == 1:
         assert p.layout() == (32, 32)
     o = oracle_mod.Oracle(data)
     Dr, Dc, _ = o.scaling()
@@ -412,6 +444,7 @@ def test_full_size_large_lp(lpmod, oracle_mod):
     say("case full size: load")
     p = lpmod.Problem(data)
     assert p.layout() == (8, 4)
+    assert (p.layout_split(0), p.layout_split(1)) == (1, 1)   # row sums split by entries, as benched
     o = oracle_mod.Oracle(data)
     Dr, Dc = p.scaling()
     Dr_o, Dc_o, _ = o.scaling()
