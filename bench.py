@@ -262,6 +262,9 @@ def main():
     ap.add_argument("--ttt-limit", type=float, default=90.0)
     ap.add_argument("--ws-train", type=int, default=2048, help="warmstart: training instances")
     ap.add_argument("--ws-eval", type=int, default=1000, help="warmstart: held-out instances")
+    ap.add_argument("--ws-label-precision", choices=["fp64", "mixed"], default="fp64",
+                    help="warmstart: precision of the label solves (mixed: FP32 products, every label's 1e-5 "
+                         "confirmed by the FP64 re-check)")
     ap.add_argument("--ws-epochs", type=int, default=120)
     ap.add_argument("--ws-time-sample", type=int, default=64,
                     help="warmstart: held-out members also timed one by one on single handles")
@@ -900,7 +903,8 @@ def bench_warmstart(args):
     log(f"generated family n={base.n} m={base.m} nnz={base.nnz}: {len(train_lps)} train, {len(eval_lps)} held out "
         f"in {time.perf_counter() - t0:.1f}s")
     t0 = time.perf_counter()
-    Z, infos = ws.solve_labels(train_lps, tol=1e-5, group=128, max_iters=20000, log=log)
+    Z, infos = ws.solve_labels(train_lps, tol=1e-5, group=128, max_iters=20000, log=log,
+                               precision=args.ws_label_precision)
     label_s = time.perf_counter() - t0
     ok = sum(1 for i in infos if i["status"] == "OPTIMAL")
     log(f"labels: {ok}/{len(infos)} optimal at 1e-5 in {label_s:.1f}s ({len(infos) / label_s:.2f} per second)")
@@ -952,7 +956,7 @@ def bench_warmstart(args):
     summ["base_start_family_omega"]["omega"] = om_fam
     # learning curve: the network trained on the first `count` labels
     curve = []
-    for count in sorted({c for c in (used // 8, used // 4, used // 2) if c >= 64}):
+    for count in sorted({c for c in (used // 8, used // 4, used // 2, 2048) if 64 <= c < used}):
         _, lc, _, pc = trained(count)
         r = mean_iters([fam.decode(v) for v in pc], f"network trained on {count}")
         curve.append({"train": count, "loss_last": lc[-1], "iters_mean": r["iters_mean"]})
@@ -986,7 +990,8 @@ def bench_warmstart(args):
         "data": "synthetic",
         "config": {"workload": "parametric_family_n200000", "n": base.n, "m1": base.m1, "m2": base.m - base.m1,
                    "nnz": base.nnz, "train": len(train_lps), "train_used": used, "held_out": len(eval_lps),
-                   "label_tol": 1e-5, "tol": 1e-4, "epochs": args.ws_epochs, "perturbation": 0.1},
+                   "label_tol": 1e-5, "label_precision": args.ws_label_precision, "tol": 1e-4,
+                   "epochs": args.ws_epochs, "perturbation": 0.1},
         "summary": summ,
         "learning_curve": curve,
         "timing": timing,
