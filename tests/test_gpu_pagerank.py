@@ -31,14 +31,16 @@ def dense_rows_lp(seed, n=30000, m1=3, m2=2000):
                       c=rng.standard_normal(n), q=rng.standard_normal(m), l=np.zeros(n), u=np.full(n, 10.0))
 
 
+@pytest.mark.parametrize("split", [-1, 1])
 @pytest.mark.parametrize("slice_kib", [2048, 1])
 @pytest.mark.parametrize("maker", ["pagerank", "dense_rows"])
-def test_spmv_long_rows(lpmod, oracle_mod, maker, slice_kib):
+def test_spmv_long_rows(lpmod, oracle_mod, maker, slice_kib, split):
     """K x and K' y against the oracle's CSR loops, default layout and 1 KiB
-    slices (32 slices: every dense row is split over them)."""
-    say(f"case spmv {maker} slice_kib={slice_kib}")
+    slices (32 slices: every dense row is split over them); split = 1 sums
+    the short-row blocks split by entries next to the long-row chunks."""
+    say(f"case spmv {maker} slice_kib={slice_kib} split={split}")
     data = gen.pagerank_lp(2, 20000) if maker == "pagerank" else dense_rows_lp(3)
-    p = lpmod.Problem(data, slice_kib=slice_kib)
+    p = lpmod.Problem(data, slice_kib=slice_kib, split_sums=split)
     o = oracle_mod.Oracle(data)
     rng = np.random.default_rng(1)
     for tr, v in [(False, rng.standard_normal(data.n)), (True, rng.standard_normal(data.m))]:
