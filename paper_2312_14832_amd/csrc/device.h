@@ -395,29 +395,46 @@ __device__ inline void step_factors(long long k, double &f_lo, double &f_hi)
     f_hi = 1.0 + pow(kk, -0.6);
 }
 
+// The adaptive step rule of one attempt with step size eta (the factors of
+// the current accepted count given, step_factors): 1 accept, 0 reject, -1 a
+// NaN in the test; eta_new is the next step size (eta itself on a NaN or
+// with a fixed step).
+__device__ inline int step_rule(double eta, double omega, int fixed_step, double dx2, double dy2, double inter,
+                                double f_lo, double f_hi, double &eta_new)
+{
+    eta_new = eta;
+    if (fixed_step) return 1;
+    const double N = omega * dx2 + dy2 / omega;
+    const double D = 2.0 * fabs(inter);
+    if (isnan(N) || isnan(D)) return -1;
+    const double eta_bar = D > 0.0 ? N / D : INFINITY;
+    const double lo = f_lo * eta_bar;
+    const double hi = f_hi * eta;
+    eta_new = lo < hi ? lo : hi;
+    return eta <= eta_bar ? 1 : 0;
+}
+
+// The check mode after an accepted step that brings the accepted count to k
+__device__ inline int mode_after_accept(long long k, int check_every, long long max_iters)
+{
+    return (k % check_every == 0 || k >= max_iters) ? MODE_CHECK : MODE_NONE;
+}
+
 // The step decision with the factors of the current accepted count given
 // (step_factors), for callers that tabulate them ahead.
 __device__ inline void step_decision_f(Ctl *ctl, double dx2, double dy2, double inter, double f_lo, double f_hi)
 {
-    const double eta = ctl->eta, omega = ctl->omega;
-    double eta_new = eta;
-    bool accept = true;
+    const double eta = ctl->eta;
+    double eta_new;
     ctl->attempts += 1;
-    if (!ctl->fixed_step) {
-        const double N = omega * dx2 + dy2 / omega;
-        const double D = 2.0 * fabs(inter);
-        if (isnan(N) || isnan(D)) {
-            ctl->numerical = 1;
-            ctl->accepted = 0;
-            ctl->mode = MODE_CHECK;
-            return;
-        }
-        const double eta_bar = D > 0.0 ? N / D : INFINITY;
-        const double lo = f_lo * eta_bar;
-        const double hi = f_hi * eta;
-        eta_new = lo < hi ? lo : hi;
-        accept = eta <= eta_bar;
+    const int rule = step_rule(eta, ctl->omega, ctl->fixed_step, dx2, dy2, inter, f_lo, f_hi, eta_new);
+    if (rule < 0) {
+        ctl->numerical = 1;
+        ctl->accepted = 0;
+        ctl->mode = MODE_CHECK;
+        return;
     }
+    const bool accept = rule == 1;
     if (accept) {
         ctl->W += eta;
         ctl->avg_w = eta / ctl->W;
@@ -426,7 +443,7 @@ __device__ inline void step_decision_f(Ctl *ctl, double dx2, double dy2, double 
         ctl->t += 1;
         ctl->cur ^= 1;
         ctl->accepted = 1;
-        ctl->mode = (ctl->k % ctl->check_every == 0 || ctl->k >= ctl->max_iters) ? MODE_CHECK : MODE_NONE;
+        ctl->mode = mode_after_accept(ctl->k, ctl->check_every, ctl->max_iters);
     } else {
         ctl->accepted = 0;
         ctl->mode = MODE_NONE;

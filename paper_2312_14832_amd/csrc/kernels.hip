@@ -310,6 +310,33 @@ __device__ __forceinline__ void small_sum(double (&v)[NV], double (*sh)[kCheckSu
     __syncthreads();
 }
 
+// small_sum with a single barrier: every thread gets the totals, and the
+// caller must pass another barrier before the next small_sum or
+// small_sum_once writes sh.
+template <int NV, int NT>
+__device__ __forceinline__ void small_sum_once(double (&v)[NV], double (*sh)[kCheckSums])
+{
+    const int lane = (int)threadIdx.x & 63, wave = (int)threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double a = v[i];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) a += __shfl_xor(a, off);
+        v[i] = a;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) sh[wave][i] = v[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        double t = sh[0][i];
+        for (int w = 1; w < NT / 64; ++w) t += sh[w][i];
+        v[i] = t;
+    }
+}
+
 // The decisions outside the loop body's register allocation: inlined, their
 // math calls would make the whole kernel spill.  Only thread 0 calls them.
 __device__ __noinline__ void small_step_decision(Ctl *c, double dx2, double dy2, double inter)
@@ -552,6 +579,8 @@ __device__ __forceinline__ void small_reg_body(const Dev<T> &d, int max_slots, d
     if (tid == 0) sc = *d.ctl;
     __syncthreads();
     const long long k0 = sc.k;
+    const int sc_fixed = sc.fixed_step, sc_every = sc.check_every;   // fixed for the launch
+    const long long sc_maxit = sc.max_iters;
     for (int t = tid; t < max_slots; t += NT) step_factors(k0 + t, tab[2 * t], tab[2 * t + 1]);
     // columns j = tid + r NT, rows i = tid + r NT
     T xc[R], xt[R], ktc[R], xa[R], kta[R], cj[R], lj[R], uj[R];
@@ -585,9 +614,15 @@ __device__ __forceinline__ void small_reg_body(const Dev<T> &d, int max_slots, d
     __syncthreads();
     for (int slot = 0; slot < max_slots; ++slot) {
         if (sc.done) break;   // the same LDS value for every thread
+        // the controller fields the step decision reads, taken before the
+        // barrier after which thread 0 updates the controller
+        const double eta = sc.eta, omega = sc.omega, W = sc.W;
+        const long long kk = sc.k;
+        int accepted, mode;
+        double eta_next, avg_w = 0.0;
         {
             // K x' and the dual step
-            const T sigma = (T)(sc.eta * sc.omega);
+            const T sigma = (T)(eta * omega);
             double v[3] = {dx2, 0.0, 0.0};
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -604,17 +639,22 @@ __device__ __forceinline__ void small_reg_body(const Dev<T> &d, int max_slots, d
                     v[2] += dd * ((double)s - (double)kxc[r]);
                 }
             }
-            small_sum<3, NT>(v, sh);
-            if (tid == 0) {
-                const int at = (int)(sc.k - k0);   // < max_slots: one accepted step per slot at most
-                step_decision_f(&sc, v[0], v[1], v[2], tab[2 * at], tab[2 * at + 1]);
-            }
-            __syncthreads();
+            small_sum_once<3, NT>(v, sh);
+            // every thread takes the step decision (the same arithmetic as
+            // thread 0's update of the controller, so no barrier is needed
+            // before the results are used)
+            const int at = (int)(kk - k0);   // < max_slots: one accepted step per slot at most
+            const int rule = step_rule(eta, omega, sc_fixed, v[0], v[1], v[2], tab[2 * at], tab[2 * at + 1], eta_next);
+            accepted = rule == 1;
+            mode = rule < 0 ? MODE_CHECK : (rule == 1 ? mode_after_accept(kk + 1, sc_every, sc_maxit) : MODE_NONE);
+            if (rule < 0) eta_next = eta;
+            if (rule == 1) avg_w = eta / (W + eta);
+            if (tid == 0) step_decision_f(&sc, v[0], v[1], v[2], tab[2 * at], tab[2 * at + 1]);
         }
         {
-            const T tau = (T)(sc.eta / sc.omega);
+            const T tau = (T)(eta_next / omega);
             dx2 = 0.0;
-            if (!sc.accepted) {
+            if (!accepted) {
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const int j = tid + r * NT;
@@ -628,8 +668,8 @@ __device__ __forceinline__ void small_reg_body(const Dev<T> &d, int max_slots, d
                 }
             } else {
                 // the trials become the current point; K'y', averages, next trial
-                const T w = (T)sc.avg_w;
-                const bool primal = sc.mode == MODE_NONE;
+                const T w = (T)avg_w;
+                const bool primal = mode == MODE_NONE;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const int i = tid + r * NT, j = i;
