@@ -19,7 +19,8 @@
 //
 // Each product is a column-sliced CSR-Stream pass (see Sliced in internal.h):
 // a workgroup stages the products v*x[col] of one row block in LDS with
-// coalesced streaming loads, then sums each row from LDS; the slice of x it
+// coalesced streaming loads, then sums the rows from LDS (one row per thread,
+// or split by entries over the threads: Sliced::split); the slice of x it
 // gathers from stays resident in its XCD's L2.  The fused epilogue kernels
 // add the slices' partial rows in a fixed order.
 // Reductions are deterministic: each lane accumulates in FP64, wave64
@@ -549,7 +550,8 @@ __global__ __launch_bounds__(kSmall) void k_small_loop(Dev<T> d, int max_slots, 
 // sums of row_sums_v / col_sums_v / ray_*_v, the bookkeeping of apply_col /
 // apply_row.  The step rule's two factors for the accepted counts this
 // launch can reach (at most max_slots of them) are tabulated in LDS at
-// entry, so the per-slot decision is plain arithmetic in thread 0, inline.
+// entry, so the per-slot step decision is plain arithmetic, which every
+// thread takes for itself while thread 0 alone updates the controller.
 // kSmallReg threads (fewer than the other forms) leave each thread enough
 // registers to hold its R columns and rows without spilling.  The body is
 // shared by the single-LP kernel and the batched one (a workgroup per LP).
