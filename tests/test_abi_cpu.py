@@ -39,6 +39,7 @@ def test_default_options_and_strerror():
     o = lp.default_options()
     assert (o.precision, o.ruiz_iters, o.pc_alpha, o.check_every, o.kkt_omega_power) == (0, 10, 1.0, 64, 2.0)
     assert o.infeas_tol == 1e-8
+    assert (o.persistent, o.split_sums, o.autotune) == (-1, -1, 0)
     L = lp.library()
     for code in [0, -1, -2, -3, -4, -5, -6, -7, -8]:
         assert L.lp_strerror(code)
@@ -92,7 +93,8 @@ def test_bad_options_rejected():
     for kw in [dict(precision=7), dict(check_every=0), dict(window=0), dict(fixed_step=1, fixed_eta=0.0),
                dict(ptr_kind=5), dict(workspace=8, workspace_bytes=1 << 20), dict(infeas_tol=-1.0),
                dict(infeas_tol=float("nan")), dict(infeas_tol=float("inf")), dict(presolve=2),
-               dict(presolve=1, ptr_kind=1), dict(presolve=1, workspace=256, workspace_bytes=1 << 20)]:
+               dict(presolve=1, ptr_kind=1), dict(presolve=1, workspace=256, workspace_bytes=1 << 20),
+               dict(split_sums=2), dict(split_sums=-2), dict(persistent=2)]:
         with pytest.raises(lp.LPError) as ei:
             lp.Problem(gen.tiny_lp(0), **kw)
         assert ei.value.code == -1
@@ -150,7 +152,8 @@ def test_batch_rejects_unsupported_options():
     """lp_batch_load checks its options before any GPU work: device pointers,
     a workspace and presolve are not supported for batches."""
     lp = _lib()
-    for kw in [dict(ptr_kind=1), dict(workspace=256, workspace_bytes=1 << 20), dict(presolve=1), dict(precision=3)]:
+    for kw in [dict(ptr_kind=1), dict(workspace=256, workspace_bytes=1 << 20), dict(presolve=1), dict(precision=3),
+               dict(split_sums=5)]:
         with pytest.raises(lp.LPError) as ei:
             lp.Batch([gen.tiny_lp(0), gen.tiny_lp(1)], **kw)
         assert ei.value.code == -1, kw
